@@ -1,0 +1,130 @@
+"""Residual and energy at any size by sub-cluster inclusion-exclusion.
+
+Every term of H_k acts on at most k pairs, and T only excites.  In
+<mu| e^{-T} H_k e^{T} |0> a term h contributes only through amplitudes whose
+pairs lie in X = labels(mu) U labels(h): amplitudes touching other pairs leave
+those pairs excited, and nothing but h can return them to the reference.  So
+with R^{(Y)} the residual of the sub-system made of the pairs Y alone (same f,
+v and t restricted to Y, evaluated by the definitional tier),
+
+  R_mu = sum_{X >= labels(mu), |X| <= |labels(mu)| + k} dR^{(X)}_mu,
+  dR^{(X)} = sum_{labels(mu) <= Y <= X} (-1)^{|X|-|Y|} R^{(Y)}            (Moebius)
+
+and likewise E_c = sum_{|X| <= k} dE^{(X)} (only h acts on the reference).
+Each dR^{(X)} is the part connected across exactly the pairs X, so the sum
+over X stays well conditioned.  Cost: one small definitional evaluation per
+sub-cluster, so any single output block is available at any N.
+"""
+from __future__ import annotations
+
+import itertools
+from math import comb
+
+import numpy as np
+
+from . import layout
+from .tier_a import TierA
+
+
+class TierB:
+    def __init__(self, npair: int, k: int, f: np.ndarray, eri_packed: np.ndarray):
+        self.N, self.k = npair, k
+        self.f = f
+        self.eri = eri_packed
+        self._engines = {}
+        self._cache = {}
+
+    def engine(self, n: int) -> TierA:
+        if n not in self._engines:
+            self._engines[n] = TierA(n, self.k)
+        return self._engines[n]
+
+    # ------------------------------------------------------------ sub-systems
+    def sub_inputs(self, Y, t):
+        """f, dense truncated integrals and amplitudes of the pairs Y."""
+        N, k = self.N, self.k
+        n = len(Y)
+        orbs = list(Y) + [N + y for y in Y]
+        f_sub = self.f[np.ix_(orbs, orbs)]
+        sub_eri = np.zeros(layout.eri_count(n, k))
+        for size in range(1, min(k, n) + 1):
+            quads = layout.eri_quads(size)
+            goff = layout.eri_block_offset(N, size)
+            gsets = comb(N, size)
+            loff = layout.eri_block_offset(n, size)
+            lsets = comb(n, size)
+            for loc in itertools.combinations(range(n), size):
+                glob = tuple(Y[i] for i in loc)
+                gi = layout.set_index(glob)
+                li = layout.set_index(loc)
+                for u in range(len(quads)):
+                    sub_eri[loff + u * lsets + li] = self.eri[goff + u * gsets + gi]
+        eri_sub = layout.unpack_eri(sub_eri, n, k)
+        t_sub = np.zeros(layout.amp_count(n, k))
+        gmap = np.zeros(layout.amp_count(n, k), dtype=np.int64)
+        for pos, loc, tup in layout.iter_amp_slots(n, k):
+            m = layout.pattern_tuples(len(loc)).index(tup)
+            g = layout.amp_slot(N, tuple(Y[i] for i in loc), m)
+            gmap[pos] = g
+            if t is not None:
+                t_sub[pos] = t[g]
+        return f_sub, eri_sub, t_sub, gmap
+
+    def sub_residual(self, Y, t):
+        """(R^{(Y)} keyed by global slot, E^{(Y)}) with caching per Y."""
+        key = tuple(Y)
+        if key not in self._cache:
+            f_sub, eri_sub, t_sub, gmap = self.sub_inputs(key, t)
+            R, E = self.engine(len(key)).residual(f_sub, eri_sub, t_sub)
+            self._cache[key] = (dict(zip(gmap.tolist(), R.tolist())), E)
+        return self._cache[key]
+
+    def clear(self):
+        self._cache.clear()
+
+    # ---------------------------------------------------------------- results
+    def residual_block(self, L, t):
+        """R for every slot whose label set is exactly L (sorted tuple).
+
+        Returns {global slot: value}.
+        """
+        L = tuple(sorted(L))
+        N, k = self.N, self.k
+        others = [x for x in range(N) if x not in L]
+        slots = [layout.amp_slot(N, L, m) for m in range(len(layout.pattern_tuples(len(L))))]
+        total = {s: 0.0 for s in slots}
+        for extra in range(0, k + 1):
+            for add in itertools.combinations(others, extra):
+                # dR^{(X)} for X = L + add
+                d = {s: 0.0 for s in slots}
+                for j in range(extra + 1):
+                    for sub in itertools.combinations(add, j):
+                        Y = tuple(sorted(L + sub))
+                        RY, _ = self.sub_residual(Y, t)
+                        sg = (-1.0) ** (extra - j)
+                        for s in slots:
+                            d[s] += sg * RY[s]
+                for s in slots:
+                    total[s] += d[s]
+        return total
+
+    def energy(self, t) -> float:
+        N, k = self.N, self.k
+        total = 0.0
+        for size in range(1, k + 1):
+            for X in itertools.combinations(range(N), size):
+                d = 0.0
+                for j in range(1, size + 1):
+                    for Y in itertools.combinations(X, j):
+                        d += (-1.0) ** (size - j) * self.sub_residual(Y, t)[1]
+                total += d
+        return total
+
+    def residual(self, t):
+        """The full packed residual (only for small N: every block is evaluated)."""
+        R = np.zeros(layout.amp_count(self.N, self.k))
+        for size in range(1, self.k + 1):
+            for L in itertools.combinations(range(self.N), size):
+                for s, v in self.residual_block(L, t).items():
+                    R[s] = v
+        return R

@@ -1,0 +1,91 @@
+"""A second, deliberately different fermion implementation used only to pin
+the oracle: determinants are sorted tuples of spin orbitals in interleaved
+order (2*spatial + spin), states are dicts, and every operator is applied one
+at a time.  It shares nothing with oracle/determinants.py."""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def so(spatial: int, spin: int) -> int:
+    return 2 * spatial + spin
+
+
+def apply_op(state: dict, create: bool, orb: int) -> dict:
+    out = {}
+    for det, c in state.items():
+        occ = orb in det
+        if create == occ:
+            continue
+        sign = -1.0 if sum(1 for x in det if x < orb) % 2 else 1.0
+        nd = tuple(sorted(det + (orb,))) if create else tuple(x for x in det if x != orb)
+        out[nd] = out.get(nd, 0.0) + sign * c
+    return out
+
+
+def apply_string(state: dict, ops) -> dict:
+    """ops: list of (create, spin-orbital), leftmost first."""
+    for cre, o in reversed(ops):
+        state = apply_op(state, cre, o)
+    return state
+
+
+def reference(npair: int) -> dict:
+    return {tuple(sorted(so(p, s) for p in range(npair) for s in (0, 1))): 1.0}
+
+
+def slot_ops(npair: int, labels, tup):
+    ops = []
+    for P, e in zip(labels, tup):
+        if e & 1:
+            ops.append((False, so(P, 0)))
+        if e & 2:
+            ops.append((False, so(P, 1)))
+        if e & 4:
+            ops.append((True, so(npair + P, 0)))
+        if e & 8:
+            ops.append((True, so(npair + P, 1)))
+    return ops
+
+
+def overlap(a: dict, b: dict) -> float:
+    return sum(c * b.get(d, 0.0) for d, c in a.items())
+
+
+def antisym(eri: np.ndarray, p, q, r, s) -> float:
+    """<pq||rs> over spin orbitals from chemists' spatial integrals."""
+    P, sp = divmod(p, 2)
+    Q, sq = divmod(q, 2)
+    R, sr = divmod(r, 2)
+    S, ss = divmod(s, 2)
+    v = 0.0
+    if sp == sr and sq == ss:
+        v += eri[P, R, Q, S]
+    if sp == ss and sq == sr:
+        v -= eri[P, S, Q, R]
+    return v
+
+
+def hn_on_reference(npair: int, f: np.ndarray, eri: np.ndarray) -> dict:
+    """H_N |0> = sum f_ai a+_a a_i |0> + 1/4 sum <ab||ij> a+_a a+_b a_j a_i |0>."""
+    occ = [so(p, s) for p in range(npair) for s in (0, 1)]
+    vir = [so(npair + p, s) for p in range(npair) for s in (0, 1)]
+    ref = reference(npair)
+    out: dict = {}
+
+    def add(st, c):
+        for d, x in st.items():
+            out[d] = out.get(d, 0.0) + c * x
+
+    for a in vir:
+        for i in occ:
+            if a % 2 == i % 2 and f[a // 2, i // 2] != 0.0:
+                add(apply_string(ref, [(True, a), (False, i)]), f[a // 2, i // 2])
+    for a, b in itertools.permutations(vir, 2):
+        for i, j in itertools.permutations(occ, 2):
+            v = antisym(eri, a, b, i, j)
+            if v != 0.0:
+                add(apply_string(ref, [(True, a), (True, b), (False, j), (False, i)]), 0.25 * v)
+    return out

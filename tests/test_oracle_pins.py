@@ -1,0 +1,304 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test fails for a plausible mistake in the oracle: a dropped term, a
+wrong sign or index, a transposed operand or a wrong truncation.
+"""
+import itertools
+from math import comb
+
+import numpy as np
+import pytest
+
+from inputs import chain_problem, random_amplitudes, random_bfactors, random_fock
+from oracle import integrals, layout, solver, tier_a, tier_b
+import fermi_ref as fr
+
+
+def _solve_tier_a(N, k, f, eri_packed, tol=1e-12):
+    ta = tier_a.TierA(N, k)
+    eri_t = layout.unpack_eri(eri_packed, N, k)
+    D = solver.denominators(f, N, k)
+    res = solver.solve(lambda t: ta.residual(f, eri_t, t)[0],
+                       lambda t: ta.energy(f, eri_t, t), D, tol=tol, max_iter=300)
+    assert res.converged
+    return res
+
+
+# ------------------------------------------------------------- counts (Table II)
+def test_manifold_counts():
+    # unique excitations per label set: 3, 29, 303 (and 6, 43, 84 unique integrals)
+    assert [len(layout.pattern_tuples(n)) for n in (1, 2, 3)] == [3, 29, 303]
+    assert [len(layout.eri_quads(n)) for n in (1, 2, 3)] == [6, 43, 84]
+    # PQ at N=2 and PH at N=3 span the whole determinant space but the reference
+    assert layout.amp_count(2, 2) == comb(4, 2) ** 2 - 1
+    assert layout.amp_count(3, 3) == comb(6, 3) ** 2 - 1
+
+    def rank(tup):
+        return sum(bin(e & 3).count("1") for e in tup)
+    # Table II, rank-1 column: T1 has 2 subtensors (alpha, beta), T2 has 1
+    r1 = [rank(t) for t in layout.pattern_tuples(1)]
+    assert r1.count(1) == 2 and r1.count(2) == 1
+    # rank-2 singles: t_P^Q alpha and beta, 2 subtensors, each both orders unique
+    r2 = [rank(t) for t in layout.pattern_tuples(2)]
+    assert r2.count(1) == 2 * 2
+    assert max(r2) == 4 and r2.count(4) == 1
+    r3 = [rank(t) for t in layout.pattern_tuples(3)]
+    assert max(r3) == 6 and r3.count(6) == 1
+
+
+# ------------------------------------------------------- exactness (Sec. I, Table VI)
+def test_pq_exact_for_4e4o():
+    prob = chain_problem(4, U=4.0, seed=4)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    res = _solve_tier_a(2, 2, f, layout.pack_eri(eri, 2, 2))
+    efci, eref = tier_a.TierA(2, 2).fci(f, eri)
+    assert abs(res.energy - efci) < 1e-10
+    assert abs(eref + prob.E_core - prob.E_rhf) < 1e-10
+
+
+def test_ph_exact_for_6e6o():
+    prob = chain_problem(6, U=4.0, seed=6)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    res = _solve_tier_a(3, 3, f, layout.pack_eri(eri, 3, 3))
+    efci, _ = tier_a.TierA(3, 3).fci(f, eri)
+    assert abs(res.energy - efci) < 1e-10
+
+
+def test_pq_not_exact_for_6e6o():
+    # PQ truncates integrals and amplitudes at three pairs: not FCI there
+    prob = chain_problem(6, U=4.0, seed=6)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    res = _solve_tier_a(3, 2, f, layout.pack_eri(eri, 3, 2))
+    efci, _ = tier_a.TierA(3, 3).fci(f, eri)
+    assert abs(res.energy - efci) > 1e-5
+
+
+def test_dimer_closed_form():
+    # 2-site chain: covalent/ionic 2x2 problem; core-charge form shifts by -V
+    prob = chain_problem(2, U=4.0, seed=2)
+    t = prob.h_site[0, 1]
+    U = prob.U
+    V = prob.V[0, 1]
+    exact = 0.5 * (U + V) - np.sqrt((0.5 * (U - V)) ** 2 + 4 * t * t) - V
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    for k in (1, 2, 3):
+        res = _solve_tier_a(1, k, f, layout.pack_eri(eri, 1, k))
+        assert abs(prob.E_rhf + res.energy - exact) < 1e-10
+
+
+def test_pp_is_sum_of_pair_fci():
+    # k=1 with a diagonal Fock matrix: independent pairs (Sec. II on PP)
+    prob = chain_problem(6, U=3.0, seed=11)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    assert np.abs(f - np.diag(np.diag(f))).max() < 1e-9
+    f = np.diag(np.diag(f))
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    res = _solve_tier_a(3, 1, f, layout.pack_eri(eri, 3, 1))
+    total = 0.0
+    for P in range(3):
+        orbs = [P, 3 + P]
+        fs = f[np.ix_(orbs, orbs)]
+        es = eri[np.ix_(orbs, orbs, orbs, orbs)]
+        total += tier_a.TierA(1, 1).fci(fs, es)[0]
+    assert abs(res.energy - total) < 1e-10
+
+
+# ------------------------------------------------------------- closed forms
+def _random_system(N, k, seed):
+    f = random_fock(N, seed=seed)
+    B = random_bfactors(N, seed=seed + 1)
+    eri_full = integrals.eri_dense_from_b(B)
+    packed = integrals.eri_packed_from_b(B, N, k)
+    return f, eri_full, packed
+
+
+@pytest.mark.parametrize("N,k", [(2, 2), (3, 2), (3, 3)])
+def test_residual_at_zero_amplitudes(N, k):
+    """R(t=0)_mu = <g^mu 0| H_N |0>: f_ai for singles, <ab||ij> for doubles,
+    zero for triples and up; built here with a separate fermion code."""
+    f, eri_full, packed = _random_system(N, k, 7)
+    eri_t = layout.unpack_eri(packed, N, k)
+    R, E = tier_a.TierA(N, k).residual(f, eri_t, np.zeros(layout.amp_count(N, k)))
+    assert abs(E) < 1e-14
+    hn0 = fr.hn_on_reference(N, f, eri_t)
+    for pos, labels, tup in layout.iter_amp_slots(N, k):
+        d = fr.apply_string(fr.reference(N), fr.slot_ops(N, labels, tup))
+        assert abs(R[pos] - fr.overlap(d, hn0)) < 1e-13
+
+
+@pytest.mark.parametrize("N,k", [(2, 2), (3, 2), (3, 3)])
+def test_energy_formula(N, k):
+    """E_c = sum f_ia t_i^a + 1/4 sum <ij||ab> t_ij^ab + 1/2 sum <ij||ab> t_i^a t_j^b
+    (Eqs. (2)-(3) give its doubles part), with the slot signs found by applying
+    the slot operators to the reference."""
+    f, eri_full, packed = _random_system(N, k, 9)
+    eri_t = layout.unpack_eri(packed, N, k)
+    t = random_amplitudes(N, "pq" if k == 2 else "ph", seed=10, scale=0.2)
+    E = tier_a.TierA(N, k).energy(f, eri_t, t)
+    ref = fr.reference(N)
+    occ = [fr.so(p, s) for p in range(N) for s in (0, 1)]
+    vir = [fr.so(N + p, s) for p in range(N) for s in (0, 1)]
+    t1 = {}
+    t2 = {}
+    for pos, labels, tup in layout.iter_amp_slots(N, k):
+        st = fr.apply_string(ref, fr.slot_ops(N, labels, tup))
+        (det, c), = st.items()
+        refdet = set(next(iter(ref)))
+        holes = sorted(refdet - set(det))
+        parts = sorted(set(det) - refdet)
+        if len(holes) == 1:
+            # a+_a a_i |0> has the same determinant; its sign fixes t_i^a
+            s = fr.apply_string(ref, [(True, parts[0]), (False, holes[0])])[det]
+            t1[holes[0], parts[0]] = c * s * t[pos]
+        elif len(holes) == 2:
+            i, j = holes
+            a, b = parts
+            s = fr.apply_string(ref, [(True, a), (True, b), (False, j), (False, i)])[det]
+            t2[i, j, a, b] = c * s * t[pos]
+    e = 0.0
+    for (i, a), v in t1.items():
+        e += f[i // 2, a // 2] * v if i % 2 == a % 2 else 0.0
+    for (i, j, a, b), v in t2.items():          # i<j, a<b: the 1/4 cancels
+        e += fr.antisym(eri_t, i, j, a, b) * v
+    for (i, a), v in t1.items():
+        for (j, b), w in t1.items():
+            e += 0.5 * fr.antisym(eri_t, i, j, a, b) * v * w
+    assert abs(E - e) < 1e-13
+
+
+# ------------------------------------------------------------- invariants
+def test_residual_polynomial_degree_four():
+    N, k = 3, 2
+    f, _, packed = _random_system(N, k, 13)
+    eri_t = layout.unpack_eri(packed, N, k)
+    ta = tier_a.TierA(N, k)
+    t = random_amplitudes(N, "pq", seed=14, scale=0.1)
+    d = random_amplitudes(N, "pq", seed=15, scale=0.1)
+    vals = [ta.residual(f, eri_t, t + s * d)[0] for s in range(6)]
+    fifth = sum((-1) ** (5 - s) * comb(5, s) * vals[s] for s in range(6))
+    fourth = sum((-1) ** (4 - s) * comb(4, s) * vals[s] for s in range(5))
+    assert np.abs(fifth).max() < 1e-11
+    assert np.abs(fourth).max() > 1e-6       # the quartic terms are there
+
+
+def test_residual_linear_in_hamiltonian():
+    N, k = 3, 2
+    f1, _, p1 = _random_system(N, k, 17)
+    f2, _, p2 = _random_system(N, k, 19)
+    ta = tier_a.TierA(N, k)
+    t = random_amplitudes(N, "pq", seed=20, scale=0.1)
+    a, b = 0.7, -1.3
+    R1 = ta.residual(f1, layout.unpack_eri(p1, N, k), t)[0]
+    R2 = ta.residual(f2, layout.unpack_eri(p2, N, k), t)[0]
+    R12 = ta.residual(a * f1 + b * f2, layout.unpack_eri(a * p1 + b * p2, N, k), t)[0]
+    assert np.abs(R12 - a * R1 - b * R2).max() < 1e-12
+
+
+def _permute_system(N, k, perm, f, packed, t):
+    """Relabel pairs P -> perm[P] in f, integrals and amplitudes."""
+    orb = np.concatenate([perm, N + np.asarray(perm)])
+    fp = np.zeros_like(f)
+    fp[np.ix_(orb, orb)] = f
+    full = layout.unpack_eri(packed, N, k)
+    fullp = np.zeros_like(full)
+    fullp[np.ix_(orb, orb, orb, orb)] = full
+    packed_p = layout.pack_eri(fullp, N, k)
+    tp = np.zeros_like(t)
+    for pos, labels, tup in layout.iter_amp_slots(N, k):
+        new = [(perm[P], e) for P, e in zip(labels, tup)]
+        order = sorted(range(len(new)), key=lambda i: new[i][0])
+        # sign of reordering the pair factors g^e (parity |e|)
+        sgn = 1.0
+        par = [bin(e).count("1") % 2 for _, e in new]
+        for i in range(len(order)):
+            for j in range(i + 1, len(order)):
+                if order[i] > order[j] and par[order[i]] and par[order[j]]:
+                    sgn = -sgn
+        nl = tuple(new[i][0] for i in order)
+        nt = tuple(new[i][1] for i in order)
+        m = layout.pattern_tuples(len(nl)).index(nt)
+        tp[layout.amp_slot(N, nl, m)] = sgn * t[pos]
+    return fp, packed_p, tp
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_pair_relabelling_invariance(k):
+    N = 4 if k == 2 else 3
+    f, _, packed = _random_system(N, k, 23)
+    t = random_amplitudes(N, "pq" if k == 2 else "ph", seed=24, scale=0.1)
+    perm = [2, 0, 3, 1] if N == 4 else [2, 0, 1]
+    ta = tier_a.TierA(N, k)
+    R, E = ta.residual(f, layout.unpack_eri(packed, N, k), t)
+    fp, pp, tp = _permute_system(N, k, perm, f, packed, t)
+    Rp, Ep = ta.residual(fp, layout.unpack_eri(pp, N, k), tp)
+    _, _, Rmapped = _permute_system(N, k, perm, f, packed, R)
+    assert abs(E - Ep) < 1e-12
+    assert np.abs(Rp - Rmapped).max() < 1e-12
+
+
+def test_not_invariant_to_occupied_rotation():
+    # rotating o_0 with o_1 changes the PQ energy at N>=3 (Sec. II)
+    prob = chain_problem(6, U=4.0, seed=6)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    e0 = _solve_tier_a(3, 2, f, layout.pack_eri(eri, 3, 2)).energy
+    th = 0.3
+    C2 = prob.C.copy()
+    c, s = np.cos(th), np.sin(th)
+    C2[:, [0, 1]] = prob.C[:, [0, 1]] @ np.array([[c, -s], [s, c]])
+    f2 = integrals.mo_fock(prob.F_site, C2)
+    eri2 = integrals.eri_dense_zdo(C2, prob.V)
+    e1 = _solve_tier_a(3, 2, f2, layout.pack_eri(eri2, 3, 2)).energy
+    assert abs(e1 - e0) > 1e-6
+
+
+def test_size_consistency():
+    """Two non-interacting 4-site chains with fragment-local pairs:
+    E_PQ(A+B) = E_PQ(A) + E_PQ(B) (size extensivity, Sec. II)."""
+    pa = chain_problem(4, U=4.0, seed=31)
+    pb = chain_problem(4, U=3.0, seed=32)
+    fa, fb = (integrals.mo_fock(p.F_site, p.C) for p in (pa, pb))
+    ea, eb = (integrals.eri_dense_zdo(p.C, p.V) for p in (pa, pb))
+    N = 4
+    # pairs 0,1 from A and 2,3 from B; orbitals [o0..o3, v0..v3]
+    oa = [0, 1, 4, 5]
+    ob = [2, 3, 6, 7]
+    f = np.zeros((8, 8))
+    f[np.ix_(oa, oa)] = fa
+    f[np.ix_(ob, ob)] = fb
+    eri = np.zeros((8,) * 4)
+    eri[np.ix_(oa, oa, oa, oa)] = ea
+    eri[np.ix_(ob, ob, ob, ob)] = eb
+    res = _solve_tier_a(N, 2, f, layout.pack_eri(eri, N, 2))
+    efa = tier_a.TierA(2, 2).fci(fa, ea)[0]
+    efb = tier_a.TierA(2, 2).fci(fb, eb)[0]
+    assert abs(res.energy - efa - efb) < 1e-10
+
+
+def test_tier_b_equals_tier_a_beyond_cluster_size():
+    """The sub-cluster sum is complete: at N=5 (PQ) every residual block and
+    the energy agree with the full determinant-space evaluation."""
+    N, k = 5, 2
+    f, _, packed = _random_system(N, k, 41)
+    t = random_amplitudes(N, "pq", seed=42, scale=0.1)
+    RA, EA = tier_a.TierA(N, k).residual(f, layout.unpack_eri(packed, N, k), t)
+    tb = tier_b.TierB(N, k, f, packed)
+    for L in [(0,), (3,), (0, 4), (1, 2), (2, 4)]:
+        for s, v in tb.residual_block(L, t).items():
+            assert abs(RA[s] - v) < 1e-13
+    assert abs(tb.energy(t) - EA) < 1e-13
+
+
+def test_packed_integrals_match_dense():
+    prob = chain_problem(8, U=4.0, seed=8)
+    eri = integrals.eri_dense_zdo(prob.C, prob.V)
+    for k in (2, 3):
+        assert np.abs(integrals.eri_packed_zdo(prob.C, prob.V, 4, k)
+                      - layout.pack_eri(eri, 4, k)).max() < 1e-13
+    # 8-fold symmetry of the site-basis transformation
+    assert np.abs(eri - eri.transpose(1, 0, 2, 3)).max() < 1e-13
+    assert np.abs(eri - eri.transpose(2, 3, 0, 1)).max() < 1e-13
