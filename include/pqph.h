@@ -1,0 +1,163 @@
+/*
+ * pqph.h -- C ABI of the MI355X (gfx950) library for the perfect quadruples
+ * (PQ) and perfect hextuples (PH) pair-truncated coupled-cluster models
+ * (Lehtola, Parkhill, Head-Gordon, arXiv:1609.00077).
+ *
+ * Everything is FP64.  Matrices are row-major.  Unless marked "host", every
+ * pointer is a device pointer, and all work is issued on the stream given to
+ * pqph_create; calls that return results to host memory synchronise that
+ * stream.  The caller owns every array.  The context owns only its workspace,
+ * which it grows on demand and frees in pqph_destroy.  Errors are returned
+ * as status codes and never abort; pqph_last_error gives the message of the
+ * last failure on the context.  Device errors surface at the next call that
+ * synchronises.  Use one context per stream and do not call one context from
+ * two threads at once.
+ *
+ * ---------------------------------------------------------------- orbitals
+ * The active space has N pairs (Sec. II, Fig. 1).  Pair P is the orbital
+ * quartet of the occupied orbital o_P (HOMO-P) and the virtual v_P (LUMO+P),
+ * both spins.  Spatial orbital index P is o_P and N+P is v_P.
+ *
+ * ----------------------------------------------------- amplitude layout (t, r)
+ * Each pair carries four excitation generators, by bit: 0 = a(o_P alpha),
+ * 1 = a(o_P beta), 2 = a+(v_P alpha), 3 = a+(v_P beta).  A local pattern e in
+ * 1..15 is a set of these bits; g_P^e is the product of its generators in
+ * ascending bit order; its charge per spin is particles minus holes.  The
+ * excitation on labels P0 < P1 < ... with patterns (e0, e1, ...) (each
+ * nonempty, total charge zero per spin) is the operator g_P0^e0 g_P1^e1 ...,
+ * and T = sum over slots of t(slot) times that operator.  The model keeps the
+ * excitations on at most k pairs (Sec. II: k = 2 for PQ, 3 for PH; Eq. (1)
+ * lists the eight opposite-spin doubles subtensors of PQ).  Packed vector,
+ * class-major, unique excitations only (3, 29 and 303 per label set):
+ *     [ 3 x N ][ 29 x C(N,2) ][ 303 x C(N,3), PH only ]
+ * Pattern tuples of one label-set size run lexicographically; pairs P<Q are
+ * indexed Q(Q-1)/2+P and triples P<Q<R by R(R-1)(R-2)/6+Q(Q-1)/2+P.  The
+ * residual r has the same layout: r(slot) is the coefficient of the slot's
+ * operator in e^{-T} H_N e^{T}, i.e. <g^mu 0| e^{-T} H_N e^{T} |0>, not divided
+ * by any denominator.
+ *
+ * ---------------------------------------------------- integral layout (eri)
+ * Chemists' (pq|rs), real, 8-fold symmetric, each unique integral stored
+ * once, grouped by its label set; only label sets of at most k pairs are
+ * stored (Table I caption: PQ keeps rank-1 and rank-2 integral subtensors,
+ * PH up to rank 3).  Within a set with ascending labels, local orbital
+ * 2*role+type (type 0 = o, 1 = v) is numbered; the stored quadruples are
+ * p>=q, r>=s, pq>=rs with pq = p(p+1)/2+q, in lexicographic (pq, rs) order,
+ * keeping those whose orbitals cover every label of the set (6, 43, 84):
+ *     [ 6 x N ][ 43 x C(N,2) ][ 84 x C(N,3), PH only ]
+ *
+ * ------------------------------------------------------ Hamiltonian (h)
+ * h is the 2N x 2N Fock matrix f in the paired MO order, whole (the paper
+ * truncates the two-electron integrals, not f; Sec. III takes f from the SCF).
+ * The model Hamiltonian is H_N = sum_pq f_pq {p+ q} + 1/4 sum <pq||rs> {p+ q+ s r}
+ * with <pq||rs> built from the stored integrals; f is read as a general matrix.
+ *
+ * Energies returned are correlation energies E_c = <0|H_N e^T|0> (Eqs. (2)-(3)
+ * give its doubles part in subtensor form), not total energies.
+ */
+#ifndef PQPH_H
+#define PQPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pqph_status;
+#define PQPH_OK 0
+#define PQPH_INVALID_ARG (-1)    /* bad size, null pointer, unsupported option */
+#define PQPH_DEVICE (-2)         /* a HIP call failed                          */
+#define PQPH_OOM (-3)            /* device workspace could not be allocated    */
+#define PQPH_NONFINITE (-4)      /* NaN/Inf in the inputs or the iterates      */
+#define PQPH_NOT_CONVERGED (-5)  /* max_iter reached                           */
+#define PQPH_DIVERGED (-6)       /* residual norm grew past the allowed bound  */
+
+typedef struct pqph_ctx pqph_ctx;
+
+/* Solver options (host struct).  Jacobi updates t <- t - r/D with the
+ * orbital-energy denominators D = sum f_aa - sum f_ii over the particles and
+ * holes of each excitation plus level_shift (Table IV: denominator
+ * application), accelerated by DIIS (Sec. III) on the last diis_dim iterates
+ * once iteration diis_start is reached (0 disables DIIS).  Convergence: 2-norm
+ * of r over the packed unique slots <= tol.  Divergence: the norm exceeds
+ * diverge_factor times the smallest norm seen, or 1e3 in absolute value. */
+typedef struct {
+    int max_iter;          /* default 200                                */
+    double tol;            /* default 1e-8                               */
+    int diis_dim;          /* default 8, at most 16                      */
+    int diis_start;        /* default 2                                  */
+    double level_shift;    /* default 0                                  */
+    double diverge_factor; /* default 1e4                                */
+} pqph_solve_opts;
+
+/* Per-solve report (host struct). */
+typedef struct {
+    int iterations;        /* residual evaluations performed             */
+    double rnorm;          /* final residual 2-norm                      */
+    int status;            /* same code the call returned                */
+    double solve_ms;       /* wall time of the solve on the stream       */
+} pqph_solve_info;
+
+/* Fill *opts with the defaults above. */
+void pqph_default_opts(pqph_solve_opts* opts);
+
+/* Create a context bound to a device and a HIP stream (hipStream_t passed as
+ * void*; NULL means the default stream).  The context allocates nothing
+ * until first use. */
+pqph_status pqph_create(pqph_ctx** ctx, int device, void* hip_stream);
+void pqph_destroy(pqph_ctx* ctx);
+const char* pqph_last_error(const pqph_ctx* ctx);
+
+/* Element counts of the packed layouts (host; no context needed). */
+size_t pq_amp_len(int npair);
+size_t ph_amp_len(int npair);
+size_t pq_eri_len(int npair);
+size_t ph_eri_len(int npair);
+
+/* Integral transformation into pair blocks (Sec. III, RI/CD paragraph: the
+ * two-electron integrals are formed from three-index factors, picking only
+ * the elements needed).  For a zero-differential-overlap site Hamiltonian of
+ * n = 2*npair sites with site-basis Fock matrix F (n x n), site interaction
+ * matrix V (n x n) and paired MO coefficients C (n x n, columns
+ * [o_0..o_{N-1}, v_0..v_{N-1}]):
+ *     f   = C^T F C                                    (n x n, row-major)
+ *     eri = packed (pq|rs) = sum_ij C_ip C_iq V_ij C_jr C_js
+ *           for the label sets of at most k pairs (k = 2 or 3).
+ * f_out holds n*n doubles, eri_out pq_eri_len / ph_eri_len doubles. */
+pqph_status pqph_integrals(pqph_ctx* ctx, int npair, int k, const double* F,
+                           const double* V, const double* C, double* f_out,
+                           double* eri_out);
+
+/* PQ residual r(t) = <mu| e^{-T} H_N e^{T} |0> for every packed slot (Sec. II,
+ * Eq. (1) decomposition with k = 2).  t and r: pq_amp_len(npair) doubles;
+ * eri: pq_eri_len(npair); h: (2N)^2.  Stream-ordered, no host sync.
+ * npair in [1, 256]. */
+pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h,
+                        const double* eri, const double* t, double* r);
+
+/* PQ correlation energy at amplitudes t (Eqs. (2)-(3)); energy is a host
+ * pointer; the call synchronises the stream. */
+pqph_status pq_energy(pqph_ctx* ctx, int npair, const double* h,
+                      const double* eri, const double* t, double* energy);
+
+/* PQ amplitude solve: Jacobi + DIIS from t_inout (zeros for the usual
+ * start) until the residual norm is at most opts->tol.  On return t_inout
+ * holds the last iterate, *energy (host) its correlation energy and *info
+ * (host, may be NULL) the report.  opts may be NULL for the defaults. */
+pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
+                     const double* eri, const pqph_solve_opts* opts,
+                     double* t_inout, double* energy, pqph_solve_info* info);
+
+/* Orbital-energy denominators of the packed slots (length pq_amp_len or
+ * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
+ * + shift.  Exposed for callers that run their own update. */
+pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h,
+                              double shift, double* D);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PQPH_H */

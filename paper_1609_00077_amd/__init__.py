@@ -1,0 +1,136 @@
+"""MI355X-native perfect quadruples (PQ) and perfect hextuples (PH) library.
+
+The hot path of the paper's method -- the pair-truncated coupled-cluster
+amplitude residuals over dense pair-indexed tensors inside Jacobi/DIIS
+iterations (Sec. II-III of arXiv:1609.00077) -- runs in hand-written HIP
+kernels behind the C ABI of include/pqph.h.  This module only marshals torch
+tensors (device memory and the current HIP stream) into those calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+__all__ = ["pq_residual", "pq_energy", "pq_solve", "integrals", "denominators",
+           "amp_len", "eri_len", "SolveResult", "PQPHError"]
+
+PQPHError = _lib.PQPHError
+_ctx_cache: dict = {}
+
+
+def _ctx(device: torch.device):
+    lib = _lib.load()
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    key = (idx, stream)
+    ctx = _ctx_cache.get(key)
+    if ctx is None:
+        h = C.c_void_p()
+        st = lib.pqph_create(C.byref(h), idx, C.c_void_p(stream))
+        if st != 0:
+            raise PQPHError(st, lib.pqph_last_error(None).decode())
+        ctx = h
+        _ctx_cache[key] = ctx
+    return lib, ctx
+
+
+def _check(lib, ctx, st):
+    if st != 0:
+        raise PQPHError(st, lib.pqph_last_error(ctx).decode())
+
+
+def _dev(x: torch.Tensor, name: str, n: int | None = None):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if n is not None and x.numel() != n:
+        raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
+    return C.c_void_p(x.data_ptr())
+
+
+def amp_len(npair: int, model: str = "pq") -> int:
+    lib = _lib.load()
+    return int(lib.pq_amp_len(npair) if model == "pq" else lib.ph_amp_len(npair))
+
+
+def eri_len(npair: int, model: str = "pq") -> int:
+    lib = _lib.load()
+    return int(lib.pq_eri_len(npair) if model == "pq" else lib.ph_eri_len(npair))
+
+
+def integrals(F: torch.Tensor, V: torch.Tensor, Cmo: torch.Tensor, k: int = 2):
+    """(f, packed eri) of a ZDO site Hamiltonian; see pqph_integrals."""
+    n = F.shape[0]
+    npair = n // 2
+    lib, ctx = _ctx(F.device)
+    f = torch.empty((n, n), dtype=torch.float64, device=F.device)
+    eri = torch.empty(eri_len(npair, "pq" if k == 2 else "ph"), dtype=torch.float64, device=F.device)
+    _check(lib, ctx, lib.pqph_integrals(ctx, npair, k, _dev(F, "F", n * n), _dev(V, "V", n * n),
+                                        _dev(Cmo, "C", n * n), _dev(f, "f"), _dev(eri, "eri")))
+    return f, eri
+
+
+def pq_residual(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, out: torch.Tensor | None = None):
+    """Packed PQ residual r(t) (no host sync)."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair)
+    if out is None:
+        out = torch.empty(na, dtype=torch.float64, device=h.device)
+    _check(lib, ctx, lib.pq_residual(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                     _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
+                                     _dev(out, "out", na)))
+    return out
+
+
+def pq_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    e = C.c_double()
+    _check(lib, ctx, lib.pq_energy(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                   _dev(eri, "eri", eri_len(npair)), _dev(t, "t", amp_len(npair)),
+                                   C.byref(e)))
+    return e.value
+
+
+def denominators(h: torch.Tensor, k: int = 2, shift: float = 0.0) -> torch.Tensor:
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    D = torch.empty(amp_len(npair, "pq" if k == 2 else "ph"), dtype=torch.float64, device=h.device)
+    _check(lib, ctx, lib.pqph_denominators(ctx, npair, k, _dev(h, "h", 4 * npair * npair),
+                                           float(shift), _dev(D, "D")))
+    return D
+
+
+@dataclass
+class SolveResult:
+    t: torch.Tensor
+    energy: float
+    iterations: int
+    rnorm: float
+    status: str
+    solve_ms: float
+
+
+def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
+             tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
+             level_shift: float = 0.0, diverge_factor: float = 1e4,
+             raise_on_failure: bool = True) -> SolveResult:
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair)
+    t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    info = _lib.SolveInfo()
+    e = C.c_double()
+    st = lib.pq_solve(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", eri_len(npair)),
+                      C.byref(opts), _dev(t, "t", na), C.byref(e), C.byref(info))
+    if st != 0 and raise_on_failure:
+        _check(lib, ctx, st)
+    return SolveResult(t, e.value, info.iterations, info.rnorm, _lib.STATUS.get(st, str(st)),
+                       info.solve_ms)

@@ -1,0 +1,512 @@
+// PQ residual, energy and denominators on gfx950.
+//
+// R_mu = <mu| e^{-T} H_N e^{T} |0> for the two-pair truncated manifold (Sec. II,
+// Eq. (1) and the k = 2 truncation of the integrals, Table I caption).  The
+// terms come from the pair-site derivation in derive/ (constant tables in
+// pq_tables.h); roles P, Q are output pairs and A, B spectators.  Kernels:
+//   k_vertex1/2   Hamiltonian vertices h1[key][P], h2[key][P][Q] from f and the
+//                 packed integrals (the pair-block integral subtensors)
+//   k_unpack_t2   packed t -> t2[m][P][Q] for all ordered P != Q (mirror copy
+//                 carries the reordering sign of the two pair operators)
+//   k_spec        products of factors over ordered label pairs: the R2S1 sides
+//                 X(P,A), Y(Q,A) and the dressed two-spectator vertex W(A,B)
+//   k_gemm_s1     S_p(P,Q) = sum_A X_p(P,A) Y_p(Q,A)   (one spectator)
+//   k_r1          one-pair outputs (0, 1, 2 spectators)
+//   k_r2s2        sum_{A,B} L_a(P,Q,A) W(A,B) L_b(P,Q,B)  (two spectators)
+//   k_r2          two-pair outputs: no-spectator terms + one-spectator epilogue
+//                 + the two-spectator partial sums, written to the packed r
+#include "pqph_internal.h"
+#include "pq_tables.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace {
+
+constexpr int NP2 = 29;   // pattern pairs of a two-pair label set
+
+struct View {
+    const double* t1;   // [3][N] (first block of the packed t)
+    const double* t2;   // [29][N][N]
+    const double* h1;   // [PQ_H1_N][N]
+    const double* h2;   // [PQ_H2_N][N][N]
+    const double* S;    // [PQ_S1PAIRS_N][N][N]
+    int N;
+    long NN;
+};
+
+__device__ __forceinline__ int labr(int r, int L0, int L1, int L2, int L3) {
+    return r == 0 ? L0 : (r == 1 ? L1 : (r == 2 ? L2 : L3));
+}
+
+__device__ __forceinline__ double fval(int code, int L0, int L1, int L2, int L3, const View& v) {
+    const int kind = (code >> 28) & 15;
+    const int a = labr((code >> 24) & 15, L0, L1, L2, L3);
+    const int b = labr((code >> 20) & 15, L0, L1, L2, L3);
+    const long idx = code & 0xFFFF;
+    switch (kind) {
+        case 1: return v.t1[idx * v.N + a];
+        case 2: return v.t2[idx * v.NN + (long)a * v.N + b];
+        case 3: return v.h1[idx * v.N + a];
+        case 4: return v.h2[idx * v.NN + (long)a * v.N + b];
+        case 5: return v.S[idx * v.NN + (long)L0 * v.N + L1];
+        default: return 1.0;
+    }
+}
+
+// sum of the terms of output m of an interpreted class
+__device__ __forceinline__ double class_sum(const int* start, const double* coef, const int* fac,
+                                            int m, int L0, int L1, int L2, int L3, const View& v) {
+    double acc = 0.0;
+    const int e = start[m + 1];
+    for (int i = start[m]; i < e; ++i) {
+        double x = coef[i];
+        const int* f = fac + 5 * i;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int c = f[j];
+            if (c != 0) x *= fval(c, L0, L1, L2, L3, v);
+        }
+        acc += x;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void decode_pair(long ip, int& P, int& Q) {
+    int q = (int)((1.0 + sqrt(1.0 + 8.0 * (double)ip)) * 0.5);
+    while ((long)q * (q - 1) / 2 > ip) --q;
+    while ((long)(q + 1) * q / 2 <= ip) ++q;
+    Q = q;
+    P = (int)(ip - (long)q * (q - 1) / 2);
+}
+
+// ------------------------------------------------------------------ vertices
+__global__ void k_vertex1(int N, const double* __restrict__ f, const double* __restrict__ eri,
+                          double* __restrict__ h1) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    const int key = blockIdx.y;
+    if (P >= N) return;
+    const long n2 = 2L * N;
+    double v = 0.0;
+    for (int i = pq_h1_start[key]; i < pq_h1_start[key + 1]; ++i) {
+        const double w = pq_h1_w[i];
+        if (pq_h1_kind[i] == 0) {
+            const int p = P + N * (pq_h1_a[i] & 1), q = P + N * (pq_h1_b[i] & 1);
+            v += w * f[p * n2 + q];
+        } else {
+            v += w * eri[(long)pq_h1_a[i] * N + P];
+        }
+    }
+    h1[(long)key * N + P] = v;
+}
+
+__global__ void k_vertex2(int N, const double* __restrict__ f, const double* __restrict__ eri,
+                          double* __restrict__ h2) {
+    const int Q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = blockIdx.y, key = blockIdx.z;
+    if (Q >= N) return;
+    const long NN = (long)N * N, n2 = 2L * N;
+    double v = 0.0;
+    if (P != Q) {
+        const long np2 = (long)N * (N - 1) / 2;
+        const int lo = min(P, Q), hi = max(P, Q);
+        const long pidx = (long)hi * (hi - 1) / 2 + lo;
+        const double* e2 = eri + 6L * N;
+        for (int i = pq_h2_start[key]; i < pq_h2_start[key + 1]; ++i) {
+            const double w = pq_h2_w[i];
+            if (pq_h2_kind[i] == 0) {
+                const int a = pq_h2_a[i], b = pq_h2_b[i];
+                const int p = ((a >> 1) ? Q : P) + N * (a & 1);
+                const int q = ((b >> 1) ? Q : P) + N * (b & 1);
+                v += w * f[p * n2 + q];
+            } else {
+                const int u = P < Q ? pq_h2_a[i] : pq_h2_b[i];
+                v += w * e2[(long)u * np2 + pidx];
+            }
+        }
+    }
+    h2[(long)key * NN + (long)P * N + Q] = v;
+}
+
+// ---------------------------------------------------------------- amplitudes
+__global__ void k_unpack_t2(int N, const double* __restrict__ t, double* __restrict__ t2) {
+    const int Q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = blockIdx.y, m = blockIdx.z;
+    if (Q >= N) return;
+    const long NN = (long)N * N, np2 = (long)N * (N - 1) / 2;
+    const double* tp = t + 3L * N;
+    double v = 0.0;
+    if (P < Q)
+        v = tp[(long)m * np2 + (long)Q * (Q - 1) / 2 + P];
+    else if (P > Q)
+        v = pq_swap2_sign[m] * tp[(long)pq_swap2[m] * np2 + (long)P * (P - 1) / 2 + Q];
+    t2[(long)m * NN + (long)P * N + Q] = v;
+}
+
+// ---------------------------------------------------------- factor products
+__device__ __forceinline__ const int* spec_start(int which) {
+    return which == 0 ? pq_x_start : (which == 1 ? pq_y_start : (which == 2 ? pq_w_start : pq_l_start));
+}
+__device__ __forceinline__ const int* spec_fac(int which) {
+    return which == 0 ? pq_x_fac : (which == 1 ? pq_y_fac : (which == 2 ? pq_w_fac : pq_l_fac));
+}
+
+__global__ void k_spec(int N, int which, View v, double* __restrict__ out) {
+    const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int L0 = blockIdx.y, s = blockIdx.z;
+    if (L1 >= N) return;
+    const int* st = spec_start(which);
+    const int* fc = spec_fac(which);
+    double x = 0.0;
+    if (L0 != L1) {
+        x = 1.0;
+        for (int i = st[s]; i < st[s + 1]; ++i) x *= fval(fc[i], L0, L1, 0, 0, v);
+    }
+    out[(long)s * v.NN + (long)L0 * N + L1] = x;
+}
+
+__device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View& v) {
+    double x = 1.0;
+    for (int i = pq_l_start[s]; i < pq_l_start[s + 1]; ++i) x *= fval(pq_l_fac[i], P, Q, A, 0, v);
+    return x;
+}
+
+// ------------------------------------------------------------ one spectator
+constexpr int GT = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
+                                                 const double* __restrict__ Y,
+                                                 double* __restrict__ S) {
+    const int p = blockIdx.z;
+    const int x = pq_s1pairs[2 * p], y = pq_s1pairs[2 * p + 1];
+    const int tilesQ = (N + GT - 1) / GT;
+    const int tP = blockIdx.x / tilesQ, tQ = blockIdx.x % tilesQ;
+    if (tP > tQ) return;                 // only P < Q is read
+    const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
+    const long NN = (long)N * N;
+    __shared__ double Xs[GT][GT + 1];
+    __shared__ double Ys[GT][GT + 1];
+    const double* Xp = X + (long)x * NN;
+    const double* Yp = Y + (long)y * NN;
+    double acc = 0.0;
+    for (int a0 = 0; a0 < N; a0 += GT) {
+        const int A = a0 + tx;
+        const int Pr = tP * GT + ty, Qr = tQ * GT + ty;
+        Xs[ty][tx] = (Pr < N && A < N) ? Xp[(long)Pr * N + A] : 0.0;
+        Ys[ty][tx] = (Qr < N && A < N) ? Yp[(long)Qr * N + A] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GT; ++kk) acc += Xs[ty][kk] * Ys[tx][kk];
+        __syncthreads();
+    }
+    const int P = tP * GT + ty, Q = tQ * GT + tx;
+    if (P < N && Q < N) S[(long)p * NN + (long)P * N + Q] = acc;
+}
+
+// ----------------------------------------------------------- one-pair outputs
+__global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ R) {
+    const int P = blockIdx.x;
+    const int tid = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (tid == 0) {
+        a0 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, P, 0, 0, 0, v);
+        a1 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, P, 0, 0, 0, v);
+        a2 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, P, 0, 0, 0, v);
+    }
+    for (int A = tid; A < N; A += blockDim.x) {
+        if (A == P) continue;
+        a0 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, P, A, 0, 0, v);
+        a1 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, P, A, 0, 0, v);
+        a2 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, P, A, 0, 0, v);
+    }
+    const long NN = (long)N * N;
+    for (long ab = tid; ab < NN; ab += blockDim.x) {
+        const int A = (int)(ab / N), B = (int)(ab % N);
+        if (A == P || B == P || A == B) continue;
+        a0 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 0, P, A, B, 0, v);
+        a1 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 1, P, A, B, 0, v);
+        a2 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 2, P, A, B, 0, v);
+    }
+    __shared__ double red[3][256];
+    red[0][tid] = a0;
+    red[1][tid] = a1;
+    red[2][tid] = a2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[0][tid] += red[0][tid + s];
+            red[1][tid] += red[1][tid + s];
+            red[2][tid] += red[2][tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        R[P] = red[0][0];
+        R[N + P] = red[1][0];
+        R[2 * N + P] = red[2][0];
+    }
+}
+
+// ----------------------------------------------------------- two spectators
+constexpr int S2_ROWS = 16;
+constexpr int S2_TPR = 16;
+
+template <int MAXC>
+__global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __restrict__ W,
+                                              int gchunk, double* __restrict__ part) {
+    extern __shared__ double sm[];
+    double* La = sm;                       // [S2_ROWS][N]
+    double* acc = sm + S2_ROWS * N;        // [S2_ROWS][29]
+    const long np2 = (long)N * (N - 1) / 2;
+    const int tid = threadIdx.x, row = tid / S2_TPR, lane = tid % S2_TPR;
+    const long ip = (long)blockIdx.x * S2_ROWS + row;
+    const bool valid = ip < np2;
+    int P = 0, Q = 1;
+    if (valid) decode_pair(ip, P, Q);
+    for (int i = tid; i < S2_ROWS * NP2; i += blockDim.x) acc[i] = 0.0;
+    const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
+    for (int g = g0; g < g1; ++g) {
+        const int w = pq_g_w[g], a = pq_g_a[g];
+        __syncthreads();
+        for (int A = lane; A < N; A += S2_TPR)
+            La[row * N + A] = (valid && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
+        __syncthreads();
+        double V[MAXC];
+#pragma unroll
+        for (int j = 0; j < MAXC; ++j) V[j] = 0.0;
+        const double* Wg = W + (long)w * v.NN;
+        for (int A = 0; A < N; ++A) {
+            const double la = La[row * N + A];
+            const double* Wr = Wg + (long)A * N;
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j) {
+                const int B = lane + j * S2_TPR;
+                if (B < N) V[j] += la * Wr[B];
+            }
+        }
+        for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
+            const int b = pq_g_b[i], m = pq_g_mu[i];
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < MAXC; ++j) {
+                const int B = lane + j * S2_TPR;
+                if (B < N && B != P && B != Q) s += V[j] * spec_l(b, P, Q, B, v);
+            }
+            // reduce over the S2_TPR lanes of this row (consecutive lanes)
+            for (int o = S2_TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) acc[row * NP2 + m] += pq_g_coef[i] * s;
+        }
+    }
+    __syncthreads();
+    if (lane == 0 && valid)
+        for (int m = 0; m < NP2; ++m)
+            part[((long)blockIdx.y * NP2 + m) * np2 + ip] = acc[row * NP2 + m];
+}
+
+// ----------------------------------------------------------- two-pair outputs
+__global__ void k_r2(int N, View v, const double* __restrict__ part, int nchunk,
+                     double* __restrict__ R) {
+    const long np2 = (long)N * (N - 1) / 2;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= NP2 * np2) return;
+    const int m = (int)(gid / np2);
+    const long ip = gid % np2;
+    int P, Q;
+    decode_pair(ip, P, Q);
+    double acc = class_sum(pq_r2s0_start, pq_r2s0_coef, pq_r2s0_fac, m, P, Q, 0, 0, v);
+    acc += class_sum(pq_r2s1_start, pq_r2s1_coef, pq_r2s1_fac, m, P, Q, 0, 0, v);
+    for (int c = 0; c < nchunk; ++c) acc += part[((long)c * NP2 + m) * np2 + ip];
+    R[3L * N + m * np2 + ip] = acc;
+}
+
+// ------------------------------------------------------------------- energy
+__global__ __launch_bounds__(256) void k_energy(int N, View v, double* __restrict__ partial) {
+    const long NN = (long)N * N;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (gid < NN) {
+        const int P = (int)(gid / N), Q = (int)(gid % N);
+        if (P == Q)
+            e = class_sum(pq_e1_start, pq_e1_coef, pq_e1_fac, 0, P, 0, 0, 0, v);
+        else
+            e = 0.5 * class_sum(pq_e2_start, pq_e2_coef, pq_e2_fac, 0, P, Q, 0, 0, v);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_fixed(const double* __restrict__ partial, int n, double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ------------------------------------------------------------- denominators
+__global__ void k_denom(int N, const double* __restrict__ f, double shift, double* __restrict__ D) {
+    const long np2 = (long)N * (N - 1) / 2;
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n1 = 3L * N;
+    if (s >= n1 + NP2 * np2) return;
+    const long n2 = 2L * N;
+    auto foo = [&](int P) { return f[(long)P * n2 + P]; };
+    auto fvv = [&](int P) { return f[(long)(N + P) * n2 + N + P]; };
+    double d;
+    if (s < n1) {
+        const int k = (int)(s / N), P = (int)(s % N);
+        d = pq_cnt1[2 * k + 1] * fvv(P) - pq_cnt1[2 * k] * foo(P);
+    } else {
+        const int m = (int)((s - n1) / np2);
+        int P, Q;
+        decode_pair((s - n1) % np2, P, Q);
+        d = pq_cnt2[4 * m + 1] * fvv(P) - pq_cnt2[4 * m] * foo(P) + pq_cnt2[4 * m + 3] * fvv(Q) -
+            pq_cnt2[4 * m + 2] * foo(Q);
+    }
+    D[s] = d + shift;
+}
+
+struct Carve {
+    double *t2, *h1, *h2, *X, *Y, *S, *W, *part, *epart, *scal;
+    int nchunk, gchunk, nblkE;
+};
+
+inline int s2_rowtiles(int N) {
+    const long np2 = (long)N * (N - 1) / 2;
+    return (int)((np2 + S2_ROWS - 1) / S2_ROWS);
+}
+
+inline void s2_chunks(int N, int& nchunk, int& gchunk) {
+    const int rt = std::max(1, s2_rowtiles(N));
+    nchunk = std::min(64, std::max(1, (2048 + rt - 1) / rt));
+    gchunk = (PQ_G_N + nchunk - 1) / nchunk;
+    nchunk = (PQ_G_N + gchunk - 1) / gchunk;
+}
+
+Carve carve(double* ws, int N) {
+    const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
+    Carve c;
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t at = o; o += n; return ws + at; };
+    c.t2 = take(NP2 * NN);
+    c.h1 = take((size_t)PQ_H1_N * N);
+    c.h2 = take((size_t)PQ_H2_N * NN);
+    c.X = take((size_t)PQ_X_N * NN);
+    c.Y = take((size_t)PQ_Y_N * NN);
+    c.S = take((size_t)PQ_S1PAIRS_N * NN);
+    c.W = take((size_t)PQ_W_N * NN);
+    s2_chunks(N, c.nchunk, c.gchunk);
+    c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
+    c.nblkE = (int)((NN + 255) / 256);
+    c.epart = take(c.nblkE);
+    c.scal = take(8);
+    return c;
+}
+
+size_t carve_size(int N) {
+    const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
+    int nchunk, gchunk;
+    s2_chunks(N, nchunk, gchunk);
+    return NP2 * NN + (size_t)PQ_H1_N * N +
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_S1PAIRS_N + PQ_W_N) * NN +
+           (size_t)nchunk * NP2 * std::max(np2, (size_t)1) + (NN + 255) / 256 + 8;
+}
+
+View make_view(const double* t, const Carve& c, int N) {
+    View v;
+    v.t1 = t;
+    v.t2 = c.t2;
+    v.h1 = c.h1;
+    v.h2 = c.h2;
+    v.S = c.S;
+    v.N = N;
+    v.NN = (long)N * N;
+    return v;
+}
+
+pqph_status prepare(pqph_ctx* ctx, int N, const double* h, const double* eri, const double* t,
+                    const Carve& c) {
+    hipStream_t s = ctx->stream;
+    const int tb = 64;
+    const int gx = (N + tb - 1) / tb;
+    hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1);
+    if (N > 1) {
+        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2);
+        hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2);
+    }
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
+}  // namespace
+
+size_t pq_ws_doubles(int npair) { return carve_size(npair); }
+
+pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* eri,
+                           const double* t, double* r, double* ws) {
+    hipStream_t s = ctx->stream;
+    Carve c = carve(ws, N);
+    pqph_status st = prepare(ctx, N, h, eri, t, c);
+    if (st) return st;
+    View v = make_view(t, c, N);
+    const int tb = 64;
+    const int gx = (N + tb - 1) / tb;
+    if (N > 1) {
+        const long np2 = (long)N * (N - 1) / 2;
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W);
+        const int tiles = (N + GT - 1) / GT;
+        hipLaunchKernelGGL(k_gemm_s1, dim3(tiles * tiles, 1, PQ_S1PAIRS_N), dim3(256), 0, s, N,
+                           c.X, c.Y, c.S);
+        const size_t lds = (size_t)(S2_ROWS * N + S2_ROWS * NP2) * sizeof(double);
+        dim3 g2(s2_rowtiles(N), c.nchunk);
+        const int maxc = (N + S2_TPR - 1) / S2_TPR;
+        if (maxc <= 2)
+            hipLaunchKernelGGL(k_r2s2<2>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        else if (maxc <= 4)
+            hipLaunchKernelGGL(k_r2s2<4>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        else if (maxc <= 8)
+            hipLaunchKernelGGL(k_r2s2<8>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        else
+            hipLaunchKernelGGL(k_r2s2<16>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        const long nth = NP2 * np2;
+        hipLaunchKernelGGL(k_r2, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, N, v,
+                           c.part, c.nchunk, r);
+    }
+    hipLaunchKernelGGL(k_r1, dim3(N), dim3(256), 0, s, N, v, r);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
+pqph_status pq_energy_ws(pqph_ctx* ctx, int N, const double* h, const double* eri,
+                         const double* t, double* dst, double* ws) {
+    hipStream_t s = ctx->stream;
+    Carve c = carve(ws, N);
+    pqph_status st = prepare(ctx, N, h, eri, t, c);
+    if (st) return st;
+    View v = make_view(t, c, N);
+    hipLaunchKernelGGL(k_energy, dim3(c.nblkE), dim3(256), 0, s, N, v, c.epart);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, c.epart, c.nblkE, dst);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
+pqph_status pq_denominators_dev(pqph_ctx* ctx, int N, const double* h, double shift, double* D) {
+    const long n = (long)pq_amp_len(N);
+    hipLaunchKernelGGL(k_denom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, N,
+                       h, shift, D);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}

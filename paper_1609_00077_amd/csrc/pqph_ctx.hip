@@ -1,0 +1,442 @@
+// Context, workspace and the C ABI entry points of libpqph.
+#include "pqph_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_no_ctx_error;
+
+// ------------------------------------------------------------ vector kernels
+__global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, size_t n,
+                              double* __restrict__ partial) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[j] = sum of partial[j*nblk .. (j+1)*nblk)
+__global__ void k_sum_rows(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(size_t)j * nblk + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// e = -r/D ; tn = t + e ; also ||r||^2 partials are computed separately
+__global__ void k_jacobi(const double* __restrict__ t, const double* __restrict__ r,
+                         const double* __restrict__ D, size_t n, double* __restrict__ tn,
+                         double* __restrict__ e) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double d = -r[i] / D[i];
+        e[i] = d;
+        tn[i] = t[i] + d;
+    }
+}
+
+// t = sum_i c[i] * hist[slot_i]
+__global__ void k_combine(const double* __restrict__ hist, const double* __restrict__ c, int m,
+                          size_t n, double* __restrict__ t) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += c[j] * hist[(size_t)j * n + i];
+        t[i] = s;
+    }
+}
+
+// several dot products against one vector: out[j] partials for a[j] . b
+__global__ void k_dots_partial(const double* __restrict__ A, int m, const double* __restrict__ b,
+                               size_t n, int nblk, double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int j = blockIdx.y;
+    double s = 0.0;
+    const double* a = A + (size_t)j * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = red[0];
+}
+
+int stream_blocks(size_t n) { return (int)std::min<size_t>(1024, (n + 255) / 256); }
+
+// Solve the (m+1) x (m+1) DIIS system with partial pivoting; false if singular.
+bool diis_solve(const std::vector<double>& B, int m, std::vector<double>& c) {
+    const int n = m + 1;
+    std::vector<double> A((size_t)n * (n + 1));
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(B[(size_t)i * 16 + i]));
+    if (!(scale > 0.0)) return false;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) {
+            double v;
+            if (i < m && j < m) v = B[(size_t)i * 16 + j] / scale;
+            else if (i == m && j == m) v = 0.0;
+            else v = -1.0;
+            A[(size_t)i * (n + 1) + j] = v;
+        }
+        A[(size_t)i * (n + 1) + n] = (i == m) ? -1.0 : 0.0;
+    }
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < n; ++i)
+            if (std::fabs(A[(size_t)i * (n + 1) + col]) > std::fabs(A[(size_t)piv * (n + 1) + col]))
+                piv = i;
+        if (std::fabs(A[(size_t)piv * (n + 1) + col]) < 1e-300) return false;
+        if (piv != col)
+            for (int j = 0; j <= n; ++j)
+                std::swap(A[(size_t)piv * (n + 1) + j], A[(size_t)col * (n + 1) + j]);
+        for (int i = 0; i < n; ++i) {
+            if (i == col) continue;
+            const double fct = A[(size_t)i * (n + 1) + col] / A[(size_t)col * (n + 1) + col];
+            for (int j = col; j <= n; ++j) A[(size_t)i * (n + 1) + j] -= fct * A[(size_t)col * (n + 1) + j];
+        }
+    }
+    c.assign(m, 0.0);
+    for (int i = 0; i < m; ++i) c[i] = A[(size_t)i * (n + 1) + n] / A[(size_t)i * (n + 1) + i];
+    for (double x : c)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- helpers
+pqph_status pqph_fail(pqph_ctx* ctx, pqph_status st, const std::string& msg) {
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_no_ctx_error = msg;
+    return st;
+}
+
+static pqph_status ensure_dev(pqph_ctx* ctx, double*& buf, size_t& have, size_t bytes) {
+    if (bytes <= have) return PQPH_OK;
+    if (buf) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(buf);
+        buf = nullptr;
+        have = 0;
+    }
+    size_t want = std::max(bytes, have + have / 4);
+    if (hipMalloc((void**)&buf, want) != hipSuccess) {
+        buf = nullptr;
+        (void)hipGetLastError();
+        if (hipMalloc((void**)&buf, bytes) != hipSuccess) {
+            buf = nullptr;
+            (void)hipGetLastError();
+            return pqph_fail(ctx, PQPH_OOM, "device workspace allocation of " +
+                                                std::to_string(bytes) + " bytes failed");
+        }
+        want = bytes;
+    }
+    have = want;
+    return PQPH_OK;
+}
+
+pqph_status pqph_ensure_ws(pqph_ctx* ctx, size_t bytes) {
+    return ensure_dev(ctx, ctx->ws, ctx->ws_bytes, bytes);
+}
+pqph_status pqph_ensure_sv(pqph_ctx* ctx, size_t bytes) {
+    return ensure_dev(ctx, ctx->sv, ctx->sv_bytes, bytes);
+}
+pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n) {
+    if (n <= ctx->host_n) return PQPH_OK;
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    ctx->host = nullptr;
+    ctx->host_n = 0;
+    if (hipHostMalloc((void**)&ctx->host, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        ctx->host = nullptr;
+        (void)hipGetLastError();
+        return pqph_fail(ctx, PQPH_OOM, "pinned host allocation failed");
+    }
+    ctx->host_n = n;
+    return PQPH_OK;
+}
+
+void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,
+                    int nblk) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, s, a, b, n, partial);
+}
+
+static pqph_status check_pq(pqph_ctx* ctx, int npair) {
+    if (!ctx) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null context");
+    if (npair < 1 || npair > 256)
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "npair must be in [1, 256]");
+    PQPH_HIP(ctx, hipSetDevice(ctx->device));
+    return PQPH_OK;
+}
+
+// ================================================================== C ABI
+extern "C" {
+
+void pqph_default_opts(pqph_solve_opts* o) {
+    if (!o) return;
+    o->max_iter = 200;
+    o->tol = 1e-8;
+    o->diis_dim = 8;
+    o->diis_start = 2;
+    o->level_shift = 0.0;
+    o->diverge_factor = 1e4;
+}
+
+pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
+    if (!out) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return pqph_fail(nullptr, PQPH_INVALID_ARG, "no such HIP device");
+    pqph_ctx* ctx = new pqph_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->ev0) != hipSuccess ||
+        hipEventCreate(&ctx->ev1) != hipSuccess) {
+        delete ctx;
+        return pqph_fail(nullptr, PQPH_DEVICE, "device setup failed");
+    }
+    *out = ctx;
+    return PQPH_OK;
+}
+
+void pqph_destroy(pqph_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->sv) (void)hipFree(ctx->sv);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+const char* pqph_last_error(const pqph_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_no_ctx_error.c_str();
+}
+
+size_t pq_amp_len(int n) {
+    if (n < 1) return 0;
+    return 3 * (size_t)n + 29 * ((size_t)n * (n - 1) / 2);
+}
+size_t ph_amp_len(int n) {
+    if (n < 1) return 0;
+    return pq_amp_len(n) + 303 * ((size_t)n * (n - 1) * (n - 2) / 6);
+}
+size_t pq_eri_len(int n) {
+    if (n < 1) return 0;
+    return 6 * (size_t)n + 43 * ((size_t)n * (n - 1) / 2);
+}
+size_t ph_eri_len(int n) {
+    if (n < 1) return 0;
+    return pq_eri_len(n) + 84 * ((size_t)n * (n - 1) * (n - 2) / 6);
+}
+
+pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                        const double* t, double* r) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
+    if (st) return st;
+    return pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+}
+
+pqph_status pq_energy(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                      const double* t, double* energy) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    const size_t wsd = pq_ws_doubles(npair);
+    st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double));
+    if (st) return st;
+    double* dst = ctx->ws + wsd;
+    st = pq_energy_ws(ctx, npair, h, eri, t, dst, ctx->ws);
+    if (st) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(energy, dst, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(*energy)) return pqph_fail(ctx, PQPH_NONFINITE, "non-finite energy");
+    return PQPH_OK;
+}
+
+pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, double shift,
+                              double* D) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (k != 2) return pqph_fail(ctx, PQPH_INVALID_ARG, "only k = 2 is built");
+    if (!h || !D) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    return pq_denominators_dev(ctx, npair, h, shift, D);
+}
+
+pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                     const pqph_solve_opts* opts_in, double* t, double* energy,
+                     pqph_solve_info* info) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    pqph_solve_opts o;
+    pqph_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
+        !(o.diverge_factor > 1.0))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
+    const size_t n = pq_amp_len(npair);
+    const int m = std::max(o.diis_dim, 1);
+    const int nblk = stream_blocks(n);
+    // solver buffers: D, r, e, tn, t-history (m), e-history (m), partials, scalars
+    const size_t svd = n * (4 + 2 * (size_t)m) + (size_t)nblk * (m + 1) + 64;
+    st = pqph_ensure_sv(ctx, svd * sizeof(double));
+    if (st) return st;
+    const size_t wsd = pq_ws_doubles(npair);
+    st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double));
+    if (st) return st;
+    st = pqph_ensure_host(ctx, 64);
+    if (st) return st;
+    double* D = ctx->sv;
+    double* r = D + n;
+    double* e = r + n;
+    double* tn = e + n;
+    double* th = tn + n;
+    double* eh = th + (size_t)m * n;
+    double* part = eh + (size_t)m * n;
+    double* scal = part + (size_t)nblk * (m + 1);
+    double* hst = ctx->host;
+    hipStream_t s = ctx->stream;
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    st = pq_denominators_dev(ctx, npair, h, o.level_shift, D);
+    if (st) return st;
+    // the denominators must not vanish
+    {
+        std::vector<double> Dh(n);
+        PQPH_HIP(ctx, hipMemcpyAsync(Dh.data(), D, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        PQPH_HIP(ctx, hipStreamSynchronize(s));
+        for (size_t i = 0; i < n; ++i)
+            if (!(std::fabs(Dh[i]) > 1e-12))
+                return pqph_fail(ctx, PQPH_INVALID_ARG, "vanishing orbital-energy denominator");
+    }
+    std::vector<double> B(16 * 16, 0.0), c;
+    int stored = 0, next = 0, it = 0;
+    double rn = INFINITY, rmin = INFINITY;
+    pqph_status result = PQPH_NOT_CONVERGED;
+    for (it = 1; it <= o.max_iter; ++it) {
+        st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+        if (st) return st;
+        vec_dot_launch(s, r, r, n, part, nblk);
+        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, part, nblk, scal);
+        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        PQPH_HIP(ctx, hipStreamSynchronize(s));
+        rn = std::sqrt(hst[0]);
+        if (!std::isfinite(rn)) {
+            result = PQPH_NONFINITE;
+            pqph_fail(ctx, result, "non-finite residual at iteration " + std::to_string(it));
+            break;
+        }
+        rmin = std::min(rmin, rn);
+        if (rn <= o.tol) {
+            result = PQPH_OK;
+            break;
+        }
+        if (rn > 1e3 || rn > o.diverge_factor * rmin) {
+            result = PQPH_DIVERGED;
+            pqph_fail(ctx, result, "residual norm diverged at iteration " + std::to_string(it));
+            break;
+        }
+        if (it == o.max_iter) break;
+        hipLaunchKernelGGL(k_jacobi, dim3(stream_blocks(n)), dim3(256), 0, s, t, r, D, n, tn, e);
+        if (o.diis_dim == 0) {
+            PQPH_HIP(ctx, hipMemcpyAsync(t, tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            continue;
+        }
+        const int slot = next;
+        next = (next + 1) % m;
+        stored = std::min(stored + 1, m);
+        PQPH_HIP(ctx, hipMemcpyAsync(th + (size_t)slot * n, tn, n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        // Gram row of the new error vector against every stored one
+        hipLaunchKernelGGL(k_dots_partial, dim3(nblk, m), dim3(256), 0, s, eh, m,
+                           eh + (size_t)slot * n, n, nblk, part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(m), dim3(256), 0, s, part, nblk, scal);
+        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        PQPH_HIP(ctx, hipStreamSynchronize(s));
+        for (int j = 0; j < m; ++j) {
+            B[(size_t)slot * 16 + j] = hst[j];
+            B[(size_t)j * 16 + slot] = hst[j];
+        }
+        bool use = (it >= o.diis_start) && stored >= 2;
+        if (use) {
+            // compact the stored slots into a dense system
+            std::vector<int> slots;
+            for (int j = 0; j < m; ++j)
+                if (j < stored) slots.push_back(j);
+            const int ms = (int)slots.size();
+            std::vector<double> Bs(16 * 16, 0.0);
+            for (int a = 0; a < ms; ++a)
+                for (int b = 0; b < ms; ++b) Bs[(size_t)a * 16 + b] = B[(size_t)slots[a] * 16 + slots[b]];
+            if (diis_solve(Bs, ms, c)) {
+                std::vector<double> cm(m, 0.0);
+                for (int a = 0; a < ms; ++a) cm[slots[a]] = c[a];
+                for (int j = 0; j < m; ++j) hst[8 + j] = cm[j];
+                PQPH_HIP(ctx, hipMemcpyAsync(scal + 16, hst + 8, m * sizeof(double),
+                                             hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_combine, dim3(stream_blocks(n)), dim3(256), 0, s, th,
+                                   scal + 16, m, n, t);
+                // keep the pinned staging alive until the copy has run
+                PQPH_HIP(ctx, hipStreamSynchronize(s));
+                continue;
+            }
+        }
+        PQPH_HIP(ctx, hipMemcpyAsync(t, tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (result == PQPH_NOT_CONVERGED)
+        pqph_fail(ctx, result, "not converged in " + std::to_string(o.max_iter) + " iterations");
+    double* edst = ctx->ws + wsd;
+    st = pq_energy_ws(ctx, npair, h, eri, t, edst, ctx->ws);
+    if (st) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(hst, edst, sizeof(double), hipMemcpyDeviceToHost, s));
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));
+    PQPH_HIP(ctx, hipStreamSynchronize(s));
+    *energy = hst[0];
+    if (info) {
+        info->iterations = std::min(it, o.max_iter);
+        info->rnorm = rn;
+        info->status = result;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        info->solve_ms = ms;
+    }
+    if (result == PQPH_OK && !std::isfinite(*energy)) {
+        result = PQPH_NONFINITE;
+        pqph_fail(ctx, result, "non-finite energy");
+    }
+    return result;
+}
+
+}  // extern "C"

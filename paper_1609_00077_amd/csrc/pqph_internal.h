@@ -1,0 +1,56 @@
+// Internal declarations shared by the translation units of libpqph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pqph.h"
+
+struct pqph_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // one growable device workspace, carved per call
+    double* ws = nullptr;
+    size_t ws_bytes = 0;
+    // persistent solver buffers (separate so residual calls can reuse ws)
+    double* sv = nullptr;
+    size_t sv_bytes = 0;
+    // pinned host staging for small reductions
+    double* host = nullptr;
+    size_t host_n = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// error helpers -----------------------------------------------------------
+pqph_status pqph_fail(pqph_ctx* ctx, pqph_status st, const std::string& msg);
+#define PQPH_HIP(ctx, call)                                                       \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return pqph_fail(ctx, PQPH_DEVICE, std::string(#call) + ": " +        \
+                                                   hipGetErrorString(e_));        \
+    } while (0)
+
+pqph_status pqph_ensure_ws(pqph_ctx* ctx, size_t bytes);
+pqph_status pqph_ensure_sv(pqph_ctx* ctx, size_t bytes);
+pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n);
+
+// PQ residual pieces (pq_residual.hip) --------------------------------------
+size_t pq_ws_doubles(int npair);
+// residual into r using workspace ws (already large enough); no host sync
+pqph_status pq_residual_ws(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                           const double* t, double* r, double* ws);
+// energy partials: writes one double (the energy) to dst (device), no sync
+pqph_status pq_energy_ws(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                         const double* t, double* dst, double* ws);
+pqph_status pq_denominators_dev(pqph_ctx* ctx, int npair, const double* h, double shift,
+                                double* D);
+
+// streaming vector kernels (solve.hip) ---------------------------------------
+void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,
+                    int nblk);

@@ -1,0 +1,352 @@
+"""Turn the derived PQ terms into the constant tables of the HIP library.
+
+Kernel plan for the PQ residual (k = 2), by output block and spectators:
+
+  R1S0, R1S1, R1S2   one-pair outputs with 0/1/2 spectators: interpreted term
+                     tables, one output pair per workgroup, spectators over
+                     threads (O(N), O(N^2), O(N^3) total work)
+  R2S0               two-pair outputs, no spectator: interpreted per pair (O(N^2))
+  R2S1               one spectator A: every A-dependent factor product is
+                     split into a P-A side X[x](P,A) and a Q-A side Y[y](Q,A);
+                     S_p(P,Q) = sum_A X[x_p](P,A) Y[y_p](Q,A) for the distinct
+                     (x, y) pairs is a batched GEMM (O(N^3)); an epilogue
+                     multiplies by the A-free factors (O(N^2))
+  R2S2               two spectators A, B: L_a(P,Q,A) W_w(A,B) L'_b(P,Q,B) with
+                     the dressed spectator vertex W_w = h_AB x (t_A, t_B, t_AB
+                     factors) tabulated per Hamiltonian/iteration (O(N^4))
+  E1, E2             correlation energy (label sets of one and two pairs)
+
+Factor codes (int32): kind << 28 | r0 << 24 | r1 << 20 | r2 << 16 | idx
+  kind 1: t1[idx][L(r0)]                  kind 2: t2[idx][L(r0)][L(r1)]
+  kind 3: h1[idx][L(r0)]                  kind 4: h2[idx][L(r0)][L(r1)]
+  kind 5: intermediate[idx] of the class (S_p for R2S1)
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import algebra
+from .terms import enumerate_class, merge_terms
+
+KIND_T1, KIND_T2, KIND_H1, KIND_H2, KIND_S = 1, 2, 3, 4, 5
+MAXF = 5
+
+
+def fcode(kind, roles, idx):
+    r = list(roles) + [0] * (3 - len(roles))
+    assert 0 <= idx < (1 << 16)
+    return (kind << 28) | (r[0] << 24) | (r[1] << 20) | (r[2] << 16) | idx
+
+
+@dataclass
+class TermTable:
+    """Terms grouped by output pattern: terms of output m are
+    [start[m], start[m+1])."""
+    start: np.ndarray
+    coef: np.ndarray
+    fac: np.ndarray      # (nterm, MAXF) int32, 0 = unit factor
+
+
+@dataclass
+class PQTables:
+    k: int = 2
+    h1_keys: list = field(default_factory=list)
+    h2_keys: list = field(default_factory=list)
+    # vertex symbol tables
+    h1_sym: dict = None
+    h2_sym: dict = None
+    swap2: np.ndarray = None       # pattern pair m -> mirrored index
+    swap2_sign: np.ndarray = None
+    denom: np.ndarray = None       # (#slots) per pattern: particle/hole counts
+    classes: dict = field(default_factory=dict)
+    r2s1_x: list = None            # spec tuples (codes) with roles 0 (P), 1 (A)
+    r2s1_y: list = None            # spec tuples with roles 0 (Q), 1 (A)
+    r2s1_pairs: np.ndarray = None  # (npair, 2) x, y
+    r2s2_l: list = None            # A-side link specs, roles 0 P, 1 Q, 2 A
+    r2s2_w: list = None            # vertex specs, roles 0 A, 1 B
+    r2s2_groups: list = None       # per (w, a): list of (b, coef, mu)
+
+
+def _hkey_index(tables, hroles, hkey):
+    """Index of a Hamiltonian term with roles relabelled to 0..len-1."""
+    rmap = {r: i for i, r in enumerate(hroles)}
+    I, J = hkey
+    re = lambda g: 4 * rmap[g // 4] + g % 4
+    key = (tuple(re(g) for g in I), tuple(re(g) for g in J))
+    keys = tables.h1_keys if len(hroles) == 1 else tables.h2_keys
+    return keys.index(key)
+
+
+def _slot_code(rho, pats, rolemap):
+    m = algebra.pattern_tuples(len(pats)).index(pats)
+    roles = [rolemap[r] for r in rho]
+    if len(rho) == 1:
+        return fcode(KIND_T1, roles, m)
+    return fcode(KIND_T2, roles, m)
+
+
+def _h_code(tables, hroles, hkey, rolemap):
+    idx = _hkey_index(tables, hroles, hkey)
+    roles = [rolemap[r] for r in hroles]
+    return fcode(KIND_H1 if len(hroles) == 1 else KIND_H2, roles, idx)
+
+
+def _table(nout_pats, rows):
+    """rows: list of (mu_index, coef, [codes])."""
+    rows = sorted(rows, key=lambda r: r[0])
+    start = np.zeros(nout_pats + 1, dtype=np.int32)
+    coef = np.zeros(len(rows))
+    fac = np.zeros((len(rows), MAXF), dtype=np.int32)
+    for i, (m, c, codes) in enumerate(rows):
+        assert len(codes) <= MAXF
+        start[m + 1] += 1
+        coef[i] = c
+        fac[i, :len(codes)] = codes
+    start = np.cumsum(start).astype(np.int32)
+    return TermTable(start, coef, fac)
+
+
+def _interp_rows(tables, terms, nout):
+    ident = {r: r for r in range(8)}
+    rows = []
+    for t in terms:
+        m = algebra.pattern_tuples(nout).index(t.mu) if nout else 0
+        codes = [_h_code(tables, t.hroles, t.hkey, ident)]
+        codes += [_slot_code(rho, p, ident) for rho, p in t.slots]
+        rows.append((m, float(t.sign), codes))
+    return rows
+
+
+def eri_quads(size):
+    """Stored quadruples of the packed integral layout (include/pqph.h)."""
+    norb = 2 * size
+    pairs = [(p, q) for p in range(norb) for q in range(p + 1)]
+    out = []
+    for ipq, (p, q) in enumerate(pairs):
+        for irs in range(ipq + 1):
+            r, s = pairs[irs]
+            if len({p // 2, q // 2, r // 2, s // 2}) == size:
+                out.append((p, q, r, s))
+    return out
+
+
+def eri_unique_index(size, quad):
+    """Packed index u of (pq|rs) (local orbitals of a sorted label set)."""
+    p, q, r, s = quad
+    if p < q:
+        p, q = q, p
+    if r < s:
+        r, s = s, r
+    pq, rs = p * (p + 1) // 2 + q, r * (r + 1) // 2 + s
+    if pq < rs:
+        p, q, r, s = r, s, p, q
+    return eri_quads(size).index((p, q, r, s))
+
+
+def build_pq_tables() -> PQTables:
+    k = 2
+    tb = PQTables(k=k)
+    tb.h1_keys = sorted(algebra.hamiltonian_terms((0,), k).keys())
+    tb.h2_keys = sorted(algebra.hamiltonian_terms((0, 1), k).keys())
+    # vertex symbol reading rules ------------------------------------------
+    # h1: symbols on role 0; local orbital x -> type x%2 of the single label.
+    h1 = []
+    for key in tb.h1_keys:
+        ent = []
+        for sym, w in sorted(algebra.hamiltonian_terms((0,), k)[key].items()):
+            if sym[0] == "f":
+                ent.append((w, 0, sym[1] % 2, sym[2] % 2, 0, 0))        # f(type_p, type_q)
+            else:
+                u = eri_unique_index(1, sym[1:])
+                ent.append((w, 1, u, u, 0, 0))
+        h1.append(ent)
+    h2 = []
+    for key in tb.h2_keys:
+        ent = []
+        for sym, w in sorted(algebra.hamiltonian_terms((0, 1), k)[key].items()):
+            if sym[0] == "f":
+                # f between (role_p, type_p) and (role_q, type_q)
+                ent.append((w, 0, sym[1], sym[2], 0, 0))
+            else:
+                quad = sym[1:]
+                u_lt = eri_unique_index(2, quad)                       # L(0) < L(1)
+                sw = tuple((x ^ 2) for x in quad)                       # roles swapped
+                u_gt = eri_unique_index(2, sw)                         # L(0) > L(1)
+                ent.append((w, 1, u_lt, u_gt, 0, 0))
+        h2.append(ent)
+    tb.h1_sym, tb.h2_sym = h1, h2
+    # mirror map of pattern pairs --------------------------------------------
+    pt2 = algebra.pattern_tuples(2)
+    tb.swap2 = np.array([pt2.index((b, a)) for a, b in pt2], dtype=np.int32)
+    pc = lambda e: bin(e).count("1") % 2
+    tb.swap2_sign = np.array([-1.0 if pc(a) and pc(b) else 1.0 for a, b in pt2])
+    # interpreted classes ----------------------------------------------------
+    for name, nout, nspec in (("E1", 0, 1), ("E2", 0, 2), ("R1S0", 1, 0),
+                              ("R1S1", 1, 1), ("R1S2", 1, 2), ("R2S0", 2, 0)):
+        terms = merge_terms(enumerate_class(k, nout, nspec))
+        tb.classes[name] = _table(max(1, len(algebra.pattern_tuples(nout)) if nout else 1),
+                                  _interp_rows(tb, terms, nout))
+    # R2S1: P=0, Q=1, A=2 ----------------------------------------------------
+    terms = merge_terms(enumerate_class(k, 2, 1))
+    xs, ys, pairs, rows = {}, {}, {}, []
+    for t in terms:
+        X, Y, Z = [], [], []
+        hx = set(t.hroles)
+        if hx == {1, 2}:
+            Y.append(_h_code(tb, t.hroles, t.hkey, {1: 0, 2: 1}))
+        else:
+            X.append(_h_code(tb, t.hroles, t.hkey, {0: 0, 2: 1}))
+        for rho, p in t.slots:
+            if 2 in rho:
+                if 1 in rho:
+                    Y.append(_slot_code(rho, p, {1: 0, 2: 1}))
+                else:
+                    X.append(_slot_code(rho, p, {0: 0, 2: 1}))
+            else:
+                Z.append(_slot_code(rho, p, {0: 0, 1: 1}))
+        X, Y = tuple(sorted(X)), tuple(sorted(Y))
+        xi = xs.setdefault(X, len(xs))
+        yi = ys.setdefault(Y, len(ys))
+        pi = pairs.setdefault((xi, yi), len(pairs))
+        m = algebra.pattern_tuples(2).index(t.mu)
+        rows.append((m, float(t.sign), sorted(Z) + [fcode(KIND_S, [], pi)]))
+    tb.r2s1_x = [list(x) for x in sorted(xs, key=xs.get)]
+    tb.r2s1_y = [list(y) for y in sorted(ys, key=ys.get)]
+    tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
+    tb.classes["R2S1"] = _table(29, rows)
+    # R2S2: P=0, Q=1, A=2, B=3 -----------------------------------------------
+    terms = merge_terms(enumerate_class(k, 2, 2))
+    ls, ws, groups = {}, {}, {}
+    for t in terms:
+        LA, LB, W = [], [], [_h_code(tb, t.hroles, t.hkey, {2: 0, 3: 1})]
+        for rho, p in t.slots:
+            if rho in ((0, 2), (1, 2)):
+                LA.append(_slot_code(rho, p, {0: 0, 1: 1, 2: 2}))
+            elif rho in ((0, 3), (1, 3)):
+                LB.append(_slot_code(rho, p, {0: 0, 1: 1, 3: 2}))
+            else:
+                W.append(_slot_code(rho, p, {2: 0, 3: 1}))
+        LA, LB, W = tuple(sorted(LA)), tuple(sorted(LB)), tuple(sorted(W))
+        ai = ls.setdefault(LA, len(ls))
+        bi = ls.setdefault(LB, len(ls))
+        wi = ws.setdefault(W, len(ws))
+        m = algebra.pattern_tuples(2).index(t.mu)
+        groups.setdefault((wi, ai), []).append((bi, 0.5 * t.sign, m))
+    tb.r2s2_l = [list(x) for x in sorted(ls, key=ls.get)]
+    tb.r2s2_w = [list(x) for x in sorted(ws, key=ws.get)]
+    tb.r2s2_groups = sorted(groups.items())
+    return tb
+
+
+# ------------------------------------------------------------------ emitter
+def _arr(name, ctype, vals, per_line=16):
+    vals = list(vals)
+    if not vals:
+        vals = [0]
+    if ctype == "double":
+        fmt = lambda v: repr(float(v))
+    else:
+        fmt = lambda v: str(int(v))
+    lines = []
+    for i in range(0, len(vals), per_line):
+        lines.append("  " + ", ".join(fmt(v) for v in vals[i:i + per_line]))
+    return f"__device__ const {ctype} {name}[{len(vals)}] = {{\n" + ",\n".join(lines) + "\n};\n"
+
+
+def _spec_arrays(prefix, specs):
+    start = [0]
+    codes = []
+    for sp in specs:
+        codes += sp
+        start.append(len(codes))
+    return (_arr(prefix + "_start", "int", start) + _arr(prefix + "_fac", "int", codes)
+            + f"#define {prefix.upper()}_N {len(specs)}\n")
+
+
+def _vertex_arrays(prefix, syms):
+    start = [0]
+    w, kind, a, b = [], [], [], []
+    for ent in syms:
+        for (ww, kk, aa, bb, _, _) in ent:
+            w.append(ww)
+            kind.append(kk)
+            a.append(aa)
+            b.append(bb)
+        start.append(len(w))
+    return (_arr(prefix + "_start", "int", start) + _arr(prefix + "_w", "double", w)
+            + _arr(prefix + "_kind", "int", kind) + _arr(prefix + "_a", "int", a)
+            + _arr(prefix + "_b", "int", b) + f"#define {prefix.upper()}_N {len(syms)}\n")
+
+
+def _class_arrays(prefix, tab: TermTable):
+    return (_arr(prefix + "_start", "int", tab.start) + _arr(prefix + "_coef", "double", tab.coef)
+            + _arr(prefix + "_fac", "int", tab.fac.reshape(-1))
+            + f"#define {prefix.upper()}_NOUT {len(tab.start) - 1}\n"
+            + f"#define {prefix.upper()}_NTERM {len(tab.coef)}\n")
+
+
+def _pattern_counts():
+    """(holes, particles) per pattern tuple entry, for the denominators."""
+    out1 = []
+    for (e,) in algebra.pattern_tuples(1):
+        out1 += [bin(e & 3).count("1"), bin(e & 12).count("1")]
+    out2 = []
+    for a, b in algebra.pattern_tuples(2):
+        out2 += [bin(a & 3).count("1"), bin(a & 12).count("1"),
+                 bin(b & 3).count("1"), bin(b & 12).count("1")]
+    return out1, out2
+
+
+def emit_pq_header(tb: PQTables, path: str):
+    parts = ["// Generated by paper_1609_00077_amd/derive/codegen.py -- do not edit.\n"
+             "// Constant tables of the PQ residual: Hamiltonian vertices, interpreted\n"
+             "// term classes and the factorisation of the spectator sums.\n"
+             "#pragma once\n"]
+    parts.append(_vertex_arrays("pq_h1", tb.h1_sym))
+    parts.append(_vertex_arrays("pq_h2", tb.h2_sym))
+    parts.append(_arr("pq_swap2", "int", tb.swap2) + _arr("pq_swap2_sign", "double", tb.swap2_sign))
+    c1, c2 = _pattern_counts()
+    parts.append(_arr("pq_cnt1", "int", c1) + _arr("pq_cnt2", "int", c2))
+    for name in ("E1", "E2", "R1S0", "R1S1", "R1S2", "R2S0", "R2S1"):
+        parts.append(_class_arrays("pq_" + name.lower(), tb.classes[name]))
+    parts.append(_spec_arrays("pq_x", tb.r2s1_x))
+    parts.append(_spec_arrays("pq_y", tb.r2s1_y))
+    parts.append(_arr("pq_s1pairs", "int", tb.r2s1_pairs.reshape(-1))
+                 + f"#define PQ_S1PAIRS_N {len(tb.r2s1_pairs)}\n")
+    parts.append(_spec_arrays("pq_l", tb.r2s2_l))
+    parts.append(_spec_arrays("pq_w", tb.r2s2_w))
+    gw, ga, gs, gb, gc, gm = [], [], [0], [], [], []
+    for (wi, ai), lst in tb.r2s2_groups:
+        gw.append(wi)
+        ga.append(ai)
+        for bi, c, m in lst:
+            gb.append(bi)
+            gc.append(c)
+            gm.append(m)
+        gs.append(len(gb))
+    parts.append(_arr("pq_g_w", "int", gw) + _arr("pq_g_a", "int", ga) + _arr("pq_g_start", "int", gs)
+                 + _arr("pq_g_b", "int", gb) + _arr("pq_g_coef", "double", gc) + _arr("pq_g_mu", "int", gm)
+                 + f"#define PQ_G_N {len(gw)}\n")
+    for size in (1, 2, 3):
+        q = eri_quads(size)
+        parts.append(_arr(f"pqph_quads{size}", "int", [x for quad in q for x in quad])
+                     + f"#define PQPH_QUADS{size}_N {len(q)}\n")
+    maxlen = max(len(s) for s in tb.r2s1_x + tb.r2s1_y + tb.r2s2_l + tb.r2s2_w)
+    parts.append(f"#define PQ_SPEC_MAXLEN {maxlen}\n")
+    with open(path, "w") as fh:
+        fh.write("\n".join(parts))
+
+
+def main():
+    import os
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    out = sys.argv[1] if len(sys.argv) > 1 else os.path.join(here, "..", "csrc", "pq_tables.h")
+    emit_pq_header(build_pq_tables(), out)
+
+
+if __name__ == "__main__":
+    main()
