@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the PQ hot path on one MI355X.
+
+Step = one complete PQ solve of the 140-site PPP chain (140 electrons in 140
+orbitals, 70 pairs; U = 4, seed 140): integral transformation into pair
+blocks, Jacobi/DIIS iterations from t = 0 to ||R|| <= 1e-8 (each iteration one
+residual evaluation, the norm check, the Jacobi update and the DIIS
+extrapolation) and the final correlation energy.  Value = residual
+evaluations per second over the timed steps.  The orbitals come from a
+host-side RHF outside the timed region (input preparation, like the paper's
+external SCF); all inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  Also reported: the back-to-back residual rate
+at the converged amplitudes, per-kernel HIP-event times, the roofline of the
+dominant kernel, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from math import comb
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sites", type=int, default=140)
+    ap.add_argument("--U", type=float, default=4.0)
+    ap.add_argument("--seed", type=int, default=140)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--profile-reps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, seconds: float):
+    """The oracle as it stands (sub-cluster inclusion-exclusion over the
+    definitional determinant-space evaluation), timed on a bounded sample.
+
+    A full residual needs every sub-cluster of at most 4 pairs once (with the
+    oracle's cache): C(N,s) evaluations of size s.  The sample times a number
+    of random sub-clusters of each size and scales by those counts.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from inputs import random_amplitudes
+    from oracle import integrals, tier_b
+
+    N = prob.npair
+    f, eri = integrals.chain_integrals(prob, 2)
+    t = random_amplitudes(N, "pq", seed=1400, scale=0.05)
+    tb = tier_b.TierB(N, 2, f, eri)
+    rng = np.random.default_rng(0)
+    per, nsamp = {}, {}
+    budget = {1: 0.05, 2: 0.1, 3: 0.25, 4: 0.6}
+    with threadpool_limits(limits=1):
+        for s in (1, 2, 3, 4):
+            tb.engine(s)                       # build the template outside timing
+            n, t0 = 0, time.perf_counter()
+            while True:
+                Y = tuple(sorted(rng.choice(N, s, replace=False).tolist()))
+                tb.clear()
+                tb.sub_residual(Y, t)
+                n += 1
+                el = time.perf_counter() - t0
+                if el >= budget[s] * seconds or n >= 100000:
+                    break
+            per[s] = el / n
+            nsamp[s] = n
+    total = sum(comb(N, s) * per[s] for s in per)
+    return {"value": 1.0 / total, "unit": "residual evals/s", "cores": 1, "kind": "oracle",
+            "sample": ("timed %s random sub-clusters of 1/2/3/4 pairs of the same chain and "
+                       "amplitudes; one residual = C(70,s) sub-clusters of each size s "
+                       "(%.3g s per residual)" % ("/".join(str(nsamp[s]) for s in (1, 2, 3, 4)),
+                                                  total)),
+            "seconds_per_subcluster": {str(s): per[s] for s in per}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1609_00077_amd as pq
+    from paper_1609_00077_amd import workmodel
+    from inputs import chain_problem
+
+    dev = torch.device("cuda:0")
+    prob = chain_problem(args.sites, U=args.U, seed=args.seed)
+    N = prob.npair
+    F = torch.as_tensor(prob.F_site, device=dev).contiguous()
+    V = torch.as_tensor(prob.V, device=dev).contiguous()
+    Cm = torch.as_tensor(prob.C, device=dev).contiguous()
+    torch.cuda.synchronize()
+
+    def step():
+        f, eri = pq.integrals(F, V, Cm, k=2)
+        return pq.pq_solve(f, eri, tol=args.tol), f, eri
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, f, eri = step()
+        iters += res.iterations
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    value = iters / T
+
+    # back-to-back residuals at the converged amplitudes (HIP events on the stream)
+    t_conv = res.t
+    r = torch.empty_like(t_conv)
+    nrep = 20
+    for _ in range(3):
+        pq.pq_residual(f, eri, t_conv, out=r)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(nrep):
+        pq.pq_residual(f, eri, t_conv, out=r)
+    ev1.record()
+    torch.cuda.synchronize()
+    resid_ms = ev0.elapsed_time(ev1) / nrep
+
+    # per-kernel times: events recorded by the library on its own stream
+    acc = {}
+    for _ in range(args.profile_reps):
+        _, phases = pq.pq_residual_profile(f, eri, t_conv)
+        for name, ms in phases:
+            acc[name] = acc.get(name, 0.0) + ms / args.profile_reps
+    flops = workmodel.pq_kernel_flops(N)
+    dom = max(acc, key=acc.get)
+    achieved = flops[dom] / (acc[dom] * 1e-3) / 1e12
+    peak = workmodel.PEAK_FP64_VECTOR_TFLOPS
+    line = {
+        "metric": "PQ residual evals/s at 140e/140o",
+        "value": value,
+        "unit": "residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"PQ solve of a {args.sites}-site PPP chain ({N} pairs, "
+                               f"U={args.U}, seed {args.seed}) from t=0 to ||R||<={args.tol:g}, "
+                               "integral transform included", "sites": args.sites, "pairs": N,
+                   "iterations_per_solve": res.iterations, "energy": res.energy},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "flops_per_launch": flops[dom], "ms_per_launch": acc[dom]},
+        "residual_ms": resid_ms,
+        "residual_evals_per_s_back_to_back": 1e3 / resid_ms,
+        "residual_flops": sum(flops.values()),
+        "residual_tflops": sum(flops.values()) / (resid_ms * 1e-3) / 1e12,
+        "residual_compulsory_bytes": workmodel.pq_compulsory_bytes(N),
+        "kernel_ms": acc,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

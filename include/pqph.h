@@ -150,6 +150,19 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
                      const double* eri, const pqph_solve_opts* opts,
                      double* t_inout, double* energy, pqph_solve_info* info);
 
+/* Diagnostic (per-phase tracing): one pq_residual with a HIP event recorded on
+ * the context's stream after every kernel; phase_ms (host, nphase entries)
+ * receives the elapsed time of each kernel in launch order and *nphase_out
+ * their number (10 for npair >= 2: vertex1, vertex2, unpack_t2, spec_x,
+ * spec_y, spec_w, gemm_s1, r2s2, r2, r1).  Synchronises the stream.  Fails
+ * with INVALID_ARG if nphase is too small. */
+pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h,
+                                const double* eri, const double* t, double* r,
+                                double* phase_ms, int nphase, int* nphase_out);
+/* Name of phase i of pq_residual_profile for npair >= 2 ("" if out of range;
+ * the string is static). */
+const char* pq_residual_phase_name(int i);
+
 /* Orbital-energy denominators of the packed slots (length pq_amp_len or
  * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
  * + shift.  Exposed for callers that run their own update. */

@@ -88,6 +88,23 @@ def pq_residual(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, out: torch.
     return out
 
 
+def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
+    """One residual with per-kernel HIP-event times: (r, [(kernel, ms), ...])."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair)
+    out = torch.empty(na, dtype=torch.float64, device=h.device)
+    ms = (C.c_double * 16)()
+    n = C.c_int()
+    _check(lib, ctx, lib.pq_residual_profile(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                             _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
+                                             _dev(out, "out", na), ms, 16, C.byref(n)))
+    names = [lib.pq_residual_phase_name(i).decode() for i in range(10)]
+    if n.value != 10:      # npair == 1: vertex1 and r1 only
+        names = ["k_vertex1", "k_r1"]
+    return out, list(zip(names, [ms[i] for i in range(n.value)]))
+
+
 def pq_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)

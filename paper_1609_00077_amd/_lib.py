@@ -43,6 +43,9 @@ SIGNATURES = {
     "pq_solve": (C.c_int, [P, C.c_int, P, P, C.POINTER(SolveOpts), P, C.POINTER(C.c_double),
                            C.POINTER(SolveInfo)]),
     "pqph_denominators": (C.c_int, [P, C.c_int, C.c_int, P, C.c_double, P]),
+    "pq_residual_profile": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_double), C.c_int,
+                                      C.POINTER(C.c_int)]),
+    "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
 }
 
 _lib = None

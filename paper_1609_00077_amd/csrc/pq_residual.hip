@@ -441,9 +441,12 @@ pqph_status prepare(pqph_ctx* ctx, int N, const double* h, const double* eri, co
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1);
+    pqph_mark(ctx);
     if (N > 1) {
         hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2);
+        pqph_mark(ctx);
         hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2);
+        pqph_mark(ctx);
     }
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
@@ -465,11 +468,15 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* 
     if (N > 1) {
         const long np2 = (long)N * (N - 1) / 2;
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X);
+        pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y);
+        pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W);
+        pqph_mark(ctx);
         const int tiles = (N + GT - 1) / GT;
         hipLaunchKernelGGL(k_gemm_s1, dim3(tiles * tiles, 1, PQ_S1PAIRS_N), dim3(256), 0, s, N,
                            c.X, c.Y, c.S);
+        pqph_mark(ctx);
         const size_t lds = (size_t)(S2_ROWS * N + S2_ROWS * NP2) * sizeof(double);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int maxc = (N + S2_TPR - 1) / S2_TPR;
@@ -481,11 +488,14 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* 
             hipLaunchKernelGGL(k_r2s2<8>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
         else
             hipLaunchKernelGGL(k_r2s2<16>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        pqph_mark(ctx);
         const long nth = NP2 * np2;
         hipLaunchKernelGGL(k_r2, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, N, v,
                            c.part, c.nchunk, r);
+        pqph_mark(ctx);
     }
     hipLaunchKernelGGL(k_r1, dim3(N), dim3(256), 0, s, N, v, r);
+    pqph_mark(ctx);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
 }

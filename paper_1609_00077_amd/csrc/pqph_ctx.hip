@@ -181,6 +181,11 @@ pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n) {
     return PQPH_OK;
 }
 
+void pqph_mark(pqph_ctx* ctx) {
+    if (!ctx->profiling || ctx->prof_n >= 16) return;
+    (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
+}
+
 void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,
                     int nblk) {
     hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, s, a, b, n, partial);
@@ -234,6 +239,8 @@ void pqph_destroy(pqph_ctx* ctx) {
     if (ctx->host) (void)hipHostFree(ctx->host);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (hipEvent_t e : ctx->prof)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -266,6 +273,43 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
     if (st) return st;
     return pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+}
+
+static const char* kPhaseNames[] = {"k_vertex1", "k_vertex2", "k_unpack_t2", "k_spec_x",
+                                    "k_spec_y",  "k_spec_w",  "k_gemm_s1",   "k_r2s2",
+                                    "k_r2",      "k_r1"};
+
+const char* pq_residual_phase_name(int i) {
+    return (i >= 0 && i < 10) ? kPhaseNames[i] : "";
+}
+
+pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                                const double* t, double* r, double* phase_ms, int nphase,
+                                int* nphase_out) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !r || !phase_ms || !nphase_out)
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
+    if (st) return st;
+    for (int i = 0; i < 16; ++i)
+        if (!ctx->prof[i]) PQPH_HIP(ctx, hipEventCreate(&ctx->prof[i]));
+    ctx->prof_n = 0;
+    ctx->profiling = true;
+    pqph_mark(ctx);   // start event
+    st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+    ctx->profiling = false;
+    if (st) return st;
+    PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int n = ctx->prof_n - 1;
+    if (n > nphase) return pqph_fail(ctx, PQPH_INVALID_ARG, "phase_ms too short");
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        PQPH_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof[i], ctx->prof[i + 1]));
+        phase_ms[i] = ms;
+    }
+    *nphase_out = n;
+    return PQPH_OK;
 }
 
 pqph_status pq_energy(pqph_ctx* ctx, int npair, const double* h, const double* eri,

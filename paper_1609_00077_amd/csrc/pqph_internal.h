@@ -24,7 +24,14 @@ struct pqph_ctx {
     double* host = nullptr;
     size_t host_n = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-kernel timing of one residual (diagnostic entry point only)
+    hipEvent_t prof[16] = {};
+    int prof_n = 0;       // events recorded so far
+    bool profiling = false;
 };
+
+// records an event after a launch when the context is profiling
+void pqph_mark(pqph_ctx* ctx);
 
 // error helpers -----------------------------------------------------------
 pqph_status pqph_fail(pqph_ctx* ctx, pqph_status st, const std::string& msg);
