@@ -99,9 +99,9 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     _check(lib, ctx, lib.pq_residual_profile(ctx, npair, _dev(h, "h", 4 * npair * npair),
                                              _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
                                              _dev(out, "out", na), ms, 16, C.byref(n)))
-    names = [lib.pq_residual_phase_name(i).decode() for i in range(10)]
-    if n.value != 10:      # npair == 1: vertex1 and r1 only
-        names = ["k_vertex1", "k_r1"]
+    names = [lib.pq_residual_phase_name(i).decode() for i in range(11)]
+    if n.value != 11:      # npair == 1: no two-pair outputs
+        names = ["k_vertex1", "k_r1", "k_final"]
     return out, list(zip(names, [ms[i] for i in range(n.value)]))
 
 

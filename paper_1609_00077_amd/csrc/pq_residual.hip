@@ -204,23 +204,29 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
 }
 
 // ----------------------------------------------------------- one-pair outputs
-__global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ R) {
-    const int P = blockIdx.x;
+// grid (N, nch): workgroup (P, ch) sums the chunk ch of the ordered spectator
+// pairs (A, B); chunk 0 also takes the no- and one-spectator terms.
+__global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __restrict__ part) {
+    const int P = blockIdx.x, ch = blockIdx.y;
     const int tid = threadIdx.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (tid == 0) {
-        a0 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, P, 0, 0, 0, v);
-        a1 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, P, 0, 0, 0, v);
-        a2 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, P, 0, 0, 0, v);
-    }
-    for (int A = tid; A < N; A += blockDim.x) {
-        if (A == P) continue;
-        a0 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, P, A, 0, 0, v);
-        a1 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, P, A, 0, 0, v);
-        a2 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, P, A, 0, 0, v);
+    if (ch == 0) {
+        if (tid == 0) {
+            a0 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, P, 0, 0, 0, v);
+            a1 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, P, 0, 0, 0, v);
+            a2 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, P, 0, 0, 0, v);
+        }
+        for (int A = tid; A < N; A += blockDim.x) {
+            if (A == P) continue;
+            a0 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, P, A, 0, 0, v);
+            a1 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, P, A, 0, 0, v);
+            a2 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, P, A, 0, 0, v);
+        }
     }
     const long NN = (long)N * N;
-    for (long ab = tid; ab < NN; ab += blockDim.x) {
+    const long per = (NN + nch - 1) / nch;
+    const long lo = (long)ch * per, hi = min(NN, lo + per);
+    for (long ab = lo + tid; ab < hi; ab += blockDim.x) {
         const int A = (int)(ab / N), B = (int)(ab % N);
         if (A == P || B == P || A == B) continue;
         a0 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 0, P, A, B, 0, v);
@@ -241,82 +247,184 @@ __global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ 
         __syncthreads();
     }
     if (tid == 0) {
-        R[P] = red[0][0];
-        R[N + P] = red[1][0];
-        R[2 * N + P] = red[2][0];
+        part[((long)ch * 3 + 0) * N + P] = red[0][0];
+        part[((long)ch * 3 + 1) * N + P] = red[1][0];
+        part[((long)ch * 3 + 2) * N + P] = red[2][0];
     }
 }
 
 // ----------------------------------------------------------- two spectators
-constexpr int S2_ROWS = 16;
-constexpr int S2_TPR = 16;
+// V(pq, B) = sum_A L_a(P,Q,A) W_w(A,B) is a dense GEMM over the spectator A
+// whose left operand is generated on the fly (a Khatri-Rao product of the
+// amplitudes linking P and Q to A); it runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[i][k] at lane i+16k, B[k][j] at lane j+16k,
+// D[(lane>>4)+4r][lane&15] in register r).  Each group (w, a) is then closed
+// against the B-side links L_b(P,Q,B) and accumulated per output pattern.
+// Workgroup: 64 output pairs (4 wavefronts x 16 rows) x all B; grid.y splits
+// the groups, whose partial sums are combined in k_final.
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int M2_ROWS = 64;
+constexpr int M2_KC = 16;
 
-template <int MAXC>
+template <int NCB>
 __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __restrict__ W,
                                               int gchunk, double* __restrict__ part) {
+    constexpr int NC = 16 * NCB;
     extern __shared__ double sm[];
-    double* La = sm;                       // [S2_ROWS][N]
-    double* acc = sm + S2_ROWS * N;        // [S2_ROWS][29]
+    double* La = sm;                       // [M2_ROWS][M2_KC]
+    double* Ws = La + M2_ROWS * M2_KC;     // [M2_KC][NC]
+    double* acc = Ws + M2_KC * NC;         // [M2_ROWS][29]
+    __shared__ int rowP[M2_ROWS], rowQ[M2_ROWS];
     const long np2 = (long)N * (N - 1) / 2;
-    const int tid = threadIdx.x, row = tid / S2_TPR, lane = tid % S2_TPR;
-    const long ip = (long)blockIdx.x * S2_ROWS + row;
-    const bool valid = ip < np2;
-    int P = 0, Q = 1;
-    if (valid) decode_pair(ip, P, Q);
-    for (int i = tid; i < S2_ROWS * NP2; i += blockDim.x) acc[i] = 0.0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const long ip0 = (long)blockIdx.x * M2_ROWS;
+    if (tid < M2_ROWS) {
+        int P = -1, Q = -1;
+        if (ip0 + tid < np2) decode_pair(ip0 + tid, P, Q);
+        rowP[tid] = P;
+        rowQ[tid] = Q;
+    }
+    for (int i = tid; i < M2_ROWS * NP2; i += 256) acc[i] = 0.0;
+    __syncthreads();
+    const int KP = (N + M2_KC - 1) / M2_KC * M2_KC;
     const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
     for (int g = g0; g < g1; ++g) {
         const int w = pq_g_w[g], a = pq_g_a[g];
-        __syncthreads();
-        for (int A = lane; A < N; A += S2_TPR)
-            La[row * N + A] = (valid && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
-        __syncthreads();
-        double V[MAXC];
-#pragma unroll
-        for (int j = 0; j < MAXC; ++j) V[j] = 0.0;
         const double* Wg = W + (long)w * v.NN;
-        for (int A = 0; A < N; ++A) {
-            const double la = La[row * N + A];
-            const double* Wr = Wg + (long)A * N;
+        d4 D[NCB];
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j) {
-                const int B = lane + j * S2_TPR;
-                if (B < N) V[j] += la * Wr[B];
+        for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kc = 0; kc < KP; kc += M2_KC) {
+            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
+                const int row = i / M2_KC, A = kc + i % M2_KC;
+                const int P = rowP[row], Q = rowQ[row];
+                La[i] = (P >= 0 && A < N && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
             }
+            for (int i = tid; i < M2_KC * NC; i += 256) {
+                const int A = kc + i / NC, col = i % NC;
+                Ws[i] = (A < N && col < N) ? Wg[(long)A * N + col] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < M2_KC; k4 += 4) {
+                const double av = La[(wave * 16 + (lane & 15)) * M2_KC + k4 + (lane >> 4)];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const double bv = Ws[(k4 + (lane >> 4)) * NC + cb * 16 + (lane & 15)];
+                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, D[cb], 0, 0, 0);
+                }
+            }
+            __syncthreads();
         }
         for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
             const int b = pq_g_b[i], m = pq_g_mu[i];
-            double s = 0.0;
+            double s[4];
 #pragma unroll
-            for (int j = 0; j < MAXC; ++j) {
-                const int B = lane + j * S2_TPR;
-                if (B < N && B != P && B != Q) s += V[j] * spec_l(b, P, Q, B, v);
+            for (int r = 0; r < 4; ++r) {
+                s[r] = 0.0;
+                const int row = wave * 16 + (lane >> 4) + 4 * r;
+                const int P = rowP[row], Q = rowQ[row];
+                if (P >= 0) {
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int col = cb * 16 + (lane & 15);
+                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * spec_l(b, P, Q, col, v);
+                    }
+                }
             }
-            // reduce over the S2_TPR lanes of this row (consecutive lanes)
-            for (int o = S2_TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            if (lane == 0) acc[row * NP2 + m] += pq_g_coef[i] * s;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                for (int o = 8; o > 0; o >>= 1) s[r] += __shfl_xor(s[r], o);
+            if ((lane & 15) == 0) {
+                const double c = pq_g_coef[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[(wave * 16 + (lane >> 4) + 4 * r) * NP2 + m] += c * s[r];
+            }
         }
     }
     __syncthreads();
-    if (lane == 0 && valid)
-        for (int m = 0; m < NP2; ++m)
-            part[((long)blockIdx.y * NP2 + m) * np2 + ip] = acc[row * NP2 + m];
+    for (int i = tid; i < M2_ROWS * NP2; i += 256) {
+        const int row = i / NP2, m = i % NP2;
+        const long ip = ip0 + row;
+        if (ip < np2) part[((long)blockIdx.y * NP2 + m) * np2 + ip] = acc[i];
+    }
 }
 
 // ----------------------------------------------------------- two-pair outputs
-__global__ void k_r2(int N, View v, const double* __restrict__ part, int nchunk,
-                     double* __restrict__ R) {
+// Interpreted no-spectator terms and the one-spectator epilogue.  Threads walk
+// the output pairs row by row (P fixed, Q fastest) so the class-major [P][Q]
+// tensors are read with unit stride; the terms of each output pattern are
+// split R2_SPLIT ways.
+constexpr int R2_SPLIT = 4;
+
+__device__ __forceinline__ void decode_rowmajor(long j, int N, int& P, int& Q) {
+    const double b = 2.0 * N - 1.0;
+    int p = (int)((b - sqrt(b * b - 8.0 * (double)j)) * 0.5);
+    auto off = [&](int x) { return (long)x * (2L * N - x - 1) / 2; };
+    while (p > 0 && off(p) > j) --p;
+    while (off(p + 1) <= j) ++p;
+    P = p;
+    Q = (int)(j - off(p)) + p + 1;
+}
+
+__global__ void k_r2(int N, View v, double* __restrict__ part) {
     const long np2 = (long)N * (N - 1) / 2;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= NP2 * np2) return;
-    const int m = (int)(gid / np2);
-    const long ip = gid % np2;
+    if (gid >= (long)R2_SPLIT * NP2 * np2) return;
+    const int q = (int)(gid / (NP2 * np2));
+    const long rest = gid % (NP2 * np2);
+    const int m = (int)(rest / np2);
+    const long j = rest % np2;
     int P, Q;
-    decode_pair(ip, P, Q);
-    double acc = class_sum(pq_r2s0_start, pq_r2s0_coef, pq_r2s0_fac, m, P, Q, 0, 0, v);
-    acc += class_sum(pq_r2s1_start, pq_r2s1_coef, pq_r2s1_fac, m, P, Q, 0, 0, v);
-    for (int c = 0; c < nchunk; ++c) acc += part[((long)c * NP2 + m) * np2 + ip];
-    R[3L * N + m * np2 + ip] = acc;
+    decode_rowmajor(j, N, P, Q);
+    double acc = 0.0;
+    {
+        const int s0 = pq_r2s0_start[m], e0 = pq_r2s0_start[m + 1];
+        const int lo = s0 + (int)((long)(e0 - s0) * q / R2_SPLIT);
+        const int hi = s0 + (int)((long)(e0 - s0) * (q + 1) / R2_SPLIT);
+        for (int i = lo; i < hi; ++i) {
+            double x = pq_r2s0_coef[i];
+            const int* f = pq_r2s0_fac + 5 * i;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (f[k] != 0) x *= fval(f[k], P, Q, 0, 0, v);
+            acc += x;
+        }
+    }
+    {
+        const int s0 = pq_r2s1_start[m], e0 = pq_r2s1_start[m + 1];
+        const int lo = s0 + (int)((long)(e0 - s0) * q / R2_SPLIT);
+        const int hi = s0 + (int)((long)(e0 - s0) * (q + 1) / R2_SPLIT);
+        for (int i = lo; i < hi; ++i) {
+            double x = pq_r2s1_coef[i];
+            const int* f = pq_r2s1_fac + 5 * i;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (f[k] != 0) x *= fval(f[k], P, Q, 0, 0, v);
+            acc += x;
+        }
+    }
+    part[((long)q * NP2 + m) * np2 + (long)Q * (Q - 1) / 2 + P] = acc;
+}
+
+// packed r from the partial sums, in a fixed order (deterministic)
+__global__ void k_final(int N, const double* __restrict__ p1, int nch1,
+                        const double* __restrict__ p2, const double* __restrict__ ps2, int nchunk,
+                        double* __restrict__ R) {
+    const long np2 = (long)N * (N - 1) / 2;
+    const long n1 = 3L * N;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n1 + NP2 * np2) return;
+    double s = 0.0;
+    if (gid < n1) {
+        const int k = (int)(gid / N), P = (int)(gid % N);
+        for (int c = 0; c < nch1; ++c) s += p1[((long)c * 3 + k) * N + P];
+    } else {
+        const long g2 = gid - n1;
+        for (int q = 0; q < R2_SPLIT; ++q) s += p2[(long)q * NP2 * np2 + g2];
+        for (int c = 0; c < nchunk; ++c) s += ps2[(long)c * NP2 * np2 + g2];
+    }
+    R[gid] = s;
 }
 
 // ------------------------------------------------------------------- energy
@@ -378,14 +486,16 @@ __global__ void k_denom(int N, const double* __restrict__ f, double shift, doubl
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *X, *Y, *S, *W, *part, *epart, *scal;
-    int nchunk, gchunk, nblkE;
+    double *t2, *h1, *h2, *X, *Y, *S, *W, *part, *p1, *p2, *epart, *scal;
+    int nchunk, gchunk, nblkE, nch1;
 };
 
 inline int s2_rowtiles(int N) {
     const long np2 = (long)N * (N - 1) / 2;
-    return (int)((np2 + S2_ROWS - 1) / S2_ROWS);
+    return (int)((np2 + M2_ROWS - 1) / M2_ROWS);
 }
+
+inline int r1_chunks(int N) { return std::max(1, std::min(64, 2048 / std::max(N, 1))); }
 
 inline void s2_chunks(int N, int& nchunk, int& gchunk) {
     const int rt = std::max(1, s2_rowtiles(N));
@@ -408,6 +518,9 @@ Carve carve(double* ws, int N) {
     c.W = take((size_t)PQ_W_N * NN);
     s2_chunks(N, c.nchunk, c.gchunk);
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
+    c.nch1 = r1_chunks(N);
+    c.p1 = take((size_t)c.nch1 * 3 * N);
+    c.p2 = take((size_t)R2_SPLIT * NP2 * std::max(np2, (size_t)1));
     c.nblkE = (int)((NN + 255) / 256);
     c.epart = take(c.nblkE);
     c.scal = take(8);
@@ -420,7 +533,8 @@ size_t carve_size(int N) {
     s2_chunks(N, nchunk, gchunk);
     return NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_S1PAIRS_N + PQ_W_N) * NN +
-           (size_t)nchunk * NP2 * std::max(np2, (size_t)1) + (NN + 255) / 256 + 8;
+           (size_t)nchunk * NP2 * std::max(np2, (size_t)1) + (size_t)r1_chunks(N) * 3 * N +
+           (size_t)R2_SPLIT * NP2 * std::max(np2, (size_t)1) + (NN + 255) / 256 + 8;
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -477,24 +591,37 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* 
         hipLaunchKernelGGL(k_gemm_s1, dim3(tiles * tiles, 1, PQ_S1PAIRS_N), dim3(256), 0, s, N,
                            c.X, c.Y, c.S);
         pqph_mark(ctx);
-        const size_t lds = (size_t)(S2_ROWS * N + S2_ROWS * NP2) * sizeof(double);
         dim3 g2(s2_rowtiles(N), c.nchunk);
-        const int maxc = (N + S2_TPR - 1) / S2_TPR;
-        if (maxc <= 2)
-            hipLaunchKernelGGL(k_r2s2<2>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
-        else if (maxc <= 4)
-            hipLaunchKernelGGL(k_r2s2<4>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
-        else if (maxc <= 8)
-            hipLaunchKernelGGL(k_r2s2<8>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
-        else
-            hipLaunchKernelGGL(k_r2s2<16>, g2, dim3(256), lds, s, N, v, c.W, c.gchunk, c.part);
+        const int ncb = (N + 15) / 16;
+        auto lds = [](int ncb_) {
+            return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_ + M2_ROWS * NP2) * sizeof(double);
+        };
+#define PQ_S2_LAUNCH(NB)                                                                       \
+    hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s, N, v, c.W, c.gchunk, c.part)
+        if (ncb <= 1) PQ_S2_LAUNCH(1);
+        else if (ncb <= 2) PQ_S2_LAUNCH(2);
+        else if (ncb <= 3) PQ_S2_LAUNCH(3);
+        else if (ncb <= 4) PQ_S2_LAUNCH(4);
+        else if (ncb <= 5) PQ_S2_LAUNCH(5);
+        else if (ncb <= 6) PQ_S2_LAUNCH(6);
+        else if (ncb <= 8) PQ_S2_LAUNCH(8);
+        else if (ncb <= 10) PQ_S2_LAUNCH(10);
+        else if (ncb <= 13) PQ_S2_LAUNCH(13);
+        else PQ_S2_LAUNCH(16);
+#undef PQ_S2_LAUNCH
         pqph_mark(ctx);
-        const long nth = NP2 * np2;
-        hipLaunchKernelGGL(k_r2, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, N, v,
-                           c.part, c.nchunk, r);
+        const long nth = (long)R2_SPLIT * NP2 * np2;
+        hipLaunchKernelGGL(k_r2, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, N, v, c.p2);
         pqph_mark(ctx);
     }
-    hipLaunchKernelGGL(k_r1, dim3(N), dim3(256), 0, s, N, v, r);
+    hipLaunchKernelGGL(k_r1, dim3(N, c.nch1), dim3(256), 0, s, N, v, c.nch1, c.p1);
+    pqph_mark(ctx);
+    {
+        const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
+        hipLaunchKernelGGL(k_final, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N, c.p1,
+                           c.nch1, c.p2, c.part, N > 1 ? c.nchunk : 0, r);
+    }
+
     pqph_mark(ctx);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;

@@ -55,6 +55,7 @@ def pq_kernel_flops(N: int) -> dict:
     out["k_r2"] = (_class_cost(c["R2S0"]) + _class_cost(c["R2S1"])) * np2
     out["k_r1"] = N * (_class_cost(c["R1S0"]) + (N - 1) * _class_cost(c["R1S1"])
                        + (N - 1) * (N - 2) * _class_cost(c["R1S2"]))
+    out["k_final"] = float((3 * N + 29 * np2) * 4)
     return out
 
 

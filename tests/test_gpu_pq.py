@@ -87,3 +87,51 @@ def test_solve_8_sites_matches_oracle_solve(pq):
     assert ref.converged
     assert abs(res.energy - ref.energy) < 1e-10
     assert np.abs(res.t.cpu().numpy() - ref.t).max() < 1e-9
+
+
+def _golden(name):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(p):
+        pytest.skip(f"golden fixture {name} not generated (tests/golden/make_golden.py)")
+    with open(p) as fh:
+        return json.load(fh)
+
+
+def test_full_size_pq140_sampled_blocks(pq):
+    """140-site chain (70 pairs, the bench workload), seeded amplitudes: the
+    sampled output blocks and the energy equal the oracle's sub-cluster values
+    stored by tests/golden/make_golden.py."""
+    g = _golden("pq140_blocks")
+    prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
+    N = prob.npair
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    t = random_amplitudes(N, "pq", seed=g["amp_seed"], scale=g["amp_scale"])
+    R = pq.pq_residual(f, eri, _d(t)).cpu().numpy()
+    for _, vals in g["blocks"].items():
+        ref = np.array(list(vals.values()))
+        got = R[[int(s) for s in vals]]
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert abs(pq.pq_energy(f, eri, _d(t)) - g["energy"]) < 1e-10
+
+
+def test_full_size_properties(pq):
+    """Properties at the bench size: R linear in (f, v); the energy is
+    invariant under relabelling the pairs (checked with a reversal of the
+    labels, which reorders every pair operator)."""
+    prob = chain_problem(140, U=4.0, seed=140)
+    N = prob.npair
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    t = _d(random_amplitudes(N, "pq", seed=7, scale=0.05))
+    R1 = pq.pq_residual(f, eri, t).clone()
+    R2 = pq.pq_residual(2.0 * f, 2.0 * eri, t)
+    assert torch.abs(R2 - 2.0 * R1).max().item() <= 1e-11 * max(1.0, torch.abs(R1).max().item())
+    # label reversal P -> N-1-P, applied through the orbitals (C columns)
+    perm = list(range(N - 1, -1, -1))
+    order = perm + [N + p for p in perm]
+    Cp = prob.C[:, order]
+    f2, eri2 = pq.integrals(_d(prob.F_site), _d(prob.V), _d(Cp), k=2)
+    e1 = pq.pq_solve(f, eri, tol=1e-10).energy
+    e2 = pq.pq_solve(f2, eri2, tol=1e-10).energy
+    assert abs(e1 - e2) < 1e-9
