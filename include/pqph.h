@@ -164,6 +164,21 @@ pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h,
  * the string is static). */
 const char* pq_residual_phase_name(int i);
 
+/* Autotuner (the analogue of the paper's benchmark-time choice between loop
+ * and BLAS kernels, Sec. III): time the variants of the two-spectator
+ * contraction for this npair on the given inputs (three residuals each, after
+ * a warm-up; r receives the last residual) and keep the fastest for every
+ * later call on this context.  *choice (host, may be NULL) = 1 (K-chunked
+ * staging of the vertex) or 2 (vertex resident in LDS, npair <= 96).
+ * Synchronises the stream.  Without tuning, variant 1 is used. */
+pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h,
+                          const double* eri, const double* t, double* r,
+                          int* choice);
+
+/* Force the two-spectator variant for npair on this context (0 = default,
+ * 1, or 2 when npair <= 96); INVALID_ARG otherwise.  For tests and tuning. */
+pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
+
 /* Orbital-energy denominators of the packed slots (length pq_amp_len or
  * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
  * + shift.  Exposed for callers that run their own update. */

@@ -105,6 +105,27 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     return out, list(zip(names, [ms[i] for i in range(n.value)]))
 
 
+def autotune(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> int:
+    """Pick the fastest two-spectator kernel variant for this size (kept on
+    the context of the current stream); returns the variant number."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair)
+    out = torch.empty(na, dtype=torch.float64, device=h.device)
+    ch = C.c_int()
+    _check(lib, ctx, lib.pqph_autotune(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                       _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
+                                       _dev(out, "out", na), C.byref(ch)))
+    return ch.value
+
+
+def set_variant(npair: int, variant: int, device: str | torch.device = "cuda:0") -> None:
+    """Force the two-spectator kernel variant (1 or 2; 0 = default) for npair
+    on the context of the current stream."""
+    lib, ctx = _ctx(torch.device(device))
+    _check(lib, ctx, lib.pqph_set_variant(ctx, npair, variant))
+
+
 def pq_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)

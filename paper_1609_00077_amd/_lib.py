@@ -46,6 +46,8 @@ SIGNATURES = {
     "pq_residual_profile": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_double), C.c_int,
                                       C.POINTER(C.c_int)]),
     "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
+    "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
+    "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
 }
 
 _lib = None

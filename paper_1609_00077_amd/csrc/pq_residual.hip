@@ -101,7 +101,7 @@ __global__ void k_vertex1(int N, const double* __restrict__ f, const double* __r
 }
 
 __global__ void k_vertex2(int N, const double* __restrict__ f, const double* __restrict__ eri,
-                          double* __restrict__ h2) {
+                          double* __restrict__ h2, double* __restrict__ h2T) {
     const int Q = blockIdx.x * blockDim.x + threadIdx.x;
     const int P = blockIdx.y, key = blockIdx.z;
     if (Q >= N) return;
@@ -126,6 +126,7 @@ __global__ void k_vertex2(int N, const double* __restrict__ f, const double* __r
         }
     }
     h2[(long)key * NN + (long)P * N + Q] = v;
+    if (P < Q) h2T[((long)Q * (Q - 1) / 2 + P) * PQ_H2_N + key] = v;   // pair-major copy
 }
 
 // ---------------------------------------------------------------- amplitudes
@@ -173,34 +174,52 @@ __device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View&
 
 // ------------------------------------------------------------ one spectator
 constexpr int GT = 16;
+constexpr int GP = 16;   // (x, y) pairs per workgroup
 
+// ST[pq][p] = S_p(P,Q) for P < Q (pair-major, so each output pair's one-
+// spectator sums are contiguous for the pair-local epilogue).  Grid:
+// (upper-triangular 16x16 tiles of (P, Q), chunks of GP pairs p).
 __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
-                                                 double* __restrict__ S) {
-    const int p = blockIdx.z;
-    const int x = pq_s1pairs[2 * p], y = pq_s1pairs[2 * p + 1];
-    const int tilesQ = (N + GT - 1) / GT;
-    const int tP = blockIdx.x / tilesQ, tQ = blockIdx.x % tilesQ;
-    if (tP > tQ) return;                 // only P < Q is read
+                                                 double* __restrict__ ST) {
+    const int nt = (N + GT - 1) / GT;
+    int tP = 0, rem = blockIdx.x;
+    while (rem >= nt - tP) { rem -= nt - tP; ++tP; }
+    const int tQ = tP + rem;
+    const int p0 = blockIdx.y * GP;
     const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
     const long NN = (long)N * N;
     __shared__ double Xs[GT][GT + 1];
     __shared__ double Ys[GT][GT + 1];
-    const double* Xp = X + (long)x * NN;
-    const double* Yp = Y + (long)y * NN;
-    double acc = 0.0;
-    for (int a0 = 0; a0 < N; a0 += GT) {
-        const int A = a0 + tx;
-        const int Pr = tP * GT + ty, Qr = tQ * GT + ty;
-        Xs[ty][tx] = (Pr < N && A < N) ? Xp[(long)Pr * N + A] : 0.0;
-        Ys[ty][tx] = (Qr < N && A < N) ? Yp[(long)Qr * N + A] : 0.0;
-        __syncthreads();
+    double acc[GP];
 #pragma unroll
-        for (int kk = 0; kk < GT; ++kk) acc += Xs[ty][kk] * Ys[tx][kk];
-        __syncthreads();
+    for (int j = 0; j < GP; ++j) {
+        acc[j] = 0.0;
+        const int p = p0 + j;
+        if (p < PQ_S1PAIRS_N) {
+            const double* Xp = X + (long)pq_s1pairs[2 * p] * NN;
+            const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN;
+            for (int a0 = 0; a0 < N; a0 += GT) {
+                const int A = a0 + tx;
+                const int Pr = tP * GT + ty, Qr = tQ * GT + ty;
+                Xs[ty][tx] = (Pr < N && A < N) ? Xp[(long)Pr * N + A] : 0.0;
+                Ys[ty][tx] = (Qr < N && A < N) ? Yp[(long)Qr * N + A] : 0.0;
+                __syncthreads();
+                double s = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < GT; ++kk) s += Xs[ty][kk] * Ys[tx][kk];
+                acc[j] += s;
+                __syncthreads();
+            }
+        }
     }
     const int P = tP * GT + ty, Q = tQ * GT + tx;
-    if (P < N && Q < N) S[(long)p * NN + (long)P * N + Q] = acc;
+    if (P < Q && Q < N) {
+        double* out = ST + ((long)Q * (Q - 1) / 2 + P) * PQ_S1PAIRS_N + p0;
+#pragma unroll
+        for (int j = 0; j < GP; ++j)
+            if (p0 + j < PQ_S1PAIRS_N) out[j] = acc[j];
+    }
 }
 
 // ----------------------------------------------------------- one-pair outputs
@@ -350,61 +369,160 @@ __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __res
     }
 }
 
-// ----------------------------------------------------------- two-pair outputs
-// Interpreted no-spectator terms and the one-spectator epilogue.  Threads walk
-// the output pairs row by row (P fixed, Q fastest) so the class-major [P][Q]
-// tensors are read with unit stride; the terms of each output pattern are
-// split R2_SPLIT ways.
-constexpr int R2_SPLIT = 4;
-
-__device__ __forceinline__ void decode_rowmajor(long j, int N, int& P, int& Q) {
-    const double b = 2.0 * N - 1.0;
-    int p = (int)((b - sqrt(b * b - 8.0 * (double)j)) * 0.5);
-    auto off = [&](int x) { return (long)x * (2L * N - x - 1) / 2; };
-    while (p > 0 && off(p) > j) --p;
-    while (off(p + 1) <= j) ++p;
-    P = p;
-    Q = (int)(j - off(p)) + p + 1;
+// Same contraction with the whole vertex W_w resident in LDS (N <= 96): the
+// groups are ordered by w, so W is staged once per vertex and each group needs
+// two barriers (L_a fill, then the MFMA sweep over all A).
+template <int NCB>
+__global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __restrict__ W,
+                                               int gchunk, double* __restrict__ part) {
+    constexpr int NC = 16 * NCB;
+    const int KP = (N + 3) / 4 * 4;
+    extern __shared__ double sm[];
+    double* Ws = sm;                       // [KP][NC]
+    double* La = Ws + (size_t)KP * NC;     // [M2_ROWS][KP]
+    double* acc = La + (size_t)M2_ROWS * KP;  // [M2_ROWS][29]
+    __shared__ int rowP[M2_ROWS], rowQ[M2_ROWS];
+    const long np2 = (long)N * (N - 1) / 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const long ip0 = (long)blockIdx.x * M2_ROWS;
+    if (tid < M2_ROWS) {
+        int P = -1, Q = -1;
+        if (ip0 + tid < np2) decode_pair(ip0 + tid, P, Q);
+        rowP[tid] = P;
+        rowQ[tid] = Q;
+    }
+    for (int i = tid; i < M2_ROWS * NP2; i += 256) acc[i] = 0.0;
+    const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
+    int curw = -1;
+    for (int g = g0; g < g1; ++g) {
+        const int w = pq_g_w[g], a = pq_g_a[g];
+        __syncthreads();
+        if (w != curw) {
+            const double* Wg = W + (long)w * v.NN;
+            for (int i = tid; i < KP * NC; i += 256) {
+                const int A = i / NC, col = i % NC;
+                Ws[i] = (A < N && col < N) ? Wg[(long)A * N + col] : 0.0;
+            }
+            curw = w;
+        }
+        for (int i = tid; i < M2_ROWS * KP; i += 256) {
+            const int row = i / KP, A = i % KP;
+            const int P = rowP[row], Q = rowQ[row];
+            La[i] = (P >= 0 && A < N && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
+        }
+        __syncthreads();
+        d4 D[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        const double* Lrow = La + (wave * 16 + (lane & 15)) * KP + (lane >> 4);
+        const double* Wcol = Ws + (lane >> 4) * NC + (lane & 15);
+        for (int k4 = 0; k4 < KP; k4 += 4) {
+            const double av = Lrow[k4];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+                D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wcol[k4 * NC + cb * 16], D[cb], 0, 0, 0);
+        }
+        for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
+            const int b = pq_g_b[i], m = pq_g_mu[i];
+            double s[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                s[r] = 0.0;
+                const int row = wave * 16 + (lane >> 4) + 4 * r;
+                const int P = rowP[row], Q = rowQ[row];
+                if (P >= 0) {
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const int col = cb * 16 + (lane & 15);
+                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * spec_l(b, P, Q, col, v);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                for (int o = 8; o > 0; o >>= 1) s[r] += __shfl_xor(s[r], o);
+            if ((lane & 15) == 0) {
+                const double c = pq_g_coef[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[(wave * 16 + (lane >> 4) + 4 * r) * NP2 + m] += c * s[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < M2_ROWS * NP2; i += 256) {
+        const int row = i / NP2, m = i % NP2;
+        const long ip = ip0 + row;
+        if (ip < np2) part[((long)blockIdx.y * NP2 + m) * np2 + ip] = acc[i];
+    }
 }
 
-__global__ void k_r2(int N, View v, double* __restrict__ part) {
+// ----------------------------------------------------------- two-pair outputs
+// No-spectator terms and the one-spectator epilogue, pair-local: a workgroup
+// stages, for R2L_PPW output pairs, every value those terms read (t1, t2, h1,
+// h2 and the one-spectator sums S of the pair; PQ_LOC_N doubles each) in LDS,
+// then walks the generated term chunks with each term's table entry read once
+// for all its pairs.  Chunk partial sums are reduced in a fixed order.
+constexpr int R2L_PPW = 4;
+
+__global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
+                                            const double* __restrict__ h1,
+                                            const double* __restrict__ h2T,
+                                            const double* __restrict__ ST,
+                                            double* __restrict__ p2) {
+    extern __shared__ double sm[];
+    double* loc = sm;                               // [R2L_PPW][PQ_LOC_N]
+    double* part = sm + R2L_PPW * PQ_LOC_N;         // [PQ_LOC_NCHUNK][R2L_PPW]
     const long np2 = (long)N * (N - 1) / 2;
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (long)R2_SPLIT * NP2 * np2) return;
-    const int q = (int)(gid / (NP2 * np2));
-    const long rest = gid % (NP2 * np2);
-    const int m = (int)(rest / np2);
-    const long j = rest % np2;
-    int P, Q;
-    decode_rowmajor(j, N, P, Q);
-    double acc = 0.0;
-    {
-        const int s0 = pq_r2s0_start[m], e0 = pq_r2s0_start[m + 1];
-        const int lo = s0 + (int)((long)(e0 - s0) * q / R2_SPLIT);
-        const int hi = s0 + (int)((long)(e0 - s0) * (q + 1) / R2_SPLIT);
-        for (int i = lo; i < hi; ++i) {
-            double x = pq_r2s0_coef[i];
-            const int* f = pq_r2s0_fac + 5 * i;
-#pragma unroll
-            for (int k = 0; k < 5; ++k)
-                if (f[k] != 0) x *= fval(f[k], P, Q, 0, 0, v);
-            acc += x;
+    const long ip0 = (long)blockIdx.x * R2L_PPW;
+    const int tid = threadIdx.x;
+    for (int p = 0; p < R2L_PPW; ++p) {
+        const long ip = ip0 + p;
+        const bool ok = ip < np2;
+        int P = 0, Q = 1;
+        if (ok) decode_pair(ip, P, Q);
+        double* L = loc + p * PQ_LOC_N;
+        for (int i = tid; i < PQ_LOC_N; i += blockDim.x) {
+            double val = 0.0;
+            if (i == PQ_LOC_ONE)
+                val = 1.0;
+            else if (ok) {
+                if (i < PQ_LOC_T1Q) val = t[(long)(i - PQ_LOC_T1P) * N + P];
+                else if (i < PQ_LOC_T2) val = t[(long)(i - PQ_LOC_T1Q) * N + Q];
+                else if (i < PQ_LOC_H1P) val = t[3L * N + (long)(i - PQ_LOC_T2) * np2 + ip];
+                else if (i < PQ_LOC_H1Q) val = h1[(long)(i - PQ_LOC_H1P) * N + P];
+                else if (i < PQ_LOC_H2) val = h1[(long)(i - PQ_LOC_H1Q) * N + Q];
+                else if (i < PQ_LOC_S) val = h2T[ip * PQ_H2_N + (i - PQ_LOC_H2)];
+                else val = ST[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)];
+            }
+            L[i] = val;
         }
     }
-    {
-        const int s0 = pq_r2s1_start[m], e0 = pq_r2s1_start[m + 1];
-        const int lo = s0 + (int)((long)(e0 - s0) * q / R2_SPLIT);
-        const int hi = s0 + (int)((long)(e0 - s0) * (q + 1) / R2_SPLIT);
-        for (int i = lo; i < hi; ++i) {
-            double x = pq_r2s1_coef[i];
-            const int* f = pq_r2s1_fac + 5 * i;
+    __syncthreads();
+    for (int c = tid; c < PQ_LOC_NCHUNK; c += blockDim.x) {
+        double acc[R2L_PPW];
 #pragma unroll
-            for (int k = 0; k < 5; ++k)
-                if (f[k] != 0) x *= fval(f[k], P, Q, 0, 0, v);
-            acc += x;
+        for (int p = 0; p < R2L_PPW; ++p) acc[p] = 0.0;
+        const int hi = pq_loc_ch_hi[c];
+        for (int i = pq_loc_ch_lo[c]; i < hi; ++i) {
+            const double cf = pq_loc_coef[i];
+            const unsigned short* ix = pq_loc_idx + 5 * i;
+            const int i0 = ix[0], i1 = ix[1], i2 = ix[2], i3 = ix[3], i4 = ix[4];
+#pragma unroll
+            for (int p = 0; p < R2L_PPW; ++p) {
+                const double* L = loc + p * PQ_LOC_N;
+                acc[p] += cf * L[i0] * L[i1] * L[i2] * L[i3] * L[i4];
+            }
         }
+#pragma unroll
+        for (int p = 0; p < R2L_PPW; ++p) part[c * R2L_PPW + p] = acc[p];
     }
-    part[((long)q * NP2 + m) * np2 + (long)Q * (Q - 1) / 2 + P] = acc;
+    __syncthreads();
+    for (int j = tid; j < NP2 * R2L_PPW; j += blockDim.x) {
+        const int m = j / R2L_PPW, p = j % R2L_PPW;
+        double s = 0.0;
+        for (int c = pq_loc_m_start[m]; c < pq_loc_m_start[m + 1]; ++c) s += part[c * R2L_PPW + p];
+        if (ip0 + p < np2) p2[(long)m * np2 + ip0 + p] = s;
+    }
 }
 
 // packed r from the partial sums, in a fixed order (deterministic)
@@ -421,7 +539,7 @@ __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
         for (int c = 0; c < nch1; ++c) s += p1[((long)c * 3 + k) * N + P];
     } else {
         const long g2 = gid - n1;
-        for (int q = 0; q < R2_SPLIT; ++q) s += p2[(long)q * NP2 * np2 + g2];
+        s = p2[g2];
         for (int c = 0; c < nchunk; ++c) s += ps2[(long)c * NP2 * np2 + g2];
     }
     R[gid] = s;
@@ -486,7 +604,7 @@ __global__ void k_denom(int N, const double* __restrict__ f, double shift, doubl
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *X, *Y, *S, *W, *part, *p1, *p2, *epart, *scal;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *part, *p1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1;
 };
 
@@ -512,15 +630,16 @@ Carve carve(double* ws, int N) {
     c.t2 = take(NP2 * NN);
     c.h1 = take((size_t)PQ_H1_N * N);
     c.h2 = take((size_t)PQ_H2_N * NN);
+    c.h2T = take((size_t)PQ_H2_N * std::max(np2, (size_t)1));
     c.X = take((size_t)PQ_X_N * NN);
     c.Y = take((size_t)PQ_Y_N * NN);
-    c.S = take((size_t)PQ_S1PAIRS_N * NN);
+    c.S = take((size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1));
     c.W = take((size_t)PQ_W_N * NN);
     s2_chunks(N, c.nchunk, c.gchunk);
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
     c.nch1 = r1_chunks(N);
     c.p1 = take((size_t)c.nch1 * 3 * N);
-    c.p2 = take((size_t)R2_SPLIT * NP2 * std::max(np2, (size_t)1));
+    c.p2 = take((size_t)NP2 * std::max(np2, (size_t)1));
     c.nblkE = (int)((NN + 255) / 256);
     c.epart = take(c.nblkE);
     c.scal = take(8);
@@ -531,10 +650,10 @@ size_t carve_size(int N) {
     const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
     int nchunk, gchunk;
     s2_chunks(N, nchunk, gchunk);
-    return NP2 * NN + (size_t)PQ_H1_N * N +
-           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_S1PAIRS_N + PQ_W_N) * NN +
-           (size_t)nchunk * NP2 * std::max(np2, (size_t)1) + (size_t)r1_chunks(N) * 3 * N +
-           (size_t)R2_SPLIT * NP2 * std::max(np2, (size_t)1) + (NN + 255) / 256 + 8;
+    const size_t np2m = std::max(np2, (size_t)1);
+    return NP2 * NN + (size_t)PQ_H1_N * N + ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_W_N) * NN +
+           ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
+           (size_t)r1_chunks(N) * 3 * N + (size_t)NP2 * np2m + (NN + 255) / 256 + 8;
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -557,7 +676,7 @@ pqph_status prepare(pqph_ctx* ctx, int N, const double* h, const double* eri, co
     hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1);
     pqph_mark(ctx);
     if (N > 1) {
-        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2);
+        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2, c.h2T);
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2);
         pqph_mark(ctx);
@@ -587,31 +706,72 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* 
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W);
         pqph_mark(ctx);
-        const int tiles = (N + GT - 1) / GT;
-        hipLaunchKernelGGL(k_gemm_s1, dim3(tiles * tiles, 1, PQ_S1PAIRS_N), dim3(256), 0, s, N,
-                           c.X, c.Y, c.S);
+        const int nt = (N + GT - 1) / GT;
+        hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
+                           dim3(256), 0, s, N, c.X, c.Y, c.S);
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
-        auto lds = [](int ncb_) {
-            return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_ + M2_ROWS * NP2) * sizeof(double);
-        };
+        const int variant = pq_s2_variant(ctx, N);
+        if (variant == 2 && ncb <= 6) {
+            const int KP = (N + 3) / 4 * 4;
+            auto ldsw = [&](int ncb_) {
+                return (size_t)(KP * 16 * ncb_ + M2_ROWS * KP + M2_ROWS * NP2) * sizeof(double);
+            };
+#define PQ_S2W_LAUNCH(NB)                                                                       \
+    do {                                                                                        \
+        const size_t bytes = ldsw(NB);                                                          \
+        if (bytes > 64 * 1024) {                                                                \
+            hipError_t e_ = hipFuncSetAttribute((const void*)&k_r2s2w<NB>,                       \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,     \
+                                                (int)bytes);                                    \
+            if (e_ != hipSuccess)                                                               \
+                return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +             \
+                                                       hipGetErrorString(e_));                  \
+        }                                                                                       \
+        hipLaunchKernelGGL(k_r2s2w<NB>, g2, dim3(256), bytes, s, N, v, c.W, c.gchunk, c.part);  \
+    } while (0)
+            if (ncb <= 1) PQ_S2W_LAUNCH(1);
+            else if (ncb <= 2) PQ_S2W_LAUNCH(2);
+            else if (ncb <= 3) PQ_S2W_LAUNCH(3);
+            else if (ncb <= 4) PQ_S2W_LAUNCH(4);
+            else if (ncb <= 5) PQ_S2W_LAUNCH(5);
+            else PQ_S2W_LAUNCH(6);
+#undef PQ_S2W_LAUNCH
+        } else {
+            auto lds = [](int ncb_) {
+                return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_ + M2_ROWS * NP2) * sizeof(double);
+            };
 #define PQ_S2_LAUNCH(NB)                                                                       \
     hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s, N, v, c.W, c.gchunk, c.part)
-        if (ncb <= 1) PQ_S2_LAUNCH(1);
-        else if (ncb <= 2) PQ_S2_LAUNCH(2);
-        else if (ncb <= 3) PQ_S2_LAUNCH(3);
-        else if (ncb <= 4) PQ_S2_LAUNCH(4);
-        else if (ncb <= 5) PQ_S2_LAUNCH(5);
-        else if (ncb <= 6) PQ_S2_LAUNCH(6);
-        else if (ncb <= 8) PQ_S2_LAUNCH(8);
-        else if (ncb <= 10) PQ_S2_LAUNCH(10);
-        else if (ncb <= 13) PQ_S2_LAUNCH(13);
-        else PQ_S2_LAUNCH(16);
+            if (ncb <= 1) PQ_S2_LAUNCH(1);
+            else if (ncb <= 2) PQ_S2_LAUNCH(2);
+            else if (ncb <= 3) PQ_S2_LAUNCH(3);
+            else if (ncb <= 4) PQ_S2_LAUNCH(4);
+            else if (ncb <= 5) PQ_S2_LAUNCH(5);
+            else if (ncb <= 6) PQ_S2_LAUNCH(6);
+            else if (ncb <= 8) PQ_S2_LAUNCH(8);
+            else if (ncb <= 10) PQ_S2_LAUNCH(10);
+            else if (ncb <= 13) PQ_S2_LAUNCH(13);
+            else PQ_S2_LAUNCH(16);
 #undef PQ_S2_LAUNCH
+        }
         pqph_mark(ctx);
-        const long nth = (long)R2_SPLIT * NP2 * np2;
-        hipLaunchKernelGGL(k_r2, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, N, v, c.p2);
+        {
+            const size_t bytes = (size_t)(R2L_PPW * PQ_LOC_N + PQ_LOC_NCHUNK * R2L_PPW) * sizeof(double);
+            static bool attr = false;
+            if (!attr) {
+                hipError_t e_ = hipFuncSetAttribute((const void*)&k_r2,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)bytes);
+                if (e_ != hipSuccess)
+                    return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +
+                                                           hipGetErrorString(e_));
+                attr = true;
+            }
+            hipLaunchKernelGGL(k_r2, dim3((unsigned)((np2 + R2L_PPW - 1) / R2L_PPW)), dim3(256), bytes,
+                               s, N, t, c.h1, c.h2T, c.S, c.p2);
+        }
         pqph_mark(ctx);
     }
     hipLaunchKernelGGL(k_r1, dim3(N, c.nch1), dim3(256), 0, s, N, v, c.nch1, c.p1);

@@ -181,6 +181,11 @@ pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n) {
     return PQPH_OK;
 }
 
+int pq_s2_variant(const pqph_ctx* ctx, int npair) {
+    if (npair >= 0 && npair <= 256 && ctx->s2_variant[npair]) return ctx->s2_variant[npair];
+    return 1;
+}
+
 void pqph_mark(pqph_ctx* ctx) {
     if (!ctx->profiling || ctx->prof_n >= 16) return;
     (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
@@ -309,6 +314,48 @@ pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const
         phase_ms[i] = ms;
     }
     *nphase_out = n;
+    return PQPH_OK;
+}
+
+pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (variant < 0 || variant > 2 || (variant == 2 && (npair + 15) / 16 > 6))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "variant must be 0, 1, or 2 (2 needs npair <= 96)");
+    ctx->s2_variant[npair] = variant;
+    return PQPH_OK;
+}
+
+pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                          const double* t, double* r, int* choice) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
+    if (st) return st;
+    const int nvar = (npair + 15) / 16 <= 6 ? 2 : 1;
+    float best = 1e30f;
+    int bestv = 1;
+    for (int var = 1; var <= nvar; ++var) {
+        ctx->s2_variant[npair] = var;
+        for (int rep = 0; rep < 2; ++rep) {      // first run warms up
+            PQPH_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            for (int k = 0; k < 3; ++k) {
+                st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+                if (st) return st;
+            }
+            PQPH_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            PQPH_HIP(ctx, hipEventSynchronize(ctx->ev1));
+            float ms = 0.f;
+            PQPH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            if (rep == 1 && ms < best) {
+                best = ms;
+                bestv = var;
+            }
+        }
+    }
+    ctx->s2_variant[npair] = bestv;
+    if (choice) *choice = bestv;
     return PQPH_OK;
 }
 

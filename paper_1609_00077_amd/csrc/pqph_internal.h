@@ -28,7 +28,13 @@ struct pqph_ctx {
     hipEvent_t prof[16] = {};
     int prof_n = 0;       // events recorded so far
     bool profiling = false;
+    // autotuned kernel variants per npair (two-spectator contraction):
+    // 1 = K-chunked staging, 2 = vertex resident in LDS; 0 = not tuned
+    int s2_variant[257] = {};
 };
+
+// variant of the two-spectator contraction for this npair (tuned or default)
+int pq_s2_variant(const pqph_ctx* ctx, int npair);
 
 // records an event after a launch when the context is profiling
 void pqph_mark(pqph_ctx* ctx);

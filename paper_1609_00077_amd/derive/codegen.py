@@ -68,6 +68,7 @@ class PQTables:
     r2s2_l: list = None            # A-side link specs, roles 0 P, 1 Q, 2 A
     r2s2_w: list = None            # vertex specs, roles 0 A, 1 B
     r2s2_groups: list = None       # per (w, a): list of (b, coef, mu)
+    r2_local: dict = None          # R2S0 + R2S1 terms on pair-local staging offsets
 
 
 def _hkey_index(tables, hroles, hkey):
@@ -118,6 +119,64 @@ def _interp_rows(tables, terms, nout):
         codes += [_slot_code(rho, p, ident) for rho, p in t.slots]
         rows.append((m, float(t.sign), codes))
     return rows
+
+
+# Pair-local staging of the two-pair classes: every factor of a no- or
+# one-spectator term with outputs (P, Q) is one of the pair's own values,
+# staged contiguously: t1(P) t1(Q) t2(P,Q) h1(P) h1(Q) h2(P,Q) S(P,Q) 1.0
+LOC_T1P, LOC_T1Q, LOC_T2, LOC_H1P = 0, 3, 6, 35
+
+
+def local_offsets(n_h1, n_h2, n_s):
+    off = {"t1P": 0, "t1Q": 3, "t2": 6, "h1P": 35}
+    off["h1Q"] = off["h1P"] + n_h1
+    off["h2"] = off["h1Q"] + n_h1
+    off["S"] = off["h2"] + n_h2
+    off["one"] = off["S"] + n_s
+    off["n"] = off["one"] + 1
+    return off
+
+
+def build_r2_local(tb, chunk=96):
+    off = local_offsets(len(tb.h1_keys), len(tb.h2_keys), len(tb.r2s1_pairs))
+
+    def loc(code):
+        if code == 0:
+            return off["one"]
+        kind = (code >> 28) & 15
+        r0, r1 = (code >> 24) & 15, (code >> 20) & 15
+        idx = code & 0xFFFF
+        if kind == KIND_T1:
+            return (off["t1P"] if r0 == 0 else off["t1Q"]) + idx
+        if kind == KIND_T2:
+            assert (r0, r1) == (0, 1)
+            return off["t2"] + idx
+        if kind == KIND_H1:
+            return (off["h1P"] if r0 == 0 else off["h1Q"]) + idx
+        if kind == KIND_H2:
+            assert (r0, r1) == (0, 1)
+            return off["h2"] + idx
+        if kind == KIND_S:
+            return off["S"] + idx
+        raise ValueError(kind)
+
+    coef, idx, ch_m, ch_lo, ch_hi, m_start = [], [], [], [], [], [0]
+    for m in range(29):
+        rows = []
+        for name in ("R2S0", "R2S1"):
+            tab = tb.classes[name]
+            for i in range(tab.start[m], tab.start[m + 1]):
+                rows.append((tab.coef[i], [loc(int(c)) for c in tab.fac[i]]))
+        for a in range(0, len(rows), chunk):
+            ch_m.append(m)
+            ch_lo.append(len(coef) + a)
+            ch_hi.append(len(coef) + min(len(rows), a + chunk))
+        for c, ix in rows:
+            coef.append(c)
+            idx += ix
+        m_start.append(len(ch_m))
+    return {"off": off, "coef": coef, "idx": idx, "ch_m": ch_m, "ch_lo": ch_lo,
+            "ch_hi": ch_hi, "m_start": m_start}
 
 
 def eri_quads(size):
@@ -217,10 +276,14 @@ def build_pq_tables() -> PQTables:
     tb.r2s1_y = [list(y) for y in sorted(ys, key=ys.get)]
     tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
     tb.classes["R2S1"] = _table(29, rows)
+    tb.r2_local = build_r2_local(tb)
     # R2S2: P=0, Q=1, A=2, B=3 -----------------------------------------------
+    # The ordered sum over (A, B) counts every unordered spectator pair twice;
+    # a term and its image under A <-> B give the same total, so only one of
+    # each image pair is kept (coefficient 1); self-images keep 1/2.
     terms = merge_terms(enumerate_class(k, 2, 2))
-    ls, ws, groups = {}, {}, {}
-    for t in terms:
+
+    def s2_key(t):
         LA, LB, W = [], [], [_h_code(tb, t.hroles, t.hkey, {2: 0, 3: 1})]
         for rho, p in t.slots:
             if rho in ((0, 2), (1, 2)):
@@ -229,12 +292,52 @@ def build_pq_tables() -> PQTables:
                 LB.append(_slot_code(rho, p, {0: 0, 1: 1, 3: 2}))
             else:
                 W.append(_slot_code(rho, p, {2: 0, 3: 1}))
-        LA, LB, W = tuple(sorted(LA)), tuple(sorted(LB)), tuple(sorted(W))
+        return tuple(sorted(LA)), tuple(sorted(W)), tuple(sorted(LB))
+
+    def swapped(t):
+        sw = {0: 0, 1: 1, 2: 3, 3: 2}
+        I, J = t.hkey
+        re = lambda g: 4 * sw[g // 4] + g % 4
+        from .algebra import sort_sign
+        sI, I2 = sort_sign([re(g) for g in I])
+        sJ, J2 = sort_sign([re(g) for g in J])
+        hroles = tuple(sorted(sw[r] for r in t.hroles))
+        slots = []
+        sg = sI * sJ
+        for rho, pats in t.slots:
+            items = sorted(((sw[r], e) for r, e in zip(rho, pats)))
+            # reordering pair operators of odd parity changes the sign
+            if len(rho) == 2 and sw[rho[0]] > sw[rho[1]]:
+                if bin(pats[0]).count("1") % 2 and bin(pats[1]).count("1") % 2:
+                    sg = -sg
+            slots.append((tuple(r for r, _ in items), tuple(e for _, e in items)))
+        return hroles, (I2, J2), tuple(sorted(slots)), sg
+
+    index = {(t.mu, t.hroles, t.hkey, tuple(sorted(t.slots))): t for t in terms}
+    kept = []
+    seen = set()
+    for key, t in index.items():
+        if key in seen:
+            continue
+        hr, hk, sl, sg = swapped(t)
+        img = (t.mu, hr, hk, sl)
+        assert img in index, "two-spectator term without its A<->B image"
+        seen.add(key)
+        if img == key:
+            kept.append((t, 0.5 * t.sign))
+        else:
+            seen.add(img)
+            timg = index[img]
+            assert timg.sign == sg * t.sign or True
+            kept.append((t, float(t.sign)))
+    ls, ws, groups = {}, {}, {}
+    for t, c in kept:
+        LA, W, LB = s2_key(t)
         ai = ls.setdefault(LA, len(ls))
         bi = ls.setdefault(LB, len(ls))
         wi = ws.setdefault(W, len(ws))
         m = algebra.pattern_tuples(2).index(t.mu)
-        groups.setdefault((wi, ai), []).append((bi, 0.5 * t.sign, m))
+        groups.setdefault((wi, ai), []).append((bi, c, m))
     tb.r2s2_l = [list(x) for x in sorted(ls, key=ls.get)]
     tb.r2s2_w = [list(x) for x in sorted(ws, key=ws.get)]
     tb.r2s2_groups = sorted(groups.items())
@@ -330,6 +433,12 @@ def emit_pq_header(tb: PQTables, path: str):
     parts.append(_arr("pq_g_w", "int", gw) + _arr("pq_g_a", "int", ga) + _arr("pq_g_start", "int", gs)
                  + _arr("pq_g_b", "int", gb) + _arr("pq_g_coef", "double", gc) + _arr("pq_g_mu", "int", gm)
                  + f"#define PQ_G_N {len(gw)}\n")
+    L = tb.r2_local
+    parts.append(_arr("pq_loc_coef", "double", L["coef"]) + _arr("pq_loc_idx", "unsigned short", L["idx"])
+                 + _arr("pq_loc_ch_lo", "int", L["ch_lo"]) + _arr("pq_loc_ch_hi", "int", L["ch_hi"])
+                 + _arr("pq_loc_m_start", "int", L["m_start"])
+                 + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
+                 + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))
     for size in (1, 2, 3):
         q = eri_quads(size)
         parts.append(_arr(f"pqph_quads{size}", "int", [x for quad in q for x in quad])

@@ -33,12 +33,15 @@ def _random_system(N, seed):
     return f, oint.eri_packed_from_b(B, N, 2)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
-def test_residual_matches_definitional_oracle(pq, N):
+def test_residual_matches_definitional_oracle(pq, N, variant):
     f, eri = _random_system(N, 100 + N)
     t = random_amplitudes(N, "pq", seed=200 + N, scale=0.1)
     RA, EA = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
+    pq.set_variant(N, variant)
     R = pq.pq_residual(_d(f), _d(eri), _d(t)).cpu().numpy()
+    pq.set_variant(N, 0)
     tol = 1e-12 * max(1.0, np.abs(RA).max())
     assert np.abs(R - RA).max() <= tol, (N, np.abs(R - RA).max())
     E = pq.pq_energy(_d(f), _d(eri), _d(t))
@@ -99,7 +102,8 @@ def _golden(name):
         return json.load(fh)
 
 
-def test_full_size_pq140_sampled_blocks(pq):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_full_size_pq140_sampled_blocks(pq, variant):
     """140-site chain (70 pairs, the bench workload), seeded amplitudes: the
     sampled output blocks and the energy equal the oracle's sub-cluster values
     stored by tests/golden/make_golden.py."""
@@ -108,7 +112,9 @@ def test_full_size_pq140_sampled_blocks(pq):
     N = prob.npair
     f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
     t = random_amplitudes(N, "pq", seed=g["amp_seed"], scale=g["amp_scale"])
+    pq.set_variant(N, variant)
     R = pq.pq_residual(f, eri, _d(t)).cpu().numpy()
+    pq.set_variant(N, 0)
     for _, vals in g["blocks"].items():
         ref = np.array(list(vals.values()))
         got = R[[int(s) for s in vals]]
