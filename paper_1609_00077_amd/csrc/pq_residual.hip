@@ -172,6 +172,30 @@ __device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View&
     return x;
 }
 
+// A link spec decoded once per use: prod_f t2[m_f][P or Q][spectator]
+struct Link {
+    int n;
+    const double* base[3];   // row pointers t2[m_f][P or Q][.]
+};
+
+__device__ __forceinline__ void link_rows(int s, int P, int Q, const View& v, Link& L) {
+    L.n = pq_ld_n[s];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int m = pq_ld_m[3 * s + f];
+        const int who = pq_ld_q[3 * s + f] ? Q : P;
+        L.base[f] = v.t2 + (long)m * v.NN + (long)who * v.N;
+    }
+}
+
+__device__ __forceinline__ double link_at(const Link& L, int A) {
+    double x = 1.0;
+    if (L.n > 0) x = L.base[0][A];
+    if (L.n > 1) x *= L.base[1][A];
+    if (L.n > 2) x *= L.base[2][A];
+    return x;
+}
+
 // ------------------------------------------------------------ one spectator
 constexpr int GT = 16;
 constexpr int GP = 16;   // (x, y) pairs per workgroup
@@ -317,7 +341,13 @@ __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __res
             for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
                 const int row = i / M2_KC, A = kc + i % M2_KC;
                 const int P = rowP[row], Q = rowQ[row];
-                La[i] = (P >= 0 && A < N && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
+                double x = 0.0;
+                if (P >= 0 && A < N && A != P && A != Q) {
+                    Link L;
+                    link_rows(a, P, Q, v, L);
+                    x = link_at(L, A);
+                }
+                La[i] = x;
             }
             for (int i = tid; i < M2_KC * NC; i += 256) {
                 const int A = kc + i / NC, col = i % NC;
@@ -344,10 +374,12 @@ __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __res
                 const int row = wave * 16 + (lane >> 4) + 4 * r;
                 const int P = rowP[row], Q = rowQ[row];
                 if (P >= 0) {
+                    Link L;
+                    link_rows(b, P, Q, v, L);
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb) {
                         const int col = cb * 16 + (lane & 15);
-                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * spec_l(b, P, Q, col, v);
+                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * link_at(L, col);
                     }
                 }
             }
@@ -408,7 +440,13 @@ __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __re
         for (int i = tid; i < M2_ROWS * KP; i += 256) {
             const int row = i / KP, A = i % KP;
             const int P = rowP[row], Q = rowQ[row];
-            La[i] = (P >= 0 && A < N && A != P && A != Q) ? spec_l(a, P, Q, A, v) : 0.0;
+            double x = 0.0;
+            if (P >= 0 && A < N && A != P && A != Q) {
+                Link L;
+                link_rows(a, P, Q, v, L);
+                x = link_at(L, A);
+            }
+            La[i] = x;
         }
         __syncthreads();
         d4 D[NCB];
@@ -431,10 +469,12 @@ __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __re
                 const int row = wave * 16 + (lane >> 4) + 4 * r;
                 const int P = rowP[row], Q = rowQ[row];
                 if (P >= 0) {
+                    Link L;
+                    link_rows(b, P, Q, v, L);
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb) {
                         const int col = cb * 16 + (lane & 15);
-                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * spec_l(b, P, Q, col, v);
+                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * link_at(L, col);
                     }
                 }
             }
@@ -668,9 +708,8 @@ View make_view(const double* t, const Carve& c, int N) {
     return v;
 }
 
-pqph_status prepare(pqph_ctx* ctx, int N, const double* h, const double* eri, const double* t,
-                    const Carve& c) {
-    hipStream_t s = ctx->stream;
+pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
+                    const double* t, const Carve& c) {
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1);
@@ -689,11 +728,10 @@ pqph_status prepare(pqph_ctx* ctx, int N, const double* h, const double* eri, co
 
 size_t pq_ws_doubles(int npair) { return carve_size(npair); }
 
-pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* eri,
-                           const double* t, double* r, double* ws) {
-    hipStream_t s = ctx->stream;
+pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                           const double* eri, const double* t, double* r, double* ws) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, N, h, eri, t, c);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c);
     if (st) return st;
     View v = make_view(t, c, N);
     const int tb = 64;
@@ -787,11 +825,10 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, int N, const double* h, const double* 
     return PQPH_OK;
 }
 
-pqph_status pq_energy_ws(pqph_ctx* ctx, int N, const double* h, const double* eri,
-                         const double* t, double* dst, double* ws) {
-    hipStream_t s = ctx->stream;
+pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                         const double* eri, const double* t, double* dst, double* ws) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, N, h, eri, t, c);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c);
     if (st) return st;
     View v = make_view(t, c, N);
     hipLaunchKernelGGL(k_energy, dim3(c.nblkE), dim3(256), 0, s, N, v, c.epart);
@@ -800,9 +837,10 @@ pqph_status pq_energy_ws(pqph_ctx* ctx, int N, const double* h, const double* er
     return PQPH_OK;
 }
 
-pqph_status pq_denominators_dev(pqph_ctx* ctx, int N, const double* h, double shift, double* D) {
+pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                                double shift, double* D) {
     const long n = (long)pq_amp_len(N);
-    hipLaunchKernelGGL(k_denom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, N,
+    hipLaunchKernelGGL(k_denom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N,
                        h, shift, D);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;

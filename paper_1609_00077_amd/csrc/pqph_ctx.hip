@@ -277,7 +277,7 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
     st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
     if (st) return st;
-    return pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+    return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
 }
 
 static const char* kPhaseNames[] = {"k_vertex1", "k_vertex2", "k_unpack_t2", "k_spec_x",
@@ -302,7 +302,7 @@ pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const
     ctx->prof_n = 0;
     ctx->profiling = true;
     pqph_mark(ctx);   // start event
-    st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+    st = pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
     ctx->profiling = false;
     if (st) return st;
     PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -341,7 +341,7 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
         for (int rep = 0; rep < 2; ++rep) {      // first run warms up
             PQPH_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
             for (int k = 0; k < 3; ++k) {
-                st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+                st = pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
                 if (st) return st;
             }
             PQPH_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -368,7 +368,7 @@ pqph_status pq_energy(pqph_ctx* ctx, int npair, const double* h, const double* e
     st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double));
     if (st) return st;
     double* dst = ctx->ws + wsd;
-    st = pq_energy_ws(ctx, npair, h, eri, t, dst, ctx->ws);
+    st = pq_energy_ws(ctx, ctx->stream, npair, h, eri, t, dst, ctx->ws);
     if (st) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(energy, dst, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -382,7 +382,7 @@ pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, 
     if (st) return st;
     if (k != 2) return pqph_fail(ctx, PQPH_INVALID_ARG, "only k = 2 is built");
     if (!h || !D) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
-    return pq_denominators_dev(ctx, npair, h, shift, D);
+    return pq_denominators_dev(ctx, ctx->stream, npair, h, shift, D);
 }
 
 pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* eri,
@@ -420,7 +420,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     double* hst = ctx->host;
     hipStream_t s = ctx->stream;
     PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
-    st = pq_denominators_dev(ctx, npair, h, o.level_shift, D);
+    st = pq_denominators_dev(ctx, ctx->stream, npair, h, o.level_shift, D);
     if (st) return st;
     // the denominators must not vanish
     {
@@ -436,7 +436,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     double rn = INFINITY, rmin = INFINITY;
     pqph_status result = PQPH_NOT_CONVERGED;
     for (it = 1; it <= o.max_iter; ++it) {
-        st = pq_residual_ws(ctx, npair, h, eri, t, r, ctx->ws);
+        st = pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
         if (st) return st;
         vec_dot_launch(s, r, r, n, part, nblk);
         hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, part, nblk, scal);
@@ -509,7 +509,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     if (result == PQPH_NOT_CONVERGED)
         pqph_fail(ctx, result, "not converged in " + std::to_string(o.max_iter) + " iterations");
     double* edst = ctx->ws + wsd;
-    st = pq_energy_ws(ctx, npair, h, eri, t, edst, ctx->ws);
+    st = pq_energy_ws(ctx, ctx->stream, npair, h, eri, t, edst, ctx->ws);
     if (st) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(hst, edst, sizeof(double), hipMemcpyDeviceToHost, s));
     PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));

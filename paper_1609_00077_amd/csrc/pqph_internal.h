@@ -55,14 +55,14 @@ pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n);
 
 // PQ residual pieces (pq_residual.hip) --------------------------------------
 size_t pq_ws_doubles(int npair);
-// residual into r using workspace ws (already large enough); no host sync
-pqph_status pq_residual_ws(pqph_ctx* ctx, int npair, const double* h, const double* eri,
-                           const double* t, double* r, double* ws);
-// energy partials: writes one double (the energy) to dst (device), no sync
-pqph_status pq_energy_ws(pqph_ctx* ctx, int npair, const double* h, const double* eri,
-                         const double* t, double* dst, double* ws);
-pqph_status pq_denominators_dev(pqph_ctx* ctx, int npair, const double* h, double shift,
-                                double* D);
+// residual into r on stream s using workspace ws (already large enough); no host sync
+pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
+                           const double* eri, const double* t, double* r, double* ws);
+// energy: writes one double to dst (device) on stream s, no sync
+pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
+                         const double* eri, const double* t, double* dst, double* ws);
+pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
+                                double shift, double* D);
 
 // streaming vector kernels (solve.hip) ---------------------------------------
 void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,

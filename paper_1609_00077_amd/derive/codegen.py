@@ -439,6 +439,20 @@ def emit_pq_header(tb: PQTables, path: str):
                  + _arr("pq_loc_m_start", "int", L["m_start"])
                  + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
                  + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))
+    # link specs of the two-spectator sums, decoded: every factor is
+    # t2[m][P or Q][spectator]; up to 3 factors
+    ln, lm, lq = [], [], []
+    for sp in tb.r2s2_l:
+        assert len(sp) <= 3
+        ln.append(len(sp))
+        mm, qq = [0, 0, 0], [0, 0, 0]
+        for f, code in enumerate(sp):
+            assert (code >> 28) & 15 == KIND_T2 and (code >> 20) & 15 == 2
+            mm[f] = code & 0xFFFF
+            qq[f] = (code >> 24) & 15
+        lm += mm
+        lq += qq
+    parts.append(_arr("pq_ld_n", "int", ln) + _arr("pq_ld_m", "int", lm) + _arr("pq_ld_q", "int", lq))
     for size in (1, 2, 3):
         q = eri_quads(size)
         parts.append(_arr(f"pqph_quads{size}", "int", [x for quad in q for x in quad])
