@@ -179,6 +179,24 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h,
  * 1, or 2 when npair <= 96); INVALID_ARG otherwise.  For tests and tuning. */
 pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
 
+/* Batched PQ solves (many Hamiltonians of uneven pair counts, solved
+ * together; each chain runs its own Jacobi + DIIS exactly as pq_solve and
+ * converges on its own).  Chain c has npair[c] pairs (host array) and reads
+ * its Fock matrix at h + h_off[c], its packed integrals at eri + eri_off[c]
+ * and its amplitudes at t_inout + t_off[c] (offsets in doubles, host arrays;
+ * the caller packs the chains into three device buffers).  energies (host,
+ * nbatch) receives each chain's correlation energy and infos (host, may be
+ * NULL) each chain's report.  Returns OK if every chain converged, otherwise
+ * the first failing chain's status; one bad chain does not stop the others.
+ * Device memory: the residual workspace of the largest chain per stream (up
+ * to 8 streams) plus (4 + 2*diis_dim) amplitude vectors per chain. */
+pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* npair,
+                             const int64_t* h_off, const int64_t* eri_off,
+                             const int64_t* t_off, const double* h,
+                             const double* eri, const pqph_solve_opts* opts,
+                             double* t_inout, double* energies,
+                             pqph_solve_info* infos);
+
 /* Orbital-energy denominators of the packed slots (length pq_amp_len or
  * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
  * + shift.  Exposed for callers that run their own update. */

@@ -9,7 +9,8 @@ and draws seeded random amplitudes and integral factors.  The integral
 transformation into pair blocks, the residuals, energies, solves and gradients
 are computed separately by the oracle and by the HIP library.
 """
-from .ppp import ppp_chain, rhf, mirror_pairing, chain_problem, ChainProblem  # noqa: F401
+from .ppp import (ppp_chain, rhf, mirror_pairing, chain_problem, ChainProblem,  # noqa: F401
+                  batch_problems)
 from .random_inputs import (  # noqa: F401
     random_amplitudes, random_fock, random_bfactors, batch_chain_specs,
     n_amp_pq, n_amp_ph, n_eri_pq, n_eri_ph,

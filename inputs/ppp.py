@@ -52,11 +52,27 @@ def _fock(h, V, P):
 
 
 def rhf(h, V, nocc: int, E_core: float = 0.0, tol: float = 1e-12,
-        max_iter: int = 1000, diis_dim: int = 8):
+        max_iter: int = 1000, diis_dim: int = 8, shift: float = 0.0):
     """Closed-shell RHF with DIIS, converged to max|FP - PF| <= tol.
 
-    Returns (C, eps, F, P, E) with orbitals sorted by ascending energy.
+    Returns (C, eps, F, P, E) with orbitals sorted by ascending energy.  If
+    plain DIIS stalls, the solve is repeated with a virtual-space level shift
+    (which changes the path, not the converged orbitals).
     """
+    try:
+        return _rhf(h, V, nocc, E_core, tol, 300 if shift == 0.0 else max_iter, diis_dim, shift)
+    except RuntimeError:
+        if shift != 0.0:
+            raise
+    for s in (0.5, 2.0):
+        try:
+            return _rhf(h, V, nocc, E_core, tol, max_iter, diis_dim, s)
+        except RuntimeError:
+            continue
+    raise RuntimeError("RHF did not converge even with level shifts")
+
+
+def _rhf(h, V, nocc, E_core, tol, max_iter, diis_dim, shift):
     n = h.shape[0]
     eps, C = np.linalg.eigh(h)          # Hueckel guess
     P = 2.0 * C[:, :nocc] @ C[:, :nocc].T
@@ -86,6 +102,8 @@ def rhf(h, V, nocc: int, E_core: float = 0.0, tol: float = 1e-12,
                 F = sum(ci * Fi for ci, Fi in zip(c, focks))
             except np.linalg.LinAlgError:
                 pass
+        if shift:
+            F = F + shift * (np.eye(n) - 0.5 * P)
         eps, C = np.linalg.eigh(F)
         P = 2.0 * C[:, :nocc] @ C[:, :nocc].T
     else:
@@ -146,3 +164,25 @@ def chain_problem(n_sites: int, U: float = 4.0, seed: int = 0,
     C, eps, F, _, E = rhf(h, V, nocc, E_core=E_core)
     Cp, ep = mirror_pairing(C, eps, nocc)
     return ChainProblem(n_sites, U, seed, h, V, E_core, Cp, ep, F, E)
+
+
+def _problem_of(spec):
+    n, U, seed = spec
+    return chain_problem(n, U=U, seed=seed)
+
+
+def _single_thread_blas():
+    from threadpoolctl import threadpool_limits
+    global _LIMIT
+    _LIMIT = threadpool_limits(limits=1)
+
+
+def batch_problems(specs, processes: int = 8):
+    """chain_problem for every (n_sites, U, seed) spec, in a process pool of
+    single-threaded workers (a threaded BLAS per worker would oversubscribe)."""
+    import multiprocessing as mp
+    if processes <= 1 or len(specs) < 4:
+        return [_problem_of(s) for s in specs]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(processes, initializer=_single_thread_blas) as pool:
+        return pool.map(_problem_of, specs, chunksize=2)

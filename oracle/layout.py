@@ -175,7 +175,7 @@ def unpack_eri(packed: np.ndarray, npair: int, k: int) -> np.ndarray:
     """Dense (2N)^4 tensor holding the packed integrals at all 8 symmetric
     positions and zero for every label set of more than k pairs."""
     n = 2 * npair
-    full = np.zeros((n, n, n, n))
+    full = np.zeros((n, n, n, n), dtype=np.asarray(packed).dtype)
     for size in range(1, k + 1):
         quads = eri_quads(size)
         nsets = comb(npair, size)

@@ -109,8 +109,8 @@ class TierA:
             out += term
         return out
 
-    def reference(self) -> np.ndarray:
-        v = np.zeros(self.shape)
+    def reference(self, dtype=float) -> np.ndarray:
+        v = np.zeros(self.shape, dtype=dtype)
         v[self.ref, self.ref] = 1.0
         return v
 
@@ -118,15 +118,17 @@ class TierA:
     def residual(self, f: np.ndarray, eri_trunc: np.ndarray, t: np.ndarray):
         """(R packed, E_c) at amplitudes t; eri_trunc is the dense truncated tensor."""
         hb = self.bare_onebody(f, eri_trunc)
-        ref = self.reference()
+        dt = np.result_type(f, eri_trunc, t)      # complex inputs allow complex-step derivatives
+        ref = self.reference(dt)
         e_ref = self.sigma(hb, eri_trunc, ref)[self.ref, self.ref]
         psi = self.exp_T(t, ref, 1.0)
         phi = self.sigma(hb, eri_trunc, psi) - e_ref * psi
         chi = self.exp_T(t, phi, -1.0)
-        R = np.zeros(layout.amp_count(self.n, self.k))
+        R = np.zeros(layout.amp_count(self.n, self.k), dtype=dt)
         for pos, _, (sg, ia, ib) in self.slots:
             R[pos] = sg * chi[ia, ib]
-        return R, float(chi[self.ref, self.ref])
+        e = chi[self.ref, self.ref]
+        return R, (e if np.iscomplexobj(e) else float(e))
 
     def energy(self, f, eri_trunc, t) -> float:
         """E_c = <0| (H_k - E_ref) e^T |0>."""

@@ -146,6 +146,52 @@ def denominators(h: torch.Tensor, k: int = 2, shift: float = 0.0) -> torch.Tenso
 
 
 @dataclass
+class BatchResult:
+    t: torch.Tensor            # packed amplitudes of every chain, concatenated
+    t_off: list
+    energies: list
+    iterations: list
+    rnorms: list
+    statuses: list
+    solve_ms: float
+
+
+def pq_solve_batched(hs, eris, *, tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8,
+                     diis_start: int = 2, level_shift: float = 0.0,
+                     diverge_factor: float = 1e4) -> BatchResult:
+    """Solve many PQ problems together.  hs, eris: lists of per-chain Fock
+    matrices and packed integrals (device tensors), packed here into one
+    buffer each."""
+    dev = hs[0].device
+    lib, ctx = _ctx(dev)
+    nb = len(hs)
+    npairs = [h.shape[0] // 2 for h in hs]
+    h_all = torch.cat([h.reshape(-1) for h in hs]).contiguous()
+    e_all = torch.cat([e.reshape(-1) for e in eris]).contiguous()
+    h_off, e_off, t_off = [], [], []
+    a = b = c = 0
+    for h, e, n in zip(hs, eris, npairs):
+        if e.numel() != eri_len(n):
+            raise ValueError("integral vector of the wrong length in the batch")
+        h_off.append(a); e_off.append(b); t_off.append(c)
+        a += h.numel(); b += e.numel(); c += amp_len(n)
+    t = torch.zeros(c, dtype=torch.float64, device=dev)
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    infos = (_lib.SolveInfo * nb)()
+    en = (C.c_double * nb)()
+    st = lib.pq_solve_batched(ctx, nb, (C.c_int * nb)(*npairs), (C.c_int64 * nb)(*h_off),
+                              (C.c_int64 * nb)(*e_off), (C.c_int64 * nb)(*t_off),
+                              _dev(h_all, "h"), _dev(e_all, "eri"), C.byref(opts), _dev(t, "t"),
+                              en, infos)
+    if st not in (0, -4, -5, -6):
+        _check(lib, ctx, st)
+    return BatchResult(t, t_off, [en[i] for i in range(nb)], [infos[i].iterations for i in range(nb)],
+                       [infos[i].rnorm for i in range(nb)],
+                       [_lib.STATUS.get(infos[i].status, str(infos[i].status)) for i in range(nb)],
+                       infos[0].solve_ms if nb else 0.0)
+
+
+@dataclass
 class SolveResult:
     t: torch.Tensor
     energy: float

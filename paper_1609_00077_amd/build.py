@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpqph.so")
-SOURCES = ["pqph_ctx.hip", "pq_residual.hip", "integrals.hip"]
+SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "integrals.hip", "batched.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (wrong results seen on this part)

@@ -11,121 +11,6 @@ namespace {
 
 thread_local std::string g_no_ctx_error;
 
-// ------------------------------------------------------------ vector kernels
-__global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, size_t n,
-                              double* __restrict__ partial) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        s += a[i] * b[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// out[j] = sum of partial[j*nblk .. (j+1)*nblk)
-__global__ void k_sum_rows(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
-    __shared__ double red[256];
-    const int j = blockIdx.x;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(size_t)j * nblk + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[j] = red[0];
-}
-
-// e = -r/D ; tn = t + e ; also ||r||^2 partials are computed separately
-__global__ void k_jacobi(const double* __restrict__ t, const double* __restrict__ r,
-                         const double* __restrict__ D, size_t n, double* __restrict__ tn,
-                         double* __restrict__ e) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double d = -r[i] / D[i];
-        e[i] = d;
-        tn[i] = t[i] + d;
-    }
-}
-
-// t = sum_i c[i] * hist[slot_i]
-__global__ void k_combine(const double* __restrict__ hist, const double* __restrict__ c, int m,
-                          size_t n, double* __restrict__ t) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int j = 0; j < m; ++j) s += c[j] * hist[(size_t)j * n + i];
-        t[i] = s;
-    }
-}
-
-// several dot products against one vector: out[j] partials for a[j] . b
-__global__ void k_dots_partial(const double* __restrict__ A, int m, const double* __restrict__ b,
-                               size_t n, int nblk, double* __restrict__ partial) {
-    __shared__ double red[256];
-    const int j = blockIdx.y;
-    double s = 0.0;
-    const double* a = A + (size_t)j * n;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        s += a[i] * b[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = red[0];
-}
-
-int stream_blocks(size_t n) { return (int)std::min<size_t>(1024, (n + 255) / 256); }
-
-// Solve the (m+1) x (m+1) DIIS system with partial pivoting; false if singular.
-bool diis_solve(const std::vector<double>& B, int m, std::vector<double>& c) {
-    const int n = m + 1;
-    std::vector<double> A((size_t)n * (n + 1));
-    double scale = 0.0;
-    for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(B[(size_t)i * 16 + i]));
-    if (!(scale > 0.0)) return false;
-    for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < n; ++j) {
-            double v;
-            if (i < m && j < m) v = B[(size_t)i * 16 + j] / scale;
-            else if (i == m && j == m) v = 0.0;
-            else v = -1.0;
-            A[(size_t)i * (n + 1) + j] = v;
-        }
-        A[(size_t)i * (n + 1) + n] = (i == m) ? -1.0 : 0.0;
-    }
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int i = col + 1; i < n; ++i)
-            if (std::fabs(A[(size_t)i * (n + 1) + col]) > std::fabs(A[(size_t)piv * (n + 1) + col]))
-                piv = i;
-        if (std::fabs(A[(size_t)piv * (n + 1) + col]) < 1e-300) return false;
-        if (piv != col)
-            for (int j = 0; j <= n; ++j)
-                std::swap(A[(size_t)piv * (n + 1) + j], A[(size_t)col * (n + 1) + j]);
-        for (int i = 0; i < n; ++i) {
-            if (i == col) continue;
-            const double fct = A[(size_t)i * (n + 1) + col] / A[(size_t)col * (n + 1) + col];
-            for (int j = col; j <= n; ++j) A[(size_t)i * (n + 1) + j] -= fct * A[(size_t)col * (n + 1) + j];
-        }
-    }
-    c.assign(m, 0.0);
-    for (int i = 0; i < m; ++i) c[i] = A[(size_t)i * (n + 1) + n] / A[(size_t)i * (n + 1) + i];
-    for (double x : c)
-        if (!std::isfinite(x)) return false;
-    return true;
-}
-
 }  // namespace
 
 // ----------------------------------------------------------------- helpers
@@ -191,11 +76,6 @@ void pqph_mark(pqph_ctx* ctx) {
     (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
 }
 
-void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,
-                    int nblk) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(256), 0, s, a, b, n, partial);
-}
-
 static pqph_status check_pq(pqph_ctx* ctx, int npair) {
     if (!ctx) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null context");
     if (npair < 1 || npair > 256)
@@ -246,6 +126,9 @@ void pqph_destroy(pqph_ctx* ctx) {
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->prof)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
+    for (hipStream_t st : ctx->bstreams) (void)hipStreamDestroy(st);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
 }
 
@@ -438,8 +321,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     for (it = 1; it <= o.max_iter; ++it) {
         st = pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
         if (st) return st;
-        vec_dot_launch(s, r, r, n, part, nblk);
-        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, part, nblk, scal);
+        launch_norm2(s, r, n, part, nblk, scal);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
         rn = std::sqrt(hst[0]);
@@ -459,7 +341,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
             break;
         }
         if (it == o.max_iter) break;
-        hipLaunchKernelGGL(k_jacobi, dim3(stream_blocks(n)), dim3(256), 0, s, t, r, D, n, tn, e);
+        launch_jacobi(s, t, r, D, n, tn, e);
         if (o.diis_dim == 0) {
             PQPH_HIP(ctx, hipMemcpyAsync(t, tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             continue;
@@ -472,9 +354,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
         PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
                                      hipMemcpyDeviceToDevice, s));
         // Gram row of the new error vector against every stored one
-        hipLaunchKernelGGL(k_dots_partial, dim3(nblk, m), dim3(256), 0, s, eh, m,
-                           eh + (size_t)slot * n, n, nblk, part);
-        hipLaunchKernelGGL(k_sum_rows, dim3(m), dim3(256), 0, s, part, nblk, scal);
+        launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, m * sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
         for (int j = 0; j < m; ++j) {
@@ -497,8 +377,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
                 for (int j = 0; j < m; ++j) hst[8 + j] = cm[j];
                 PQPH_HIP(ctx, hipMemcpyAsync(scal + 16, hst + 8, m * sizeof(double),
                                              hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_combine, dim3(stream_blocks(n)), dim3(256), 0, s, th,
-                                   scal + 16, m, n, t);
+                launch_combine(s, th, scal + 16, m, n, t);
                 // keep the pinned staging alive until the copy has run
                 PQPH_HIP(ctx, hipStreamSynchronize(s));
                 continue;

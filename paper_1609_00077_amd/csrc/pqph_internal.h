@@ -31,6 +31,10 @@ struct pqph_ctx {
     // autotuned kernel variants per npair (two-spectator contraction):
     // 1 = K-chunked staging, 2 = vertex resident in LDS; 0 = not tuned
     int s2_variant[257] = {};
+    // streams and events of batched solves (default priority), created on first use
+    std::vector<hipStream_t> bstreams;
+    std::vector<hipEvent_t> bevents;
+    hipEvent_t fork = nullptr;
 };
 
 // variant of the two-spectator contraction for this npair (tuned or default)
@@ -64,6 +68,19 @@ pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* 
 pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                                 double shift, double* D);
 
-// streaming vector kernels (solve.hip) ---------------------------------------
-void vec_dot_launch(hipStream_t s, const double* a, const double* b, size_t n, double* partial,
-                    int nblk);
+// streaming kernels of the solver (solver_kernels.hip) ---------------------
+int stream_blocks(size_t n);
+// (m+1)x(m+1) DIIS system from the Gram matrix B (row stride 16); false if singular
+bool diis_solve(const std::vector<double>& B, int m, std::vector<double>& c);
+// out[0] = ||r||^2 (fixed-order reduction over nblk partials)
+void launch_norm2(hipStream_t s, const double* r, size_t n, double* part, int nblk, double* out);
+// e = -r/D, tn = t + e
+void launch_jacobi(hipStream_t s, const double* t, const double* r, const double* D, size_t n,
+                   double* tn, double* e);
+// out[j] = eh[j] . enew for j < m (part holds m*nblk partials)
+void launch_gram(hipStream_t s, const double* eh, int m, const double* enew, size_t n, double* part,
+                 int nblk, double* out);
+// out[0] = min |a_i|
+void launch_absmin(hipStream_t s, const double* a, size_t n, double* part, int nblk, double* out);
+// t = sum_j c[j] th[j]
+void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
