@@ -197,6 +197,35 @@ pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* npair,
                              double* t_inout, double* energies,
                              pqph_solve_info* infos);
 
+/* Transposed-residual contraction (the adjoint of pq_residual and pq_energy,
+ * Sec. II: the de-excitation amplitudes lambda of the Lagrangian
+ * L = E_c + lambda . R are truncated like t):
+ *     tbar   = sum_mu lam_mu dR_mu/dt   + energy_weight dE_c/dt   (packed t layout)
+ *     hbar   = sum_mu lam_mu dR_mu/dh   + energy_weight dE_c/dh   (2N x 2N, f read
+ *              as a general matrix)
+ *     eribar = the same with respect to each stored integral (packed layout).
+ * hbar and eribar may both be NULL (then only tbar is formed).  t, lam: packed
+ * amplitude vectors.  Stream-ordered, no host sync.  Accumulation uses FP64
+ * atomics, so results may differ from run to run in the last bits. */
+pqph_status pq_vjp(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                   const double* t, const double* lam, double energy_weight,
+                   double* tbar, double* hbar, double* eribar);
+
+/* PQ energy and its gradient with respect to the Hamiltonian.  If t is NULL
+ * the amplitudes are solved here from zero (opts); otherwise t must hold
+ * converged amplitudes.  lambda then solves J^T lambda = -dE/dt (J = dR/dt) by
+ * the same Jacobi + DIIS (opts) and
+ *     dE/dh = dE_c/dh + lambda . dR/dh,  dE/deri = dE_c/deri + lambda . dR/deri
+ * (raw partials: dE = sum dE_dh . dh + sum dE_deri . deri over the stored
+ * elements).  energy: host; dE_dh: 2N x 2N device; dE_deri: packed device;
+ * lambda_out: device or NULL; info (host, may be NULL) reports the lambda
+ * solve (iterations, residual norm) and the total time. */
+pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h,
+                           const double* eri, const double* t,
+                           const pqph_solve_opts* opts, double* energy,
+                           double* dE_dh, double* dE_deri, double* lambda_out,
+                           pqph_solve_info* info);
+
 /* Orbital-energy denominators of the packed slots (length pq_amp_len or
  * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
  * + shift.  Exposed for callers that run their own update. */

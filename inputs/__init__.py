@@ -12,6 +12,6 @@ are computed separately by the oracle and by the HIP library.
 from .ppp import (ppp_chain, rhf, mirror_pairing, chain_problem, ChainProblem,  # noqa: F401
                   batch_problems)
 from .random_inputs import (  # noqa: F401
-    random_amplitudes, random_fock, random_bfactors, batch_chain_specs,
+    random_amplitudes, random_vector, random_fock, random_bfactors, batch_chain_specs,
     n_amp_pq, n_amp_ph, n_eri_pq, n_eri_ph,
 )

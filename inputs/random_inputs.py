@@ -37,6 +37,11 @@ def random_amplitudes(npair: int, model: str = "pq", seed: int = 0,
     return rng.uniform(-scale, scale, n)
 
 
+def random_vector(n: int, seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """Uniform(-scale, scale) values of length n (test directions, multipliers)."""
+    return np.random.default_rng(seed).uniform(-scale, scale, n)
+
+
 def random_fock(npair: int, seed: int = 0, offdiag: float = 0.1) -> np.ndarray:
     """Symmetric 2N x 2N one-body matrix in the paired orbital order.
 

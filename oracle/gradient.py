@@ -51,3 +51,53 @@ def lagrangian_gradient(N: int, k: int, f: np.ndarray, eri_packed: np.ndarray, t
         R, E = ta.residual(f.astype(complex), layout.unpack_eri(ec, N, k), t.astype(complex))
         ge[u] = (E.imag + lam @ R.imag) / H
     return gf, ge, lam
+
+
+def vjp(N: int, k: int, f: np.ndarray, eri_packed: np.ndarray, t: np.ndarray,
+        lam: np.ndarray, energy_weight: float):
+    """Gradient of phi = lam . R(t) + w E_c(t) with respect to t, f (general
+    2N x 2N) and the packed integrals, at any t (converged or not): the
+    transposed-residual contraction.  Complex-step derivatives."""
+    ta = TierA(N, k)
+    eri_t = layout.unpack_eri(eri_packed, N, k)
+
+    def phi(fc, ec, tc):
+        R, E = ta.residual(fc, ec, tc)
+        return (lam @ R + energy_weight * E).imag / H
+
+    fc0, ec0, tc0 = f.astype(complex), eri_t.astype(complex), t.astype(complex)
+    tbar = np.zeros(len(t))
+    for j in range(len(t)):
+        tc = tc0.copy()
+        tc[j] += 1j * H
+        tbar[j] = phi(fc0, ec0, tc)
+    n = 2 * N
+    hbar = np.zeros((n, n))
+    for p in range(n):
+        for q in range(n):
+            fc = fc0.copy()
+            fc[p, q] += 1j * H
+            hbar[p, q] = phi(fc, ec0, tc0)
+    eribar = np.zeros(len(eri_packed))
+    for u in range(len(eri_packed)):
+        ec = eri_packed.astype(complex)
+        ec[u] += 1j * H
+        eribar[u] = phi(fc0, layout.unpack_eri(ec, N, k), tc0)
+    return tbar, hbar, eribar
+
+
+def directional_vjp_blocks(N: int, k: int, f, eri_packed, t, lam_blocks: dict,
+                           energy_weight: float, dt, df, deri, keep_cache: bool = False) -> float:
+    """d/ds [sum_mu lam_mu R_mu + w E_c] along (dt, df, deri), where lam is
+    nonzero only on the slots of lam_blocks ({label tuple: {slot: value}}).
+    Evaluated at any N by the sub-cluster sums (one complex step)."""
+    from .tier_b import TierB
+    tb = TierB(N, k, f + 1j * H * df, eri_packed + 1j * H * deri)
+    tc = t + 1j * H * dt
+    total = energy_weight * tb.energy(tc)
+    for L, vals in lam_blocks.items():
+        R = tb.residual_block(L, tc)
+        total += sum(v * R[s] for s, v in vals.items())
+        if not keep_cache:
+            tb.clear()
+    return float(np.imag(total) / H)

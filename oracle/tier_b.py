@@ -46,7 +46,8 @@ class TierB:
         n = len(Y)
         orbs = list(Y) + [N + y for y in Y]
         f_sub = self.f[np.ix_(orbs, orbs)]
-        sub_eri = np.zeros(layout.eri_count(n, k))
+        dt = np.result_type(self.f, self.eri, t if t is not None else 0.0)
+        sub_eri = np.zeros(layout.eri_count(n, k), dtype=dt)
         for size in range(1, min(k, n) + 1):
             quads = layout.eri_quads(size)
             goff = layout.eri_block_offset(N, size)
@@ -60,7 +61,7 @@ class TierB:
                 for u in range(len(quads)):
                     sub_eri[loff + u * lsets + li] = self.eri[goff + u * gsets + gi]
         eri_sub = layout.unpack_eri(sub_eri, n, k)
-        t_sub = np.zeros(layout.amp_count(n, k))
+        t_sub = np.zeros(layout.amp_count(n, k), dtype=dt)
         gmap = np.zeros(layout.amp_count(n, k), dtype=np.int64)
         for pos, loc, tup in layout.iter_amp_slots(n, k):
             m = layout.pattern_tuples(len(loc)).index(tup)
@@ -92,11 +93,11 @@ class TierB:
         N, k = self.N, self.k
         others = [x for x in range(N) if x not in L]
         slots = [layout.amp_slot(N, L, m) for m in range(len(layout.pattern_tuples(len(L))))]
-        total = {s: 0.0 for s in slots}
+        total = {s: 0 for s in slots}
         for extra in range(0, k + 1):
             for add in itertools.combinations(others, extra):
                 # dR^{(X)} for X = L + add
-                d = {s: 0.0 for s in slots}
+                d = {s: 0 for s in slots}
                 for j in range(extra + 1):
                     for sub in itertools.combinations(add, j):
                         Y = tuple(sorted(L + sub))
@@ -122,7 +123,7 @@ class TierB:
 
     def residual(self, t):
         """The full packed residual (only for small N: every block is evaluated)."""
-        R = np.zeros(layout.amp_count(self.N, self.k))
+        R = np.zeros(layout.amp_count(self.N, self.k), dtype=np.result_type(self.f, self.eri, t))
         for size in range(1, self.k + 1):
             for L in itertools.combinations(range(self.N), size):
                 for s, v in self.residual_block(L, t).items():

@@ -15,8 +15,9 @@ import torch
 
 from . import _lib
 
-__all__ = ["pq_residual", "pq_energy", "pq_solve", "integrals", "denominators",
-           "amp_len", "eri_len", "SolveResult", "PQPHError"]
+__all__ = ["pq_residual", "pq_energy", "pq_solve", "pq_solve_batched", "pq_vjp",
+           "pq_energy_grad", "PQEnergy", "pq_energy_autograd", "integrals", "denominators",
+           "amp_len", "eri_len", "SolveResult", "GradResult", "BatchResult", "PQPHError"]
 
 PQPHError = _lib.PQPHError
 _ctx_cache: dict = {}
@@ -218,3 +219,88 @@ def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None,
         _check(lib, ctx, st)
     return SolveResult(t, e.value, info.iterations, info.rnorm, _lib.STATUS.get(st, str(st)),
                        info.solve_ms)
+
+
+def pq_vjp(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, lam: torch.Tensor,
+           energy_weight: float = 0.0, with_hamiltonian: bool = True):
+    """Transposed residual contraction (no host sync): returns (tbar, hbar,
+    eribar) with tbar = lam . dR/dt + w dE_c/dt and hbar, eribar the same
+    with respect to f and the packed integrals (None unless with_hamiltonian)."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na, ne = amp_len(npair), eri_len(npair)
+    tbar = torch.empty(na, dtype=torch.float64, device=h.device)
+    hbar = eribar = None
+    hp = ep = None
+    if with_hamiltonian:
+        hbar = torch.empty_like(h)
+        eribar = torch.empty(ne, dtype=torch.float64, device=h.device)
+        hp, ep = _dev(hbar, "hbar"), _dev(eribar, "eribar")
+    _check(lib, ctx, lib.pq_vjp(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),
+                                _dev(t, "t", na), _dev(lam, "lam", na), float(energy_weight),
+                                _dev(tbar, "tbar"), hp, ep))
+    return tbar, hbar, eribar
+
+
+@dataclass
+class GradResult:
+    energy: float
+    dE_dh: torch.Tensor        # 2N x 2N, f read as a general matrix
+    dE_deri: torch.Tensor      # packed integral layout
+    lam: torch.Tensor          # de-excitation amplitudes of the Lagrangian
+    iterations: int            # lambda iterations
+    rnorm: float
+    status: str
+    solve_ms: float
+
+
+def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
+                   tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
+                   level_shift: float = 0.0, diverge_factor: float = 1e4,
+                   raise_on_failure: bool = True) -> GradResult:
+    """PQ correlation energy and dE/dh, dE/d(packed eri) through the lambda
+    equations; t: converged amplitudes, or None to solve them here."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na, ne = amp_len(npair), eri_len(npair)
+    gh = torch.empty_like(h)
+    ge = torch.empty(ne, dtype=torch.float64, device=h.device)
+    lam = torch.empty(na, dtype=torch.float64, device=h.device)
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    info = _lib.SolveInfo()
+    e = C.c_double()
+    st = lib.pq_energy_grad(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),
+                            None if t is None else _dev(t, "t", na), C.byref(opts), C.byref(e),
+                            _dev(gh, "dE_dh"), _dev(ge, "dE_deri"), _dev(lam, "lambda"),
+                            C.byref(info))
+    if st != 0 and raise_on_failure:
+        _check(lib, ctx, st)
+    return GradResult(e.value, gh, ge, lam, info.iterations, info.rnorm,
+                      _lib.STATUS.get(st, str(st)), info.solve_ms)
+
+
+class PQEnergy(torch.autograd.Function):
+    """E_c(f, eri) of the converged PQ model as a differentiable function.
+
+    Forward solves the amplitudes; backward solves the lambda equations at
+    the saved amplitudes and returns grad_E * (dE/dh, dE/deri)."""
+
+    @staticmethod
+    def forward(ctx, h, eri, tol=1e-10, max_iter=200):
+        h = h.detach().contiguous()
+        eri = eri.detach().contiguous()
+        res = pq_solve(h, eri, tol=tol, max_iter=max_iter)
+        ctx.save_for_backward(h, eri, res.t)
+        ctx.tol, ctx.max_iter = tol, max_iter
+        return torch.tensor(res.energy, dtype=torch.float64, device=h.device)
+
+    @staticmethod
+    def backward(ctx, gE):
+        h, eri, t = ctx.saved_tensors
+        g = pq_energy_grad(h, eri, t, tol=ctx.tol, max_iter=ctx.max_iter)
+        return gE * g.dE_dh, gE * g.dE_deri, None, None
+
+
+def pq_energy_autograd(h: torch.Tensor, eri: torch.Tensor, tol: float = 1e-10,
+                       max_iter: int = 200) -> torch.Tensor:
+    return PQEnergy.apply(h, eri, tol, max_iter)

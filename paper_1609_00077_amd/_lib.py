@@ -48,6 +48,9 @@ SIGNATURES = {
     "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
     "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
     "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
+    "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),
+    "pq_energy_grad": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),
+                                 P, P, P, C.POINTER(SolveInfo)]),
     "pq_solve_batched": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P,
                                    C.POINTER(SolveOpts), P, C.POINTER(C.c_double),

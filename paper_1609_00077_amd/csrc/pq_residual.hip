@@ -82,7 +82,8 @@ __device__ __forceinline__ void decode_pair(long ip, int& P, int& Q) {
 
 // ------------------------------------------------------------------ vertices
 __global__ void k_vertex1(int N, const double* __restrict__ f, const double* __restrict__ eri,
-                          double* __restrict__ h1) {
+                          double* __restrict__ h1, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     const int key = blockIdx.y;
     if (P >= N) return;
@@ -101,7 +102,8 @@ __global__ void k_vertex1(int N, const double* __restrict__ f, const double* __r
 }
 
 __global__ void k_vertex2(int N, const double* __restrict__ f, const double* __restrict__ eri,
-                          double* __restrict__ h2, double* __restrict__ h2T) {
+                          double* __restrict__ h2, double* __restrict__ h2T, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int Q = blockIdx.x * blockDim.x + threadIdx.x;
     const int P = blockIdx.y, key = blockIdx.z;
     if (Q >= N) return;
@@ -130,7 +132,8 @@ __global__ void k_vertex2(int N, const double* __restrict__ f, const double* __r
 }
 
 // ---------------------------------------------------------------- amplitudes
-__global__ void k_unpack_t2(int N, const double* __restrict__ t, double* __restrict__ t2) {
+__global__ void k_unpack_t2(int N, const double* __restrict__ t, double* __restrict__ t2, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int Q = blockIdx.x * blockDim.x + threadIdx.x;
     const int P = blockIdx.y, m = blockIdx.z;
     if (Q >= N) return;
@@ -152,7 +155,8 @@ __device__ __forceinline__ const int* spec_fac(int which) {
     return which == 0 ? pq_x_fac : (which == 1 ? pq_y_fac : (which == 2 ? pq_w_fac : pq_l_fac));
 }
 
-__global__ void k_spec(int N, int which, View v, double* __restrict__ out) {
+__global__ void k_spec(int N, int which, View v, double* __restrict__ out, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
     const int L0 = blockIdx.y, s = blockIdx.z;
     if (L1 >= N) return;
@@ -205,7 +209,8 @@ constexpr int GP = 16;   // (x, y) pairs per workgroup
 // (upper-triangular 16x16 tiles of (P, Q), chunks of GP pairs p).
 __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
-                                                 double* __restrict__ ST) {
+                                                 double* __restrict__ ST, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int nt = (N + GT - 1) / GT;
     int tP = 0, rem = blockIdx.x;
     while (rem >= nt - tP) { rem -= nt - tP; ++tP; }
@@ -249,7 +254,8 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
 // ----------------------------------------------------------- one-pair outputs
 // grid (N, nch): workgroup (P, ch) sums the chunk ch of the ordered spectator
 // pairs (A, B); chunk 0 also takes the no- and one-spectator terms.
-__global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int P = blockIdx.x, ch = blockIdx.y;
     const int tid = threadIdx.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -311,7 +317,8 @@ constexpr int M2_KC = 16;
 
 template <int NCB>
 __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __restrict__ W,
-                                              int gchunk, double* __restrict__ part) {
+                                              int gchunk, double* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     constexpr int NC = 16 * NCB;
     extern __shared__ double sm[];
     double* La = sm;                       // [M2_ROWS][M2_KC]
@@ -406,7 +413,8 @@ __global__ __launch_bounds__(256) void k_r2s2(int N, View v, const double* __res
 // two barriers (L_a fill, then the MFMA sweep over all A).
 template <int NCB>
 __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __restrict__ W,
-                                               int gchunk, double* __restrict__ part) {
+                                               int gchunk, double* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     constexpr int NC = 16 * NCB;
     const int KP = (N + 3) / 4 * 4;
     extern __shared__ double sm[];
@@ -508,7 +516,8 @@ __global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
                                             const double* __restrict__ h1,
                                             const double* __restrict__ h2T,
                                             const double* __restrict__ ST,
-                                            double* __restrict__ p2) {
+                                            double* __restrict__ p2, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     extern __shared__ double sm[];
     double* loc = sm;                               // [R2L_PPW][PQ_LOC_N]
     double* part = sm + R2L_PPW * PQ_LOC_N;         // [PQ_LOC_NCHUNK][R2L_PPW]
@@ -568,7 +577,8 @@ __global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
 // packed r from the partial sums, in a fixed order (deterministic)
 __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
                         const double* __restrict__ p2, const double* __restrict__ ps2, int nchunk,
-                        double* __restrict__ R) {
+                        double* __restrict__ R, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
     const long np2 = (long)N * (N - 1) / 2;
     const long n1 = 3L * N;
     const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -643,6 +653,399 @@ __global__ void k_denom(int N, const double* __restrict__ f, double shift, doubl
     D[s] = d + shift;
 }
 
+
+// =================================================================== adjoint
+// Reverse mode of every kernel above: given weights lam on the residual
+// outputs (and ew on the energy), accumulate
+//   tbar = sum_mu lam_mu dR_mu/dt + ew dE/dt,   and optionally the same for
+//   the Hamiltonian vertices, pulled back to f and the packed integrals.
+// This is the transposed-residual contraction of the Lagrangian
+// L = E + lam . R (Sec. II: lambda truncated like t; Table IV caption).
+// Accumulation uses FP64 atomics (order-dependent in the last bits only).
+struct AdjView {
+    double* tb1;   // [3][N]
+    double* tb2;   // [29][N][N]
+    double* hb1;   // [PQ_H1_N][N]
+    double* hb2;   // [PQ_H2_N][N][N]
+    int N;
+    long NN;
+};
+
+__device__ __forceinline__ void fadj(int code, int L0, int L1, int L2, int L3, const AdjView& a,
+                                     double d) {
+    const int kind = (code >> 28) & 15;
+    const int x = labr((code >> 24) & 15, L0, L1, L2, L3);
+    const int y = labr((code >> 20) & 15, L0, L1, L2, L3);
+    const long idx = code & 0xFFFF;
+    switch (kind) {
+        case 1: atomicAdd(&a.tb1[idx * a.N + x], d); break;
+        case 2: atomicAdd(&a.tb2[idx * a.NN + (long)x * a.N + y], d); break;
+        case 3: atomicAdd(&a.hb1[idx * a.N + x], d); break;
+        case 4: atomicAdd(&a.hb2[idx * a.NN + (long)x * a.N + y], d); break;
+        default: break;
+    }
+}
+
+// adjoint of one interpreted term: d(term)/d(factor k) * w for every factor
+__device__ __forceinline__ void term_adj(const int* f, double w, int L0, int L1, int L2, int L3,
+                                         const View& v, const AdjView& a) {
+    double fv[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) fv[j] = f[j] ? fval(f[j], L0, L1, L2, L3, v) : 1.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (!f[k]) continue;
+        double d = w;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (j != k) d *= fv[j];
+        if (d != 0.0) fadj(f[k], L0, L1, L2, L3, a, d);
+    }
+}
+
+__device__ __forceinline__ void class_adj(const int* start, const double* coef, const int* fac, int m,
+                                          double w, int L0, int L1, int L2, int L3, const View& v,
+                                          const AdjView& a) {
+    if (w == 0.0) return;
+    for (int i = start[m]; i < start[m + 1]; ++i) term_adj(fac + 5 * i, w * coef[i], L0, L1, L2, L3, v, a);
+}
+
+// one-pair outputs: weights lam1[k][P]
+__global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __restrict__ lam, int nch,
+                                                AdjView a) {
+    const int P = blockIdx.x, ch = blockIdx.y, tid = threadIdx.x;
+    const double l0 = lam[P], l1 = lam[N + P], l2 = lam[2 * N + P];
+    if (ch == 0) {
+        if (tid == 0) {
+            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, l0, P, 0, 0, 0, v, a);
+            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, l1, P, 0, 0, 0, v, a);
+            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, l2, P, 0, 0, 0, v, a);
+        }
+        for (int A = tid; A < N; A += blockDim.x) {
+            if (A == P) continue;
+            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, l0, P, A, 0, 0, v, a);
+            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, l1, P, A, 0, 0, v, a);
+            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, l2, P, A, 0, 0, v, a);
+        }
+    }
+    const long NN = (long)N * N;
+    const long per = (NN + nch - 1) / nch;
+    const long lo = (long)ch * per, hi = min(NN, lo + per);
+    for (long ab = lo + tid; ab < hi; ab += blockDim.x) {
+        const int A = (int)(ab / N), B = (int)(ab % N);
+        if (A == P || B == P || A == B) continue;
+        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 0, 0.5 * l0, P, A, B, 0, v, a);
+        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 1, 0.5 * l1, P, A, B, 0, v, a);
+        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 2, 0.5 * l2, P, A, B, 0, v, a);
+    }
+}
+
+__global__ void k_energy_adj(int N, View v, double ew, AdjView a) {
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)N * N) return;
+    const int P = (int)(gid / N), Q = (int)(gid % N);
+    if (P == Q)
+        class_adj(pq_e1_start, pq_e1_coef, pq_e1_fac, 0, ew, P, 0, 0, 0, v, a);
+    else
+        class_adj(pq_e2_start, pq_e2_coef, pq_e2_fac, 0, 0.5 * ew, P, Q, 0, 0, v, a);
+}
+
+// pair-local adjoint of the no-spectator terms and the one-spectator epilogue
+constexpr int R2A_PPW = 2;
+
+__global__ __launch_bounds__(256) void k_r2_adj(int N, const double* __restrict__ t,
+                                                const double* __restrict__ h1,
+                                                const double* __restrict__ h2T,
+                                                const double* __restrict__ ST,
+                                                const double* __restrict__ lam, AdjView a,
+                                                double* __restrict__ Sb) {
+    extern __shared__ double sm[];
+    double* loc = sm;                                  // [R2A_PPW][PQ_LOC_N]
+    double* locb = sm + R2A_PPW * PQ_LOC_N;            // [R2A_PPW][PQ_LOC_N]
+    double* laml = locb + R2A_PPW * PQ_LOC_N;          // [R2A_PPW][29]
+    const long np2 = (long)N * (N - 1) / 2;
+    const long ip0 = (long)blockIdx.x * R2A_PPW;
+    const int tid = threadIdx.x;
+    int PP[R2A_PPW], QQ[R2A_PPW];
+    for (int p = 0; p < R2A_PPW; ++p) {
+        const long ip = ip0 + p;
+        const bool ok = ip < np2;
+        int P = 0, Q = 1;
+        if (ok) decode_pair(ip, P, Q);
+        PP[p] = ok ? P : -1;
+        QQ[p] = Q;
+        double* L = loc + p * PQ_LOC_N;
+        for (int i = tid; i < PQ_LOC_N; i += blockDim.x) {
+            double val = 0.0;
+            if (i == PQ_LOC_ONE)
+                val = 1.0;
+            else if (ok) {
+                if (i < PQ_LOC_T1Q) val = t[(long)(i - PQ_LOC_T1P) * N + P];
+                else if (i < PQ_LOC_T2) val = t[(long)(i - PQ_LOC_T1Q) * N + Q];
+                else if (i < PQ_LOC_H1P) val = t[3L * N + (long)(i - PQ_LOC_T2) * np2 + ip];
+                else if (i < PQ_LOC_H1Q) val = h1[(long)(i - PQ_LOC_H1P) * N + P];
+                else if (i < PQ_LOC_H2) val = h1[(long)(i - PQ_LOC_H1Q) * N + Q];
+                else if (i < PQ_LOC_S) val = h2T[ip * PQ_H2_N + (i - PQ_LOC_H2)];
+                else val = ST[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)];
+            }
+            L[i] = val;
+            locb[p * PQ_LOC_N + i] = 0.0;
+        }
+        if (tid < NP2) laml[p * NP2 + tid] = ok ? lam[3L * N + (long)tid * np2 + ip] : 0.0;
+    }
+    __syncthreads();
+    for (int c = tid; c < PQ_LOC_NCHUNK; c += blockDim.x) {
+        const int m = pq_loc_ch_m[c];
+        const int hi = pq_loc_ch_hi[c];
+        for (int i = pq_loc_ch_lo[c]; i < hi; ++i) {
+            const double cf = pq_loc_coef[i];
+            const unsigned short* ix = pq_loc_idx + 5 * i;
+#pragma unroll
+            for (int p = 0; p < R2A_PPW; ++p) {
+                const double w = cf * laml[p * NP2 + m];
+                if (w == 0.0) continue;
+                const double* L = loc + p * PQ_LOC_N;
+                double fv[5];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) fv[j] = L[ix[j]];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    if (ix[k] == PQ_LOC_ONE) continue;
+                    double d = w;
+#pragma unroll
+                    for (int j = 0; j < 5; ++j)
+                        if (j != k) d *= fv[j];
+                    atomicAdd(&locb[p * PQ_LOC_N + ix[k]], d);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < R2A_PPW; ++p) {
+        const int P = PP[p], Q = QQ[p];
+        if (P < 0) continue;
+        const long ip = ip0 + p;
+        const double* Lb = locb + p * PQ_LOC_N;
+        for (int i = tid; i < PQ_LOC_ONE; i += blockDim.x) {
+            const double d = Lb[i];
+            if (i >= PQ_LOC_S) {
+                Sb[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)] = d;
+                continue;
+            }
+            if (d == 0.0) continue;
+            if (i < PQ_LOC_T1Q) atomicAdd(&a.tb1[(long)(i - PQ_LOC_T1P) * N + P], d);
+            else if (i < PQ_LOC_T2) atomicAdd(&a.tb1[(long)(i - PQ_LOC_T1Q) * N + Q], d);
+            else if (i < PQ_LOC_H1P) atomicAdd(&a.tb2[(long)(i - PQ_LOC_T2) * a.NN + (long)P * N + Q], d);
+            else if (i < PQ_LOC_H1Q) atomicAdd(&a.hb1[(long)(i - PQ_LOC_H1P) * N + P], d);
+            else if (i < PQ_LOC_H2) atomicAdd(&a.hb1[(long)(i - PQ_LOC_H1Q) * N + Q], d);
+            else atomicAdd(&a.hb2[(long)(i - PQ_LOC_H2) * a.NN + (long)P * N + Q], d);
+        }
+    }
+}
+
+// one-spectator GEMM adjoint: Xb_x(P,A) += sum_{Q>P} Sb_p(P,Q) Y_y(Q,A),
+//                             Yb_y(Q,A) += sum_{P<Q} Sb_p(P,Q) X_x(P,A)
+__global__ void k_gemm_s1_adj(int N, const double* __restrict__ X, const double* __restrict__ Y,
+                              const double* __restrict__ Sb, double* __restrict__ Xb,
+                              double* __restrict__ Yb) {
+    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    const int L = blockIdx.y, p = blockIdx.z;
+    if (A >= N || A == L) return;
+    const long NN = (long)N * N;
+    const int x = pq_s1pairs[2 * p], y = pq_s1pairs[2 * p + 1];
+    double s = 0.0;
+    for (int Q = L + 1; Q < N; ++Q)
+        s += Sb[((long)Q * (Q - 1) / 2 + L) * PQ_S1PAIRS_N + p] * Y[(long)y * NN + (long)Q * N + A];
+    if (s != 0.0) atomicAdd(&Xb[(long)x * NN + (long)L * N + A], s);
+    s = 0.0;
+    for (int P = 0; P < L; ++P)
+        s += Sb[((long)L * (L - 1) / 2 + P) * PQ_S1PAIRS_N + p] * X[(long)x * NN + (long)P * N + A];
+    if (s != 0.0) atomicAdd(&Yb[(long)y * NN + (long)L * N + A], s);
+}
+
+// adjoint of the factor products X, Y, W
+__global__ void k_spec_adj(int N, int which, View v, const double* __restrict__ sb, AdjView a) {
+    const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int L0 = blockIdx.y, s = blockIdx.z;
+    if (L1 >= N || L0 == L1) return;
+    const double d0 = sb[(long)s * v.NN + (long)L0 * N + L1];
+    if (d0 == 0.0) return;
+    const int* st = spec_start(which);
+    const int* fc = spec_fac(which);
+    const int b = st[s], n = st[s + 1] - st[s];
+    double fv[PQ_SPEC_MAXLEN];
+    for (int j = 0; j < n; ++j) fv[j] = fval(fc[b + j], L0, L1, 0, 0, v);
+    for (int k = 0; k < n; ++k) {
+        double d = d0;
+        for (int j = 0; j < n; ++j)
+            if (j != k) d *= fv[j];
+        fadj(fc[b + k], L0, L1, 0, 0, a, d);
+    }
+}
+
+// link adjoint: scatter dL * d(prod)/d(factor) into t2bar
+__device__ __forceinline__ void link_adj(int s, int P, int Q, int A, double dL, const View& v,
+                                         const AdjView& a) {
+    if (dL == 0.0) return;
+    const int n = pq_ld_n[s];
+    double fv[3];
+    int who[3], mm[3];
+    for (int f = 0; f < n; ++f) {
+        mm[f] = pq_ld_m[3 * s + f];
+        who[f] = pq_ld_q[3 * s + f] ? Q : P;
+        fv[f] = v.t2[(long)mm[f] * v.NN + (long)who[f] * v.N + A];
+    }
+    for (int k = 0; k < n; ++k) {
+        double d = dL;
+        for (int j = 0; j < n; ++j)
+            if (j != k) d *= fv[j];
+        atomicAdd(&a.tb2[(long)mm[k] * a.NN + (long)who[k] * a.N + A], d);
+    }
+}
+
+// two-spectator adjoint (VALU): per row (pair) and group (w, a) with its b list
+//   V = L_a W,  Vbar(B) = sum_b w_b L_b(B),  Lbar_b = w_b V,  Lbar_a = Vbar W^T,
+//   Wbar += L_a^T Vbar (rows of the workgroup summed, then one atomic per (A,B))
+constexpr int S2A_ROWS = 16;
+
+__global__ __launch_bounds__(256) void k_r2s2_adj(int N, View v, const double* __restrict__ W,
+                                                  const double* __restrict__ lam, int gchunk,
+                                                  AdjView a, double* __restrict__ Wb) {
+    extern __shared__ double sm[];
+    double* La = sm;                        // [S2A_ROWS][N]
+    double* Vb = La + S2A_ROWS * N;         // [S2A_ROWS][N]
+    __shared__ int rowP[S2A_ROWS], rowQ[S2A_ROWS];
+    __shared__ double lamr[S2A_ROWS][NP2];
+    const long np2 = (long)N * (N - 1) / 2;
+    const int tid = threadIdx.x, row = tid / 16, lane = tid % 16;
+    const long ip0 = (long)blockIdx.x * S2A_ROWS;
+    if (tid < S2A_ROWS) {
+        int P = -1, Q = -1;
+        if (ip0 + tid < np2) decode_pair(ip0 + tid, P, Q);
+        rowP[tid] = P;
+        rowQ[tid] = Q;
+    }
+    for (int i = tid; i < S2A_ROWS * NP2; i += 256) {
+        const int r = i / NP2, m = i % NP2;
+        lamr[r][m] = (ip0 + r < np2) ? lam[3L * N + (long)m * np2 + ip0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int P = rowP[row], Q = rowQ[row];
+    const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
+    for (int g = g0; g < g1; ++g) {
+        const int w = pq_g_w[g], sa = pq_g_a[g];
+        const double* Wg = W + (long)w * v.NN;
+        __syncthreads();
+        for (int A = lane; A < N; A += 16) {
+            double x = 0.0;
+            if (P >= 0 && A != P && A != Q) {
+                Link L;
+                link_rows(sa, P, Q, v, L);
+                x = link_at(L, A);
+            }
+            La[row * N + A] = x;
+        }
+        __syncthreads();
+        for (int B = lane; B < N; B += 16) {
+            double vb = 0.0;
+            if (P >= 0 && B != P && B != Q) {
+                double Vv = 0.0;
+                for (int A = 0; A < N; ++A) Vv += La[row * N + A] * Wg[(long)A * N + B];
+                for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
+                    const double wb = pq_g_coef[i] * lamr[row][pq_g_mu[i]];
+                    if (wb == 0.0) continue;
+                    Link L;
+                    link_rows(pq_g_b[i], P, Q, v, L);
+                    vb += wb * link_at(L, B);
+                    link_adj(pq_g_b[i], P, Q, B, wb * Vv, v, a);
+                }
+            }
+            Vb[row * N + B] = vb;
+        }
+        __syncthreads();
+        // Lbar_a(A) = sum_B Vb(B) W(A,B)
+        for (int A = lane; A < N; A += 16) {
+            if (P < 0 || A == P || A == Q) continue;
+            double s = 0.0;
+            for (int B = 0; B < N; ++B) s += Vb[row * N + B] * Wg[(long)A * N + B];
+            link_adj(sa, P, Q, A, s, v, a);
+        }
+        // Wbar(A,B) += sum_rows La(row,A) Vb(row,B)
+        for (long ab = tid; ab < (long)N * N; ab += 256) {
+            const int A = (int)(ab / N), B = (int)(ab % N);
+            if (A == B) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < S2A_ROWS; ++r) s += La[r * N + A] * Vb[r * N + B];
+            if (s != 0.0) atomicAdd(&Wb[(long)w * v.NN + ab], s);
+        }
+    }
+}
+
+// packed tbar from the adjoints of t1 and the mirrored t2
+__global__ void k_pack_tbar(int N, const double* __restrict__ tb1, const double* __restrict__ tb2,
+                            double* __restrict__ tbar) {
+    const long np2 = (long)N * (N - 1) / 2;
+    const long n1 = 3L * N;
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n1 + NP2 * np2) return;
+    if (s < n1) {
+        tbar[s] = tb1[s];
+        return;
+    }
+    const int m = (int)((s - n1) / np2);
+    int X, Y;
+    decode_pair((s - n1) % np2, X, Y);
+    const long NN = (long)N * N;
+    tbar[s] = tb2[(long)m * NN + (long)X * N + Y] +
+              pq_swap2_sign[m] * tb2[(long)pq_swap2[m] * NN + (long)Y * N + X];
+}
+
+// pull the vertex adjoints back to f (general matrix) and the packed integrals
+__global__ void k_vertex1_adj(int N, const double* __restrict__ hb1, double* __restrict__ fb,
+                              double* __restrict__ erib) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    const int key = blockIdx.y;
+    if (P >= N) return;
+    const double d = hb1[(long)key * N + P];
+    if (d == 0.0) return;
+    const long n2 = 2L * N;
+    for (int i = pq_h1_start[key]; i < pq_h1_start[key + 1]; ++i) {
+        const double w = pq_h1_w[i] * d;
+        if (pq_h1_kind[i] == 0) {
+            const int p = P + N * (pq_h1_a[i] & 1), q = P + N * (pq_h1_b[i] & 1);
+            atomicAdd(&fb[p * n2 + q], w);
+        } else {
+            atomicAdd(&erib[(long)pq_h1_a[i] * N + P], w);
+        }
+    }
+}
+
+__global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __restrict__ fb,
+                              double* __restrict__ erib) {
+    const int Q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = blockIdx.y, key = blockIdx.z;
+    if (Q >= N || P == Q) return;
+    const long NN = (long)N * N, n2 = 2L * N;
+    const double d = hb2[(long)key * NN + (long)P * N + Q];
+    if (d == 0.0) return;
+    const long np2 = (long)N * (N - 1) / 2;
+    const int lo = min(P, Q), hi = max(P, Q);
+    const long pidx = (long)hi * (hi - 1) / 2 + lo;
+    for (int i = pq_h2_start[key]; i < pq_h2_start[key + 1]; ++i) {
+        const double w = pq_h2_w[i] * d;
+        if (pq_h2_kind[i] == 0) {
+            const int a2 = pq_h2_a[i], b2 = pq_h2_b[i];
+            const int p = ((a2 >> 1) ? Q : P) + N * (a2 & 1);
+            const int q = ((b2 >> 1) ? Q : P) + N * (b2 & 1);
+            atomicAdd(&fb[p * n2 + q], w);
+        } else {
+            const int u = P < Q ? pq_h2_a[i] : pq_h2_b[i];
+            atomicAdd(&erib[6L * N + (long)u * np2 + pidx], w);
+        }
+    }
+}
+
 struct Carve {
     double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *part, *p1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1;
@@ -709,15 +1112,16 @@ View make_view(const double* t, const Carve& c, int N) {
 }
 
 pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
-                    const double* t, const Carve& c) {
+                    const double* t, const Carve& c, const int* gate) {
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
-    hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1);
+    hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1, gate);
     pqph_mark(ctx);
     if (N > 1) {
-        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2, c.h2T);
+        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2, c.h2T,
+                           gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2);
+        hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2, gate);
         pqph_mark(ctx);
     }
     PQPH_HIP(ctx, hipGetLastError());
@@ -729,24 +1133,25 @@ pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const 
 size_t pq_ws_doubles(int npair) { return carve_size(npair); }
 
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
-                           const double* eri, const double* t, double* r, double* ws) {
+                           const double* eri, const double* t, double* r, double* ws,
+                           const int* gate) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, s, N, h, eri, t, c);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate);
     if (st) return st;
     View v = make_view(t, c, N);
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     if (N > 1) {
         const long np2 = (long)N * (N - 1) / 2;
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, gate);
         pqph_mark(ctx);
         const int nt = (N + GT - 1) / GT;
         hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
-                           dim3(256), 0, s, N, c.X, c.Y, c.S);
+                           dim3(256), 0, s, N, c.X, c.Y, c.S, gate);
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
@@ -767,7 +1172,8 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +             \
                                                        hipGetErrorString(e_));                  \
         }                                                                                       \
-        hipLaunchKernelGGL(k_r2s2w<NB>, g2, dim3(256), bytes, s, N, v, c.W, c.gchunk, c.part);  \
+        hipLaunchKernelGGL(k_r2s2w<NB>, g2, dim3(256), bytes, s, N, v, c.W, c.gchunk, c.part,  \
+                           gate);                                                       \
     } while (0)
             if (ncb <= 1) PQ_S2W_LAUNCH(1);
             else if (ncb <= 2) PQ_S2W_LAUNCH(2);
@@ -781,7 +1187,8 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_ + M2_ROWS * NP2) * sizeof(double);
             };
 #define PQ_S2_LAUNCH(NB)                                                                       \
-    hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s, N, v, c.W, c.gchunk, c.part)
+    hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s, N, v, c.W, c.gchunk, c.part, \
+                       gate)
             if (ncb <= 1) PQ_S2_LAUNCH(1);
             else if (ncb <= 2) PQ_S2_LAUNCH(2);
             else if (ncb <= 3) PQ_S2_LAUNCH(3);
@@ -808,16 +1215,16 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 attr = true;
             }
             hipLaunchKernelGGL(k_r2, dim3((unsigned)((np2 + R2L_PPW - 1) / R2L_PPW)), dim3(256), bytes,
-                               s, N, t, c.h1, c.h2T, c.S, c.p2);
+                               s, N, t, c.h1, c.h2T, c.S, c.p2, gate);
         }
         pqph_mark(ctx);
     }
-    hipLaunchKernelGGL(k_r1, dim3(N, c.nch1), dim3(256), 0, s, N, v, c.nch1, c.p1);
+    hipLaunchKernelGGL(k_r1, dim3(N, c.nch1), dim3(256), 0, s, N, v, c.nch1, c.p1, gate);
     pqph_mark(ctx);
     {
         const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
         hipLaunchKernelGGL(k_final, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N, c.p1,
-                           c.nch1, c.p2, c.part, N > 1 ? c.nchunk : 0, r);
+                           c.nch1, c.p2, c.part, N > 1 ? c.nchunk : 0, r, gate);
     }
 
     pqph_mark(ctx);
@@ -828,7 +1235,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
 pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                          const double* eri, const double* t, double* dst, double* ws) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, s, N, h, eri, t, c);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
     if (st) return st;
     View v = make_view(t, c, N);
     hipLaunchKernelGGL(k_energy, dim3(c.nblkE), dim3(256), 0, s, N, v, c.epart);
@@ -842,6 +1249,96 @@ pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const doubl
     const long n = (long)pq_amp_len(N);
     hipLaunchKernelGGL(k_denom, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N,
                        h, shift, D);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
+
+// ------------------------------------------------------------------ adjoint
+size_t pq_adj_doubles(int N) {
+    const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
+    return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_W_N) * NN + (size_t)PQ_S1PAIRS_N * np2 + 8;
+}
+
+pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
+                      const double* t, const double* lam, double ew, double* tbar, double* hbar,
+                      double* eribar, double* ws, double* aws) {
+    Carve c = carve(ws, N);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
+    if (st) return st;
+    View v = make_view(t, c, N);
+    const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
+    AdjView a;
+    a.N = N;
+    a.NN = (long)NN;
+    double* p = aws;
+    a.tb1 = p; p += 3 * (size_t)N;
+    a.tb2 = p; p += NP2 * NN;
+    a.hb1 = p; p += (size_t)PQ_H1_N * N;
+    a.hb2 = p; p += (size_t)PQ_H2_N * NN;
+    double* Xb = p; p += (size_t)PQ_X_N * NN;
+    double* Yb = p; p += (size_t)PQ_Y_N * NN;
+    double* Wb = p; p += (size_t)PQ_W_N * NN;
+    double* Sb = p;
+    const size_t nzero = (size_t)(Sb - aws);
+    PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
+    const int tb = 64, gx = (N + tb - 1) / tb;
+    if (N > 1) {
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, nullptr);
+        const int nt = (N + GT - 1) / GT;
+        hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
+                           dim3(256), 0, s, N, c.X, c.Y, c.S, nullptr);
+        {
+            const size_t bytes =
+                (size_t)(2 * R2A_PPW * PQ_LOC_N + R2A_PPW * NP2) * sizeof(double);
+            static bool attr = false;
+            if (!attr) {
+                hipError_t e_ = hipFuncSetAttribute((const void*)&k_r2_adj,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)bytes);
+                if (e_ != hipSuccess)
+                    return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +
+                                                           hipGetErrorString(e_));
+                attr = true;
+            }
+            hipLaunchKernelGGL(k_r2_adj, dim3((unsigned)((np2 + R2A_PPW - 1) / R2A_PPW)), dim3(256),
+                               bytes, s, N, t, c.h1, c.h2T, c.S, lam, a, Sb);
+        }
+        {
+            const int rt = (int)((np2 + S2A_ROWS - 1) / S2A_ROWS);
+            const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt, 1)));
+            const int gchunk = (PQ_G_N + nchunk - 1) / nchunk;
+            const size_t bytes = (size_t)(2 * S2A_ROWS * N) * sizeof(double);
+            hipLaunchKernelGGL(k_r2s2_adj, dim3(rt, (PQ_G_N + gchunk - 1) / gchunk), dim3(256), bytes,
+                               s, N, v, c.W, lam, gchunk, a, Wb);
+        }
+        hipLaunchKernelGGL(k_gemm_s1_adj, dim3(gx, N, PQ_S1PAIRS_N), dim3(tb), 0, s, N, c.X, c.Y, Sb,
+                           Xb, Yb);
+        hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, Xb, a);
+        hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, Yb, a);
+        hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, Wb, a);
+    }
+    hipLaunchKernelGGL(k_r1_adj, dim3(N, c.nch1), dim3(256), 0, s, N, v, lam, c.nch1, a);
+    if (ew != 0.0)
+        hipLaunchKernelGGL(k_energy_adj, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, N, v, ew,
+                           a);
+    {
+        const long ntot = 3L * N + (long)NP2 * (long)np2;
+        hipLaunchKernelGGL(k_pack_tbar, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N,
+                           a.tb1, a.tb2, tbar);
+    }
+    if (hbar || eribar) {
+        if (!hbar || !eribar) return pqph_fail(ctx, PQPH_INVALID_ARG, "hbar and eribar go together");
+        PQPH_HIP(ctx, hipMemsetAsync(hbar, 0, 4 * NN * sizeof(double), s));
+        PQPH_HIP(ctx, hipMemsetAsync(eribar, 0, pq_eri_len(N) * sizeof(double), s));
+        hipLaunchKernelGGL(k_vertex1_adj, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, a.hb1, hbar, eribar);
+        if (N > 1)
+            hipLaunchKernelGGL(k_vertex2_adj, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, a.hb2, hbar,
+                               eribar);
+    }
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
 }

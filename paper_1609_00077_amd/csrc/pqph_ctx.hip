@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 namespace {
@@ -268,58 +269,39 @@ pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, 
     return pq_denominators_dev(ctx, ctx->stream, npair, h, shift, D);
 }
 
-pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* eri,
-                     const pqph_solve_opts* opts_in, double* t, double* energy,
-                     pqph_solve_info* info) {
-    pqph_status st = check_pq(ctx, npair);
-    if (st) return st;
-    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
-    pqph_solve_opts o;
-    pqph_default_opts(&o);
-    if (opts_in) o = *opts_in;
-    if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0))
-        return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
-    const size_t n = pq_amp_len(npair);
+}  // extern "C"
+
+// ------------------------------------------------------ Jacobi/DIIS driver
+// x <- x - r/D with DIIS on the last m iterates (Sec. III; Table IV), where
+// resid(x, r) enqueues r = F(x) on the context stream.  bufs holds
+// n*(3 + 2m) + nblk*(m+1) + 64 doubles.  Host syncs: two per iteration.
+namespace {
+size_t driver_doubles(size_t n, int m) {
+    return n * (3 + 2 * (size_t)m) + (size_t)stream_blocks(n) * (m + 1) + 64;
+}
+
+pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
+                        const pqph_solve_opts& o,
+                        const std::function<pqph_status(const double*, double*)>& resid,
+                        double* bufs, int& iters, double& rn, pqph_status& result) {
     const int m = std::max(o.diis_dim, 1);
     const int nblk = stream_blocks(n);
-    // solver buffers: D, r, e, tn, t-history (m), e-history (m), partials, scalars
-    const size_t svd = n * (4 + 2 * (size_t)m) + (size_t)nblk * (m + 1) + 64;
-    st = pqph_ensure_sv(ctx, svd * sizeof(double));
-    if (st) return st;
-    const size_t wsd = pq_ws_doubles(npair);
-    st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double));
-    if (st) return st;
-    st = pqph_ensure_host(ctx, 64);
-    if (st) return st;
-    double* D = ctx->sv;
-    double* r = D + n;
+    double* r = bufs;
     double* e = r + n;
-    double* tn = e + n;
-    double* th = tn + n;
-    double* eh = th + (size_t)m * n;
+    double* xn = e + n;
+    double* xh = xn + n;
+    double* eh = xh + (size_t)m * n;
     double* part = eh + (size_t)m * n;
     double* scal = part + (size_t)nblk * (m + 1);
     double* hst = ctx->host;
     hipStream_t s = ctx->stream;
-    PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
-    st = pq_denominators_dev(ctx, ctx->stream, npair, h, o.level_shift, D);
-    if (st) return st;
-    // the denominators must not vanish
-    {
-        std::vector<double> Dh(n);
-        PQPH_HIP(ctx, hipMemcpyAsync(Dh.data(), D, n * sizeof(double), hipMemcpyDeviceToHost, s));
-        PQPH_HIP(ctx, hipStreamSynchronize(s));
-        for (size_t i = 0; i < n; ++i)
-            if (!(std::fabs(Dh[i]) > 1e-12))
-                return pqph_fail(ctx, PQPH_INVALID_ARG, "vanishing orbital-energy denominator");
-    }
     std::vector<double> B(16 * 16, 0.0), c;
     int stored = 0, next = 0, it = 0;
-    double rn = INFINITY, rmin = INFINITY;
-    pqph_status result = PQPH_NOT_CONVERGED;
+    double rmin = INFINITY;
+    rn = INFINITY;
+    result = PQPH_NOT_CONVERGED;
     for (it = 1; it <= o.max_iter; ++it) {
-        st = pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
+        pqph_status st = resid(x, r);
         if (st) return st;
         launch_norm2(s, r, n, part, nblk, scal);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -341,19 +323,18 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
             break;
         }
         if (it == o.max_iter) break;
-        launch_jacobi(s, t, r, D, n, tn, e);
+        launch_jacobi(s, x, r, D, n, xn, e);
         if (o.diis_dim == 0) {
-            PQPH_HIP(ctx, hipMemcpyAsync(t, tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            PQPH_HIP(ctx, hipMemcpyAsync(x, xn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             continue;
         }
         const int slot = next;
         next = (next + 1) % m;
         stored = std::min(stored + 1, m);
-        PQPH_HIP(ctx, hipMemcpyAsync(th + (size_t)slot * n, tn, n * sizeof(double),
+        PQPH_HIP(ctx, hipMemcpyAsync(xh + (size_t)slot * n, xn, n * sizeof(double),
                                      hipMemcpyDeviceToDevice, s));
         PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
                                      hipMemcpyDeviceToDevice, s));
-        // Gram row of the new error vector against every stored one
         launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, m * sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
@@ -361,41 +342,84 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
             B[(size_t)slot * 16 + j] = hst[j];
             B[(size_t)j * 16 + slot] = hst[j];
         }
-        bool use = (it >= o.diis_start) && stored >= 2;
-        if (use) {
-            // compact the stored slots into a dense system
-            std::vector<int> slots;
-            for (int j = 0; j < m; ++j)
-                if (j < stored) slots.push_back(j);
-            const int ms = (int)slots.size();
+        if (it >= o.diis_start && stored >= 2) {
             std::vector<double> Bs(16 * 16, 0.0);
-            for (int a = 0; a < ms; ++a)
-                for (int b = 0; b < ms; ++b) Bs[(size_t)a * 16 + b] = B[(size_t)slots[a] * 16 + slots[b]];
-            if (diis_solve(Bs, ms, c)) {
-                std::vector<double> cm(m, 0.0);
-                for (int a = 0; a < ms; ++a) cm[slots[a]] = c[a];
-                for (int j = 0; j < m; ++j) hst[8 + j] = cm[j];
+            for (int a = 0; a < stored; ++a)
+                for (int b = 0; b < stored; ++b) Bs[(size_t)a * 16 + b] = B[(size_t)a * 16 + b];
+            if (diis_solve(Bs, stored, c)) {
+                for (int j = 0; j < m; ++j) hst[8 + j] = j < stored ? c[j] : 0.0;
                 PQPH_HIP(ctx, hipMemcpyAsync(scal + 16, hst + 8, m * sizeof(double),
                                              hipMemcpyHostToDevice, s));
-                launch_combine(s, th, scal + 16, m, n, t);
-                // keep the pinned staging alive until the copy has run
-                PQPH_HIP(ctx, hipStreamSynchronize(s));
+                launch_combine(s, xh, scal + 16, m, n, x);
+                PQPH_HIP(ctx, hipStreamSynchronize(s));   // pinned staging reused next iteration
                 continue;
             }
         }
-        PQPH_HIP(ctx, hipMemcpyAsync(t, tn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        PQPH_HIP(ctx, hipMemcpyAsync(x, xn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+    iters = std::min(it, o.max_iter);
     if (result == PQPH_NOT_CONVERGED)
         pqph_fail(ctx, result, "not converged in " + std::to_string(o.max_iter) + " iterations");
-    double* edst = ctx->ws + wsd;
-    st = pq_energy_ws(ctx, ctx->stream, npair, h, eri, t, edst, ctx->ws);
+    return PQPH_OK;
+}
+
+pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts& o) {
+    pqph_default_opts(&o);
+    if (in) o = *in;
+    if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
+        !(o.diverge_factor > 1.0))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
+    return PQPH_OK;
+}
+
+pqph_status check_denominators(pqph_ctx* ctx, const double* D, size_t n, double* part) {
+    launch_absmin(ctx->stream, D, n, part, stream_blocks(n), part + stream_blocks(n));
+    PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, part + stream_blocks(n), sizeof(double),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (!(ctx->host[0] > 1e-12))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "vanishing orbital-energy denominator");
+    return PQPH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                     const pqph_solve_opts* opts_in, double* t, double* energy,
+                     pqph_solve_info* info) {
+    pqph_status st = check_pq(ctx, npair);
     if (st) return st;
-    PQPH_HIP(ctx, hipMemcpyAsync(hst, edst, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    pqph_solve_opts o;
+    if ((st = read_opts(ctx, opts_in, o))) return st;
+    const size_t n = pq_amp_len(npair);
+    const int m = std::max(o.diis_dim, 1);
+    if ((st = pqph_ensure_sv(ctx, (n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    const size_t wsd = pq_ws_doubles(npair);
+    if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_host(ctx, 64))) return st;
+    double* D = ctx->sv;
+    double* bufs = D + n;
+    hipStream_t s = ctx->stream;
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    if ((st = pq_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
+    if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    int iters = 0;
+    double rn = 0.0;
+    pqph_status result = PQPH_OK;
+    auto resid = [&](const double* x, double* r) {
+        return pq_residual_ws(ctx, s, npair, h, eri, x, r, ctx->ws);
+    };
+    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
+    double* edst = ctx->ws + wsd;
+    if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
     PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));
     PQPH_HIP(ctx, hipStreamSynchronize(s));
-    *energy = hst[0];
+    *energy = ctx->host[0];
     if (info) {
-        info->iterations = std::min(it, o.max_iter);
+        info->iterations = iters;
         info->rnorm = rn;
         info->status = result;
         float ms = 0.f;
@@ -408,5 +432,88 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     }
     return result;
 }
+
+pqph_status pq_vjp(pqph_ctx* ctx, int npair, const double* h, const double* eri, const double* t,
+                   const double* lam, double energy_weight, double* tbar, double* hbar,
+                   double* eribar) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !lam || !tbar) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    if ((hbar == nullptr) != (eribar == nullptr))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "hbar and eribar must both be given or both NULL");
+    const size_t wsd = pq_ws_doubles(npair), ad = pq_adj_doubles(npair);
+    if ((st = pqph_ensure_ws(ctx, (wsd + ad) * sizeof(double)))) return st;
+    return pq_vjp_ws(ctx, ctx->stream, npair, h, eri, t, lam, energy_weight, tbar, hbar, eribar,
+                     ctx->ws, ctx->ws + wsd);
+}
+
+pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                           const double* t_in, const pqph_solve_opts* opts_in, double* energy,
+                           double* dE_dh, double* dE_deri, double* lambda_out,
+                           pqph_solve_info* info) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !energy || !dE_dh || !dE_deri)
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    pqph_solve_opts o;
+    if ((st = read_opts(ctx, opts_in, o))) return st;
+    const size_t n = pq_amp_len(npair);
+    const int m = std::max(o.diis_dim, 1);
+    // solver memory: D, t (when solved here), lambda, tbar scratch, driver buffers
+    if ((st = pqph_ensure_sv(ctx, (4 * n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    const size_t wsd = pq_ws_doubles(npair), ad = pq_adj_doubles(npair);
+    if ((st = pqph_ensure_ws(ctx, (wsd + ad + 8) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_host(ctx, 64))) return st;
+    double* D = ctx->sv;
+    double* tl = D + n;
+    double* lam = tl + n;
+    double* tbar = lam + n;
+    double* bufs = tbar + n;
+    double* aws = ctx->ws + wsd;
+    hipStream_t s = ctx->stream;
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    if ((st = pq_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
+    if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    int iters = 0;
+    double rn = 0.0;
+    pqph_status result = PQPH_OK;
+    const double* t = t_in;
+    if (!t) {
+        PQPH_HIP(ctx, hipMemsetAsync(tl, 0, n * sizeof(double), s));
+        auto resid = [&](const double* x, double* r) {
+            return pq_residual_ws(ctx, s, npair, h, eri, x, r, ctx->ws);
+        };
+        if ((st = jacobi_diis(ctx, n, D, tl, o, resid, bufs, iters, rn, result))) return st;
+        if (result != PQPH_OK) return result;
+        t = tl;
+    }
+    double* edst = aws + ad;
+    if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(ctx->host + 32, edst, sizeof(double), hipMemcpyDeviceToHost, s));
+    PQPH_HIP(ctx, hipStreamSynchronize(s));
+    *energy = ctx->host[32];
+    // lambda equations: J^T lambda + dE/dt = 0, solved like the amplitudes
+    PQPH_HIP(ctx, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+    auto lres = [&](const double* x, double* r) {
+        return pq_vjp_ws(ctx, s, npair, h, eri, t, x, 1.0, r, nullptr, nullptr, ctx->ws, aws);
+    };
+    if ((st = jacobi_diis(ctx, n, D, lam, o, lres, bufs, iters, rn, result))) return st;
+    if ((st = pq_vjp_ws(ctx, s, npair, h, eri, t, lam, 1.0, tbar, dE_dh, dE_deri, ctx->ws, aws)))
+        return st;
+    if (lambda_out)
+        PQPH_HIP(ctx, hipMemcpyAsync(lambda_out, lam, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));
+    PQPH_HIP(ctx, hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->rnorm = rn;
+        info->status = result;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        info->solve_ms = ms;
+    }
+    return result;
+}
+
 
 }  // extern "C"

@@ -60,13 +60,23 @@ pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n);
 // PQ residual pieces (pq_residual.hip) --------------------------------------
 size_t pq_ws_doubles(int npair);
 // residual into r on stream s using workspace ws (already large enough); no host sync
+// gate: device flag; when it reads 0 every kernel returns at once (NULL: always run)
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
-                           const double* eri, const double* t, double* r, double* ws);
+                           const double* eri, const double* t, double* r, double* ws,
+                           const int* gate = nullptr);
 // energy: writes one double to dst (device) on stream s, no sync
 pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                          const double* eri, const double* t, double* dst, double* ws);
 pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                                 double shift, double* D);
+
+// adjoint (pq_residual.hip): tbar = lam . dR/dt + ew dE/dt and, when hbar and
+// eribar are given, the same pulled back to f and the packed integrals.
+// aws: pq_adj_doubles(npair) doubles of adjoint workspace.
+size_t pq_adj_doubles(int npair);
+pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h, const double* eri,
+                      const double* t, const double* lam, double ew, double* tbar, double* hbar,
+                      double* eribar, double* ws, double* aws);
 
 // streaming kernels of the solver (solver_kernels.hip) ---------------------
 int stream_blocks(size_t n);

@@ -436,6 +436,7 @@ def emit_pq_header(tb: PQTables, path: str):
     L = tb.r2_local
     parts.append(_arr("pq_loc_coef", "double", L["coef"]) + _arr("pq_loc_idx", "unsigned short", L["idx"])
                  + _arr("pq_loc_ch_lo", "int", L["ch_lo"]) + _arr("pq_loc_ch_hi", "int", L["ch_hi"])
+                 + _arr("pq_loc_ch_m", "int", L["ch_m"])
                  + _arr("pq_loc_m_start", "int", L["m_start"])
                  + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
                  + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))

@@ -17,8 +17,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from inputs import chain_problem, random_amplitudes  # noqa: E402
-from oracle import integrals, layout, tier_b  # noqa: E402
+from inputs import chain_problem, random_amplitudes, random_vector  # noqa: E402
+from oracle import gradient, integrals, layout, tier_b  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -49,6 +49,58 @@ def make(name):
         json.dump(out, fh, indent=1)
 
 
+VJP_FIXTURES = {
+    # name: (sites, U, chain seed, amplitude seed, scale, lambda seed, direction seed,
+    #        energy weight, blocks carrying lambda)
+    "pq140_vjp": (140, 4.0, 140, 1400, 0.05, 1401, 1402, 0.7, [(3,), (0, 1), (17, 52)]),
+}
+
+
+def vjp_inputs(N, lseed, dseed, blocks):
+    """lambda on the slots of the given blocks, and the directions (dt, df, deri)."""
+    lam_blocks = {}
+    for b, L in enumerate(blocks):
+        nslot = len(layout.pattern_tuples(len(L)))
+        vals = random_vector(nslot, seed=lseed + b)
+        lam_blocks[L] = {layout.amp_slot(N, L, m): float(vals[m]) for m in range(nslot)}
+    dt = random_vector(layout.amp_count(N, 2), seed=dseed)
+    df = random_vector(4 * N * N, seed=dseed + 1).reshape(2 * N, 2 * N)
+    deri = random_vector(layout.eri_count(N, 2), seed=dseed + 2)
+    return lam_blocks, dt, df, deri
+
+
+def _directional(a):
+    N, f, eri, t, lam_blocks, w, dirs = a
+    return gradient.directional_vjp_blocks(N, 2, f, eri, t, lam_blocks, w, *dirs)
+
+
+def make_vjp(name):
+    n, U, seed, aseed, scale, lseed, dseed, w, blocks = VJP_FIXTURES[name]
+    prob = chain_problem(n, U=U, seed=seed)
+    N = prob.npair
+    f, eri = integrals.chain_integrals(prob, 2)
+    t = random_amplitudes(N, "pq", seed=aseed, scale=scale)
+    lam_blocks, dt, df, deri = vjp_inputs(N, lseed, dseed, blocks)
+    t0 = time.time()
+    out = {"sites": n, "U": U, "seed": seed, "amp_seed": aseed, "amp_scale": scale,
+           "lambda_seed": lseed, "direction_seed": dseed, "energy_weight": w,
+           "blocks": [list(L) for L in blocks],
+           "citation": "d/ds [lambda . R + w E_c] along (dt, df, deri): the transposed residual "
+                       "contraction of the Lagrangian (Sec. II); sub-cluster sums of the oracle",
+           "parts": {}}
+    zt, zf, ze = np.zeros_like(dt), np.zeros_like(df), np.zeros_like(deri)
+    parts = (("t", (dt, zf, ze)), ("f", (zt, df, ze)), ("eri", (zt, zf, deri)))
+    args = [(N, f, eri, t, lam_blocks, w, dirs) for _, dirs in parts]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(len(parts)) as pool:
+        vals = pool.map(_directional, args)
+    for (part, _), v in zip(parts, vals):
+        out["parts"][part] = v
+    print(name, f"{time.time() - t0:.1f}s", flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(FIXTURES)):
-        make(nm)
+    for nm in (sys.argv[1:] or list(FIXTURES) + list(VJP_FIXTURES)):
+        (make_vjp if nm in VJP_FIXTURES else make)(nm)

@@ -5,7 +5,7 @@ under H -> sH) and tr(dE/df) restricted to... invariance of E_c under f -> f + c
 import numpy as np
 import pytest
 
-from inputs import random_amplitudes, random_bfactors, random_fock
+from inputs import random_amplitudes, random_bfactors, random_fock, random_vector
 from oracle import gradient, integrals, layout, solver, tier_a
 
 
@@ -47,3 +47,50 @@ def test_gradient_identities():
     assert abs(np.sum(gf * f) + np.sum(ge * eri) - res.energy) < 1e-10
     # f -> f + c I changes no denominator difference nor any residual: E_c invariant
     assert abs(np.trace(gf)) < 1e-10
+
+
+def _phi(N, k, f, eri, t, lam, w):
+    ta = tier_a.TierA(N, k)
+    R, E = ta.residual(f, layout.unpack_eri(eri, N, k), t)
+    return lam @ R + w * E
+
+
+def test_vjp_against_finite_differences():
+    """Transposed-residual contraction of the oracle vs central differences of
+    lam . R + w E_c along random directions (real arithmetic, no complex step)."""
+    N, k, w = 2, 2, 0.7
+    f = random_fock(N, seed=91, offdiag=0.05)
+    eri = integrals.eri_packed_from_b(random_bfactors(N, seed=92, scale=0.2), N, k)
+    t = random_amplitudes(N, seed=93, scale=0.1)
+    lam = random_vector(len(t), seed=94)
+    tbar, hbar, eribar = gradient.vjp(N, k, f, eri, t, lam, w)
+    rng = np.random.default_rng(95)
+    for _ in range(3):
+        dt, df, de = rng.normal(size=t.shape), rng.normal(size=f.shape), rng.normal(size=eri.shape)
+        s = 1e-4
+        fd = (_phi(N, k, f + s * df, eri + s * de, t + s * dt, lam, w)
+              - _phi(N, k, f - s * df, eri - s * de, t - s * dt, lam, w)) / (2 * s)
+        an = tbar @ dt + np.sum(hbar * df) + eribar @ de
+        assert abs(fd - an) < 1e-7 * max(1.0, abs(an))
+
+
+def test_subcluster_directional_vjp_matches_determinant_space():
+    """The any-size directional form (sub-cluster sums) equals the
+    determinant-space contraction dotted with the same directions."""
+    N, k, w = 3, 2, 0.3
+    f = random_fock(N, seed=101, offdiag=0.05)
+    eri = integrals.eri_packed_from_b(random_bfactors(N, seed=102, scale=0.2), N, k)
+    t = random_amplitudes(N, seed=103, scale=0.1)
+    lam = random_vector(len(t), seed=104)
+    tbar, hbar, eribar = gradient.vjp(N, k, f, eri, t, lam, w)
+    blocks = {}
+    import itertools
+    for size in (1, 2):
+        for L in itertools.combinations(range(N), size):
+            slots = [layout.amp_slot(N, L, m) for m in range(len(layout.pattern_tuples(size)))]
+            blocks[L] = {s: float(lam[s]) for s in slots}
+    rng = np.random.default_rng(105)
+    dt, df, de = rng.normal(size=t.shape), rng.normal(size=f.shape), rng.normal(size=eri.shape)
+    d = gradient.directional_vjp_blocks(N, k, f, eri, t, blocks, w, dt, df, de, keep_cache=True)
+    an = tbar @ dt + np.sum(hbar * df) + eribar @ de
+    assert abs(d - an) < 1e-10 * max(1.0, abs(an))
