@@ -91,7 +91,12 @@ def cpu_baseline(prob, seconds: float):
 def batch_leg(args, pq, torch, dev):
     """Batched PQ config: chains with pair counts drawn from 10..120 (seeded),
     U from 2..6; RHF and integrals outside the timed region.  One batched
-    solve vs the same solves one after another."""
+    solve (graph-replayed device-resident iterations, and the host-driven
+    lockstep for comparison) vs the same solves one after another.  Every
+    chain ends with a status (converged, diverged, stalled); all count as
+    solves."""
+    from collections import Counter
+
     from inputs import batch_chain_specs, batch_problems
     specs = batch_chain_specs(args.batch, 256)
     probs = batch_problems(specs, processes=min(16, os.cpu_count() or 1))
@@ -102,24 +107,32 @@ def batch_leg(args, pq, torch, dev):
         hs.append(f)
         es.append(e)
     torch.cuda.synchronize()
-    pq.pq_solve_batched(hs[:8], es[:8], tol=args.tol)          # warm-up of the code paths
-    torch.cuda.synchronize()
+    out = {}
+    for mode in ("graph", "lockstep"):
+        pq.pq_solve_batched(hs[:8], es[:8], tol=args.tol, mode=mode)      # warm-up of the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pq.pq_solve_batched(hs, es, tol=args.tol, mode=mode)
+        torch.cuda.synchronize()
+        out[mode] = (time.perf_counter() - t0, res)
     t0 = time.perf_counter()
-    res = pq.pq_solve_batched(hs, es, tol=args.tol)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    seq_e = []
-    for f, e in zip(hs, es):
-        seq_e.append(pq.pq_solve(f, e, tol=args.tol, raise_on_failure=False).energy)
+    seq = [pq.pq_solve(f, e, tol=args.tol, raise_on_failure=False) for f, e in zip(hs, es)]
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
-    nok = sum(s == "OK" for s in res.statuses)
-    return {"batched_solves_per_s": len(hs) / tb, "sequential_solves_per_s": len(hs) / ts,
-            "batched_speedup": ts / tb, "batch_size": len(hs), "batch_converged": nok,
+    tb, res = out["graph"]
+    tl, resl = out["lockstep"]
+    ok = [i for i, s in enumerate(res.statuses) if s == "OK"]
+    return {"batched_solves_per_s": len(hs) / tb, "lockstep_solves_per_s": len(hs) / tl,
+            "sequential_solves_per_s": len(hs) / ts, "batched_speedup": ts / tb,
+            "batch_size": len(hs), "batch_statuses": dict(Counter(res.statuses)),
+            "sequential_statuses": dict(Counter(r.status for r in seq)),
             "batch_total_pairs": sum(p.npair for p in probs),
             "batch_residual_evals": sum(res.iterations),
-            "batch_max_energy_diff_vs_sequential": max(abs(a - b) for a, b in zip(res.energies, seq_e))}
+            "sequential_residual_evals": sum(r.iterations for r in seq),
+            "batch_max_energy_diff_vs_sequential_converged":
+                max((abs(res.energies[i] - seq[i].energy) for i in ok), default=None),
+            "lockstep_max_energy_diff_vs_graph_converged":
+                max((abs(res.energies[i] - resl.energies[i]) for i in ok), default=None)}
 
 
 def main():

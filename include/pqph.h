@@ -90,6 +90,9 @@ typedef struct {
     int diis_start;        /* default 2                                  */
     double level_shift;    /* default 0                                  */
     double diverge_factor; /* default 1e4                                */
+    int stall_window;      /* default 40: stop (NOT_CONVERGED) once the best
+                              ||R|| has not halved over this many
+                              iterations; 0 = never                      */
 } pqph_solve_opts;
 
 /* Per-solve report (host struct). */
@@ -189,13 +192,26 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
  * NULL) each chain's report.  Returns OK if every chain converged, otherwise
  * the first failing chain's status; one bad chain does not stop the others.
  * Device memory: the residual workspace of the largest chain per stream (up
- * to 8 streams) plus (4 + 2*diis_dim) amplitude vectors per chain. */
+ * to 8 streams) plus (4 + 2*diis_dim) amplitude vectors per chain and about
+ * 4.3 KB of solver state per chain.  By default the iterations run entirely
+ * on the device: one iteration of the whole batch is captured into a HIP graph
+ * and replayed, and the host only polls the chains' finished flags every few
+ * replays (opts->stall_window must be below 257 here).  The t_inout values are
+ * the starting amplitudes; iterates of converged chains stop changing.
+ * Enqueued on the context's stream order (internal streams wait for it, and
+ * it waits for them); the call returns after the results are on the host. */
 pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* npair,
                              const int64_t* h_off, const int64_t* eri_off,
                              const int64_t* t_off, const double* h,
                              const double* eri, const pqph_solve_opts* opts,
                              double* t_inout, double* energies,
                              pqph_solve_info* infos);
+
+/* Execution mode of pq_solve_batched on this context: 0 (default) = device-
+ * resident iterations replayed from a HIP graph; 1 = host-driven lockstep
+ * (three host synchronisations per iteration for the whole batch; kept for
+ * comparison).  INVALID_ARG for other values. */
+pqph_status pqph_set_batch_mode(pqph_ctx* ctx, int mode);
 
 /* Transposed-residual contraction (the adjoint of pq_residual and pq_energy,
  * Sec. II: the de-excitation amplitudes lambda of the Lagrangian

@@ -159,12 +159,17 @@ class BatchResult:
 
 def pq_solve_batched(hs, eris, *, tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8,
                      diis_start: int = 2, level_shift: float = 0.0,
-                     diverge_factor: float = 1e4) -> BatchResult:
+                     diverge_factor: float = 1e4, stall_window: int = 40,
+                     mode: str = "graph") -> BatchResult:
     """Solve many PQ problems together.  hs, eris: lists of per-chain Fock
     matrices and packed integrals (device tensors), packed here into one
-    buffer each."""
+    buffer each.  mode: "graph" (device-resident iterations replayed from a
+    HIP graph) or "lockstep" (host-driven)."""
     dev = hs[0].device
     lib, ctx = _ctx(dev)
+    if mode not in ("graph", "lockstep"):
+        raise ValueError("mode must be 'graph' or 'lockstep'")
+    _check(lib, ctx, lib.pqph_set_batch_mode(ctx, 0 if mode == "graph" else 1))
     nb = len(hs)
     npairs = [h.shape[0] // 2 for h in hs]
     h_all = torch.cat([h.reshape(-1) for h in hs]).contiguous()
@@ -177,7 +182,8 @@ def pq_solve_batched(hs, eris, *, tol: float = 1e-8, max_iter: int = 200, diis_d
         h_off.append(a); e_off.append(b); t_off.append(c)
         a += h.numel(); b += e.numel(); c += amp_len(n)
     t = torch.zeros(c, dtype=torch.float64, device=dev)
-    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
+                          stall_window)
     infos = (_lib.SolveInfo * nb)()
     en = (C.c_double * nb)()
     st = lib.pq_solve_batched(ctx, nb, (C.c_int * nb)(*npairs), (C.c_int64 * nb)(*h_off),
@@ -204,13 +210,14 @@ class SolveResult:
 
 def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
              tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-             level_shift: float = 0.0, diverge_factor: float = 1e4,
+             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
              raise_on_failure: bool = True) -> SolveResult:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)
     na = amp_len(npair)
     t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
-    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
+                          stall_window)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_solve(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", eri_len(npair)),
@@ -256,7 +263,7 @@ class GradResult:
 
 def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
                    tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-                   level_shift: float = 0.0, diverge_factor: float = 1e4,
+                   level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
                    raise_on_failure: bool = True) -> GradResult:
     """PQ correlation energy and dE/dh, dE/d(packed eri) through the lambda
     equations; t: converged amplitudes, or None to solve them here."""
@@ -266,7 +273,8 @@ def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = 
     gh = torch.empty_like(h)
     ge = torch.empty(ne, dtype=torch.float64, device=h.device)
     lam = torch.empty(na, dtype=torch.float64, device=h.device)
-    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor)
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
+                          stall_window)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_energy_grad(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),

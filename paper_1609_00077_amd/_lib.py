@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpqph.so")
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("diis_dim", C.c_int),
                 ("diis_start", C.c_int), ("level_shift", C.c_double),
-                ("diverge_factor", C.c_double)]
+                ("diverge_factor", C.c_double), ("stall_window", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -48,6 +48,7 @@ SIGNATURES = {
     "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
     "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
     "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
+    "pqph_set_batch_mode": (C.c_int, [P, C.c_int]),
     "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),
     "pq_energy_grad": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),
                                  P, P, P, C.POINTER(SolveInfo)]),

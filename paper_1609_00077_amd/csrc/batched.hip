@@ -1,12 +1,21 @@
 // Batched PQ solves: many Hamiltonians of uneven pair counts iterated together.
 //
 // Every chain keeps its own Jacobi/DIIS state (Sec. III) and converges on its
-// own; all chains advance in lockstep, spread over several HIP streams in
-// longest-processing-time order so their kernels run concurrently, and the
-// per-chain norms and DIIS Gram rows are reduced on the device into one array
-// each, so the whole batch needs three host synchronisations per iteration
-// (norms, Gram rows, DIIS coefficients) instead of three per chain.  Chains
-// sharing a stream share its residual workspace.
+// own.  Chains are spread over several HIP streams in longest-processing-time
+// order so their kernels run concurrently; chains sharing a stream share its
+// residual workspace.
+//
+// Default (graph) mode: the whole iteration of every chain runs on the device
+// -- residual, norm, convergence/divergence/stall check, Jacobi step written
+// straight into the DIIS history, Gram row, the (m+1)x(m+1) DIIS solve by one
+// thread, extrapolation -- with the chain's state (flags, counters, B matrix,
+// coefficients, best-norm ring) in device memory.  One iteration of the whole
+// batch is captured once into a HIP graph and replayed; a finished chain
+// closes its gate flag and all of its later kernels return at once.  The host
+// only polls the gate flags every few replays.
+//
+// Lockstep mode (pqph_set_batch_mode 1): the same iteration driven from the
+// host, with three host synchronisations per iteration for the whole batch.
 #include "pqph_internal.h"
 
 #include <algorithm>
@@ -31,6 +40,7 @@ struct Chain {
     double rn = INFINITY, rmin = INFINITY;
     pqph_status st = PQPH_NOT_CONVERGED;
     std::vector<double> B;
+    std::vector<double> best;     // smallest norm so far, per iteration
 };
 
 pqph_status make_streams(pqph_ctx* ctx, int ns) {
@@ -62,7 +72,434 @@ pqph_status join(pqph_ctx* ctx, int ns) {
     return PQPH_OK;
 }
 
+
+// ------------------------------------------------- device-resident iteration
+constexpr int kRing = 257;            // best-norm ring; stall_window <= kRing - 1
+
+struct DevChain {
+    int active, iters, next, stored, status, use, last, pad;
+    double rn, rmin;
+    double B[16 * 16];
+    double coef[16];
+    double best[kRing];
+};
+
+struct BOpts {
+    int max_iter, diis_dim, diis_start, stall_window;
+    double tol, diverge_factor;
+};
+
+__global__ void k_b_init(DevChain* st, int nb) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    DevChain& s = st[c];
+    s.active = 1;
+    s.iters = s.next = s.stored = s.use = s.last = s.pad = 0;
+    s.status = PQPH_NOT_CONVERGED;
+    s.rn = s.rmin = INFINITY;
+    for (int i = 0; i < 16 * 16; ++i) s.B[i] = 0.0;
+    for (int i = 0; i < 16; ++i) s.coef[i] = 0.0;
+}
+
+// partial sums of ||r||^2 (grid-stride, fixed order)
+__global__ void k_b_norm_partial(const DevChain* __restrict__ st, const double* __restrict__ r,
+                                 size_t n, double* __restrict__ partial) {
+    if (!st->active) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        s += r[i] * r[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[j] = sum of partial[j*nblk .. (j+1)*nblk)
+__global__ void k_b_sum_rows(const DevChain* __restrict__ st, const double* __restrict__ partial,
+                             int nblk, double* __restrict__ out) {
+    if (!st->active) return;
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(size_t)j * nblk + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// convergence, failure and stall decisions of one iteration (one thread)
+__global__ void k_b_check(DevChain* __restrict__ st, const double* __restrict__ norm2, BOpts o) {
+    DevChain& s = *st;
+    if (!s.active) return;
+    const int it = ++s.iters;
+    const double rn = sqrt(*norm2);
+    s.rn = rn;
+    s.rmin = fmin(s.rmin, rn);
+    s.best[(it - 1) % kRing] = s.rmin;
+    const bool stalled = o.stall_window > 0 && it > o.stall_window &&
+                         s.rmin > 0.5 * s.best[(it - 1 - o.stall_window) % kRing];
+    int stt = 1;   // 1 = keep going
+    if (!isfinite(rn)) stt = PQPH_NONFINITE;
+    else if (rn <= o.tol) stt = PQPH_OK;
+    else if (rn > 1e3 || rn > o.diverge_factor * s.rmin) stt = PQPH_DIVERGED;
+    else if (stalled || it >= o.max_iter) stt = PQPH_NOT_CONVERGED;
+    if (stt != 1) {
+        s.status = stt;
+        s.active = 0;
+    }
+}
+
+// e = -r/D and tn = t + e, written into the history slot `next`
+__global__ void k_b_jacobi(const DevChain* __restrict__ st, const double* __restrict__ t,
+                           const double* __restrict__ r, const double* __restrict__ D, size_t n,
+                           double* __restrict__ th, double* __restrict__ eh) {
+    if (!st->active) return;
+    const size_t off = (size_t)st->next * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double d = -r[i] / D[i];
+        eh[off + i] = d;
+        th[off + i] = t[i] + d;
+    }
+}
+
+// partial sums of <e_j, e_new> for every history slot j (blockIdx.y)
+__global__ void k_b_gram_partial(const DevChain* __restrict__ st, const double* __restrict__ eh,
+                                 size_t n, int nblk, double* __restrict__ partial) {
+    if (!st->active) return;
+    __shared__ double red[256];
+    const int j = blockIdx.y;
+    const double* a = eh + (size_t)j * n;
+    const double* b = eh + (size_t)st->next * n;
+    double s = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = red[0];
+}
+
+// B-matrix update and the bordered DIIS system (Pulay), by one thread:
+// [B/scale -1; -1 0] [c; l] = [0; -1], partial pivoting; on a (near) singular
+// system the plain Jacobi step is taken.
+__global__ void k_b_diis(DevChain* __restrict__ st, const double* __restrict__ grow, int m,
+                         int diis_start, int diis_on) {
+    DevChain& s = *st;
+    if (!s.active) return;
+    const int slot = s.next;
+    s.last = slot;
+    s.next = (slot + 1) % m;
+    s.use = 0;
+    if (!diis_on) return;
+    s.stored = min(s.stored + 1, m);
+    for (int j = 0; j < m; ++j) {
+        s.B[slot * 16 + j] = grow[j];
+        s.B[j * 16 + slot] = grow[j];
+    }
+    const int k = s.stored;
+    if (s.iters < diis_start || k < 2) return;
+    __shared__ double A[17 * 18];
+    const int n = k + 1, w = n + 1;
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(s.B[i * 16 + i]));
+    if (!(scale > 0.0)) return;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) {
+            double v;
+            if (i < k && j < k) v = s.B[i * 16 + j] / scale;
+            else if (i == k && j == k) v = 0.0;
+            else v = -1.0;
+            A[i * w + j] = v;
+        }
+        A[i * w + n] = (i == k) ? -1.0 : 0.0;
+    }
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < n; ++i)
+            if (fabs(A[i * w + col]) > fabs(A[piv * w + col])) piv = i;
+        if (fabs(A[piv * w + col]) < 1e-300) return;
+        if (piv != col)
+            for (int j = 0; j <= n; ++j) {
+                const double x = A[piv * w + j];
+                A[piv * w + j] = A[col * w + j];
+                A[col * w + j] = x;
+            }
+        for (int i = 0; i < n; ++i) {
+            if (i == col) continue;
+            const double fct = A[i * w + col] / A[col * w + col];
+            for (int j = col; j <= n; ++j) A[i * w + j] -= fct * A[col * w + j];
+        }
+    }
+    double c[16];
+    for (int i = 0; i < k; ++i) {
+        c[i] = A[i * w + n] / A[i * w + i];
+        if (!isfinite(c[i])) return;
+    }
+    for (int i = 0; i < 16; ++i) s.coef[i] = i < k ? c[i] : 0.0;
+    s.use = 1;
+}
+
+// t = sum_j c_j tn_j (DIIS) or the Jacobi iterate of this step
+__global__ void k_b_update(const DevChain* __restrict__ st, const double* __restrict__ th, int m,
+                           size_t n, double* __restrict__ t) {
+    if (!st->active) return;
+    const bool use = st->use;
+    const int k = min(st->stored, m);          // valid history slots 0..k-1
+    const double* last = th + (size_t)st->last * n;
+    double c[16];
+    for (int j = 0; j < 16; ++j) c[j] = st->coef[j];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (use) {
+            double v = 0.0;
+            for (int j = 0; j < k; ++j) v += c[j] * th[(size_t)j * n + i];
+            t[i] = v;
+        } else {
+            t[i] = last[i];
+        }
+    }
+}
+
 }  // namespace
+
+namespace {
+
+struct Batch {
+    int nb, ns, m;
+    pqph_solve_opts o;
+    std::vector<Chain> ch;
+    std::vector<int> order;
+    std::vector<double*> ws;
+    double *norms, *gram, *coef, *edev, *dmin;
+    DevChain* dst;
+};
+
+pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
+    const pqph_solve_opts& o = b.o;
+    const int nbatch = b.nb, ns = b.ns, m = b.m;
+    auto& ch = b.ch;
+    double* hst = ctx->host;
+    auto S = [&](const Chain& x) { return ctx->bstreams[x.stream]; };
+    pqph_status st;
+    std::vector<double> cvec;
+    int nactive = nbatch;
+    for (int it = 1; it <= o.max_iter && nactive > 0; ++it) {
+        // residuals and their norms
+        if ((st = fork(ctx, ns))) return st;
+        for (int c : b.order) {
+            Chain& x = ch[c];
+            if (!x.active) continue;
+            if ((st = pq_residual_ws(ctx, S(x), x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream]))) return st;
+            launch_norm2(S(x), x.r, x.n, x.part, x.nblk, b.norms + c);
+        }
+        if ((st = join(ctx, ns))) return st;
+        PQPH_HIP(ctx, hipMemcpyAsync(hst, b.norms, nbatch * sizeof(double), hipMemcpyDeviceToHost,
+                                     ctx->stream));
+        PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int c = 0; c < nbatch; ++c) {
+            Chain& x = ch[c];
+            if (!x.active) continue;
+            x.iters = it;
+            x.rn = std::sqrt(hst[c]);
+            x.rmin = std::min(x.rmin, x.rn);
+            x.best.push_back(x.rmin);
+            const bool stalled = o.stall_window > 0 && it > o.stall_window &&
+                                 x.rmin > 0.5 * x.best[it - 1 - o.stall_window];
+            if (!std::isfinite(x.rn)) x.st = PQPH_NONFINITE;
+            else if (x.rn <= o.tol) x.st = PQPH_OK;
+            else if (x.rn > 1e3 || x.rn > o.diverge_factor * x.rmin) x.st = PQPH_DIVERGED;
+            else if (stalled || it == o.max_iter) x.st = PQPH_NOT_CONVERGED;
+            else continue;
+            x.active = false;
+            --nactive;
+        }
+        if (nactive == 0) break;
+        // Jacobi step, DIIS history and Gram rows
+        if ((st = fork(ctx, ns))) return st;
+        for (int c : b.order) {
+            Chain& x = ch[c];
+            if (!x.active) continue;
+            launch_jacobi(S(x), x.t, x.r, x.D, x.n, x.tn, x.e);
+            if (o.diis_dim == 0) continue;
+            const int slot = x.next;
+            PQPH_HIP(ctx, hipMemcpyAsync(x.th + (size_t)slot * x.n, x.tn, x.n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, S(x)));
+            PQPH_HIP(ctx, hipMemcpyAsync(x.eh + (size_t)slot * x.n, x.e, x.n * sizeof(double),
+                                         hipMemcpyDeviceToDevice, S(x)));
+            launch_gram(S(x), x.eh, m, x.eh + (size_t)slot * x.n, x.n, x.part, x.nblk,
+                        b.gram + (size_t)c * m);
+        }
+        if ((st = join(ctx, ns))) return st;
+        std::vector<char> use(nbatch, 0);
+        if (o.diis_dim > 0) {
+            PQPH_HIP(ctx, hipMemcpyAsync(hst, b.gram, (size_t)nbatch * m * sizeof(double),
+                                         hipMemcpyDeviceToHost, ctx->stream));
+            PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            std::vector<double> cm((size_t)nbatch * m, 0.0);
+            for (int c = 0; c < nbatch; ++c) {
+                Chain& x = ch[c];
+                if (!x.active) continue;
+                const int slot = x.next;
+                x.next = (x.next + 1) % m;
+                x.stored = std::min(x.stored + 1, m);
+                for (int j = 0; j < m; ++j) {
+                    x.B[(size_t)slot * 16 + j] = hst[(size_t)c * m + j];
+                    x.B[(size_t)j * 16 + slot] = hst[(size_t)c * m + j];
+                }
+                if (it >= o.diis_start && x.stored >= 2) {
+                    std::vector<double> Bs(16 * 16, 0.0);
+                    for (int a = 0; a < x.stored; ++a)
+                        for (int q = 0; q < x.stored; ++q) Bs[(size_t)a * 16 + q] = x.B[(size_t)a * 16 + q];
+                    if (diis_solve(Bs, x.stored, cvec)) {
+                        for (int a = 0; a < x.stored; ++a) cm[(size_t)c * m + a] = cvec[a];
+                        use[c] = 1;
+                    }
+                }
+            }
+            for (size_t i = 0; i < cm.size(); ++i) hst[i] = cm[i];
+            PQPH_HIP(ctx, hipMemcpyAsync(b.coef, hst, cm.size() * sizeof(double), hipMemcpyHostToDevice,
+                                         ctx->stream));
+        }
+        if ((st = fork(ctx, ns))) return st;
+        for (int c : b.order) {
+            Chain& x = ch[c];
+            if (!x.active) continue;
+            if (use[c])
+                launch_combine(S(x), x.th, b.coef + (size_t)c * m, x.stored, x.n, x.t);
+            else
+                PQPH_HIP(ctx, hipMemcpyAsync(x.t, x.tn, x.n * sizeof(double), hipMemcpyDeviceToDevice,
+                                             S(x)));
+        }
+        if ((st = join(ctx, ns))) return st;
+        // the pinned coefficients must stay untouched until the copy has run
+        PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return PQPH_OK;
+}
+
+// one iteration of every chain, enqueued on the batch streams (captured)
+pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
+    pqph_status st;
+    for (int c : b.order) {
+        Chain& x = b.ch[c];
+        hipStream_t s = ctx->bstreams[x.stream];
+        DevChain* d = b.dst + c;
+        const int* gate = &d->active;
+        if ((st = pq_residual_ws(ctx, s, x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream], gate))) return st;
+        hipLaunchKernelGGL(k_b_norm_partial, dim3(x.nblk), dim3(256), 0, s, d, x.r, x.n, x.part);
+        hipLaunchKernelGGL(k_b_sum_rows, dim3(1), dim3(256), 0, s, d, x.part, x.nblk, b.norms + c);
+        hipLaunchKernelGGL(k_b_check, dim3(1), dim3(1), 0, s, d, b.norms + c, bo);
+        hipLaunchKernelGGL(k_b_jacobi, dim3(x.nblk), dim3(256), 0, s, d, x.t, x.r, x.D, x.n, x.th,
+                           x.eh);
+        if (b.o.diis_dim > 0) {
+            hipLaunchKernelGGL(k_b_gram_partial, dim3(x.nblk, b.m), dim3(256), 0, s, d, x.eh, x.n,
+                               x.nblk, x.part);
+            hipLaunchKernelGGL(k_b_sum_rows, dim3(b.m), dim3(256), 0, s, d, x.part, x.nblk,
+                               b.gram + (size_t)c * b.m);
+        }
+        hipLaunchKernelGGL(k_b_diis, dim3(1), dim3(1), 0, s, d, b.gram + (size_t)c * b.m, b.m,
+                           b.o.diis_start, b.o.diis_dim > 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_b_update, dim3(x.nblk), dim3(256), 0, s, d, x.th, b.m, x.n, x.t);
+    }
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
+pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
+    const int ns = b.ns, nb = b.nb;
+    BOpts bo{b.o.max_iter, b.o.diis_dim, b.o.diis_start, b.o.stall_window, b.o.tol,
+             b.o.diverge_factor};
+    hipStream_t s0 = ctx->bstreams[0];
+    pqph_status st;
+    hipLaunchKernelGGL(k_b_init, dim3((nb + 63) / 64), dim3(64), 0, ctx->stream, b.dst, nb);
+    PQPH_HIP(ctx, hipGetLastError());
+    // s0 starts after everything already on the context stream
+    PQPH_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
+    PQPH_HIP(ctx, hipStreamWaitEvent(s0, ctx->fork, 0));
+    PQPH_HIP(ctx, hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
+    // fork the other streams from s0, enqueue, join them back into s0
+    bool capturing = true;
+    auto body = [&]() -> pqph_status {
+        PQPH_HIP(ctx, hipEventRecord(ctx->fork, s0));
+        for (int i = 1; i < ns; ++i) PQPH_HIP(ctx, hipStreamWaitEvent(ctx->bstreams[i], ctx->fork, 0));
+        pqph_status e = enqueue_iteration(ctx, b, bo);
+        if (e) return e;
+        for (int i = 1; i < ns; ++i) {
+            PQPH_HIP(ctx, hipEventRecord(ctx->bevents[i], ctx->bstreams[i]));
+            PQPH_HIP(ctx, hipStreamWaitEvent(s0, ctx->bevents[i], 0));
+        }
+        return PQPH_OK;
+    };
+    st = body();
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(s0, &graph);
+    capturing = false;
+    (void)capturing;
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ec != hipSuccess || !graph)
+        return pqph_fail(ctx, PQPH_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ec != hipSuccess)
+        return pqph_fail(ctx, PQPH_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ec));
+    // replay; poll the gate flags after a few replays, then every other one
+    int* flags = reinterpret_cast<int*>(ctx->host);
+    pqph_status result = PQPH_OK;
+    int launched = 0;
+    int next_poll = std::min(b.o.max_iter, 8);
+    while (launched < b.o.max_iter) {
+        ec = hipGraphLaunch(exec, s0);
+        if (ec != hipSuccess) {
+            result = pqph_fail(ctx, PQPH_DEVICE, std::string("graph launch: ") + hipGetErrorString(ec));
+            break;
+        }
+        ++launched;
+        if (launched < next_poll && launched < b.o.max_iter) continue;
+        ec = hipMemcpy2DAsync(flags, sizeof(int), &b.dst[0].active, sizeof(DevChain), sizeof(int), nb,
+                              hipMemcpyDeviceToHost, s0);
+        if (ec == hipSuccess) ec = hipStreamSynchronize(s0);
+        if (ec != hipSuccess) {
+            result = pqph_fail(ctx, PQPH_DEVICE, std::string("poll: ") + hipGetErrorString(ec));
+            break;
+        }
+        int any = 0;
+        for (int c = 0; c < nb; ++c) any |= flags[c];
+        if (!any) break;
+        next_poll = launched + 2;
+    }
+    (void)hipGraphExecDestroy(exec);
+    if (result) return result;
+    PQPH_HIP(ctx, hipEventRecord(ctx->bevents[0], s0));
+    PQPH_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->bevents[0], 0));
+    return PQPH_OK;
+}
+
+}  // namespace
+
+extern "C" pqph_status pqph_set_batch_mode(pqph_ctx* ctx, int mode) {
+    if (!ctx) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null context");
+    if (mode != 0 && mode != 1) return pqph_fail(ctx, PQPH_INVALID_ARG, "batch mode must be 0 or 1");
+    ctx->batch_mode = mode;
+    return PQPH_OK;
+}
 
 extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* npair,
                                         const int64_t* h_off, const int64_t* eri_off,
@@ -76,23 +513,27 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
         if (npair[c] < 1 || npair[c] > 256 || h_off[c] < 0 || eri_off[c] < 0 || t_off[c] < 0)
             return pqph_fail(ctx, PQPH_INVALID_ARG,
                              "chain " + std::to_string(c) + ": npair must be in [1, 256], offsets >= 0");
-    pqph_solve_opts o;
+    Batch b;
+    pqph_solve_opts& o = b.o;
     pqph_default_opts(&o);
     if (opts_in) o = *opts_in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0))
-        return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
+        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kRing)
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options (batched: stall_window < 257)");
     PQPH_HIP(ctx, hipSetDevice(ctx->device));
-    const int m = std::max(o.diis_dim, 1);
-    const int ns = std::min(kMaxStreams, nbatch);
+    const int m = b.m = std::max(o.diis_dim, 1);
+    const int ns = b.ns = std::min(kMaxStreams, nbatch);
+    b.nb = nbatch;
     pqph_status st = make_streams(ctx, ns);
     if (st) return st;
 
     // longest processing time first: the two-spectator work grows as N^4
-    std::vector<Chain> ch(nbatch);
-    std::vector<int> order(nbatch);
+    auto& ch = b.ch;
+    auto& order = b.order;
+    ch.resize(nbatch);
+    order.resize(nbatch);
     std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return npair[a] > npair[b]; });
+    std::sort(order.begin(), order.end(), [&](int a, int q) { return npair[a] > npair[q]; });
     std::vector<double> load(ns, 0.0);
     std::vector<size_t> ws_need(ns, 0);
     for (int c : order) {
@@ -111,19 +552,22 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
         ws_need[s] = std::max(ws_need[s], pq_ws_doubles(x.N) + 8);
     }
     // device memory: per-stream residual workspace, per-chain solver state,
-    // and the batch-wide arrays of norms, Gram rows, coefficients, energies
+    // the batch-wide arrays of norms, Gram rows, coefficients, energies, and
+    // the device-resident chain states
     size_t total = 0;
     for (int s = 0; s < ns; ++s) total += ws_need[s];
     for (auto& x : ch) total += x.n * (4 + 2 * (size_t)m) + (size_t)x.nblk * (m + 1);
     const size_t nsmall = (size_t)nbatch * (2 * m + 4);
     total += nsmall;
+    const size_t dstd = (sizeof(DevChain) * nbatch + sizeof(double) - 1) / sizeof(double);
+    total += dstd + 32;
     st = pqph_ensure_sv(ctx, total * sizeof(double));
     if (st) return st;
     st = pqph_ensure_host(ctx, nsmall);
     if (st) return st;
     double* p = ctx->sv;
-    std::vector<double*> ws(ns);
-    for (int s = 0; s < ns; ++s) { ws[s] = p; p += ws_need[s]; }
+    b.ws.resize(ns);
+    for (int s = 0; s < ns; ++s) { b.ws[s] = p; p += ws_need[s]; }
     for (auto& x : ch) {
         x.D = p; p += x.n;
         x.r = p; p += x.n;
@@ -133,11 +577,13 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
         x.eh = p; p += (size_t)m * x.n;
         x.part = p; p += (size_t)x.nblk * (m + 1);
     }
-    double* norms = p; p += nbatch;
-    double* gram = p; p += (size_t)nbatch * m;
-    double* coef = p; p += (size_t)nbatch * m;
-    double* edev = p; p += nbatch;
-    double* dmin = p; p += nbatch;
+    b.norms = p; p += nbatch;
+    b.gram = p; p += (size_t)nbatch * m;
+    b.coef = p; p += (size_t)nbatch * m;
+    b.edev = p; p += nbatch;
+    b.dmin = p; p += nbatch;
+    p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
+    b.dst = reinterpret_cast<DevChain*>(p);
     double* hst = ctx->host;
     auto S = [&](const Chain& x) { return ctx->bstreams[x.stream]; };
 
@@ -146,114 +592,39 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     for (int c : order) {
         Chain& x = ch[c];
         if ((st = pq_denominators_dev(ctx, S(x), x.N, x.h, o.level_shift, x.D))) return st;
-        launch_absmin(S(x), x.D, x.n, x.part, x.nblk, dmin + c);
+        launch_absmin(S(x), x.D, x.n, x.part, x.nblk, b.dmin + c);
     }
     if ((st = join(ctx, ns))) return st;
-    PQPH_HIP(ctx, hipMemcpyAsync(hst, dmin, nbatch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    PQPH_HIP(ctx, hipMemcpyAsync(hst, b.dmin, nbatch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int c = 0; c < nbatch; ++c)
         if (!(hst[c] > 1e-12))
             return pqph_fail(ctx, PQPH_INVALID_ARG,
                              "chain " + std::to_string(c) + ": vanishing orbital-energy denominator");
 
-    std::vector<double> cvec;
-    int nactive = nbatch;
-    for (int it = 1; it <= o.max_iter && nactive > 0; ++it) {
-        // residuals and their norms
-        if ((st = fork(ctx, ns))) return st;
-        for (int c : order) {
-            Chain& x = ch[c];
-            if (!x.active) continue;
-            if ((st = pq_residual_ws(ctx, S(x), x.N, x.h, x.eri, x.t, x.r, ws[x.stream]))) return st;
-            launch_norm2(S(x), x.r, x.n, x.part, x.nblk, norms + c);
-        }
-        if ((st = join(ctx, ns))) return st;
-        PQPH_HIP(ctx, hipMemcpyAsync(hst, norms, nbatch * sizeof(double), hipMemcpyDeviceToHost,
+    if (ctx->batch_mode == 1) {
+        if ((st = lockstep(ctx, b))) return st;
+    } else {
+        if ((st = graph_mode(ctx, b))) return st;
+        // per-chain reports from the device states
+        std::vector<DevChain> hs(nbatch);
+        PQPH_HIP(ctx, hipMemcpyAsync(hs.data(), b.dst, sizeof(DevChain) * nbatch, hipMemcpyDeviceToHost,
                                      ctx->stream));
         PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
         for (int c = 0; c < nbatch; ++c) {
-            Chain& x = ch[c];
-            if (!x.active) continue;
-            x.iters = it;
-            x.rn = std::sqrt(hst[c]);
-            x.rmin = std::min(x.rmin, x.rn);
-            if (!std::isfinite(x.rn)) x.st = PQPH_NONFINITE;
-            else if (x.rn <= o.tol) x.st = PQPH_OK;
-            else if (x.rn > 1e3 || x.rn > o.diverge_factor * x.rmin) x.st = PQPH_DIVERGED;
-            else if (it == o.max_iter) x.st = PQPH_NOT_CONVERGED;
-            else continue;
-            x.active = false;
-            --nactive;
+            ch[c].iters = hs[c].iters;
+            ch[c].rn = hs[c].rn;
+            ch[c].st = hs[c].active ? PQPH_NOT_CONVERGED : hs[c].status;
         }
-        if (nactive == 0) break;
-        // Jacobi step, DIIS history and Gram rows
-        if ((st = fork(ctx, ns))) return st;
-        for (int c : order) {
-            Chain& x = ch[c];
-            if (!x.active) continue;
-            launch_jacobi(S(x), x.t, x.r, x.D, x.n, x.tn, x.e);
-            if (o.diis_dim == 0) continue;
-            const int slot = x.next;
-            PQPH_HIP(ctx, hipMemcpyAsync(x.th + (size_t)slot * x.n, x.tn, x.n * sizeof(double),
-                                         hipMemcpyDeviceToDevice, S(x)));
-            PQPH_HIP(ctx, hipMemcpyAsync(x.eh + (size_t)slot * x.n, x.e, x.n * sizeof(double),
-                                         hipMemcpyDeviceToDevice, S(x)));
-            launch_gram(S(x), x.eh, m, x.eh + (size_t)slot * x.n, x.n, x.part, x.nblk,
-                        gram + (size_t)c * m);
-        }
-        if ((st = join(ctx, ns))) return st;
-        std::vector<char> use(nbatch, 0);
-        if (o.diis_dim > 0) {
-            PQPH_HIP(ctx, hipMemcpyAsync(hst, gram, (size_t)nbatch * m * sizeof(double),
-                                         hipMemcpyDeviceToHost, ctx->stream));
-            PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            std::vector<double> cm((size_t)nbatch * m, 0.0);
-            for (int c = 0; c < nbatch; ++c) {
-                Chain& x = ch[c];
-                if (!x.active) continue;
-                const int slot = x.next;
-                x.next = (x.next + 1) % m;
-                x.stored = std::min(x.stored + 1, m);
-                for (int j = 0; j < m; ++j) {
-                    x.B[(size_t)slot * 16 + j] = hst[(size_t)c * m + j];
-                    x.B[(size_t)j * 16 + slot] = hst[(size_t)c * m + j];
-                }
-                if (it >= o.diis_start && x.stored >= 2) {
-                    std::vector<double> Bs(16 * 16, 0.0);
-                    for (int a = 0; a < x.stored; ++a)
-                        for (int b = 0; b < x.stored; ++b) Bs[(size_t)a * 16 + b] = x.B[(size_t)a * 16 + b];
-                    if (diis_solve(Bs, x.stored, cvec)) {
-                        for (int a = 0; a < x.stored; ++a) cm[(size_t)c * m + a] = cvec[a];
-                        use[c] = 1;
-                    }
-                }
-            }
-            for (size_t i = 0; i < cm.size(); ++i) hst[i] = cm[i];
-            PQPH_HIP(ctx, hipMemcpyAsync(coef, hst, cm.size() * sizeof(double), hipMemcpyHostToDevice,
-                                         ctx->stream));
-        }
-        if ((st = fork(ctx, ns))) return st;
-        for (int c : order) {
-            Chain& x = ch[c];
-            if (!x.active) continue;
-            if (use[c])
-                launch_combine(S(x), x.th, coef + (size_t)c * m, m, x.n, x.t);
-            else
-                PQPH_HIP(ctx, hipMemcpyAsync(x.t, x.tn, x.n * sizeof(double), hipMemcpyDeviceToDevice,
-                                             S(x)));
-        }
-        if ((st = join(ctx, ns))) return st;
-        // the pinned coefficients must stay untouched until the copy has run
-        PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
     // energies of the last iterates
     if ((st = fork(ctx, ns))) return st;
     for (int c : order) {
         Chain& x = ch[c];
-        if ((st = pq_energy_ws(ctx, S(x), x.N, x.h, x.eri, x.t, edev + c, ws[x.stream]))) return st;
+        if ((st = pq_energy_ws(ctx, S(x), x.N, x.h, x.eri, x.t, b.edev + c, b.ws[x.stream]))) return st;
     }
     if ((st = join(ctx, ns))) return st;
-    PQPH_HIP(ctx, hipMemcpyAsync(hst, edev, nbatch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    PQPH_HIP(ctx, hipMemcpyAsync(hst, b.edev, nbatch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     PQPH_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;

@@ -96,6 +96,7 @@ void pqph_default_opts(pqph_solve_opts* o) {
     o->diis_start = 2;
     o->level_shift = 0.0;
     o->diverge_factor = 1e4;
+    o->stall_window = 40;
 }
 
 pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
@@ -298,6 +299,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     std::vector<double> B(16 * 16, 0.0), c;
     int stored = 0, next = 0, it = 0;
     double rmin = INFINITY;
+    std::vector<double> best;      // best[i]: smallest norm up to iteration i + 1
     rn = INFINITY;
     result = PQPH_NOT_CONVERGED;
     for (it = 1; it <= o.max_iter; ++it) {
@@ -313,9 +315,16 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
             break;
         }
         rmin = std::min(rmin, rn);
+        best.push_back(rmin);
         if (rn <= o.tol) {
             result = PQPH_OK;
             break;
+        }
+        if (o.stall_window > 0 && it > o.stall_window && rmin > 0.5 * best[it - 1 - o.stall_window]) {
+            pqph_fail(ctx, result, "stalled: ||R|| did not halve in " + std::to_string(o.stall_window) +
+                                       " iterations (iteration " + std::to_string(it) + ")");
+            iters = it;
+            return PQPH_OK;
         }
         if (rn > 1e3 || rn > o.diverge_factor * rmin) {
             result = PQPH_DIVERGED;
@@ -350,7 +359,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
                 for (int j = 0; j < m; ++j) hst[8 + j] = j < stored ? c[j] : 0.0;
                 PQPH_HIP(ctx, hipMemcpyAsync(scal + 16, hst + 8, m * sizeof(double),
                                              hipMemcpyHostToDevice, s));
-                launch_combine(s, xh, scal + 16, m, n, x);
+                launch_combine(s, xh, scal + 16, stored, n, x);   // only written slots
                 PQPH_HIP(ctx, hipStreamSynchronize(s));   // pinned staging reused next iteration
                 continue;
             }
@@ -367,7 +376,7 @@ pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts&
     pqph_default_opts(&o);
     if (in) o = *in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0))
+        !(o.diverge_factor > 1.0) || o.stall_window < 0)
         return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
     return PQPH_OK;
 }

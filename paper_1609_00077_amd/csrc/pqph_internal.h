@@ -35,6 +35,9 @@ struct pqph_ctx {
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> bevents;
     hipEvent_t fork = nullptr;
+    // batched solves: 0 = device-resident iterations captured in a HIP graph,
+    // 1 = host-driven lockstep (three host synchronisations per iteration)
+    int batch_mode = 0;
 };
 
 // variant of the two-spectator contraction for this npair (tuned or default)

@@ -75,3 +75,31 @@ def test_batched_flags_a_bad_chain_without_stopping_others(pq):
     res = pq.pq_solve_batched([hs[0], hs[1], hs[2]], [es[0], bad, es[2]], tol=1e-10)
     assert res.statuses[1] == "NONFINITE"
     assert res.statuses[0] == "OK" and res.statuses[2] == "OK"
+
+
+def test_graph_and_lockstep_modes_agree(pq):
+    """The device-resident, graph-replayed iterations reach the same solutions
+    as the host-driven lockstep iterations (same Jacobi/DIIS steps; the DIIS
+    solve runs on the device in one mode and on the host in the other)."""
+    chains = _chains(SPECS)
+    hs = [_d(f) for _, f, _ in chains]
+    es = [_d(e) for _, _, e in chains]
+    g = pq.pq_solve_batched(hs, es, tol=1e-11, mode="graph")
+    s = pq.pq_solve_batched(hs, es, tol=1e-11, mode="lockstep")
+    assert g.statuses == s.statuses
+    for a, b in zip(g.energies, s.energies):
+        assert abs(a - b) < 1e-10
+    for a, b in zip(g.iterations, s.iterations):
+        assert abs(a - b) <= 1
+
+
+def test_batched_iteration_limit(pq):
+    """Chains stopped by the iteration limit report NOT_CONVERGED with the
+    limit as their iteration count, in both modes."""
+    chains = _chains(SPECS[:3])
+    hs = [_d(f) for _, f, _ in chains]
+    es = [_d(e) for _, _, e in chains]
+    for mode in ("graph", "lockstep"):
+        res = pq.pq_solve_batched(hs, es, tol=1e-14, max_iter=3, mode=mode)
+        assert all(st == "NOT_CONVERGED" for st in res.statuses), res.statuses
+        assert res.iterations == [3, 3, 3]
