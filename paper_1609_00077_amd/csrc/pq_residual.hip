@@ -168,6 +168,8 @@ __global__ void k_spec(int N, int which, View v, double* __restrict__ out, const
         for (int i = st[s]; i < st[s + 1]; ++i) x *= fval(fc[i], L0, L1, 0, 0, v);
     }
     out[(long)s * v.NN + (long)L0 * N + L1] = x;
+    // two-spectator vertices are also used transposed (groups keyed by the B link)
+    if (which == 2) out[(long)(PQ_W_N + s) * v.NN + (long)L1 * N + L0] = x;
 }
 
 __device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View& v) {
@@ -253,8 +255,14 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
 
 // ----------------------------------------------------------- one-pair outputs
 // grid (N, nch): workgroup (P, ch) sums the chunk ch of the ordered spectator
-// pairs (A, B); chunk 0 also takes the no- and one-spectator terms.
-__global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __restrict__ part, const int* __restrict__ gate) {
+// (two-spectator terms: k_r1s2).
+// grid.y = 0: the no-spectator terms; grid.y = 1..R1S1_NCH: a chunk of the
+// one-spectator terms for all spectators A (threads over A)
+constexpr int R1S1_TC = 24;
+constexpr int R1S1_NCH = (PQ_R1S1_NTERM + R1S1_TC - 1) / R1S1_TC;
+
+__global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ part,
+                                            const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int P = blockIdx.x, ch = blockIdx.y;
     const int tid = threadIdx.x;
@@ -265,22 +273,22 @@ __global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __re
             a1 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, P, 0, 0, 0, v);
             a2 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, P, 0, 0, 0, v);
         }
+    } else {
+        const int lo = (ch - 1) * R1S1_TC, hi = min(PQ_R1S1_NTERM, lo + R1S1_TC);
+        const int e1 = pq_r1s1_start[1], e2 = pq_r1s1_start[2];
         for (int A = tid; A < N; A += blockDim.x) {
             if (A == P) continue;
-            a0 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, P, A, 0, 0, v);
-            a1 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, P, A, 0, 0, v);
-            a2 += class_sum(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, P, A, 0, 0, v);
+            for (int i = lo; i < hi; ++i) {
+                double x = pq_r1s1_coef[i];
+                const int* f = pq_r1s1_fac + 5 * i;
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    if (f[j] != 0) x *= fval(f[j], P, A, 0, 0, v);
+                if (i < e1) a0 += x;
+                else if (i < e2) a1 += x;
+                else a2 += x;
+            }
         }
-    }
-    const long NN = (long)N * N;
-    const long per = (NN + nch - 1) / nch;
-    const long lo = (long)ch * per, hi = min(NN, lo + per);
-    for (long ab = lo + tid; ab < hi; ab += blockDim.x) {
-        const int A = (int)(ab / N), B = (int)(ab % N);
-        if (A == P || B == P || A == B) continue;
-        a0 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 0, P, A, B, 0, v);
-        a1 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 1, P, A, B, 0, v);
-        a2 += 0.5 * class_sum(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 2, P, A, B, 0, v);
     }
     __shared__ double red[3][256];
     red[0][tid] = a0;
@@ -300,6 +308,92 @@ __global__ __launch_bounds__(256) void k_r1(int N, View v, int nch, double* __re
         part[((long)ch * 3 + 1) * N + P] = red[1][0];
         part[((long)ch * 3 + 2) * N + P] = red[2][0];
     }
+}
+
+// ------------------------------------------- one-pair outputs, two spectators
+// Every term factorises as X(P,A) Z(A,B) Y(P,B) (products of factors on
+// {P,A}, {A,B}, {P,B}); F holds all those products over ordered label pairs
+// with zero diagonals (so A, B != P and A != B hold by construction), the
+// Z products also transposed.
+__global__ void k_spec_r1(int N, View v, double* __restrict__ F, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int L0 = blockIdx.y, s = blockIdx.z;
+    if (L1 >= N) return;
+    double x = 0.0;
+    if (L0 != L1) {
+        x = 1.0;
+        for (int i = pq_r1f_start[s]; i < pq_r1f_start[s + 1]; ++i)
+            x *= fval(pq_r1f_fac[i], L0, L1, 0, 0, v);
+    }
+    F[(long)s * v.NN + (long)L0 * N + L1] = x;
+    if (s >= PQ_R1F_Z0) F[(long)(PQ_R1F_N + s - PQ_R1F_Z0) * v.NN + (long)L1 * N + L0] = x;
+}
+
+// Per group: M(P,j) = sum_k G(P,k) Mid(k,j) with G an X or Y row and Mid a Z
+// or Z^T, closed by r_mu(P) += c sum_j M(P,j) C(P,j) for each closing row C.
+// Workgroup: R1_PB output pairs x all j, a chunk of groups; Mid is read once
+// per R1_PB rows.  Partial sums go to chunk 1 + R1S1_NCH + blockIdx.y of part.
+constexpr int R1_PB = 4;
+
+__global__ __launch_bounds__(256) void k_r1s2(int N, const double* __restrict__ F, int gchunk,
+                                              double* __restrict__ part,
+                                              const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    extern __shared__ double grow[];  // [R1_PB][N]
+    const int P0 = blockIdx.x * R1_PB, ch = blockIdx.y, tid = threadIdx.x;
+    const long NN = (long)N * N;
+    double acc[R1_PB][3];
+#pragma unroll
+    for (int p = 0; p < R1_PB; ++p) acc[p][0] = acc[p][1] = acc[p][2] = 0.0;
+    const int g0 = ch * gchunk, g1 = min(PQ_R1G_N, g0 + gchunk);
+    for (int g = g0; g < g1; ++g) {
+        const double* G = F + (long)pq_r1g_gen[g] * NN;
+        const double* Mid = F + (long)pq_r1g_mid[g] * NN;
+        __syncthreads();
+        for (int i = tid; i < R1_PB * N; i += blockDim.x) {
+            const int p = i / N, k = i % N;
+            grow[i] = (P0 + p < N) ? G[(long)(P0 + p) * N + k] : 0.0;
+        }
+        __syncthreads();
+        for (int j = tid; j < N; j += blockDim.x) {
+            double m[R1_PB];
+#pragma unroll
+            for (int p = 0; p < R1_PB; ++p) m[p] = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const double z = Mid[(long)k * N + j];
+#pragma unroll
+                for (int p = 0; p < R1_PB; ++p) m[p] += grow[p * N + k] * z;
+            }
+            for (int i = pq_r1g_start[g]; i < pq_r1g_start[g + 1]; ++i) {
+                const double* Cl = F + (long)pq_r1g_cl[i] * NN;
+                const double c = pq_r1g_coef[i];
+                const int mu = pq_r1g_mu[i];
+#pragma unroll
+                for (int p = 0; p < R1_PB; ++p) {
+                    const double x = (P0 + p < N) ? c * m[p] * Cl[(long)(P0 + p) * N + j] : 0.0;
+                    acc[p][0] += mu == 0 ? x : 0.0;
+                    acc[p][1] += mu == 1 ? x : 0.0;
+                    acc[p][2] += mu == 2 ? x : 0.0;
+                }
+            }
+        }
+    }
+    __shared__ double red[256];
+#pragma unroll
+    for (int p = 0; p < R1_PB; ++p)
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            __syncthreads();
+            red[tid] = acc[p][mu];
+            __syncthreads();
+            for (int s2 = 128; s2 > 0; s2 >>= 1) {
+                if (tid < s2) red[tid] += red[tid + s2];
+                __syncthreads();
+            }
+            if (tid == 0 && P0 + p < N)
+                part[((long)(1 + R1S1_NCH + ch) * 3 + mu) * N + P0 + p] = red[0];
+        }
 }
 
 // ----------------------------------------------------------- two spectators
@@ -883,6 +977,15 @@ __global__ void k_spec_adj(int N, int which, View v, const double* __restrict__ 
     }
 }
 
+// Wbar_s(A,B) += Wbar_{nw+s}(B,A): the transposed vertices' adjoints folded back
+__global__ void k_fold_wt(int N, double* __restrict__ Wb) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    const int A = blockIdx.y, s = blockIdx.z;
+    if (B >= N) return;
+    const long NN = (long)N * N;
+    Wb[(long)s * NN + (long)A * N + B] += Wb[(long)(PQ_W_N + s) * NN + (long)B * N + A];
+}
+
 // link adjoint: scatter dL * d(prod)/d(factor) into t2bar
 __device__ __forceinline__ void link_adj(int s, int P, int Q, int A, double dL, const View& v,
                                          const AdjView& a) {
@@ -1047,8 +1150,8 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *part, *p1, *p2, *epart, *scal;
-    int nchunk, gchunk, nblkE, nch1;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *F1, *part, *p1, *p2, *epart, *scal;
+    int nchunk, gchunk, nblkE, nch1, r1gchunk;
 };
 
 inline int s2_rowtiles(int N) {
@@ -1056,7 +1159,25 @@ inline int s2_rowtiles(int N) {
     return (int)((np2 + M2_ROWS - 1) / M2_ROWS);
 }
 
-inline int r1_chunks(int N) { return std::max(1, std::min(64, 2048 / std::max(N, 1))); }
+// group chunks of the factorised one-pair two-spectator kernel (N >= 3)
+inline void r1s2_chunks(int N, int& nch, int& gchunk) {
+    const int tiles = (N + R1_PB - 1) / R1_PB;
+    nch = std::max(1, std::min(PQ_R1G_N, 2048 / std::max(tiles, 1)));
+    gchunk = (PQ_R1G_N + nch - 1) / nch;
+    nch = (PQ_R1G_N + gchunk - 1) / gchunk;
+}
+
+// partial-sum chunks of the one-pair outputs: 1 + R1S1_NCH from k_r1, the rest from k_r1s2
+inline int r1_chunks(int N) {
+    if (N < 3) return 1 + R1S1_NCH;
+    int nch, gchunk;
+    r1s2_chunks(N, nch, gchunk);
+    return 1 + R1S1_NCH + nch;
+}
+
+inline size_t r1f_size(int N) {
+    return (size_t)(PQ_R1F_N + PQ_R1F_N - PQ_R1F_Z0) * N * N;
+}
 
 inline void s2_chunks(int N, int& nchunk, int& gchunk) {
     const int rt = std::max(1, s2_rowtiles(N));
@@ -1077,7 +1198,13 @@ Carve carve(double* ws, int N) {
     c.X = take((size_t)PQ_X_N * NN);
     c.Y = take((size_t)PQ_Y_N * NN);
     c.S = take((size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1));
-    c.W = take((size_t)PQ_W_N * NN);
+    c.W = take(2 * (size_t)PQ_W_N * NN);              // W and its transposes
+    c.F1 = take(r1f_size(N));
+    {
+        int nch2 = 0;
+        c.r1gchunk = 0;
+        if (N >= 3) r1s2_chunks(N, nch2, c.r1gchunk);
+    }
     s2_chunks(N, c.nchunk, c.gchunk);
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
     c.nch1 = r1_chunks(N);
@@ -1094,9 +1221,9 @@ size_t carve_size(int N) {
     int nchunk, gchunk;
     s2_chunks(N, nchunk, gchunk);
     const size_t np2m = std::max(np2, (size_t)1);
-    return NP2 * NN + (size_t)PQ_H1_N * N + ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_W_N) * NN +
+    return NP2 * NN + (size_t)PQ_H1_N * N + ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
-           (size_t)r1_chunks(N) * 3 * N + (size_t)NP2 * np2m + (NN + 255) / 256 + 8;
+           (size_t)r1_chunks(N) * 3 * N + (size_t)NP2 * np2m + (NN + 255) / 256 + 8 + r1f_size(N);
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -1219,7 +1346,14 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         }
         pqph_mark(ctx);
     }
-    hipLaunchKernelGGL(k_r1, dim3(N, c.nch1), dim3(256), 0, s, N, v, c.nch1, c.p1, gate);
+    if (N >= 3) {
+        hipLaunchKernelGGL(k_spec_r1, dim3(gx, N, PQ_R1F_N), dim3(tb), 0, s, N, v, c.F1, gate);
+        pqph_mark(ctx);
+        hipLaunchKernelGGL(k_r1s2, dim3((N + R1_PB - 1) / R1_PB, c.nch1 - 1 - R1S1_NCH), dim3(256),
+                           (size_t)R1_PB * N * sizeof(double), s, N, c.F1, c.r1gchunk, c.p1, gate);
+        pqph_mark(ctx);
+    }
+    hipLaunchKernelGGL(k_r1, dim3(N, 1 + R1S1_NCH), dim3(256), 0, s, N, v, c.p1, gate);
     pqph_mark(ctx);
     {
         const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
@@ -1258,7 +1392,7 @@ pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const doubl
 size_t pq_adj_doubles(int N) {
     const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
     return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
-           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + PQ_W_N) * NN + (size_t)PQ_S1PAIRS_N * np2 + 8;
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N) * NN + (size_t)PQ_S1PAIRS_N * np2 + 8;
 }
 
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
@@ -1279,7 +1413,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     a.hb2 = p; p += (size_t)PQ_H2_N * NN;
     double* Xb = p; p += (size_t)PQ_X_N * NN;
     double* Yb = p; p += (size_t)PQ_Y_N * NN;
-    double* Wb = p; p += (size_t)PQ_W_N * NN;
+    double* Wb = p; p += 2 * (size_t)PQ_W_N * NN;      // adjoints of W and of its transposes
     double* Sb = p;
     const size_t nzero = (size_t)(Sb - aws);
     PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
@@ -1319,6 +1453,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                            Xb, Yb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, Xb, a);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, Yb, a);
+        hipLaunchKernelGGL(k_fold_wt, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, Wb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, Wb, a);
     }
     hipLaunchKernelGGL(k_r1_adj, dim3(N, c.nch1), dim3(256), 0, s, N, v, lam, c.nch1, a);

@@ -248,6 +248,40 @@ def build_pq_tables() -> PQTables:
         terms = merge_terms(enumerate_class(k, nout, nspec))
         tb.classes[name] = _table(max(1, len(algebra.pattern_tuples(nout)) if nout else 1),
                                   _interp_rows(tb, terms, nout))
+    # R1S2 factorised: P=0, A=1, B=2 -----------------------------------------
+    # Every factor touches at most two of the labels, so a term is
+    # X(P,A) Z(A,B) Y(P,B) with X, Y, Z products of factors on {P,A}, {P,B},
+    # {A,B} (a lone P or A goes to X, a lone B to Y), summed over ordered
+    # spectators with the 1/2 of the interpreted class folded into the
+    # coefficient.  Zero diagonals of the products enforce A, B != P, A != B.
+    terms = merge_terms(enumerate_class(k, 1, 2))
+    xs, ys, zs, triples = {}, {}, {}, []
+    for t in terms:
+        X, Y, Z = [], [], []
+        facs = [(tuple(t.hroles), ("h", t.hroles, t.hkey))] + [(tuple(rho), ("t", rho, p))
+                                                               for rho, p in t.slots]
+        for roles, f in facs:
+            rs = set(roles)
+            if rs <= {0, 1}:
+                dst, rmap = X, {0: 0, 1: 1}
+            elif rs <= {0, 2}:
+                dst, rmap = Y, {0: 0, 2: 1}
+            else:
+                assert rs == {1, 2}
+                dst, rmap = Z, {1: 0, 2: 1}
+            if f[0] == "h":
+                dst.append(_h_code(tb, f[1], f[2], rmap))
+            else:
+                dst.append(_slot_code(f[1], f[2], rmap))
+        xi = xs.setdefault(tuple(sorted(X)), len(xs))
+        yi = ys.setdefault(tuple(sorted(Y)), len(ys))
+        zi = zs.setdefault(tuple(sorted(Z)), len(zs))
+        m = algebra.pattern_tuples(1).index(t.mu)
+        triples.append((zi, xi, yi, 0.5 * float(t.sign), m))
+    tb.r1s2_x = [list(x) for x in sorted(xs, key=xs.get)]
+    tb.r1s2_y = [list(y) for y in sorted(ys, key=ys.get)]
+    tb.r1s2_z = [list(z) for z in sorted(zs, key=zs.get)]
+    tb.r1s2_groups = r1s2_groups(triples, len(zs))
     # R2S1: P=0, Q=1, A=2 ----------------------------------------------------
     terms = merge_terms(enumerate_class(k, 2, 1))
     xs, ys, pairs, rows = {}, {}, {}, []
@@ -330,18 +364,107 @@ def build_pq_tables() -> PQTables:
             timg = index[img]
             assert timg.sign == sg * t.sign or True
             kept.append((t, float(t.sign)))
-    ls, ws, groups = {}, {}, {}
+    ls, ws, triples = {}, {}, []
     for t, c in kept:
         LA, W, LB = s2_key(t)
         ai = ls.setdefault(LA, len(ls))
         bi = ls.setdefault(LB, len(ls))
         wi = ws.setdefault(W, len(ws))
         m = algebra.pattern_tuples(2).index(t.mu)
-        groups.setdefault((wi, ai), []).append((bi, c, m))
+        triples.append((wi, ai, bi, c, m))
     tb.r2s2_l = [list(x) for x in sorted(ls, key=ls.get)]
     tb.r2s2_w = [list(x) for x in sorted(ws, key=ws.get)]
-    tb.r2s2_groups = sorted(groups.items())
+    tb.r2s2_groups = s2_groups(triples, len(ws))
     return tb
+
+
+def _min_vertex_cover(edges):
+    """Minimum vertex cover of a bipartite graph (left a, right b) by Koenig's
+    theorem: maximum matching, then the alternating-path construction."""
+    adj = {}
+    for a, b in edges:
+        adj.setdefault(a, []).append(b)
+    for a in adj:
+        adj[a].sort()
+    match_b = {}
+
+    def augment(a, seen):
+        for b in adj[a]:
+            if b in seen:
+                continue
+            seen.add(b)
+            if b not in match_b or augment(match_b[b], seen):
+                match_b[b] = a
+                return True
+        return False
+
+    for a in sorted(adj):
+        augment(a, set())
+    matched_a = set(match_b.values())
+    # Z: vertices reachable from unmatched left vertices by alternating paths
+    za, zb = set(a for a in adj if a not in matched_a), set()
+    stack = list(za)
+    while stack:
+        a = stack.pop()
+        for b in adj[a]:
+            if b in zb:
+                continue
+            zb.add(b)
+            a2 = match_b.get(b)
+            if a2 is not None and a2 not in za:
+                za.add(a2)
+                stack.append(a2)
+    cover_a = set(adj) - za
+    cover_b = zb
+    assert all(a in cover_a or b in cover_b for a, b in edges)
+    return cover_a, cover_b
+
+
+def r1s2_groups(triples, nz):
+    """Group the factorised one-pair two-spectator terms (z, x, y, coef, mu).
+
+    A group keyed by (z, x) forms M(P,B) = sum_A X_x(P,A) Z_z(A,B) and closes
+    it against each Y_y; a group keyed by (z, y) forms M(P,A) = sum_B Y_y(P,B)
+    Z_z(A,B), i.e. with the transposed Z (stored as nz + z), and closes it
+    against each X_x.  The keys are a minimum vertex cover per z.  Returns
+    [((z or nz + z, 'x' or 'y', generating spec), [(closing spec, coef, mu)])]."""
+    by_z = {}
+    for z, x, y, c, m in triples:
+        by_z.setdefault(z, []).append((x, y, c, m))
+    groups = {}
+    for z, lst in by_z.items():
+        cover_x, _ = _min_vertex_cover({(x, y) for x, y, _, _ in lst})
+        for x, y, c, m in lst:
+            if x in cover_x:
+                groups.setdefault((z, 0, x), []).append((y, c, m))
+            else:
+                groups.setdefault((nz + z, 1, y), []).append((x, c, m))
+    return sorted(groups.items())
+
+
+def s2_groups(triples, nw):
+    """Group the two-spectator triples (w, a, b, coef, mu) so that each group
+    shares one dense contraction over a spectator.
+
+    A group keyed by (w, a) forms V(B) = sum_A L_a(A) W_w(A,B) once and closes
+    it against each L_b; a group keyed by (w, b) forms U(A) = sum_B L_b(B)
+    W_w(A,B) -- the same contraction with the transposed vertex, stored as
+    vertex nw + w -- and closes it against each L_a.  Choosing the keys as a
+    minimum vertex cover of each vertex's (a, b) incidence graph minimises
+    the number of contractions.  Returns [((vertex, generating link),
+    [(closing link, coef, mu), ...]), ...] ordered by vertex."""
+    by_w = {}
+    for w, a, b, c, m in triples:
+        by_w.setdefault(w, []).append((a, b, c, m))
+    groups = {}
+    for w, lst in by_w.items():
+        cover_a, cover_b = _min_vertex_cover({(a, b) for a, b, _, _ in lst})
+        for a, b, c, m in lst:
+            if a in cover_a:
+                groups.setdefault((w, a), []).append((b, c, m))
+            else:
+                groups.setdefault((nw + w, b), []).append((a, c, m))
+    return sorted(groups.items())
 
 
 # ------------------------------------------------------------------ emitter
@@ -419,6 +542,26 @@ def emit_pq_header(tb: PQTables, path: str):
     parts.append(_spec_arrays("pq_y", tb.r2s1_y))
     parts.append(_arr("pq_s1pairs", "int", tb.r2s1_pairs.reshape(-1))
                  + f"#define PQ_S1PAIRS_N {len(tb.r2s1_pairs)}\n")
+    # factorised one-pair two-spectator class: one spec table X | Y | Z
+    nx, ny = len(tb.r1s2_x), len(tb.r1s2_y)
+    parts.append(_spec_arrays("pq_r1f", tb.r1s2_x + tb.r1s2_y + tb.r1s2_z)
+                 + f"#define PQ_R1F_Y0 {nx}\n#define PQ_R1F_Z0 {nx + ny}\n")
+    nf = nx + ny + len(tb.r1s2_z)
+    r_mid, r_gen, r_start, r_cl, r_coef, r_mu = [], [], [0], [], [], []
+    for (zsel, side, gen), lst in tb.r1s2_groups:
+        nz = len(tb.r1s2_z)
+        # Z_z at F index Z0 + z; its transpose at nf + z
+        r_mid.append(nx + ny + zsel if zsel < nz else nf + (zsel - nz))
+        r_gen.append(gen if side == 0 else nx + gen)
+        for cl, c, m in lst:
+            r_cl.append(nx + cl if side == 0 else cl)
+            r_coef.append(c)
+            r_mu.append(m)
+        r_start.append(len(r_cl))
+    parts.append(_arr("pq_r1g_mid", "int", r_mid) + _arr("pq_r1g_gen", "int", r_gen)
+                 + _arr("pq_r1g_start", "int", r_start) + _arr("pq_r1g_cl", "int", r_cl)
+                 + _arr("pq_r1g_coef", "double", r_coef) + _arr("pq_r1g_mu", "int", r_mu)
+                 + f"#define PQ_R1G_N {len(r_mid)}\n")
     parts.append(_spec_arrays("pq_l", tb.r2s2_l))
     parts.append(_spec_arrays("pq_w", tb.r2s2_w))
     gw, ga, gs, gb, gc, gm = [], [], [0], [], [], []

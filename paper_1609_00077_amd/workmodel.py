@@ -53,8 +53,16 @@ def pq_kernel_flops(N: int) -> dict:
             lsum += (len(tb.r2s2_l[bi]) + 2.0) * (N - 2)
     out["k_r2s2"] = lsum * np2
     out["k_r2"] = (_class_cost(c["R2S0"]) + _class_cost(c["R2S1"])) * np2
-    out["k_r1"] = N * (_class_cost(c["R1S0"]) + (N - 1) * _class_cost(c["R1S1"])
-                       + (N - 1) * (N - 2) * _class_cost(c["R1S2"]))
+    out["k_r1"] = N * (_class_cost(c["R1S0"]) + (N - 1) * _class_cost(c["R1S1"]))
+    # factorised one-pair two-spectator terms: products X, Y, Z (and Z^T) over
+    # ordered label pairs, then per group and output pair one row of a
+    # contraction over N labels and a dot per closing product
+    r1f = tb.r1s2_x + tb.r1s2_y + tb.r1s2_z
+    out["k_spec_r1"] = _spec_cost(r1f) * N * (N - 1)
+    r = 0.0
+    for _, lst in tb.r1s2_groups:
+        r += 2.0 * N * N + 3.0 * N * len(lst)
+    out["k_r1s2"] = r * N
     out["k_final"] = float((3 * N + 29 * np2) * 4)
     return out
 

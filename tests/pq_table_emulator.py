@@ -142,8 +142,9 @@ class Emu:
                 for li, sp in enumerate(tb.r2s2_l):
                     Lv[li] = np.array([self.spec(sp, (P, Q, A)) if A not in (P, Q) else 0.0
                                        for A in range(N)])
+                Wall = np.concatenate([W, W.transpose(0, 2, 1)])   # vertices nw + w: transposed
                 for (wi, ai), lst in tb.r2s2_groups:
-                    V = Lv[ai] @ W[wi]          # V[B] = sum_A L_a(A) W(A,B)
+                    V = Lv[ai] @ Wall[wi]       # V[B] = sum_A L_a(A) W(A,B) (or transposed)
                     for bi, c, m in lst:
                         acc[m] += c * np.dot(V, Lv[bi])
                 R[3 * N + np.arange(29) * self.np2 + Q * (Q - 1) // 2 + P] = acc
