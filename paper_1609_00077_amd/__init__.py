@@ -95,13 +95,13 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     lib, ctx = _ctx(h.device)
     na = amp_len(npair)
     out = torch.empty(na, dtype=torch.float64, device=h.device)
-    ms = (C.c_double * 16)()
+    ms = (C.c_double * 24)()
     n = C.c_int()
     _check(lib, ctx, lib.pq_residual_profile(ctx, npair, _dev(h, "h", 4 * npair * npair),
                                              _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
-                                             _dev(out, "out", na), ms, 16, C.byref(n)))
-    names = [lib.pq_residual_phase_name(i).decode() for i in range(13)]
-    if n.value == 11:      # npair == 2: no one-pair two-spectator terms
+                                             _dev(out, "out", na), ms, 24, C.byref(n)))
+    names = [lib.pq_residual_phase_name(i).decode() for i in range(15)]
+    if n.value == 13:      # npair == 2: no one-pair two-spectator terms
         names = [x for x in names if x not in ("k_spec_r1", "k_r1s2")]
     elif n.value == 3:     # npair == 1: no two-pair outputs
         names = ["k_vertex1", "k_r1", "k_final"]

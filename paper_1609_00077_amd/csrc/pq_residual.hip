@@ -31,6 +31,8 @@ struct View {
     const double* h1;   // [PQ_H1_N][N]
     const double* h2;   // [PQ_H2_N][N][N]
     const double* S;    // [PQ_S1PAIRS_N][N][N]
+    const double* W;    // [2 PQ_W_N][N][N] two-spectator vertices and their transposes
+    const double* D;    // [PQ_DR_N][N][N] dressed vertices
     int N;
     long NN;
 };
@@ -50,6 +52,8 @@ __device__ __forceinline__ double fval(int code, int L0, int L1, int L2, int L3,
         case 3: return v.h1[idx * v.N + a];
         case 4: return v.h2[idx * v.NN + (long)a * v.N + b];
         case 5: return v.S[idx * v.NN + (long)L0 * v.N + L1];
+        case 6: return v.W[idx * v.NN + (long)a * v.N + b];
+        case 7: return v.D[idx * v.NN + (long)a * v.N + b];
         default: return 1.0;
     }
 }
@@ -148,11 +152,21 @@ __global__ void k_unpack_t2(int N, const double* __restrict__ t, double* __restr
 }
 
 // ---------------------------------------------------------- factor products
+// spec tables: 0 X, 1 Y (one-spectator sides), 2 W (two-spectator vertices),
+// 3 L (links), 4 lambda (one-sided links of the dressed vertices)
 __device__ __forceinline__ const int* spec_start(int which) {
-    return which == 0 ? pq_x_start : (which == 1 ? pq_y_start : (which == 2 ? pq_w_start : pq_l_start));
+    return which == 0 ? pq_x_start
+         : which == 1 ? pq_y_start
+         : which == 2 ? pq_w_start
+         : which == 3 ? pq_l_start
+                      : pq_lam_start;
 }
 __device__ __forceinline__ const int* spec_fac(int which) {
-    return which == 0 ? pq_x_fac : (which == 1 ? pq_y_fac : (which == 2 ? pq_w_fac : pq_l_fac));
+    return which == 0 ? pq_x_fac
+         : which == 1 ? pq_y_fac
+         : which == 2 ? pq_w_fac
+         : which == 3 ? pq_l_fac
+                      : pq_lam_fac;
 }
 
 __global__ void k_spec(int N, int which, View v, double* __restrict__ out, const int* __restrict__ gate) {
@@ -170,6 +184,29 @@ __global__ void k_spec(int N, int which, View v, double* __restrict__ out, const
     out[(long)s * v.NN + (long)L0 * N + L1] = x;
     // two-spectator vertices are also used transposed (groups keyed by the B link)
     if (which == 2) out[(long)(PQ_W_N + s) * v.NN + (long)L1 * N + L0] = x;
+}
+
+// Dressed vertices D_k(s, A) = sum_B lambda(s, B) W(A, B) over every label B
+// (lambda = the one-sided link of the reduced two-spectator terms, or 1); W is
+// read through its stored transpose so that threads over A load contiguously.
+__global__ void k_dress(int N, const double* __restrict__ lam, const double* __restrict__ W,
+                        double* __restrict__ D, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    const int A = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y, k = blockIdx.z;
+    if (A >= N) return;
+    const long NN = (long)N * N;
+    const int li = pq_dr_lam[k], we = pq_dr_w[k];
+    const int wt = we < PQ_W_N ? we + PQ_W_N : we - PQ_W_N;
+    const double* Wt = W + (long)wt * NN;          // Wt[B][A] = W_we[A][B]
+    double x = 0.0;
+    if (li < 0) {
+        for (int B = 0; B < N; ++B) x += Wt[(long)B * N + A];
+    } else {
+        const double* L = lam + (long)li * NN + (long)s * N;
+        for (int B = 0; B < N; ++B) x += L[B] * Wt[(long)B * N + A];
+    }
+    D[(long)k * NN + (long)s * N + A] = x;
 }
 
 __device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View& v) {
@@ -761,6 +798,8 @@ struct AdjView {
     double* tb2;   // [29][N][N]
     double* hb1;   // [PQ_H1_N][N]
     double* hb2;   // [PQ_H2_N][N][N]
+    double* Wb;    // [2 PQ_W_N][N][N]
+    double* Db;    // [PQ_DR_N][N][N]
     int N;
     long NN;
 };
@@ -776,6 +815,8 @@ __device__ __forceinline__ void fadj(int code, int L0, int L1, int L2, int L3, c
         case 2: atomicAdd(&a.tb2[idx * a.NN + (long)x * a.N + y], d); break;
         case 3: atomicAdd(&a.hb1[idx * a.N + x], d); break;
         case 4: atomicAdd(&a.hb2[idx * a.NN + (long)x * a.N + y], d); break;
+        case 6: atomicAdd(&a.Wb[idx * a.NN + (long)x * a.N + y], d); break;
+        case 7: atomicAdd(&a.Db[idx * a.NN + (long)x * a.N + y], d); break;
         default: break;
     }
 }
@@ -977,6 +1018,29 @@ __global__ void k_spec_adj(int N, int which, View v, const double* __restrict__ 
     }
 }
 
+// adjoint of the dressed vertices D_k(s,A) = sum_B lambda(s,B) W(A,B):
+//   lambda_bar(s,B) += sum_A Dbar(s,A) W(A,B),  W_bar(A,B) += sum_s Dbar(s,A) lambda(s,B)
+// (grid.y runs over s for the first and over A for the second)
+__global__ void k_dress_adj(int N, const double* __restrict__ lam, const double* __restrict__ W,
+                            const double* __restrict__ Db, double* __restrict__ Lamb,
+                            double* __restrict__ Wb) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y, k = blockIdx.z;
+    if (B >= N) return;
+    const long NN = (long)N * N;
+    const int li = pq_dr_lam[k], we = pq_dr_w[k];
+    const double* Dk = Db + (long)k * NN;
+    if (li >= 0) {
+        double x = 0.0;
+        for (int A = 0; A < N; ++A) x += Dk[(long)r * N + A] * W[(long)we * NN + (long)A * N + B];
+        if (x != 0.0) atomicAdd(&Lamb[(long)li * NN + (long)r * N + B], x);
+    }
+    double y = 0.0;
+    for (int s2 = 0; s2 < N; ++s2)
+        y += Dk[(long)s2 * N + r] * (li >= 0 ? lam[(long)li * NN + (long)s2 * N + B] : 1.0);
+    if (y != 0.0) atomicAdd(&Wb[(long)we * NN + (long)r * N + B], y);
+}
+
 // Wbar_s(A,B) += Wbar_{nw+s}(B,A): the transposed vertices' adjoints folded back
 __global__ void k_fold_wt(int N, double* __restrict__ Wb) {
     const int B = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1150,7 +1214,7 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *F1, *part, *p1, *p2, *epart, *scal;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *part, *p1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1, r1gchunk;
 };
 
@@ -1199,6 +1263,8 @@ Carve carve(double* ws, int N) {
     c.Y = take((size_t)PQ_Y_N * NN);
     c.S = take((size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1));
     c.W = take(2 * (size_t)PQ_W_N * NN);              // W and its transposes
+    c.Lam = take((size_t)PQ_LAM_N * NN);
+    c.D = take((size_t)PQ_DR_N * NN);
     c.F1 = take(r1f_size(N));
     {
         int nch2 = 0;
@@ -1221,7 +1287,8 @@ size_t carve_size(int N) {
     int nchunk, gchunk;
     s2_chunks(N, nchunk, gchunk);
     const size_t np2m = std::max(np2, (size_t)1);
-    return NP2 * NN + (size_t)PQ_H1_N * N + ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N) * NN +
+    return NP2 * NN + (size_t)PQ_H1_N * N +
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
            (size_t)r1_chunks(N) * 3 * N + (size_t)NP2 * np2m + (NN + 255) / 256 + 8 + r1f_size(N);
 }
@@ -1233,6 +1300,8 @@ View make_view(const double* t, const Carve& c, int N) {
     v.h1 = c.h1;
     v.h2 = c.h2;
     v.S = c.S;
+    v.W = c.W;
+    v.D = c.D;
     v.N = N;
     v.NN = (long)N * N;
     return v;
@@ -1270,11 +1339,15 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     const int gx = (N + tb - 1) / tb;
     if (N > 1) {
         const long np2 = (long)N * (N - 1) / 2;
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, gate);
+        pqph_mark(ctx);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_LAM_N), dim3(tb), 0, s, N, 4, v, c.Lam, gate);
+        pqph_mark(ctx);
+        hipLaunchKernelGGL(k_dress, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, c.D, gate);
+        pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, gate);
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, gate);
-        pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, gate);
         pqph_mark(ctx);
         const int nt = (N + GT - 1) / GT;
         hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
@@ -1392,7 +1465,8 @@ pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const doubl
 size_t pq_adj_doubles(int N) {
     const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
     return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
-           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N) * NN + (size_t)PQ_S1PAIRS_N * np2 + 8;
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_DR_N + PQ_LAM_N) * NN +
+           (size_t)PQ_S1PAIRS_N * np2 + 8;
 }
 
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
@@ -1414,14 +1488,20 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     double* Xb = p; p += (size_t)PQ_X_N * NN;
     double* Yb = p; p += (size_t)PQ_Y_N * NN;
     double* Wb = p; p += 2 * (size_t)PQ_W_N * NN;      // adjoints of W and of its transposes
+    double* Db = p; p += (size_t)PQ_DR_N * NN;
+    double* Lamb = p; p += (size_t)PQ_LAM_N * NN;
+    a.Wb = Wb;
+    a.Db = Db;
     double* Sb = p;
     const size_t nzero = (size_t)(Sb - aws);
     PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
     const int tb = 64, gx = (N + tb - 1) / tb;
     if (N > 1) {
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_LAM_N), dim3(tb), 0, s, N, 4, v, c.Lam, nullptr);
+        hipLaunchKernelGGL(k_dress, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, c.D, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, nullptr);
         const int nt = (N + GT - 1) / GT;
         hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
                            dim3(256), 0, s, N, c.X, c.Y, c.S, nullptr);
@@ -1453,6 +1533,9 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                            Xb, Yb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, Xb, a);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, Yb, a);
+        hipLaunchKernelGGL(k_dress_adj, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, Db, Lamb,
+                           Wb);
+        hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_LAM_N), dim3(tb), 0, s, N, 4, v, Lamb, a);
         hipLaunchKernelGGL(k_fold_wt, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, Wb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, Wb, a);
     }

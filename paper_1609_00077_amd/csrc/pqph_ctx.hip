@@ -73,7 +73,7 @@ int pq_s2_variant(const pqph_ctx* ctx, int npair) {
 }
 
 void pqph_mark(pqph_ctx* ctx) {
-    if (!ctx->profiling || ctx->prof_n >= 16) return;
+    if (!ctx->profiling || ctx->prof_n >= 24) return;
     (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
 }
 
@@ -165,13 +165,13 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
 }
 
-static const char* kPhaseNames[] = {"k_vertex1", "k_vertex2", "k_unpack_t2", "k_spec_x",
-                                    "k_spec_y",  "k_spec_w",  "k_gemm_s1",   "k_r2s2",
-                                    "k_r2",      "k_spec_r1", "k_r1s2",      "k_r1",
-                                    "k_final"};
+static const char* kPhaseNames[] = {"k_vertex1", "k_vertex2", "k_unpack_t2", "k_spec_w",
+                                    "k_spec_lam", "k_dress",  "k_spec_x",    "k_spec_y",
+                                    "k_gemm_s1", "k_r2s2",    "k_r2",        "k_spec_r1",
+                                    "k_r1s2",    "k_r1",      "k_final"};
 
 const char* pq_residual_phase_name(int i) {
-    return (i >= 0 && i < 13) ? kPhaseNames[i] : "";
+    return (i >= 0 && i < 15) ? kPhaseNames[i] : "";
 }
 
 pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const double* eri,
@@ -183,7 +183,7 @@ pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const
         return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
     st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
     if (st) return st;
-    for (int i = 0; i < 16; ++i)
+    for (int i = 0; i < 24; ++i)
         if (!ctx->prof[i]) PQPH_HIP(ctx, hipEventCreate(&ctx->prof[i]));
     ctx->prof_n = 0;
     ctx->profiling = true;

@@ -25,7 +25,7 @@ struct pqph_ctx {
     size_t host_n = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // per-kernel timing of one residual (diagnostic entry point only)
-    hipEvent_t prof[16] = {};
+    hipEvent_t prof[24] = {};
     int prof_n = 0;       // events recorded so far
     bool profiling = false;
     // autotuned kernel variants per npair (two-spectator contraction):

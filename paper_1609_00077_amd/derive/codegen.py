@@ -32,6 +32,7 @@ from . import algebra
 from .terms import enumerate_class, merge_terms
 
 KIND_T1, KIND_T2, KIND_H1, KIND_H2, KIND_S = 1, 2, 3, 4, 5
+KIND_W, KIND_D = 6, 7      # two-spectator vertex W (and transposes); dressed vertex D
 MAXF = 5
 
 
@@ -68,6 +69,8 @@ class PQTables:
     r2s2_l: list = None            # A-side link specs, roles 0 P, 1 Q, 2 A
     r2s2_w: list = None            # vertex specs, roles 0 A, 1 B
     r2s2_groups: list = None       # per (w, a): list of (b, coef, mu)
+    r2s2_lam: list = None          # one-sided link products, roles 0 (P or Q), 1 (B)
+    r2s2_dress: list = None        # (lam index or -1 for 1, vertex): D(s,A) = sum_B lam(s,B) W(A,B)
     r2_local: dict = None          # R2S0 + R2S1 terms on pair-local staging offsets
 
 
@@ -282,35 +285,6 @@ def build_pq_tables() -> PQTables:
     tb.r1s2_y = [list(y) for y in sorted(ys, key=ys.get)]
     tb.r1s2_z = [list(z) for z in sorted(zs, key=zs.get)]
     tb.r1s2_groups = r1s2_groups(triples, len(zs))
-    # R2S1: P=0, Q=1, A=2 ----------------------------------------------------
-    terms = merge_terms(enumerate_class(k, 2, 1))
-    xs, ys, pairs, rows = {}, {}, {}, []
-    for t in terms:
-        X, Y, Z = [], [], []
-        hx = set(t.hroles)
-        if hx == {1, 2}:
-            Y.append(_h_code(tb, t.hroles, t.hkey, {1: 0, 2: 1}))
-        else:
-            X.append(_h_code(tb, t.hroles, t.hkey, {0: 0, 2: 1}))
-        for rho, p in t.slots:
-            if 2 in rho:
-                if 1 in rho:
-                    Y.append(_slot_code(rho, p, {1: 0, 2: 1}))
-                else:
-                    X.append(_slot_code(rho, p, {0: 0, 2: 1}))
-            else:
-                Z.append(_slot_code(rho, p, {0: 0, 1: 1}))
-        X, Y = tuple(sorted(X)), tuple(sorted(Y))
-        xi = xs.setdefault(X, len(xs))
-        yi = ys.setdefault(Y, len(ys))
-        pi = pairs.setdefault((xi, yi), len(pairs))
-        m = algebra.pattern_tuples(2).index(t.mu)
-        rows.append((m, float(t.sign), sorted(Z) + [fcode(KIND_S, [], pi)]))
-    tb.r2s1_x = [list(x) for x in sorted(xs, key=xs.get)]
-    tb.r2s1_y = [list(y) for y in sorted(ys, key=ys.get)]
-    tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
-    tb.classes["R2S1"] = _table(29, rows)
-    tb.r2_local = build_r2_local(tb)
     # R2S2: P=0, Q=1, A=2, B=3 -----------------------------------------------
     # The ordered sum over (A, B) counts every unordered spectator pair twice;
     # a term and its image under A <-> B give the same total, so only one of
@@ -374,7 +348,44 @@ def build_pq_tables() -> PQTables:
         triples.append((wi, ai, bi, c, m))
     tb.r2s2_l = [list(x) for x in sorted(ls, key=ls.get)]
     tb.r2s2_w = [list(x) for x in sorted(ws, key=ws.get)]
-    tb.r2s2_groups = s2_groups(triples, len(ws))
+    mixed, s2_terms, tb.r2s2_lam, tb.r2s2_dress = s2_reduce(tb, triples, len(ws))
+    tb.r2s2_groups = s2_groups(mixed, len(ws))
+    # R2S1: P=0, Q=1, A=2 ----------------------------------------------------
+    terms = merge_terms(enumerate_class(k, 2, 1))
+    xs, ys, pairs, rows = {}, {}, {}, []
+    for t in terms:
+        X, Y, Z = [], [], []
+        hx = set(t.hroles)
+        if hx == {1, 2}:
+            Y.append(_h_code(tb, t.hroles, t.hkey, {1: 0, 2: 1}))
+        else:
+            X.append(_h_code(tb, t.hroles, t.hkey, {0: 0, 2: 1}))
+        for rho, p in t.slots:
+            if 2 in rho:
+                if 1 in rho:
+                    Y.append(_slot_code(rho, p, {1: 0, 2: 1}))
+                else:
+                    X.append(_slot_code(rho, p, {0: 0, 2: 1}))
+            else:
+                Z.append(_slot_code(rho, p, {0: 0, 1: 1}))
+        X, Y = tuple(sorted(X)), tuple(sorted(Y))
+        xi = xs.setdefault(X, len(xs))
+        yi = ys.setdefault(Y, len(ys))
+        pi = pairs.setdefault((xi, yi), len(pairs))
+        m = algebra.pattern_tuples(2).index(t.mu)
+        rows.append((m, float(t.sign), sorted(Z) + [fcode(KIND_S, [], pi)]))
+    # two-spectator triples reduced to one-spectator sums (see s2_reduce)
+    for m, c, pref, X, Y in s2_terms:
+        xi = xs.setdefault(tuple(sorted(X)), len(xs))
+        yi = ys.setdefault(tuple(sorted(Y)), len(ys))
+        pi = pairs.setdefault((xi, yi), len(pairs))
+        rows.append((m, c, sorted(pref) + [fcode(KIND_S, [], pi)]))
+    rows = _merge_rows(rows)
+    tb.r2s1_x = [list(x) for x in sorted(xs, key=xs.get)]
+    tb.r2s1_y = [list(y) for y in sorted(ys, key=ys.get)]
+    tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
+    tb.classes["R2S1"] = _table(29, rows)
+    tb.r2_local = build_r2_local(tb)
     return tb
 
 
@@ -418,6 +429,82 @@ def _min_vertex_cover(edges):
     cover_b = zb
     assert all(a in cover_a or b in cover_b for a, b in edges)
     return cover_a, cover_b
+
+
+def _merge_rows(rows):
+    """Sum the coefficients of rows with the same output and factors."""
+    acc = {}
+    for m, c, codes in rows:
+        key = (m, tuple(codes))
+        acc[key] = acc.get(key, 0.0) + c
+    return [(m, c, list(codes)) for (m, codes), c in acc.items() if c != 0.0]
+
+
+def _link_parts(tb, li):
+    """(m indices on the P side, m indices on the Q side) of link spec li,
+    whose factors are t2[m][P or Q][spectator]."""
+    P, Q = [], []
+    for code in tb.r2s2_l[li]:
+        kind, r0, r1, idx = (code >> 28) & 15, (code >> 24) & 15, (code >> 20) & 15, code & 0xFFFF
+        assert kind == KIND_T2 and r1 == 2 and r0 in (0, 1)
+        (P if r0 == 0 else Q).append(idx)
+    return sorted(P), sorted(Q)
+
+
+def s2_reduce(tb, triples, nw):
+    """Reduce two-spectator triples with at most one mixed link to
+    one-spectator sums.
+
+    A triple contributes c sum_{A,B not in {P,Q}} La(A) W(A,B) Lb(B).  Take
+    the inner link beta one-sided (all its factors t2[m][s][B] on one output
+    label s; the other link, alpha = alpha_P(P,A) alpha_Q(Q,A), may be
+    mixed; if only La is one-sided the roles swap and W is transposed).  With
+    the dressed vertex D(s,A) = sum_B beta(s,B) W(A,B) over all B (beta(s,s)
+    = 0, W(A,A) = 0) the B-sum is D(s,A) - W(A,s') beta(s,s') for the other
+    label s', so the triple becomes
+        c sum_A alpha_P(P,A) alpha_Q(Q,A) D(s,A)
+      - c beta(s,s') sum_A alpha_P(P,A) alpha_Q(Q,A) W(A,s'),
+    two sums over one spectator of products of one-label-pair factors, with
+    the pair-local prefactor beta(s,s') = prod t2[m][s][s'].  A link without
+    factors (beta = 1) has D(A) = sum_B W(A,B) and two boundary terms.
+    Triples with both links mixed are returned for the dense two-spectator
+    contraction.  Returns (mixed triples, [(mu, coef, prefactor codes,
+    X codes, Y codes)], lambda specs, dressings)."""
+    swap2, sgn2 = tb.swap2, tb.swap2_sign
+    t2c = lambda m: fcode(KIND_T2, [0, 1], int(m))
+    wcode = lambda w: fcode(KIND_W, [1, 0], w)          # W(A, label), L0 = label, L1 = A
+    lams, dress = {}, {}
+    mixed, terms = [], []
+    for w, a, b, c, mu in triples:
+        aP, aQ = _link_parts(tb, a)
+        bP, bQ = _link_parts(tb, b)
+        if aP and aQ and bP and bQ:
+            mixed.append((w, a, b, c, mu))
+            continue
+        if not (bP and bQ):
+            (oP, oQ), (iP, iQ), weff = (aP, aQ), (bP, bQ), w
+        else:
+            (oP, oQ), (iP, iQ), weff = (bP, bQ), (aP, aQ), nw + w
+        X = [t2c(m) for m in oP]
+        Y = [t2c(m) for m in oQ]
+        inner = iP or iQ
+        li = lams.setdefault(tuple(inner), len(lams)) if inner else -1
+        di = dress.setdefault((li, weff), len(dress))
+        dcode = fcode(KIND_D, [0, 1], di)
+        if iP:                                      # s = P, s' = Q
+            terms.append((mu, c, [], X + [dcode], Y))
+            terms.append((mu, -c, [t2c(m) for m in iP], X, Y + [wcode(weff)]))
+        elif iQ:                                    # s = Q, s' = P
+            terms.append((mu, c, [], X, Y + [dcode]))
+            sg = float(np.prod([sgn2[m] for m in iQ]))
+            terms.append((mu, -c * sg, [t2c(swap2[m]) for m in iQ], X + [wcode(weff)], Y))
+        else:                                       # beta = 1
+            terms.append((mu, c, [], X + [dcode], Y))
+            terms.append((mu, -c, [], X + [wcode(weff)], Y))
+            terms.append((mu, -c, [], X, Y + [wcode(weff)]))
+    lam_specs = [[t2c(m) for m in key] for key in sorted(lams, key=lams.get)]
+    dressings = sorted(dress, key=dress.get)
+    return mixed, terms, lam_specs, dressings
 
 
 def r1s2_groups(triples, nz):
@@ -564,6 +651,10 @@ def emit_pq_header(tb: PQTables, path: str):
                  + f"#define PQ_R1G_N {len(r_mid)}\n")
     parts.append(_spec_arrays("pq_l", tb.r2s2_l))
     parts.append(_spec_arrays("pq_w", tb.r2s2_w))
+    parts.append(_spec_arrays("pq_lam", tb.r2s2_lam or [[]]))
+    parts.append(_arr("pq_dr_lam", "int", [li for li, _ in tb.r2s2_dress])
+                 + _arr("pq_dr_w", "int", [w for _, w in tb.r2s2_dress])
+                 + f"#define PQ_DR_N {len(tb.r2s2_dress)}\n")
     gw, ga, gs, gb, gc, gm = [], [], [0], [], [], []
     for (wi, ai), lst in tb.r2s2_groups:
         gw.append(wi)
@@ -601,7 +692,8 @@ def emit_pq_header(tb: PQTables, path: str):
         q = eri_quads(size)
         parts.append(_arr(f"pqph_quads{size}", "int", [x for quad in q for x in quad])
                      + f"#define PQPH_QUADS{size}_N {len(q)}\n")
-    maxlen = max(len(s) for s in tb.r2s1_x + tb.r2s1_y + tb.r2s2_l + tb.r2s2_w)
+    maxlen = max(len(s) for s in tb.r2s1_x + tb.r2s1_y + tb.r2s2_l + tb.r2s2_w
+                 + tb.r2s2_lam + tb.r1s2_x + tb.r1s2_y + tb.r1s2_z)
     parts.append(f"#define PQ_SPEC_MAXLEN {maxlen}\n")
     with open(path, "w") as fh:
         fh.write("\n".join(parts))

@@ -72,6 +72,10 @@ class Emu:
             return self.h2[idx, lab[r[0]], lab[r[1]]]
         if kind == 5:
             return S(idx)
+        if kind == 6:
+            return self.Wall[idx, lab[r[0]], lab[r[1]]]
+        if kind == 7:
+            return self.D[idx, lab[r[0]], lab[r[1]]]
         raise ValueError(kind)
 
     def interp(self, table, lab, S=None):
@@ -97,6 +101,29 @@ class Emu:
             v *= self.fval(int(c), lab)
         return v
 
+    def r1s2_factorised(self):
+        """One-pair two-spectator terms through the X.Z.Y groups (amplitudes
+        already set): M = G Mid per group, closed by each row of C."""
+        tb, N = self.tb, self.N
+        F = []
+        for sp in tb.r1s2_x + tb.r1s2_y + tb.r1s2_z:
+            Fm = np.zeros((N, N))
+            for a in range(N):
+                for b in range(N):
+                    if a != b:
+                        Fm[a, b] = self.spec(sp, (a, b))
+            F.append(Fm)
+        nx, ny, nz = len(tb.r1s2_x), len(tb.r1s2_y), len(tb.r1s2_z)
+        out = np.zeros((3, N))
+        for (zsel, side, gen), lst in tb.r1s2_groups:
+            Z = F[nx + ny + zsel] if zsel < nz else F[nx + ny + zsel - nz].T
+            G = F[gen] if side == 0 else F[nx + gen]
+            M = G @ Z
+            for cl, c, m in lst:
+                C = F[nx + cl] if side == 0 else F[cl]
+                out[m] += c * np.sum(M * C, axis=1)
+        return out
+
     def residual(self, t):
         tb, N = self.tb, self.N
         self.set_t(t)
@@ -112,6 +139,24 @@ class Emu:
                     if len({P, A, B}) == 3:
                         acc += 0.5 * self.interp(C["R1S2"], (P, A, B))
             R[np.arange(3) * N + P] = acc
+        # R2S2 vertices (and transposes), one-sided link products, dressed vertices
+        W = np.zeros((len(tb.r2s2_w), N, N))
+        for i, sp in enumerate(tb.r2s2_w):
+            for A in range(N):
+                for B in range(N):
+                    if A != B:
+                        W[i, A, B] = self.spec(sp, (A, B))
+        self.Wall = np.concatenate([W, W.transpose(0, 2, 1)])
+        lam = np.zeros((len(tb.r2s2_lam), N, N))
+        for i, sp in enumerate(tb.r2s2_lam):
+            for a in range(N):
+                for b in range(N):
+                    if a != b:
+                        lam[i, a, b] = self.spec(sp, (a, b))
+        self.D = np.zeros((len(tb.r2s2_dress), N, N))
+        for k, (li, we) in enumerate(tb.r2s2_dress):
+            L = np.ones((N, N)) if li < 0 else lam[li]
+            self.D[k] = L @ self.Wall[we].T          # D(s, A) = sum_B L(s, B) W(A, B)
         # R2S1 intermediates
         X = np.zeros((len(tb.r2s1_x), N, N))
         Y = np.zeros((len(tb.r2s1_y), N, N))
@@ -126,13 +171,6 @@ class Emu:
                     if Q != A:
                         Y[i, Q, A] = self.spec(sp, (Q, A))
         Spairs = np.einsum("xpa,xqa->xpq", X[tb.r2s1_pairs[:, 0]], Y[tb.r2s1_pairs[:, 1]])
-        # R2S2 vertices
-        W = np.zeros((len(tb.r2s2_w), N, N))
-        for i, sp in enumerate(tb.r2s2_w):
-            for A in range(N):
-                for B in range(N):
-                    if A != B:
-                        W[i, A, B] = self.spec(sp, (A, B))
         for Q in range(N):
             for P in range(Q):
                 acc = self.interp(C["R2S0"], (P, Q))
@@ -142,7 +180,7 @@ class Emu:
                 for li, sp in enumerate(tb.r2s2_l):
                     Lv[li] = np.array([self.spec(sp, (P, Q, A)) if A not in (P, Q) else 0.0
                                        for A in range(N)])
-                Wall = np.concatenate([W, W.transpose(0, 2, 1)])   # vertices nw + w: transposed
+                Wall = self.Wall                                   # vertices nw + w: transposed
                 for (wi, ai), lst in tb.r2s2_groups:
                     V = Lv[ai] @ Wall[wi]       # V[B] = sum_A L_a(A) W(A,B) (or transposed)
                     for bi, c, m in lst:

@@ -50,5 +50,27 @@ def test_table_sizes(tables):
     # the class sizes the kernels are built around
     assert len(tables.h1_keys) == 26 and len(tables.h2_keys) == 308
     assert tables.classes["R2S0"].coef.size == 17268
-    assert len(tables.r2s1_pairs) == 2064
-    assert sum(len(l) for _, l in tables.r2s2_groups) == 862
+    # one-spectator pairs: 2064 of the one-spectator class itself plus those of
+    # the two-spectator triples reduced to one-spectator sums
+    assert len(tables.r2s1_pairs) == 3406
+    # two-spectator triples left for the dense contraction (both links mixed)
+    assert sum(len(l) for _, l in tables.r2s2_groups) == 62 and len(tables.r2s2_groups) == 26
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_factorised_one_pair_two_spectator_class(tables, N):
+    """The X.Z.Y grouping of the one-pair two-spectator terms equals the
+    interpreted class summed over ordered spectator pairs."""
+    from pq_table_emulator import Emu
+    f, eri = _system(N, 700 + N)
+    t = random_amplitudes(N, "pq", seed=800 + N, scale=0.1)
+    em = Emu(tables, N, f, eri)
+    em.set_t(t)
+    ref = np.zeros((3, N))
+    for P in range(N):
+        for A in range(N):
+            for B in range(N):
+                if len({P, A, B}) == 3:
+                    ref[:, P] += 0.5 * em.interp(tables.classes["R1S2"], (P, A, B))
+    got = em.r1s2_factorised()
+    assert np.abs(got - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
