@@ -243,9 +243,16 @@ __device__ __forceinline__ double link_at(const Link& L, int A) {
 constexpr int GT = 16;
 constexpr int GP = 16;   // (x, y) pairs per workgroup
 
-// ST[pq][p] = S_p(P,Q) for P < Q (pair-major, so each output pair's one-
-// spectator sums are contiguous for the pair-local epilogue).  Grid:
-// (upper-triangular 16x16 tiles of (P, Q), chunks of GP pairs p).
+// ST[pq][p] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: A[i][k] at lane i+16k, B[k][j] at lane
+// j+16k, D[(lane>>4)+4r][lane&15] in register r).  Workgroup: one upper-
+// triangular 16x16 tile of (P, Q) and GP consecutive pairs p (4 per
+// wavefront); the results are staged in LDS and written pair-major so that
+// each output pair's GP sums are one contiguous 128-byte store (the pair-
+// local epilogue reads them contiguously).  Zero diagonals of X and Y keep
+// A != P, Q.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
                                                  double* __restrict__ ST, const int* __restrict__ gate) {
@@ -255,38 +262,37 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
     while (rem >= nt - tP) { rem -= nt - tP; ++tP; }
     const int tQ = tP + rem;
     const int p0 = blockIdx.y * GP;
-    const int ty = threadIdx.x / GT, tx = threadIdx.x % GT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const long NN = (long)N * N;
-    __shared__ double Xs[GT][GT + 1];
-    __shared__ double Ys[GT][GT + 1];
-    double acc[GP];
-#pragma unroll
-    for (int j = 0; j < GP; ++j) {
-        acc[j] = 0.0;
+    __shared__ double res[GT * GT][GP + 1];
+    const int i = lane & 15, kq = lane >> 4;
+    const int Pi = tP * GT + i, Qi = tQ * GT + i;
+    const bool okP = Pi < N, okQ = Qi < N;
+    const int KP = (N + 3) & ~3;
+    for (int jj = 0; jj < GP / 4; ++jj) {
+        const int j = wave * (GP / 4) + jj;
         const int p = p0 + j;
+        d4 D = {0.0, 0.0, 0.0, 0.0};
         if (p < PQ_S1PAIRS_N) {
-            const double* Xp = X + (long)pq_s1pairs[2 * p] * NN;
-            const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN;
-            for (int a0 = 0; a0 < N; a0 += GT) {
-                const int A = a0 + tx;
-                const int Pr = tP * GT + ty, Qr = tQ * GT + ty;
-                Xs[ty][tx] = (Pr < N && A < N) ? Xp[(long)Pr * N + A] : 0.0;
-                Ys[ty][tx] = (Qr < N && A < N) ? Yp[(long)Qr * N + A] : 0.0;
-                __syncthreads();
-                double s = 0.0;
-#pragma unroll
-                for (int kk = 0; kk < GT; ++kk) s += Xs[ty][kk] * Ys[tx][kk];
-                acc[j] += s;
-                __syncthreads();
+            const double* Xp = X + (long)pq_s1pairs[2 * p] * NN + (long)(okP ? Pi : 0) * N;
+            const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN + (long)(okQ ? Qi : 0) * N;
+#pragma unroll 6
+            for (int k4 = 0; k4 < KP; k4 += 4) {
+                const int A = k4 + kq;
+                const double a = (okP && A < N) ? Xp[A] : 0.0;
+                const double b = (okQ && A < N) ? Yp[A] : 0.0;
+                D = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, D, 0, 0, 0);
             }
         }
-    }
-    const int P = tP * GT + ty, Q = tQ * GT + tx;
-    if (P < Q && Q < N) {
-        double* out = ST + ((long)Q * (Q - 1) / 2 + P) * PQ_S1PAIRS_N + p0;
 #pragma unroll
-        for (int j = 0; j < GP; ++j)
-            if (p0 + j < PQ_S1PAIRS_N) out[j] = acc[j];
+        for (int r = 0; r < 4; ++r) res[(kq + 4 * r) * GT + i][j] = D[r];
+    }
+    __syncthreads();
+    for (int e = tid; e < GT * GT * GP; e += 256) {
+        const int pq = e / GP, j = e % GP;
+        const int P = tP * GT + pq / GT, Q = tQ * GT + pq % GT;
+        if (P < Q && Q < N && p0 + j < PQ_S1PAIRS_N)
+            ST[((long)Q * (Q - 1) / 2 + P) * PQ_S1PAIRS_N + p0 + j] = res[pq][j];
     }
 }
 
@@ -442,7 +448,6 @@ __global__ __launch_bounds__(256) void k_r1s2(int N, const double* __restrict__ 
 // against the B-side links L_b(P,Q,B) and accumulated per output pattern.
 // Workgroup: 64 output pairs (4 wavefronts x 16 rows) x all B; grid.y splits
 // the groups, whose partial sums are combined in k_final.
-typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int M2_ROWS = 64;
 constexpr int M2_KC = 16;
 
@@ -650,7 +655,9 @@ __global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
                                             double* __restrict__ p2, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
     extern __shared__ double sm[];
-    double* loc = sm;                               // [R2L_PPW][PQ_LOC_N]
+    // staged values interleaved by pair, loc[i][p], so that one term reads
+    // the R2L_PPW values of a factor as one contiguous 32-byte LDS access
+    double* loc = sm;                               // [PQ_LOC_N][R2L_PPW]
     double* part = sm + R2L_PPW * PQ_LOC_N;         // [PQ_LOC_NCHUNK][R2L_PPW]
     const long np2 = (long)N * (N - 1) / 2;
     const long ip0 = (long)blockIdx.x * R2L_PPW;
@@ -660,7 +667,6 @@ __global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
         const bool ok = ip < np2;
         int P = 0, Q = 1;
         if (ok) decode_pair(ip, P, Q);
-        double* L = loc + p * PQ_LOC_N;
         for (int i = tid; i < PQ_LOC_N; i += blockDim.x) {
             double val = 0.0;
             if (i == PQ_LOC_ONE)
@@ -674,27 +680,37 @@ __global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
                 else if (i < PQ_LOC_S) val = h2T[ip * PQ_H2_N + (i - PQ_LOC_H2)];
                 else val = ST[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)];
             }
-            L[i] = val;
+            loc[i * R2L_PPW + p] = val;
         }
     }
     __syncthreads();
+    static_assert(R2L_PPW == 4, "the term loop reads the pairs as two double2");
+    const double2* L2 = reinterpret_cast<const double2*>(loc);
     for (int c = tid; c < PQ_LOC_NCHUNK; c += blockDim.x) {
-        double acc[R2L_PPW];
-#pragma unroll
-        for (int p = 0; p < R2L_PPW; ++p) acc[p] = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         const int hi = pq_loc_ch_hi[c];
         for (int i = pq_loc_ch_lo[c]; i < hi; ++i) {
             const double cf = pq_loc_coef[i];
             const unsigned short* ix = pq_loc_idx + 5 * i;
-            const int i0 = ix[0], i1 = ix[1], i2 = ix[2], i3 = ix[3], i4 = ix[4];
+            double x0 = cf, x1 = cf, x2 = cf, x3 = cf;
 #pragma unroll
-            for (int p = 0; p < R2L_PPW; ++p) {
-                const double* L = loc + p * PQ_LOC_N;
-                acc[p] += cf * L[i0] * L[i1] * L[i2] * L[i3] * L[i4];
+            for (int j = 0; j < 5; ++j) {
+                const int k = ix[j];
+                const double2 u = L2[2 * k], w = L2[2 * k + 1];
+                x0 *= u.x;
+                x1 *= u.y;
+                x2 *= w.x;
+                x3 *= w.y;
             }
+            a0 += x0;
+            a1 += x1;
+            a2 += x2;
+            a3 += x3;
         }
-#pragma unroll
-        for (int p = 0; p < R2L_PPW; ++p) part[c * R2L_PPW + p] = acc[p];
+        part[c * R2L_PPW + 0] = a0;
+        part[c * R2L_PPW + 1] = a1;
+        part[c * R2L_PPW + 2] = a2;
+        part[c * R2L_PPW + 3] = a3;
     }
     __syncthreads();
     for (int j = tid; j < NP2 * R2L_PPW; j += blockDim.x) {

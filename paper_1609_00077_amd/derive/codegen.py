@@ -140,7 +140,21 @@ def local_offsets(n_h1, n_h2, n_s):
     return off
 
 
-def build_r2_local(tb, chunk=96):
+def _balanced_chunk(counts, threads=256, max_chunks=1024):
+    """Chunk length that minimises the per-thread work ceil(#chunks/threads)
+    * length when each output's rows are cut into chunks (longest wins ties)."""
+    best = None
+    for ch in range(16, 257):
+        n = sum(-(-c // ch) for c in counts)
+        if n > max_chunks:
+            continue
+        key = (-(-n // threads) * ch, -ch)
+        if best is None or key < best[0]:
+            best = (key, ch)
+    return best[1]
+
+
+def build_r2_local(tb, chunk=None):
     off = local_offsets(len(tb.h1_keys), len(tb.h2_keys), len(tb.r2s1_pairs))
 
     def loc(code):
@@ -163,6 +177,10 @@ def build_r2_local(tb, chunk=96):
             return off["S"] + idx
         raise ValueError(kind)
 
+    if chunk is None:
+        counts = [sum(tb.classes[nm].start[m + 1] - tb.classes[nm].start[m] for nm in ("R2S0", "R2S1"))
+                  for m in range(29)]
+        chunk = _balanced_chunk(counts)
     coef, idx, ch_m, ch_lo, ch_hi, m_start = [], [], [], [], [], [0]
     for m in range(29):
         rows = []
