@@ -169,11 +169,14 @@ __device__ __forceinline__ const int* spec_fac(int which) {
                       : pq_lam_fac;
 }
 
-__global__ void k_spec(int N, int which, View v, double* __restrict__ out, const int* __restrict__ gate) {
+// grid (ceil(N*N/256), number of specs): thread -> ordered label pair (L0, L1)
+__global__ __launch_bounds__(256) void k_spec(int N, int which, View v, double* __restrict__ out,
+                                              const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int L0 = blockIdx.y, s = blockIdx.z;
-    if (L1 >= N) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (e >= N * N) return;
+    const int L0 = e / N, L1 = e - L0 * N;
     const int* st = spec_start(which);
     const int* fc = spec_fac(which);
     double x = 0.0;
@@ -189,12 +192,14 @@ __global__ void k_spec(int N, int which, View v, double* __restrict__ out, const
 // Dressed vertices D_k(s, A) = sum_B lambda(s, B) W(A, B) over every label B
 // (lambda = the one-sided link of the reduced two-spectator terms, or 1); W is
 // read through its stored transpose so that threads over A load contiguously.
-__global__ void k_dress(int N, const double* __restrict__ lam, const double* __restrict__ W,
-                        double* __restrict__ D, const int* __restrict__ gate) {
+__global__ __launch_bounds__(256) void k_dress(int N, const double* __restrict__ lam,
+                                               const double* __restrict__ W, double* __restrict__ D,
+                                               const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int A = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y, k = blockIdx.z;
-    if (A >= N) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (e >= N * N) return;
+    const int s = e / N, A = e - s * N;
     const long NN = (long)N * N;
     const int li = pq_dr_lam[k], we = pq_dr_w[k];
     const int wt = we < PQ_W_N ? we + PQ_W_N : we - PQ_W_N;
@@ -258,10 +263,18 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
                                                  double* __restrict__ ST, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
     const int nt = (N + GT - 1) / GT;
-    int tP = 0, rem = blockIdx.x;
+    const int ntile = nt * (nt + 1) / 2;
+    const int nitem = ntile * ((PQ_S1PAIRS_N + GP - 1) / GP);
+    // XCD-aware order: workgroup b runs on XCD b % 8, so item ranges are dealt
+    // out per XCD and the tiles of one pair chunk (which read the same X and
+    // Y) share that XCD's L2
+    const int per = (int)(gridDim.x / 8);
+    const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (w >= nitem) return;
+    int tP = 0, rem = w % ntile;
     while (rem >= nt - tP) { rem -= nt - tP; ++tP; }
     const int tQ = tP + rem;
-    const int p0 = blockIdx.y * GP;
+    const int p0 = (w / ntile) * GP;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const long NN = (long)N * N;
     __shared__ double res[GT * GT][GP + 1];
@@ -358,11 +371,13 @@ __global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ 
 // {P,A}, {A,B}, {P,B}); F holds all those products over ordered label pairs
 // with zero diagonals (so A, B != P and A != B hold by construction), the
 // Z products also transposed.
-__global__ void k_spec_r1(int N, View v, double* __restrict__ F, const int* __restrict__ gate) {
+__global__ __launch_bounds__(256) void k_spec_r1(int N, View v, double* __restrict__ F,
+                                                 const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int L1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int L0 = blockIdx.y, s = blockIdx.z;
-    if (L1 >= N) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (e >= N * N) return;
+    const int L0 = e / N, L1 = e - L0 * N;
     double x = 0.0;
     if (L0 != L1) {
         x = 1.0;
@@ -648,7 +663,9 @@ __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __re
 // for all its pairs.  Chunk partial sums are reduced in a fixed order.
 constexpr int R2L_PPW = 4;
 
-__global__ __launch_bounds__(256) void k_r2(int N, const double* __restrict__ t,
+constexpr int R2L_THREADS = 1024;
+
+__global__ __launch_bounds__(R2L_THREADS) void k_r2(int N, const double* __restrict__ t,
                                             const double* __restrict__ h1,
                                             const double* __restrict__ h2T,
                                             const double* __restrict__ ST,
@@ -1239,6 +1256,13 @@ inline int s2_rowtiles(int N) {
     return (int)((np2 + M2_ROWS - 1) / M2_ROWS);
 }
 
+// 1-D grid of k_gemm_s1: all (tile, pair chunk) items, padded to a multiple of 8
+inline unsigned gemm_s1_grid(int N) {
+    const int nt = (N + GT - 1) / GT;
+    const long nitem = (long)nt * (nt + 1) / 2 * ((PQ_S1PAIRS_N + GP - 1) / GP);
+    return (unsigned)((nitem + 7) / 8 * 8);
+}
+
 // group chunks of the factorised one-pair two-spectator kernel (N >= 3)
 inline void r1s2_chunks(int N, int& nch, int& gchunk) {
     const int tiles = (N + R1_PB - 1) / R1_PB;
@@ -1353,21 +1377,20 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     View v = make_view(t, c, N);
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
+    const unsigned gsq = (unsigned)((N * N + 255) / 256);
     if (N > 1) {
         const long np2 = (long)N * (N - 1) / 2;
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, gate);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_LAM_N), dim3(tb), 0, s, N, 4, v, c.Lam, gate);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_dress, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, c.D, gate);
+        hipLaunchKernelGGL(k_dress, dim3(gsq, PQ_DR_N), dim3(256), 0, s, N, c.Lam, c.W, c.D, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, gate);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, gate);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, gate);
         pqph_mark(ctx);
-        const int nt = (N + GT - 1) / GT;
-        hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
-                           dim3(256), 0, s, N, c.X, c.Y, c.S, gate);
+        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), 0, s, N, c.X, c.Y, c.S, gate);
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
@@ -1430,13 +1453,13 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                                                            hipGetErrorString(e_));
                 attr = true;
             }
-            hipLaunchKernelGGL(k_r2, dim3((unsigned)((np2 + R2L_PPW - 1) / R2L_PPW)), dim3(256), bytes,
+            hipLaunchKernelGGL(k_r2, dim3((unsigned)((np2 + R2L_PPW - 1) / R2L_PPW)), dim3(R2L_THREADS), bytes,
                                s, N, t, c.h1, c.h2T, c.S, c.p2, gate);
         }
         pqph_mark(ctx);
     }
     if (N >= 3) {
-        hipLaunchKernelGGL(k_spec_r1, dim3(gx, N, PQ_R1F_N), dim3(tb), 0, s, N, v, c.F1, gate);
+        hipLaunchKernelGGL(k_spec_r1, dim3(gsq, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, gate);
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_r1s2, dim3((N + R1_PB - 1) / R1_PB, c.nch1 - 1 - R1S1_NCH), dim3(256),
                            (size_t)R1_PB * N * sizeof(double), s, N, c.F1, c.r1gchunk, c.p1, gate);
@@ -1512,15 +1535,14 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     const size_t nzero = (size_t)(Sb - aws);
     PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
     const int tb = 64, gx = (N + tb - 1) / tb;
+    const unsigned gsq = (unsigned)((N * N + 255) / 256);
     if (N > 1) {
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, c.W, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_LAM_N), dim3(tb), 0, s, N, 4, v, c.Lam, nullptr);
-        hipLaunchKernelGGL(k_dress, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, c.D, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, c.X, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, c.Y, nullptr);
-        const int nt = (N + GT - 1) / GT;
-        hipLaunchKernelGGL(k_gemm_s1, dim3(nt * (nt + 1) / 2, (PQ_S1PAIRS_N + GP - 1) / GP),
-                           dim3(256), 0, s, N, c.X, c.Y, c.S, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, nullptr);
+        hipLaunchKernelGGL(k_dress, dim3(gsq, PQ_DR_N), dim3(256), 0, s, N, c.Lam, c.W, c.D, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, nullptr);
+        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), 0, s, N, c.X, c.Y, c.S, nullptr);
         {
             const size_t bytes =
                 (size_t)(2 * R2A_PPW * PQ_LOC_N + R2A_PPW * NP2) * sizeof(double);

@@ -178,9 +178,12 @@ def build_r2_local(tb, chunk=None):
         raise ValueError(kind)
 
     if chunk is None:
+        # k_r2: 1024 threads, one chunk each at best; the staging of 4 pairs
+        # and 4 partial sums per chunk must fit 160 KB of LDS
         counts = [sum(tb.classes[nm].start[m + 1] - tb.classes[nm].start[m] for nm in ("R2S0", "R2S1"))
                   for m in range(29)]
-        chunk = _balanced_chunk(counts)
+        max_chunks = (160 * 1024 // 8 - 4 * (off["one"] + 1)) // 4 - 16
+        chunk = _balanced_chunk(counts, threads=1024, max_chunks=max_chunks)
     coef, idx, ch_m, ch_lo, ch_hi, m_start = [], [], [], [], [], [0]
     for m in range(29):
         rows = []
