@@ -12,27 +12,49 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpqph.so")
-SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "integrals.hip", "batched.hip"]
+SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "pq_lane.hip", "integrals.hip",
+           "batched.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (wrong results seen on this part)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+OBJDIR = os.path.join(HERE, "_build")
 
 
 def generate_tables() -> None:
     from .derive import codegen
-    codegen.emit_pq_header(codegen.build_pq_tables(), os.path.join(CSRC, "pq_tables.h"))
+    tb = codegen.build_pq_tables()
+    codegen.emit_pq_header(tb, os.path.join(CSRC, "pq_tables.h"))
+    codegen.emit_lane_code(tb, os.path.join(CSRC, "pq_lane_code.h"))
 
 
 def build(verbose: bool = False) -> str:
+    """Regenerate the tables, compile every source to an object in parallel
+    (the generated straight-line kernel dominates), link the shared library."""
     generate_tables()
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJDIR, exist_ok=True)
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+        cmd = [HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                 text=True)))
+    objs, failed = [], []
+    for src, obj, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            failed.append(src)
+            sys.stderr.write(out + err)
+        elif verbose:
+            sys.stderr.write(err)
+        objs.append(obj)
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", LIB + ".tmp"] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libpqph.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc failed linking libpqph.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,0 +1,53 @@
+// No-spectator terms and one-spectator epilogue of the two-pair outputs
+// (Sec. II residual, the terms whose factors all belong to the output pair
+// (P, Q) itself), one lane per output pair.
+//
+// Every term is one streamed factor -- h1 of P or Q, h2 of the pair, or a
+// one-spectator sum S_p of the pair, read from k-major arrays so that a
+// wavefront's 64 consecutive pairs load 512 contiguous bytes -- times at most
+// four amplitudes of the pair.  The amplitudes are held in registers and the
+// terms are generated straight-line code (pq_lane_code.h, one function per
+// chunk of terms), so a term costs a few multiplies and no table or LDS
+// traffic.  Workgroup: 64 pairs x 4 chunks (one per wavefront); each chunk's
+// sums go to part[chunk][pq] and are combined per output in a fixed order.
+#include "pqph_internal.h"
+#include "pq_tables.h"
+#include "pq_lane_code.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_r2c(int N, const double* __restrict__ t,
+                                             const double* __restrict__ h1,
+                                             const double* __restrict__ h2K,
+                                             const double* __restrict__ SK,
+                                             double* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    const long np2 = (long)N * (N - 1) / 2;
+    const long ip = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (c >= PQ_LANE_NCHUNK) return;
+    const long ipc = ip < np2 ? ip : np2 - 1;
+    int P, Q;
+    decode_pair(ipc, P, Q);
+    double x[PQ_LANE_NLOC];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        x[i] = t[(long)i * N + P];
+        x[3 + i] = t[(long)i * N + Q];
+    }
+#pragma unroll
+    for (int i = PQ_LANE_T2; i < PQ_LANE_ONE; ++i) x[i] = t[3L * N + (long)(i - PQ_LANE_T2) * np2 + ipc];
+    x[PQ_LANE_ONE] = 1.0;
+    double acc = 0.0;
+    PQ_LANE_SWITCH(c, acc, x, h1, h2K, SK, (long)N, np2, (long)P, (long)Q, ipc)
+    if (ip < np2) part[(long)c * np2 + ip] = acc;
+}
+
+}  // namespace
+
+void launch_r2_lane(hipStream_t s, int N, const double* t, const double* h1, const double* h2K,
+                    const double* SK, double* part, const int* gate) {
+    const long np2 = (long)N * (N - 1) / 2;
+    hipLaunchKernelGGL(k_r2c, dim3((unsigned)((np2 + 63) / 64), (PQ_LANE_NCHUNK + 3) / 4), dim3(256), 0, s,
+                       N, t, h1, h2K, SK, part, gate);
+}

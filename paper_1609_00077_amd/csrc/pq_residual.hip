@@ -76,13 +76,6 @@ __device__ __forceinline__ double class_sum(const int* start, const double* coef
     return acc;
 }
 
-__device__ __forceinline__ void decode_pair(long ip, int& P, int& Q) {
-    int q = (int)((1.0 + sqrt(1.0 + 8.0 * (double)ip)) * 0.5);
-    while ((long)q * (q - 1) / 2 > ip) --q;
-    while ((long)(q + 1) * q / 2 <= ip) ++q;
-    Q = q;
-    P = (int)(ip - (long)q * (q - 1) / 2);
-}
 
 // ------------------------------------------------------------------ vertices
 __global__ void k_vertex1(int N, const double* __restrict__ f, const double* __restrict__ eri,
@@ -132,7 +125,10 @@ __global__ void k_vertex2(int N, const double* __restrict__ f, const double* __r
         }
     }
     h2[(long)key * NN + (long)P * N + Q] = v;
-    if (P < Q) h2T[((long)Q * (Q - 1) / 2 + P) * PQ_H2_N + key] = v;   // pair-major copy
+    if (P < Q) {   // k-major copy over output pairs: h2K[key][pq]
+        const long np2 = (long)N * (N - 1) / 2;
+        h2T[(long)key * np2 + (long)Q * (Q - 1) / 2 + P] = v;
+    }
 }
 
 // ---------------------------------------------------------------- amplitudes
@@ -248,14 +244,13 @@ __device__ __forceinline__ double link_at(const Link& L, int A) {
 constexpr int GT = 16;
 constexpr int GP = 16;   // (x, y) pairs per workgroup
 
-// ST[pq][p] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
+// S[p][pq] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
 // matrix cores (v_mfma_f64_16x16x4f64: A[i][k] at lane i+16k, B[k][j] at lane
 // j+16k, D[(lane>>4)+4r][lane&15] in register r).  Workgroup: one upper-
 // triangular 16x16 tile of (P, Q) and GP consecutive pairs p (4 per
-// wavefront); the results are staged in LDS and written pair-major so that
-// each output pair's GP sums are one contiguous 128-byte store (the pair-
-// local epilogue reads them contiguously).  Zero diagonals of X and Y keep
-// A != P, Q.
+// wavefront); the results are staged in LDS and written p-major (the lane-
+// per-pair epilogue reads S_p for consecutive output pairs contiguously).
+// Zero diagonals of X and Y keep A != P, Q.
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
@@ -301,11 +296,14 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
         for (int r = 0; r < 4; ++r) res[(kq + 4 * r) * GT + i][j] = D[r];
     }
     __syncthreads();
+    // S-major output S[p][pq]: consecutive threads take consecutive P of one
+    // Q, i.e. consecutive pq (128-byte runs)
+    const long np2 = (long)N * (N - 1) / 2;
     for (int e = tid; e < GT * GT * GP; e += 256) {
-        const int pq = e / GP, j = e % GP;
-        const int P = tP * GT + pq / GT, Q = tQ * GT + pq % GT;
+        const int j = e / (GT * GT), q = (e / GT) % GT, pl = e % GT;
+        const int P = tP * GT + pl, Q = tQ * GT + q;
         if (P < Q && Q < N && p0 + j < PQ_S1PAIRS_N)
-            ST[((long)Q * (Q - 1) / 2 + P) * PQ_S1PAIRS_N + p0 + j] = res[pq][j];
+            ST[(long)(p0 + j) * np2 + (long)Q * (Q - 1) / 2 + P] = res[pl * GT + q][j];
     }
 }
 
@@ -656,87 +654,9 @@ __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __re
 }
 
 // ----------------------------------------------------------- two-pair outputs
-// No-spectator terms and the one-spectator epilogue, pair-local: a workgroup
-// stages, for R2L_PPW output pairs, every value those terms read (t1, t2, h1,
-// h2 and the one-spectator sums S of the pair; PQ_LOC_N doubles each) in LDS,
-// then walks the generated term chunks with each term's table entry read once
-// for all its pairs.  Chunk partial sums are reduced in a fixed order.
-constexpr int R2L_PPW = 4;
-
-constexpr int R2L_THREADS = 1024;
-
-__global__ __launch_bounds__(R2L_THREADS) void k_r2(int N, const double* __restrict__ t,
-                                            const double* __restrict__ h1,
-                                            const double* __restrict__ h2T,
-                                            const double* __restrict__ ST,
-                                            double* __restrict__ p2, const int* __restrict__ gate) {
-    if (gate && *gate == 0) return;   // chain finished (batched solves)
-    extern __shared__ double sm[];
-    // staged values interleaved by pair, loc[i][p], so that one term reads
-    // the R2L_PPW values of a factor as one contiguous 32-byte LDS access
-    double* loc = sm;                               // [PQ_LOC_N][R2L_PPW]
-    double* part = sm + R2L_PPW * PQ_LOC_N;         // [PQ_LOC_NCHUNK][R2L_PPW]
-    const long np2 = (long)N * (N - 1) / 2;
-    const long ip0 = (long)blockIdx.x * R2L_PPW;
-    const int tid = threadIdx.x;
-    for (int p = 0; p < R2L_PPW; ++p) {
-        const long ip = ip0 + p;
-        const bool ok = ip < np2;
-        int P = 0, Q = 1;
-        if (ok) decode_pair(ip, P, Q);
-        for (int i = tid; i < PQ_LOC_N; i += blockDim.x) {
-            double val = 0.0;
-            if (i == PQ_LOC_ONE)
-                val = 1.0;
-            else if (ok) {
-                if (i < PQ_LOC_T1Q) val = t[(long)(i - PQ_LOC_T1P) * N + P];
-                else if (i < PQ_LOC_T2) val = t[(long)(i - PQ_LOC_T1Q) * N + Q];
-                else if (i < PQ_LOC_H1P) val = t[3L * N + (long)(i - PQ_LOC_T2) * np2 + ip];
-                else if (i < PQ_LOC_H1Q) val = h1[(long)(i - PQ_LOC_H1P) * N + P];
-                else if (i < PQ_LOC_H2) val = h1[(long)(i - PQ_LOC_H1Q) * N + Q];
-                else if (i < PQ_LOC_S) val = h2T[ip * PQ_H2_N + (i - PQ_LOC_H2)];
-                else val = ST[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)];
-            }
-            loc[i * R2L_PPW + p] = val;
-        }
-    }
-    __syncthreads();
-    static_assert(R2L_PPW == 4, "the term loop reads the pairs as two double2");
-    const double2* L2 = reinterpret_cast<const double2*>(loc);
-    for (int c = tid; c < PQ_LOC_NCHUNK; c += blockDim.x) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const int hi = pq_loc_ch_hi[c];
-        for (int i = pq_loc_ch_lo[c]; i < hi; ++i) {
-            const double cf = pq_loc_coef[i];
-            const unsigned short* ix = pq_loc_idx + 5 * i;
-            double x0 = cf, x1 = cf, x2 = cf, x3 = cf;
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int k = ix[j];
-                const double2 u = L2[2 * k], w = L2[2 * k + 1];
-                x0 *= u.x;
-                x1 *= u.y;
-                x2 *= w.x;
-                x3 *= w.y;
-            }
-            a0 += x0;
-            a1 += x1;
-            a2 += x2;
-            a3 += x3;
-        }
-        part[c * R2L_PPW + 0] = a0;
-        part[c * R2L_PPW + 1] = a1;
-        part[c * R2L_PPW + 2] = a2;
-        part[c * R2L_PPW + 3] = a3;
-    }
-    __syncthreads();
-    for (int j = tid; j < NP2 * R2L_PPW; j += blockDim.x) {
-        const int m = j / R2L_PPW, p = j % R2L_PPW;
-        double s = 0.0;
-        for (int c = pq_loc_m_start[m]; c < pq_loc_m_start[m + 1]; ++c) s += part[c * R2L_PPW + p];
-        if (ip0 + p < np2) p2[(long)m * np2 + ip0 + p] = s;
-    }
-}
+// The no-spectator terms and the one-spectator epilogue of the two-pair
+// outputs run in k_r2c (pq_lane.hip): straight-line generated code, one lane
+// per output pair.
 
 // packed r from the partial sums, in a fixed order (deterministic)
 __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
@@ -753,7 +673,9 @@ __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
         for (int c = 0; c < nch1; ++c) s += p1[((long)c * 3 + k) * N + P];
     } else {
         const long g2 = gid - n1;
-        s = p2[g2];
+        const int m = (int)(g2 / np2);
+        const long ip = g2 - (long)m * np2;
+        for (int c = pq_lane_m_start[m]; c < pq_lane_m_start[m + 1]; ++c) s += p2[(long)c * np2 + ip];
         for (int c = 0; c < nchunk; ++c) s += ps2[(long)c * NP2 * np2 + g2];
     }
     R[gid] = s;
@@ -953,8 +875,8 @@ __global__ __launch_bounds__(256) void k_r2_adj(int N, const double* __restrict_
                 else if (i < PQ_LOC_H1P) val = t[3L * N + (long)(i - PQ_LOC_T2) * np2 + ip];
                 else if (i < PQ_LOC_H1Q) val = h1[(long)(i - PQ_LOC_H1P) * N + P];
                 else if (i < PQ_LOC_H2) val = h1[(long)(i - PQ_LOC_H1Q) * N + Q];
-                else if (i < PQ_LOC_S) val = h2T[ip * PQ_H2_N + (i - PQ_LOC_H2)];
-                else val = ST[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)];
+                else if (i < PQ_LOC_S) val = h2T[(long)(i - PQ_LOC_H2) * np2 + ip];
+                else val = ST[(long)(i - PQ_LOC_S) * np2 + ip];
             }
             L[i] = val;
             locb[p * PQ_LOC_N + i] = 0.0;
@@ -1315,7 +1237,7 @@ Carve carve(double* ws, int N) {
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
     c.nch1 = r1_chunks(N);
     c.p1 = take((size_t)c.nch1 * 3 * N);
-    c.p2 = take((size_t)NP2 * std::max(np2, (size_t)1));
+    c.p2 = take((size_t)PQ_LANE_NCHUNK * std::max(np2, (size_t)1));
     c.nblkE = (int)((NN + 255) / 256);
     c.epart = take(c.nblkE);
     c.scal = take(8);
@@ -1330,7 +1252,7 @@ size_t carve_size(int N) {
     return NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
-           (size_t)r1_chunks(N) * 3 * N + (size_t)NP2 * np2m + (NN + 255) / 256 + 8 + r1f_size(N);
+           (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N);
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -1441,21 +1363,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
 #undef PQ_S2_LAUNCH
         }
         pqph_mark(ctx);
-        {
-            const size_t bytes = (size_t)(R2L_PPW * PQ_LOC_N + PQ_LOC_NCHUNK * R2L_PPW) * sizeof(double);
-            static bool attr = false;
-            if (!attr) {
-                hipError_t e_ = hipFuncSetAttribute((const void*)&k_r2,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                    (int)bytes);
-                if (e_ != hipSuccess)
-                    return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +
-                                                           hipGetErrorString(e_));
-                attr = true;
-            }
-            hipLaunchKernelGGL(k_r2, dim3((unsigned)((np2 + R2L_PPW - 1) / R2L_PPW)), dim3(R2L_THREADS), bytes,
-                               s, N, t, c.h1, c.h2T, c.S, c.p2, gate);
-        }
+        launch_r2_lane(s, N, t, c.h1, c.h2T, c.S, c.p2, gate);
         pqph_mark(ctx);
     }
     if (N >= 3) {

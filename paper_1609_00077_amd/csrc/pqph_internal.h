@@ -60,6 +60,20 @@ pqph_status pqph_ensure_ws(pqph_ctx* ctx, size_t bytes);
 pqph_status pqph_ensure_sv(pqph_ctx* ctx, size_t bytes);
 pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n);
 
+// output pair index ip = Q(Q-1)/2 + P (P < Q) -> (P, Q)
+__device__ inline void decode_pair(long ip, int& P, int& Q) {
+    int q = (int)((1.0 + sqrt(1.0 + 8.0 * (double)ip)) * 0.5);
+    while ((long)q * (q - 1) / 2 > ip) --q;
+    while ((long)(q + 1) * q / 2 <= ip) ++q;
+    Q = q;
+    P = (int)(ip - (long)q * (q - 1) / 2);
+}
+
+// no- and one-spectator terms of the two-pair outputs (pq_lane.hip): chunk
+// partial sums part[chunk][pq]; h2K, SK k-major over output pairs
+void launch_r2_lane(hipStream_t s, int npair, const double* t, const double* h1, const double* h2K,
+                    const double* SK, double* part, const int* gate);
+
 // PQ residual pieces (pq_residual.hip) --------------------------------------
 size_t pq_ws_doubles(int npair);
 // residual into r on stream s using workspace ws (already large enough); no host sync

@@ -72,6 +72,7 @@ class PQTables:
     r2s2_lam: list = None          # one-sided link products, roles 0 (P or Q), 1 (B)
     r2s2_dress: list = None        # (lam index or -1 for 1, vertex): D(s,A) = sum_B lam(s,B) W(A,B)
     r2_local: dict = None          # R2S0 + R2S1 terms on pair-local staging offsets
+    r2_lane: dict = None           # the same terms grouped by their streamed factor
 
 
 def _hkey_index(tables, hroles, hkey):
@@ -201,6 +202,122 @@ def build_r2_local(tb, chunk=None):
         m_start.append(len(ch_m))
     return {"off": off, "coef": coef, "idx": idx, "ch_m": ch_m, "ch_lo": ch_lo,
             "ch_hi": ch_hi, "m_start": m_start}
+
+
+# Lane-per-pair evaluation of the two-pair outputs' local terms: every term is
+# one streamed factor (h1 of P or Q, h2 of the pair, or a one-spectator sum
+# S_p of the pair, read from k-major arrays so that lanes over consecutive
+# pairs load contiguously) times at most four amplitudes of the pair itself,
+# staged per lane: t1(P) 0..2, t1(Q) 3..5, t2(P,Q) 6..34, 1.0 at 35.
+LANE_T1P, LANE_T1Q, LANE_T2, LANE_ONE, LANE_NLOC = 0, 3, 6, 35, 36
+STREAM_H1P, STREAM_H1Q, STREAM_H2, STREAM_S = 0, 1, 2, 3
+
+
+def build_r2_lane(tb, target=512):
+    """Terms of R2S0 + R2S1 per output m, grouped by streamed factor into
+    segments, cut into chunks of about `target` terms that never span two
+    outputs.  Returns flat arrays for the constant tables."""
+    per_m = []
+    for m in range(29):
+        groups = {}
+        for name in ("R2S0", "R2S1"):
+            tab = tb.classes[name]
+            for i in range(tab.start[m], tab.start[m + 1]):
+                stream, tl = None, []
+                for c in tab.fac[i]:
+                    c = int(c)
+                    if c == 0:
+                        continue
+                    kind, r0, r1, idx = (c >> 28) & 15, (c >> 24) & 15, (c >> 20) & 15, c & 0xFFFF
+                    if kind == KIND_T1:
+                        tl.append((LANE_T1P if r0 == 0 else LANE_T1Q) + idx)
+                    elif kind == KIND_T2:
+                        assert (r0, r1) == (0, 1)
+                        tl.append(LANE_T2 + idx)
+                    else:
+                        assert stream is None, "a local term with two streamed factors"
+                        if kind == KIND_H1:
+                            stream = (STREAM_H1P if r0 == 0 else STREAM_H1Q, idx)
+                        elif kind == KIND_H2:
+                            assert (r0, r1) == (0, 1)
+                            stream = (STREAM_H2, idx)
+                        else:
+                            assert kind == KIND_S
+                            stream = (STREAM_S, idx)
+                assert stream is not None and len(tl) <= 4
+                key = tuple(sorted(tl)) + (LANE_ONE,) * (4 - len(tl))
+                g = groups.setdefault(stream, {})
+                g[key] = g.get(key, 0.0) + float(tab.coef[i])
+        per_m.append([(st, [(c, k) for k, c in sorted(g.items()) if c != 0.0])
+                      for st, g in sorted(groups.items())])
+    coef, tidx = [], []
+    seg_kind, seg_idx, seg_lo, seg_hi = [], [], [], []
+    ch_lo, ch_hi, ch_m, m_start = [], [], [], [0]
+    for m, groups in enumerate(per_m):
+        n_m = sum(len(t) for _, t in groups)
+        nch = max(1, -(-n_m // target))
+        per = -(-n_m // nch)
+        cur, open_seg = 0, False
+        ch_lo.append(len(seg_kind))
+        ch_m.append(m)
+        for (kind, idx), terms in groups:
+            for c, k in terms:
+                if cur == per:                         # close the chunk
+                    ch_hi.append(len(seg_kind))
+                    ch_lo.append(len(seg_kind))
+                    ch_m.append(m)
+                    cur = 0
+                    open_seg = False
+                if not open_seg or seg_kind[-1] != kind or seg_idx[-1] != idx:
+                    seg_kind.append(kind)
+                    seg_idx.append(idx)
+                    seg_lo.append(len(coef))
+                    seg_hi.append(len(coef))
+                    open_seg = True
+                coef.append(c)
+                tidx += list(k)
+                seg_hi[-1] = len(coef)
+                cur += 1
+            open_seg = False
+        ch_hi.append(len(seg_kind))
+        m_start.append(len(ch_lo))
+    return {"coef": coef, "tidx": tidx, "seg_kind": seg_kind, "seg_idx": seg_idx,
+            "seg_lo": seg_lo, "seg_hi": seg_hi, "ch_lo": ch_lo, "ch_hi": ch_hi, "ch_m": ch_m,
+            "m_start": m_start}
+
+
+def emit_lane_code(tb, path):
+    """Straight-line device code for every chunk of the lane-per-pair local
+    terms: the pair's amplitudes live in registers x[0..35] (compile-time
+    indices), each streamed factor is one load, each term a few multiplies."""
+    V = tb.r2_lane
+    names = {0: "h1[{i} * N + P]", 1: "h1[{i} * N + Q]", 2: "h2K[{i} * np2 + ip]", 3: "SK[{i} * np2 + ip]"}
+    out = ["// Generated by paper_1609_00077_amd/derive/codegen.py -- do not edit.",
+           "// One function per chunk of the two-pair outputs' local terms.",
+           "#pragma once", ""]
+    for c, (lo, hi) in enumerate(zip(V["ch_lo"], V["ch_hi"])):
+        out.append(f"__device__ __forceinline__ double lane_chunk_{c}(const double* x, "
+                   "const double* __restrict__ h1, const double* __restrict__ h2K, "
+                   "const double* __restrict__ SK, long N, long np2, long P, long Q, long ip) {")
+        out.append("    double acc = 0.0;")
+        for sg in range(lo, hi):
+            terms = []
+            for i in range(V["seg_lo"][sg], V["seg_hi"][sg]):
+                fac = [f"x[{k}]" for k in V["tidx"][4 * i: 4 * i + 4] if k != LANE_ONE]
+                terms.append(" * ".join([repr(float(V["coef"][i]))] + fac))
+            src = names[V["seg_kind"][sg]].format(i=V["seg_idx"][sg])
+            out.append(f"    acc += {src} * ({' + '.join(terms)});")
+        out.append("    return acc;")
+        out.append("}")
+        out.append("")
+    out.append("#define PQ_LANE_SWITCH(c, acc, ...) \\")
+    out.append("    switch (c) { \\")
+    for c in range(len(V["ch_lo"])):
+        out.append(f"        case {c}: acc = lane_chunk_{c}(__VA_ARGS__); break; \\")
+    out.append("        default: break; \\")
+    out.append("    }")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
 
 
 def eri_quads(size):
@@ -407,6 +524,7 @@ def build_pq_tables() -> PQTables:
     tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
     tb.classes["R2S1"] = _table(29, rows)
     tb.r2_local = build_r2_local(tb)
+    tb.r2_lane = build_r2_lane(tb)
     return tb
 
 
@@ -695,6 +813,18 @@ def emit_pq_header(tb: PQTables, path: str):
                  + _arr("pq_loc_m_start", "int", L["m_start"])
                  + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
                  + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))
+    V = tb.r2_lane
+    tpack = [V["tidx"][4 * i] | (V["tidx"][4 * i + 1] << 8) | (V["tidx"][4 * i + 2] << 16)
+             | (V["tidx"][4 * i + 3] << 24) for i in range(len(V["coef"]))]
+    parts.append(_arr("pq_lane_coef", "double", V["coef"]) + _arr("pq_lane_tidx", "unsigned", tpack)
+                 + _arr("pq_lane_seg_kind", "int", V["seg_kind"]) + _arr("pq_lane_seg_idx", "int", V["seg_idx"])
+                 + _arr("pq_lane_seg_lo", "int", V["seg_lo"]) + _arr("pq_lane_seg_hi", "int", V["seg_hi"])
+                 + _arr("pq_lane_ch_lo", "int", V["ch_lo"]) + _arr("pq_lane_ch_hi", "int", V["ch_hi"])
+                 + _arr("pq_lane_m_start", "int", V["m_start"])
+                 + f"#define PQ_LANE_NCHUNK {len(V['ch_lo'])}\n#define PQ_LANE_NLOC {LANE_NLOC}\n"
+                 + f"#define PQ_LANE_MAXS {max(h - l for l, h in zip(V['ch_lo'], V['ch_hi']))}\n"
+                 + f"#define PQ_LANE_MAXT {max(V['seg_hi'][h - 1] - V['seg_lo'][l] for l, h in zip(V['ch_lo'], V['ch_hi']))}\n"
+                 + f"#define PQ_LANE_ONE {LANE_ONE}\n#define PQ_LANE_T2 {LANE_T2}\n")
     # link specs of the two-spectator sums, decoded: every factor is
     # t2[m][P or Q][spectator]; up to 3 factors
     ln, lm, lq = [], [], []

@@ -17,8 +17,9 @@ def unpack_factor(code):
 
 
 class Emu:
-    def __init__(self, tb, N, f, eri):
+    def __init__(self, tb, N, f, eri, lane=False):
         self.tb, self.N, self.f, self.eri = tb, N, f, eri
+        self.lane = lane          # evaluate the two-pair local terms through the lane tables
         self.np2 = comb(N, 2)
         self.h1 = np.zeros((len(tb.h1_keys), N))
         self.h2 = np.zeros((len(tb.h2_keys), N, N))
@@ -101,6 +102,30 @@ class Emu:
             v *= self.fval(int(c), lab)
         return v
 
+    def r2_lane_sum(self, P, Q, Spairs):
+        """No- and one-spectator terms of the two-pair outputs through the
+        lane tables (streamed factor x staged amplitudes of the pair)."""
+        tb, N = self.tb, self.N
+        V = tb.r2_lane
+        loc = np.zeros(36)
+        loc[0:3] = self.t1[:, P]
+        loc[3:6] = self.t1[:, Q]
+        loc[6:35] = self.t2[:, P, Q]
+        loc[35] = 1.0
+        out = np.zeros(29)
+        for m in range(29):
+            for c in range(V["m_start"][m], V["m_start"][m + 1]):
+                for sg in range(V["ch_lo"][c], V["ch_hi"][c]):
+                    kind, idx = V["seg_kind"][sg], V["seg_idx"][sg]
+                    sv = (self.h1[idx, P] if kind == 0 else self.h1[idx, Q] if kind == 1
+                          else self.h2[idx, P, Q] if kind == 2 else Spairs[idx, P, Q])
+                    s = 0.0
+                    for i in range(V["seg_lo"][sg], V["seg_hi"][sg]):
+                        k = V["tidx"][4 * i: 4 * i + 4]
+                        s += V["coef"][i] * loc[k[0]] * loc[k[1]] * loc[k[2]] * loc[k[3]]
+                    out[m] += sv * s
+        return out
+
     def r1s2_factorised(self):
         """One-pair two-spectator terms through the X.Z.Y groups (amplitudes
         already set): M = G Mid per group, closed by each row of C."""
@@ -173,8 +198,11 @@ class Emu:
         Spairs = np.einsum("xpa,xqa->xpq", X[tb.r2s1_pairs[:, 0]], Y[tb.r2s1_pairs[:, 1]])
         for Q in range(N):
             for P in range(Q):
-                acc = self.interp(C["R2S0"], (P, Q))
-                acc += self.interp(C["R2S1"], (P, Q), S=lambda i: Spairs[i, P, Q])
+                if self.lane:
+                    acc = self.r2_lane_sum(P, Q, Spairs)
+                else:
+                    acc = self.interp(C["R2S0"], (P, Q))
+                    acc += self.interp(C["R2S1"], (P, Q), S=lambda i: Spairs[i, P, Q])
                 specA = [A for A in range(N) if A not in (P, Q)]
                 Lv = {}
                 for li, sp in enumerate(tb.r2s2_l):

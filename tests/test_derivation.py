@@ -35,13 +35,16 @@ def tables():
     return build_pq_tables()
 
 
+@pytest.mark.parametrize("lane", [False, True])
 @pytest.mark.parametrize("N", [3, 4])
-def test_kernel_tables_reproduce_definitional_residual(tables, N):
+def test_kernel_tables_reproduce_definitional_residual(tables, N, lane):
+    """Both evaluation orders of the two-pair local terms (pair-local
+    interpretation and lane-per-pair streamed factors)."""
     from pq_table_emulator import Emu
     f, eri = _system(N, 500 + N)
     t = random_amplitudes(N, "pq", seed=600 + N, scale=0.1)
     RA, EA = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
-    em = Emu(tables, N, f, eri)
+    em = Emu(tables, N, f, eri, lane=lane)
     assert np.abs(em.residual(t) - RA).max() < 1e-13 * max(1.0, np.abs(RA).max())
     assert abs(em.energy(t) - EA) < 1e-13
 
