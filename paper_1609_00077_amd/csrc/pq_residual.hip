@@ -241,69 +241,96 @@ __device__ __forceinline__ double link_at(const Link& L, int A) {
 }
 
 // ------------------------------------------------------------ one spectator
-constexpr int GT = 16;
-constexpr int GP = 16;   // (x, y) pairs per workgroup
 
 // S[p][pq] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
 // matrix cores (v_mfma_f64_16x16x4f64: A[i][k] at lane i+16k, B[k][j] at lane
-// j+16k, D[(lane>>4)+4r][lane&15] in register r).  Workgroup: one upper-
-// triangular 16x16 tile of (P, Q) and GP consecutive pairs p (4 per
-// wavefront); the results are staged in LDS and written p-major (the lane-
-// per-pair epilogue reads S_p for consecutive output pairs contiguously).
-// Zero diagonals of X and Y keep A != P, Q.
+// j+16k, D[(lane>>4)+4r][lane&15] in register r).  Workgroup: one pair p and
+// up to S1_TPW upper-triangular 16x16 tiles of (P, Q) per wavefront; the rows
+// of X_x and Y_y are staged through LDS in K-chunks of 16 (row pitch 17:
+// conflict-free operand reads), so each operand element is fetched once per
+// workgroup.  Each finished tile is transposed through LDS and written as
+// 128-byte runs of consecutive pq (S is p-major: the lane-per-pair epilogue
+// reads S_p for consecutive output pairs).  Zero diagonals of X and Y keep
+// A != P, Q.  Workgroups are dealt out XCD by XCD, so consecutive pairs
+// (numbered in (x, y) order, sharing X_x) run on one XCD's L2.
 typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int S1_TPW = 4;                 // tiles per wavefront
+constexpr int S1_TPG = 4 * S1_TPW;        // tiles per workgroup
+constexpr int S1_PITCH = 17;
+
+inline __device__ void tile_of(int t, int nt, int& tP, int& tQ) {
+    tP = 0;
+    while (t >= nt - tP) { t -= nt - tP; ++tP; }
+    tQ = tP + t;
+}
 
 __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
-                                                 double* __restrict__ ST, const int* __restrict__ gate) {
+                                                 double* __restrict__ SK, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int nt = (N + GT - 1) / GT;
-    const int ntile = nt * (nt + 1) / 2;
-    const int nitem = ntile * ((PQ_S1PAIRS_N + GP - 1) / GP);
-    // XCD-aware order: workgroup b runs on XCD b % 8, so item ranges are dealt
-    // out per XCD and the tiles of one pair chunk (which read the same X and
-    // Y) share that XCD's L2
-    const int per = (int)(gridDim.x / 8);
-    const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    extern __shared__ double sm[];
+    const int nt = (N + 15) / 16, NR = nt * 16, ntile = nt * (nt + 1) / 2;
+    const int ngrp = (ntile + S1_TPG - 1) / S1_TPG;
+    const long nitem = (long)ngrp * PQ_S1PAIRS_N;
+    const long per = gridDim.x / 8;
+    const long w = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= nitem) return;
-    int tP = 0, rem = w % ntile;
-    while (rem >= nt - tP) { rem -= nt - tP; ++tP; }
-    const int tQ = tP + rem;
-    const int p0 = (w / ntile) * GP;
+    const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
+    double* Xs = sm;                         // [NR][S1_PITCH]
+    double* Ys = Xs + NR * S1_PITCH;         // [NR][S1_PITCH]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double* Ts = Ys + NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
     const long NN = (long)N * N;
-    __shared__ double res[GT * GT][GP + 1];
+    const double* Xp = X + (long)pq_s1pairs[2 * p] * NN;
+    const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN;
     const int i = lane & 15, kq = lane >> 4;
-    const int Pi = tP * GT + i, Qi = tQ * GT + i;
-    const bool okP = Pi < N, okQ = Qi < N;
-    const int KP = (N + 3) & ~3;
-    for (int jj = 0; jj < GP / 4; ++jj) {
-        const int j = wave * (GP / 4) + jj;
-        const int p = p0 + j;
-        d4 D = {0.0, 0.0, 0.0, 0.0};
-        if (p < PQ_S1PAIRS_N) {
-            const double* Xp = X + (long)pq_s1pairs[2 * p] * NN + (long)(okP ? Pi : 0) * N;
-            const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN + (long)(okQ ? Qi : 0) * N;
-#pragma unroll 6
-            for (int k4 = 0; k4 < KP; k4 += 4) {
-                const int A = k4 + kq;
-                const double a = (okP && A < N) ? Xp[A] : 0.0;
-                const double b = (okQ && A < N) ? Yp[A] : 0.0;
-                D = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, D, 0, 0, 0);
-            }
-        }
+    int tP[S1_TPW], tQ[S1_TPW];
+    bool tv[S1_TPW];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) res[(kq + 4 * r) * GT + i][j] = D[r];
+    for (int u = 0; u < S1_TPW; ++u) {
+        const int t = tg * S1_TPG + wave + 4 * u;
+        tv[u] = t < ntile;
+        tile_of(tv[u] ? t : 0, nt, tP[u], tQ[u]);
     }
-    __syncthreads();
-    // S-major output S[p][pq]: consecutive threads take consecutive P of one
-    // Q, i.e. consecutive pq (128-byte runs)
+    d4 D[S1_TPW];
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) D[u] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < N; kc += 16) {
+        __syncthreads();
+        for (int e = tid; e < NR * 16; e += 256) {
+            const int r = e >> 4, k = e & 15, A = kc + k;
+            const bool in = r < N && A < N;
+            Xs[r * S1_PITCH + k] = in ? Xp[(long)r * N + A] : 0.0;
+            Ys[r * S1_PITCH + k] = in ? Yp[(long)r * N + A] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < S1_TPW; ++u) {
+            if (!tv[u]) continue;
+            const double* xa = Xs + (tP[u] * 16 + i) * S1_PITCH + kq;
+            const double* yb = Ys + (tQ[u] * 16 + i) * S1_PITCH + kq;
+#pragma unroll
+            for (int k4 = 0; k4 < 16; k4 += 4)
+                D[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k4], yb[k4], D[u], 0, 0, 0);
+        }
+    }
     const long np2 = (long)N * (N - 1) / 2;
-    for (int e = tid; e < GT * GT * GP; e += 256) {
-        const int j = e / (GT * GT), q = (e / GT) % GT, pl = e % GT;
-        const int P = tP * GT + pl, Q = tQ * GT + q;
-        if (P < Q && Q < N && p0 + j < PQ_S1PAIRS_N)
-            ST[(long)(p0 + j) * np2 + (long)Q * (Q - 1) / 2 + P] = res[pl * GT + q][j];
+    double* out = SK + (long)p * np2;
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) {
+        if (!tv[u]) continue;
+        // D[u][r] = S(P = tP*16 + kq + 4r, Q = tQ*16 + i): stage as Ts[Ql][Pl]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ts[i * S1_PITCH + kq + 4 * r] = D[u][r];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int e = lane; e < 256; e += 64) {
+            const int ql = e >> 4, pl = e & 15;
+            const int P = tP[u] * 16 + pl, Q = tQ[u] * 16 + ql;
+            if (P < Q && Q < N) out[(long)Q * (Q - 1) / 2 + P] = Ts[ql * S1_PITCH + pl];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -1178,11 +1205,28 @@ inline int s2_rowtiles(int N) {
     return (int)((np2 + M2_ROWS - 1) / M2_ROWS);
 }
 
-// 1-D grid of k_gemm_s1: all (tile, pair chunk) items, padded to a multiple of 8
+// 1-D grid of k_gemm_s1: all (pair, tile group) items, padded to a multiple of 8
 inline unsigned gemm_s1_grid(int N) {
-    const int nt = (N + GT - 1) / GT;
-    const long nitem = (long)nt * (nt + 1) / 2 * ((PQ_S1PAIRS_N + GP - 1) / GP);
+    const int nt = (N + 15) / 16, ntile = nt * (nt + 1) / 2;
+    const long nitem = (long)((ntile + S1_TPG - 1) / S1_TPG) * PQ_S1PAIRS_N;
     return (unsigned)((nitem + 7) / 8 * 8);
+}
+
+inline size_t gemm_s1_lds(int N) {
+    const int NR = (N + 15) / 16 * 16;
+    return (size_t)(2 * NR * S1_PITCH + 4 * 16 * S1_PITCH) * sizeof(double);
+}
+
+// allows the largest staging (npair 256) once per process
+pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
+    static bool done = false;
+    if (done) return PQPH_OK;
+    hipError_t e = hipFuncSetAttribute((const void*)&k_gemm_s1, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)gemm_s1_lds(256));
+    if (e != hipSuccess)
+        return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
+    done = true;
+    return PQPH_OK;
 }
 
 // group chunks of the factorised one-pair two-spectator kernel (N >= 3)
@@ -1312,7 +1356,9 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), 0, s, N, c.X, c.Y, c.S, gate);
+        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
+        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, c.X, c.Y, c.S,
+                           gate);
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
@@ -1450,7 +1496,9 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
         hipLaunchKernelGGL(k_dress, dim3(gsq, PQ_DR_N), dim3(256), 0, s, N, c.Lam, c.W, c.D, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, nullptr);
-        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), 0, s, N, c.X, c.Y, c.S, nullptr);
+        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
+        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, c.X, c.Y, c.S,
+                           nullptr);
         {
             const size_t bytes =
                 (size_t)(2 * R2A_PPW * PQ_LOC_N + R2A_PPW * NP2) * sizeof(double);

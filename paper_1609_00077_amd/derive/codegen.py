@@ -521,7 +521,14 @@ def build_pq_tables() -> PQTables:
     rows = _merge_rows(rows)
     tb.r2s1_x = [list(x) for x in sorted(xs, key=xs.get)]
     tb.r2s1_y = [list(y) for y in sorted(ys, key=ys.get)]
-    tb.r2s1_pairs = np.array(sorted(pairs, key=pairs.get), dtype=np.int32).reshape(-1, 2)
+    # number the (x, y) pairs in (x, y) order: pairs sharing a side are
+    # neighbours, so the contraction's workgroups that read the same X run
+    # together (on one XCD, see k_gemm_s1)
+    order = sorted(pairs, key=lambda xy: xy)
+    renum = {pairs[xy]: k for k, xy in enumerate(order)}
+    rows = [(m, c, [fcode(KIND_S, [], renum[code & 0xFFFF]) if (code >> 28) & 15 == KIND_S else code
+                    for code in codes]) for m, c, codes in rows]
+    tb.r2s1_pairs = np.array(order, dtype=np.int32).reshape(-1, 2)
     tb.classes["R2S1"] = _table(29, rows)
     tb.r2_local = build_r2_local(tb)
     tb.r2_lane = build_r2_lane(tb)
