@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--grad-sites", type=int, default=400)
     return ap.parse_args()
 
 
@@ -135,6 +137,34 @@ def batch_leg(args, pq, torch, dev):
                 max((abs(res.energies[i] - resl.energies[i]) for i in ok), default=None)}
 
 
+def grad_leg(args, pq, torch, dev):
+    """PQ energy + adjoint gradient config: a 400-site chain (200 pairs).
+    Times the energy alone (integrals given; solve from t = 0) and the energy
+    with dE/dh and dE/d(eri) (the same solve, the lambda equations and the
+    transposed contraction), on the stream, after one warm-up of each."""
+    from inputs import chain_problem
+    prob = chain_problem(args.grad_sites, U=4.0, seed=args.grad_sites)
+    d = lambda x: torch.as_tensor(x, device=dev).contiguous()
+    f, eri = pq.integrals(d(prob.F_site), d(prob.V), d(prob.C), k=2)
+    pq.pq_solve(f, eri, tol=args.tol)
+    pq.pq_energy_grad(f, eri, tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = pq.pq_solve(f, eri, tol=args.tol)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = pq.pq_energy_grad(f, eri, tol=args.tol)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    return {"sites": args.grad_sites, "pairs": prob.npair, "energy": res.energy,
+            "energy_s": te, "energy_grad_s": tg, "grad_energy_ratio": tg / te,
+            "t_iterations": res.iterations, "lambda_iterations": g.iterations,
+            "grad_status": g.status,
+            "homogeneity_residual": abs(float(torch.sum(g.dE_dh * f) + torch.sum(g.dE_deri * eri))
+                                        - g.energy)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,6 +256,8 @@ def main():
         "residual_compulsory_bytes": workmodel.pq_compulsory_bytes(N),
         "kernel_ms": acc,
     }
+    if not args.no_grad:
+        line["energy_gradient"] = grad_leg(args, pq, torch, dev)
     if not args.no_batch:
         line["batched"] = batch_leg(args, pq, torch, dev)
     if not args.no_cpu_baseline:
