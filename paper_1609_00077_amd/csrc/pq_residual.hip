@@ -155,14 +155,16 @@ __device__ __forceinline__ const int* spec_start(int which) {
          : which == 1 ? pq_y_start
          : which == 2 ? pq_w_start
          : which == 3 ? pq_l_start
-                      : pq_lam_start;
+         : which == 4 ? pq_lam_start
+                      : pq_r1f_start;
 }
 __device__ __forceinline__ const int* spec_fac(int which) {
     return which == 0 ? pq_x_fac
          : which == 1 ? pq_y_fac
          : which == 2 ? pq_w_fac
          : which == 3 ? pq_l_fac
-                      : pq_lam_fac;
+         : which == 4 ? pq_lam_fac
+                      : pq_r1f_fac;
 }
 
 // grid (ceil(N*N/256), number of specs): thread -> ordered label pair (L0, L1)
@@ -828,33 +830,84 @@ __device__ __forceinline__ void class_adj(const int* start, const double* coef, 
 }
 
 // one-pair outputs: weights lam1[k][P]
-__global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __restrict__ lam, int nch,
+__global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __restrict__ lam,
                                                 AdjView a) {
-    const int P = blockIdx.x, ch = blockIdx.y, tid = threadIdx.x;
+    const int P = blockIdx.x, tid = threadIdx.x;
     const double l0 = lam[P], l1 = lam[N + P], l2 = lam[2 * N + P];
-    if (ch == 0) {
-        if (tid == 0) {
-            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, l0, P, 0, 0, 0, v, a);
-            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, l1, P, 0, 0, 0, v, a);
-            class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, l2, P, 0, 0, 0, v, a);
-        }
-        for (int A = tid; A < N; A += blockDim.x) {
-            if (A == P) continue;
-            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, l0, P, A, 0, 0, v, a);
-            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, l1, P, A, 0, 0, v, a);
-            class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, l2, P, A, 0, 0, v, a);
-        }
+    if (tid == 0) {
+        class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, l0, P, 0, 0, 0, v, a);
+        class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, l1, P, 0, 0, 0, v, a);
+        class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, l2, P, 0, 0, 0, v, a);
     }
+    for (int A = tid; A < N; A += blockDim.x) {
+        if (A == P) continue;
+        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, l0, P, A, 0, 0, v, a);
+        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, l1, P, A, 0, 0, v, a);
+        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, l2, P, A, 0, 0, v, a);
+    }
+}
+
+// adjoint of the factorised one-pair two-spectator terms (k_r1s2): per group
+// and tile of R1A_PB output pairs P, with M = G Mid recomputed,
+//   Mbar(P,j) = sum_i c_i lam_{mu_i}(P) C_i(P,j),  Cbar_i(P,j) += c_i lam_{mu_i}(P) M(P,j),
+//   Gbar = Mbar Mid^T,  Midbar += G^T Mbar   (into Fb, the adjoints of F)
+constexpr int R1A_PB = 8;
+
+__global__ __launch_bounds__(256) void k_r1s2_adj(int N, const double* __restrict__ F,
+                                                  const double* __restrict__ lam,
+                                                  double* __restrict__ Fb) {
+    extern __shared__ double sm[];
+    double* Gs = sm;                     // [R1A_PB][N]
+    double* Mbs = Gs + R1A_PB * N;       // [R1A_PB][N]
+    const int P0 = blockIdx.x * R1A_PB, g = blockIdx.y, tid = threadIdx.x;
     const long NN = (long)N * N;
-    const long per = (NN + nch - 1) / nch;
-    const long lo = (long)ch * per, hi = min(NN, lo + per);
-    for (long ab = lo + tid; ab < hi; ab += blockDim.x) {
-        const int A = (int)(ab / N), B = (int)(ab % N);
-        if (A == P || B == P || A == B) continue;
-        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 0, 0.5 * l0, P, A, B, 0, v, a);
-        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 1, 0.5 * l1, P, A, B, 0, v, a);
-        class_adj(pq_r1s2_start, pq_r1s2_coef, pq_r1s2_fac, 2, 0.5 * l2, P, A, B, 0, v, a);
+    const int gen = pq_r1g_gen[g], mid = pq_r1g_mid[g];
+    const double* G = F + (long)gen * NN;
+    const double* Mid = F + (long)mid * NN;
+    for (int e = tid; e < R1A_PB * N; e += blockDim.x) {
+        const int p = e / N, k = e - p * N;
+        Gs[e] = (P0 + p < N) ? G[(long)(P0 + p) * N + k] : 0.0;
     }
+    __syncthreads();
+    for (int e = tid; e < R1A_PB * N; e += blockDim.x) {
+        const int p = e / N, j = e - p * N, P = P0 + p;
+        double mb = 0.0;
+        if (P < N) {
+            double m = 0.0;
+            for (int k = 0; k < N; ++k) m += Gs[p * N + k] * Mid[(long)k * N + j];
+            for (int i = pq_r1g_start[g]; i < pq_r1g_start[g + 1]; ++i) {
+                const int cl = pq_r1g_cl[i];
+                const double w = pq_r1g_coef[i] * lam[(long)pq_r1g_mu[i] * N + P];
+                mb += w * F[(long)cl * NN + (long)P * N + j];
+                if (w * m != 0.0) atomicAdd(&Fb[(long)cl * NN + (long)P * N + j], w * m);
+            }
+        }
+        Mbs[e] = mb;
+    }
+    __syncthreads();
+    for (int e = tid; e < R1A_PB * N; e += blockDim.x) {
+        const int p = e / N, k = e - p * N, P = P0 + p;
+        if (P >= N) continue;
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) s += Mbs[p * N + j] * Mid[(long)k * N + j];
+        if (s != 0.0) atomicAdd(&Fb[(long)gen * NN + (long)P * N + k], s);
+    }
+    for (long e = tid; e < NN; e += blockDim.x) {
+        const int k = (int)(e / N), j = (int)(e - (long)k * N);
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < R1A_PB; ++p) s += Gs[p * N + k] * Mbs[p * N + j];
+        if (s != 0.0) atomicAdd(&Fb[(long)mid * NN + e], s);
+    }
+}
+
+// Fb_z(a,b) += Fb_{z transposed}(b,a) for the Z products of the one-pair class
+__global__ void k_fold_r1z(int N, double* __restrict__ Fb) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y, z = blockIdx.z;
+    if (b >= N) return;
+    const long NN = (long)N * N;
+    Fb[(long)(PQ_R1F_Z0 + z) * NN + (long)a * N + b] += Fb[(long)(PQ_R1F_N + z) * NN + (long)b * N + a];
 }
 
 __global__ void k_energy_adj(int N, View v, double ew, AdjView a) {
@@ -1459,7 +1512,7 @@ size_t pq_adj_doubles(int N) {
     const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
     return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_DR_N + PQ_LAM_N) * NN +
-           (size_t)PQ_S1PAIRS_N * np2 + 8;
+           r1f_size(N) + (size_t)PQ_S1PAIRS_N * np2 + 8;
 }
 
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
@@ -1483,6 +1536,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     double* Wb = p; p += 2 * (size_t)PQ_W_N * NN;      // adjoints of W and of its transposes
     double* Db = p; p += (size_t)PQ_DR_N * NN;
     double* Lamb = p; p += (size_t)PQ_LAM_N * NN;
+    double* F1b = p; p += r1f_size(N);
     a.Wb = Wb;
     a.Db = Db;
     double* Sb = p;
@@ -1533,7 +1587,15 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
         hipLaunchKernelGGL(k_fold_wt, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, Wb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, Wb, a);
     }
-    hipLaunchKernelGGL(k_r1_adj, dim3(N, c.nch1), dim3(256), 0, s, N, v, lam, c.nch1, a);
+    hipLaunchKernelGGL(k_r1_adj, dim3(N), dim3(256), 0, s, N, v, lam, a);
+    if (N >= 3) {
+        const unsigned gsq3 = (unsigned)((N * N + 255) / 256);
+        hipLaunchKernelGGL(k_spec_r1, dim3(gsq3, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, nullptr);
+        hipLaunchKernelGGL(k_r1s2_adj, dim3((N + R1A_PB - 1) / R1A_PB, PQ_R1G_N), dim3(256),
+                           (size_t)2 * R1A_PB * N * sizeof(double), s, N, c.F1, lam, F1b);
+        hipLaunchKernelGGL(k_fold_r1z, dim3(gx, N, PQ_R1F_N - PQ_R1F_Z0), dim3(tb), 0, s, N, F1b);
+        hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_R1F_N), dim3(tb), 0, s, N, 5, v, F1b, a);
+    }
     if (ew != 0.0)
         hipLaunchKernelGGL(k_energy_adj, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, N, v, ew,
                            a);
