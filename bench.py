@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--counter-run", type=int, default=0,
+                    help="only run this many 140-site residuals and a 256 MiB copy (for rocprofv3 --pmc)")
     ap.add_argument("--grad-sites", type=int, default=400)
     return ap.parse_args()
 
@@ -165,11 +167,61 @@ def grad_leg(args, pq, torch, dev):
                                         - g.energy)}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "pq_residual_counters_pq140.json")
+# dense contractions on the FP64 matrix cores (peak 78.6 TFLOP/s, the same as FP64 vector)
+MFMA_KERNELS = {"k_gemm_s1", "k_r2s2"}
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources and generated-table inputs: counters taken
+    from an older build do not describe the current kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for sub in ("paper_1609_00077_amd/csrc", "paper_1609_00077_amd/derive"):
+        d = os.path.join(ROOT, sub)
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".h", ".py")) and not name.startswith(("pq_tables", "pq_lane_code")):
+                with open(os.path.join(d, name), "rb") as fh:
+                    h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def hbm_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
+    WRITE_SIZE counter runs, each scaled by the same counter's reading for a
+    copy of known size; None when absent or taken on other sources."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as fh:
+        c = json.load(fh)
+    if c.get("source_hash") != source_hash() or kernel not in c.get("kernels", {}):
+        return None
+    k = c["kernels"][kernel]
+    return 1024.0 * (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"])
+
+
+def counter_run(args, pq, torch, dev):
+    from inputs import chain_problem, random_amplitudes
+    prob = chain_problem(args.sites, U=args.U, seed=args.seed)
+    d = lambda x: torch.as_tensor(x, device=dev).contiguous()
+    f, eri = pq.integrals(d(prob.F_site), d(prob.V), d(prob.C), k=2)
+    t = d(random_amplitudes(prob.npair, "pq", seed=1400, scale=0.05))
+    r = torch.empty_like(t)
+    for _ in range(args.counter_run):
+        pq.pq_residual(f, eri, t, out=r)
+    torch.cuda.synchronize()
+    a = torch.full((32 * 1024 * 1024,), 1.0, dtype=torch.float64, device=dev)   # 256 MiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_run": args.counter_run, "copy_bytes": a.numel() * 8,
+                      "source_hash": source_hash()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design in DESIGN.md)"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
@@ -178,6 +230,8 @@ def main():
     from inputs import chain_problem
 
     dev = torch.device("cuda:0")
+    if args.counter_run:
+        return counter_run(args, pq, torch, dev)
     prob = chain_problem(args.sites, U=args.U, seed=args.seed)
     N = prob.npair
     F = torch.as_tensor(prob.F_site, device=dev).contiguous()
@@ -246,8 +300,9 @@ def main():
                                "integral transform included", "sites": args.sites, "pairs": N,
                    "iterations_per_solve": res.iterations, "energy": res.energy,
                    "s2_variant": variant},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+        "roofline": {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom,
+                     "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": hbm_traffic(dom),
                      "flops_per_launch": flops[dom], "ms_per_launch": acc[dom]},
         "residual_ms": resid_ms,
         "residual_evals_per_s_back_to_back": 1e3 / resid_ms,

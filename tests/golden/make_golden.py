@@ -2,7 +2,7 @@
 
 Calls only oracle/ and the seeded input generators.  Each fixture holds the
 residual of a few sampled output blocks (by sub-cluster inclusion-exclusion,
-Sec. II) and the correlation energy for the 140-site PPP chain (BASELINE
+Sec. II) and the correlation energy for the 140-site PPP chain (the benchmark
 workload: 140 electrons in 140 orbitals, 70 pairs) at seeded amplitudes.
 
     python tests/golden/make_golden.py [name ...]
