@@ -187,30 +187,6 @@ __global__ __launch_bounds__(256) void k_spec(int N, int which, View v, double* 
     if (which == 2) out[(long)(PQ_W_N + s) * v.NN + (long)L1 * N + L0] = x;
 }
 
-// Dressed vertices D_k(s, A) = sum_B lambda(s, B) W(A, B) over every label B
-// (lambda = the one-sided link of the reduced two-spectator terms, or 1); W is
-// read through its stored transpose so that threads over A load contiguously.
-__global__ __launch_bounds__(256) void k_dress(int N, const double* __restrict__ lam,
-                                               const double* __restrict__ W, double* __restrict__ D,
-                                               const int* __restrict__ gate) {
-    if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (e >= N * N) return;
-    const int s = e / N, A = e - s * N;
-    const long NN = (long)N * N;
-    const int li = pq_dr_lam[k], we = pq_dr_w[k];
-    const int wt = we < PQ_W_N ? we + PQ_W_N : we - PQ_W_N;
-    const double* Wt = W + (long)wt * NN;          // Wt[B][A] = W_we[A][B]
-    double x = 0.0;
-    if (li < 0) {
-        for (int B = 0; B < N; ++B) x += Wt[(long)B * N + A];
-    } else {
-        const double* L = lam + (long)li * NN + (long)s * N;
-        for (int B = 0; B < N; ++B) x += L[B] * Wt[(long)B * N + A];
-    }
-    D[(long)k * NN + (long)s * N + A] = x;
-}
 
 __device__ __forceinline__ double spec_l(int s, int P, int Q, int A, const View& v) {
     double x = 1.0;
@@ -336,9 +312,90 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
     }
 }
 
+// Batched dense products C_g = A_g B_g^T of N x N row-major matrices on the
+// FP64 matrix cores, with the staging and tiling of k_gemm_s1 (full square
+// output, written directly: for fixed r the 16 lanes of a row hold 16
+// consecutive columns).  which = 0: dressed vertices D_k = lambda_k W_k^T
+// (lambda = 1 everywhere when its index is negative); which = 1: the one-pair
+// two-spectator products M_g = G_g Mid_g = G_g (Mid_g^T)^T.
+// Workgroup: one row block tP of C and the 4 column blocks tQ = 4 tq4 .. +3
+// (one per wavefront); only those rows of A and B are staged per K-chunk.
+__global__ __launch_bounds__(256) void k_bgemm(int N, int which, const double* __restrict__ Abase,
+                                               const double* __restrict__ Bbase,
+                                               double* __restrict__ Cbase, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    __shared__ double As[16 * S1_PITCH];
+    __shared__ double Bs[64 * S1_PITCH];
+    const int nt = (N + 15) / 16;
+    const int tP = blockIdx.x % nt, tq4 = blockIdx.x / nt, g = blockIdx.y;
+    const long NN = (long)N * N;
+    const int ai = which == 0 ? pq_dr_lam[g] : pq_r1g_gen[g];
+    const int bi = which == 0 ? pq_dr_w[g] : pq_r1g_midT[g];
+    const double* A = Abase + (long)(ai >= 0 ? ai : 0) * NN;
+    const double* B = Bbase + (long)bi * NN;
+    double* C = Cbase + (long)g * NN;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, kq = lane >> 4;
+    const int tQ = tq4 * 4 + wave;
+    d4 D = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < N; kc += 16) {
+        __syncthreads();
+        {
+            const int r = tid >> 4, k = tid & 15, K = kc + k, row = tP * 16 + r;
+            As[r * S1_PITCH + k] = (row < N && K < N) ? (ai >= 0 ? A[(long)row * N + K] : 1.0) : 0.0;
+        }
+        for (int e = tid; e < 64 * 16; e += 256) {
+            const int r = e >> 4, k = e & 15, K = kc + k, row = tq4 * 64 + r;
+            Bs[r * S1_PITCH + k] = (row < N && K < N) ? B[(long)row * N + K] : 0.0;
+        }
+        __syncthreads();
+        if (tQ < nt) {
+            const double* xa = As + i * S1_PITCH + kq;
+            const double* yb = Bs + (wave * 16 + i) * S1_PITCH + kq;
+#pragma unroll
+            for (int k4 = 0; k4 < 16; k4 += 4)
+                D = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k4], yb[k4], D, 0, 0, 0);
+        }
+    }
+    if (tQ < nt) {
+        const int Q = tQ * 16 + i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int P = tP * 16 + kq + 4 * r;
+            if (P < N && Q < N) C[(long)P * N + Q] = D[r];
+        }
+    }
+}
+
+// closing of the one-pair two-spectator groups: for output pair P and group g,
+// sum over closers c_i sum_j M_g(P,j) C_i(P,j), written per output pattern to
+// the group's own partial chunk (fixed order, no atomics)
+__global__ __launch_bounds__(64) void k_r1s2_close(int N, const double* __restrict__ F,
+                                                   const double* __restrict__ M, double* __restrict__ part,
+                                                   int chunk0, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    // one wavefront per (P, g): lanes over j (contiguous rows), fixed-order shuffle reduction
+    const int P = blockIdx.x, g = blockIdx.y, lane = threadIdx.x;
+    const long NN = (long)N * N;
+    const double* Mr = M + (long)g * NN + (long)P * N;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = pq_r1g_start[g]; i < pq_r1g_start[g + 1]; ++i) {
+        const double* Cr = F + (long)pq_r1g_cl[i] * NN + (long)P * N;
+        double s = 0.0;
+        for (int j = lane; j < N; j += 64) s += Mr[j] * Cr[j];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        const int mu = pq_r1g_mu[i];
+        const double x = pq_r1g_coef[i] * s;
+        a[0] += mu == 0 ? x : 0.0;
+        a[1] += mu == 1 ? x : 0.0;
+        a[2] += mu == 2 ? x : 0.0;
+    }
+    if (lane < 3) part[((long)(chunk0 + g) * 3 + lane) * N + P] = lane == 0 ? a[0] : (lane == 1 ? a[1] : a[2]);
+}
+
 // ----------------------------------------------------------- one-pair outputs
 // grid (N, nch): workgroup (P, ch) sums the chunk ch of the ordered spectator
-// (two-spectator terms: k_r1s2).
+// (two-spectator terms: k_bgemm and k_r1s2_close).
 // grid.y = 0: the no-spectator terms; grid.y = 1..R1S1_NCH: a chunk of the
 // one-spectator terms for all spectators A (threads over A)
 constexpr int R1S1_TC = 24;
@@ -415,71 +472,6 @@ __global__ __launch_bounds__(256) void k_spec_r1(int N, View v, double* __restri
     if (s >= PQ_R1F_Z0) F[(long)(PQ_R1F_N + s - PQ_R1F_Z0) * v.NN + (long)L1 * N + L0] = x;
 }
 
-// Per group: M(P,j) = sum_k G(P,k) Mid(k,j) with G an X or Y row and Mid a Z
-// or Z^T, closed by r_mu(P) += c sum_j M(P,j) C(P,j) for each closing row C.
-// Workgroup: R1_PB output pairs x all j, a chunk of groups; Mid is read once
-// per R1_PB rows.  Partial sums go to chunk 1 + R1S1_NCH + blockIdx.y of part.
-constexpr int R1_PB = 4;
-
-__global__ __launch_bounds__(256) void k_r1s2(int N, const double* __restrict__ F, int gchunk,
-                                              double* __restrict__ part,
-                                              const int* __restrict__ gate) {
-    if (gate && *gate == 0) return;   // chain finished (batched solves)
-    extern __shared__ double grow[];  // [R1_PB][N]
-    const int P0 = blockIdx.x * R1_PB, ch = blockIdx.y, tid = threadIdx.x;
-    const long NN = (long)N * N;
-    double acc[R1_PB][3];
-#pragma unroll
-    for (int p = 0; p < R1_PB; ++p) acc[p][0] = acc[p][1] = acc[p][2] = 0.0;
-    const int g0 = ch * gchunk, g1 = min(PQ_R1G_N, g0 + gchunk);
-    for (int g = g0; g < g1; ++g) {
-        const double* G = F + (long)pq_r1g_gen[g] * NN;
-        const double* Mid = F + (long)pq_r1g_mid[g] * NN;
-        __syncthreads();
-        for (int i = tid; i < R1_PB * N; i += blockDim.x) {
-            const int p = i / N, k = i % N;
-            grow[i] = (P0 + p < N) ? G[(long)(P0 + p) * N + k] : 0.0;
-        }
-        __syncthreads();
-        for (int j = tid; j < N; j += blockDim.x) {
-            double m[R1_PB];
-#pragma unroll
-            for (int p = 0; p < R1_PB; ++p) m[p] = 0.0;
-            for (int k = 0; k < N; ++k) {
-                const double z = Mid[(long)k * N + j];
-#pragma unroll
-                for (int p = 0; p < R1_PB; ++p) m[p] += grow[p * N + k] * z;
-            }
-            for (int i = pq_r1g_start[g]; i < pq_r1g_start[g + 1]; ++i) {
-                const double* Cl = F + (long)pq_r1g_cl[i] * NN;
-                const double c = pq_r1g_coef[i];
-                const int mu = pq_r1g_mu[i];
-#pragma unroll
-                for (int p = 0; p < R1_PB; ++p) {
-                    const double x = (P0 + p < N) ? c * m[p] * Cl[(long)(P0 + p) * N + j] : 0.0;
-                    acc[p][0] += mu == 0 ? x : 0.0;
-                    acc[p][1] += mu == 1 ? x : 0.0;
-                    acc[p][2] += mu == 2 ? x : 0.0;
-                }
-            }
-        }
-    }
-    __shared__ double red[256];
-#pragma unroll
-    for (int p = 0; p < R1_PB; ++p)
-#pragma unroll
-        for (int mu = 0; mu < 3; ++mu) {
-            __syncthreads();
-            red[tid] = acc[p][mu];
-            __syncthreads();
-            for (int s2 = 128; s2 > 0; s2 >>= 1) {
-                if (tid < s2) red[tid] += red[tid + s2];
-                __syncthreads();
-            }
-            if (tid == 0 && P0 + p < N)
-                part[((long)(1 + R1S1_NCH + ch) * 3 + mu) * N + P0 + p] = red[0];
-        }
-}
 
 // ----------------------------------------------------------- two spectators
 // V(pq, B) = sum_A L_a(P,Q,A) W_w(A,B) is a dense GEMM over the spectator A
@@ -847,7 +839,7 @@ __global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __r
     }
 }
 
-// adjoint of the factorised one-pair two-spectator terms (k_r1s2): per group
+// adjoint of the factorised one-pair two-spectator terms (k_bgemm, k_r1s2_close): per group
 // and tile of R1A_PB output pairs P, with M = G Mid recomputed,
 //   Mbar(P,j) = sum_i c_i lam_{mu_i}(P) C_i(P,j),  Cbar_i(P,j) += c_i lam_{mu_i}(P) M(P,j),
 //   Gbar = Mbar Mid^T,  Midbar += G^T Mbar   (into Fb, the adjoints of F)
@@ -1249,8 +1241,8 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *part, *p1, *p2, *epart, *scal;
-    int nchunk, gchunk, nblkE, nch1, r1gchunk;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p2, *epart, *scal;
+    int nchunk, gchunk, nblkE, nch1;
 };
 
 inline int s2_rowtiles(int N) {
@@ -1270,6 +1262,11 @@ inline size_t gemm_s1_lds(int N) {
     return (size_t)(2 * NR * S1_PITCH + 4 * 16 * S1_PITCH) * sizeof(double);
 }
 
+inline unsigned bgemm_tile_groups(int N) {
+    const int nt = (N + 15) / 16;
+    return (unsigned)(nt * ((nt + 3) / 4));
+}
+
 // allows the largest staging (npair 256) once per process
 pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     static bool done = false;
@@ -1282,20 +1279,11 @@ pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     return PQPH_OK;
 }
 
-// group chunks of the factorised one-pair two-spectator kernel (N >= 3)
-inline void r1s2_chunks(int N, int& nch, int& gchunk) {
-    const int tiles = (N + R1_PB - 1) / R1_PB;
-    nch = std::max(1, std::min(PQ_R1G_N, 2048 / std::max(tiles, 1)));
-    gchunk = (PQ_R1G_N + nch - 1) / nch;
-    nch = (PQ_R1G_N + gchunk - 1) / gchunk;
-}
 
-// partial-sum chunks of the one-pair outputs: 1 + R1S1_NCH from k_r1, the rest from k_r1s2
+// partial-sum chunks of the one-pair outputs: 1 + R1S1_NCH from k_r1, one per group from k_r1s2_close
 inline int r1_chunks(int N) {
     if (N < 3) return 1 + R1S1_NCH;
-    int nch, gchunk;
-    r1s2_chunks(N, nch, gchunk);
-    return 1 + R1S1_NCH + nch;
+    return 1 + R1S1_NCH + PQ_R1G_N;   // one partial chunk per one-pair two-spectator group
 }
 
 inline size_t r1f_size(int N) {
@@ -1325,11 +1313,7 @@ Carve carve(double* ws, int N) {
     c.Lam = take((size_t)PQ_LAM_N * NN);
     c.D = take((size_t)PQ_DR_N * NN);
     c.F1 = take(r1f_size(N));
-    {
-        int nch2 = 0;
-        c.r1gchunk = 0;
-        if (N >= 3) r1s2_chunks(N, nch2, c.r1gchunk);
-    }
+    c.M1 = take((size_t)PQ_R1G_N * NN);
     s2_chunks(N, c.nchunk, c.gchunk);
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
     c.nch1 = r1_chunks(N);
@@ -1349,7 +1333,8 @@ size_t carve_size(int N) {
     return NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
-           (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N);
+           (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
+           (size_t)PQ_R1G_N * NN;
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -1403,7 +1388,9 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_dress, dim3(gsq, PQ_DR_N), dim3(256), 0, s, N, c.Lam, c.W, c.D, gate);
+        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
+        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
+                           c.Lam, c.W, c.D, gate);
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, gate);
         pqph_mark(ctx);
@@ -1468,8 +1455,11 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     if (N >= 3) {
         hipLaunchKernelGGL(k_spec_r1, dim3(gsq, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_r1s2, dim3((N + R1_PB - 1) / R1_PB, c.nch1 - 1 - R1S1_NCH), dim3(256),
-                           (size_t)R1_PB * N * sizeof(double), s, N, c.F1, c.r1gchunk, c.p1, gate);
+        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_R1G_N), dim3(256), 0, s, N, 1,
+                           c.F1, c.F1, c.M1, gate);
+        pqph_mark(ctx);
+        hipLaunchKernelGGL(k_r1s2_close, dim3(N, PQ_R1G_N), dim3(64), 0, s, N, c.F1, c.M1, c.p1,
+                           1 + R1S1_NCH, gate);
         pqph_mark(ctx);
     }
     hipLaunchKernelGGL(k_r1, dim3(N, 1 + R1S1_NCH), dim3(256), 0, s, N, v, c.p1, gate);
@@ -1547,7 +1537,9 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     if (N > 1) {
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, nullptr);
-        hipLaunchKernelGGL(k_dress, dim3(gsq, PQ_DR_N), dim3(256), 0, s, N, c.Lam, c.W, c.D, nullptr);
+        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
+        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
+                           c.Lam, c.W, c.D, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, nullptr);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, nullptr);
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;

@@ -791,6 +791,9 @@ def emit_pq_header(tb: PQTables, path: str):
             r_coef.append(c)
             r_mu.append(m)
         r_start.append(len(r_cl))
+    # transposed middle factor (k_bgemm computes M = G . (Mid^T)^T)
+    r_midT = [(nx + ny + (m - nf)) if m >= nf else (nf + (m - nx - ny)) for m in r_mid]
+    parts.append(_arr("pq_r1g_midT", "int", r_midT))
     parts.append(_arr("pq_r1g_mid", "int", r_mid) + _arr("pq_r1g_gen", "int", r_gen)
                  + _arr("pq_r1g_start", "int", r_start) + _arr("pq_r1g_cl", "int", r_cl)
                  + _arr("pq_r1g_coef", "double", r_coef) + _arr("pq_r1g_mu", "int", r_mu)

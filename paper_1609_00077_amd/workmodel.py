@@ -61,10 +61,8 @@ def pq_kernel_flops(N: int) -> dict:
     # contraction over N labels and a dot per closing product
     r1f = tb.r1s2_x + tb.r1s2_y + tb.r1s2_z
     out["k_spec_r1"] = _spec_cost(r1f) * N * (N - 1)
-    r = 0.0
-    for _, lst in tb.r1s2_groups:
-        r += 2.0 * N * N + 3.0 * N * len(lst)
-    out["k_r1s2"] = r * N
+    out["k_r1s2"] = 2.0 * len(tb.r1s2_groups) * N * N * N          # M = G Mid per group
+    out["k_r1s2_close"] = 2.0 * N * N * sum(len(l) for _, l in tb.r1s2_groups)
     out["k_final"] = float((3 * N + 29 * np2) * 4)
     return out
 
