@@ -691,12 +691,14 @@ __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
     double s = 0.0;
     if (gid < n1) {
         const int k = (int)(gid / N), P = (int)(gid % N);
+#pragma unroll 8
         for (int c = 0; c < nch1; ++c) s += p1[((long)c * 3 + k) * N + P];
     } else {
         const long g2 = gid - n1;
         const int m = (int)(g2 / np2);
         const long ip = g2 - (long)m * np2;
         for (int c = pq_lane_m_start[m]; c < pq_lane_m_start[m + 1]; ++c) s += p2[(long)c * np2 + ip];
+#pragma unroll 8
         for (int c = 0; c < nchunk; ++c) s += ps2[(long)c * NP2 * np2 + g2];
     }
     R[gid] = s;
@@ -1292,7 +1294,7 @@ inline size_t r1f_size(int N) {
 
 inline void s2_chunks(int N, int& nchunk, int& gchunk) {
     const int rt = std::max(1, s2_rowtiles(N));
-    nchunk = std::min(64, std::max(1, (2048 + rt - 1) / rt));
+    nchunk = std::min(64, std::max(1, (1024 + rt - 1) / rt));
     gchunk = (PQ_G_N + nchunk - 1) / nchunk;
     nchunk = (PQ_G_N + gchunk - 1) / gchunk;
 }
