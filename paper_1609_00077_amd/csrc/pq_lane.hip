@@ -43,7 +43,56 @@ __global__ __launch_bounds__(256) void k_r2c(int N, const double* __restrict__ t
     if (ip < np2) part[(long)c * np2 + ip] = acc;
 }
 
+// One-pair outputs, one spectator: one workgroup per output pair P, one
+// wavefront per chunk of terms, lanes over the spectator A (A = lane + 64 j).
+// The staged amplitudes of P, A and (P, A) are in registers, the vertices
+// h1(A) and h2(P, A) are streamed (contiguous over A), the terms are
+// generated straight-line code.  Each wavefront reduces its lanes in a fixed
+// shuffle order and writes part[chunk][k][P].
+__global__ __launch_bounds__(256) void k_r1c(int N, const double* __restrict__ t,
+                                             const double* __restrict__ t2,
+                                             const double* __restrict__ h1,
+                                             const double* __restrict__ h2,
+                                             double* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    const long NN = (long)N * N;
+    const int P = blockIdx.x, c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (c >= PQ_R1L_NCHUNK) return;
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int A = lane; A < N; A += 64) {
+        if (A == P) continue;
+        double x[36];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            x[i] = t[(long)i * N + P];
+            x[3 + i] = t[(long)i * N + A];
+        }
+        const long e = (long)P * N + A;
+#pragma unroll
+        for (int m = 0; m < 29; ++m) x[6 + m] = t2[(long)m * NN + e];
+        x[35] = 1.0;
+        double acc[3] = {0.0, 0.0, 0.0};
+        PQ_R1L_SWITCH(c, x, acc, h1, h2, (long)N, NN, (long)P, (long)A)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sum[k] += acc[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int o = 32; o > 0; o >>= 1) sum[k] += __shfl_xor(sum[k], o);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) part[((long)c * 3 + k) * N + P] = sum[k];
+    }
+}
+
 }  // namespace
+
+void launch_r1_lane(hipStream_t s, int N, const double* t, const double* t2, const double* h1,
+                    const double* h2, double* part, const int* gate) {
+    hipLaunchKernelGGL(k_r1c, dim3(N), dim3(64 * PQ_R1L_NCHUNK), 0, s, N, t, t2, h1, h2, part, gate);
+}
+
+int r1_lane_chunks() { return PQ_R1L_NCHUNK; }
 
 void launch_r2_lane(hipStream_t s, int N, const double* t, const double* h1, const double* h2K,
                     const double* SK, double* part, const int* gate) {

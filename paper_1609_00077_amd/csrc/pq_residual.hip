@@ -396,57 +396,32 @@ __global__ __launch_bounds__(64) void k_r1s2_close(int N, const double* __restri
 // ----------------------------------------------------------- one-pair outputs
 // grid (N, nch): workgroup (P, ch) sums the chunk ch of the ordered spectator
 // (two-spectator terms: k_bgemm and k_r1s2_close).
-// grid.y = 0: the no-spectator terms; grid.y = 1..R1S1_NCH: a chunk of the
-// one-spectator terms for all spectators A (threads over A)
-constexpr int R1S1_TC = 24;
-constexpr int R1S1_NCH = (PQ_R1S1_NTERM + R1S1_TC - 1) / R1S1_TC;
-
-__global__ __launch_bounds__(256) void k_r1(int N, View v, double* __restrict__ part,
-                                            const int* __restrict__ gate) {
+// no-spectator terms of the one-pair outputs, one thread per term, fixed-order
+// block reduction (the one-spectator terms run in k_r1c, the two-spectator
+// terms in k_bgemm and k_r1s2_close)
+__global__ __launch_bounds__(64) void k_r1(int N, View v, double* __restrict__ part,
+                                           const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int P = blockIdx.x, ch = blockIdx.y;
-    const int tid = threadIdx.x;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (ch == 0) {
-        if (tid == 0) {
-            a0 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, P, 0, 0, 0, v);
-            a1 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, P, 0, 0, 0, v);
-            a2 = class_sum(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, P, 0, 0, 0, v);
-        }
-    } else {
-        const int lo = (ch - 1) * R1S1_TC, hi = min(PQ_R1S1_NTERM, lo + R1S1_TC);
-        const int e1 = pq_r1s1_start[1], e2 = pq_r1s1_start[2];
-        for (int A = tid; A < N; A += blockDim.x) {
-            if (A == P) continue;
-            for (int i = lo; i < hi; ++i) {
-                double x = pq_r1s1_coef[i];
-                const int* f = pq_r1s1_fac + 5 * i;
+    const int P = blockIdx.x, tid = threadIdx.x;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = tid; i < PQ_R1S0_NTERM; i += 64) {
+        double x = pq_r1s0_coef[i];
+        const int* f = pq_r1s0_fac + 5 * i;
 #pragma unroll
-                for (int j = 0; j < 5; ++j)
-                    if (f[j] != 0) x *= fval(f[j], P, A, 0, 0, v);
-                if (i < e1) a0 += x;
-                else if (i < e2) a1 += x;
-                else a2 += x;
-            }
-        }
+        for (int j = 0; j < 5; ++j)
+            if (f[j] != 0) x *= fval(f[j], P, 0, 0, 0, v);
+        const int m = i < pq_r1s0_start[1] ? 0 : (i < pq_r1s0_start[2] ? 1 : 2);
+        a[0] += m == 0 ? x : 0.0;
+        a[1] += m == 1 ? x : 0.0;
+        a[2] += m == 2 ? x : 0.0;
     }
-    __shared__ double red[3][256];
-    red[0][tid] = a0;
-    red[1][tid] = a1;
-    red[2][tid] = a2;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            red[0][tid] += red[0][tid + s];
-            red[1][tid] += red[1][tid + s];
-            red[2][tid] += red[2][tid + s];
-        }
-        __syncthreads();
-    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_xor(a[k], o);
     if (tid == 0) {
-        part[((long)ch * 3 + 0) * N + P] = red[0][0];
-        part[((long)ch * 3 + 1) * N + P] = red[1][0];
-        part[((long)ch * 3 + 2) * N + P] = red[2][0];
+        part[0 * N + P] = a[0];
+        part[1 * N + P] = a[1];
+        part[2 * N + P] = a[2];
     }
 }
 
@@ -681,6 +656,7 @@ __global__ __launch_bounds__(256) void k_r2s2w(int N, View v, const double* __re
 
 // packed r from the partial sums, in a fixed order (deterministic)
 __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
+                        const double* __restrict__ p1s1, int nlane1,
                         const double* __restrict__ p2, const double* __restrict__ ps2, int nchunk,
                         double* __restrict__ R, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
@@ -693,6 +669,7 @@ __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
         const int k = (int)(gid / N), P = (int)(gid % N);
 #pragma unroll 8
         for (int c = 0; c < nch1; ++c) s += p1[((long)c * 3 + k) * N + P];
+        for (int c = 0; c < nlane1; ++c) s += p1s1[((long)c * 3 + k) * N + P];
     } else {
         const long g2 = gid - n1;
         const int m = (int)(g2 / np2);
@@ -1243,7 +1220,7 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p2, *epart, *scal;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p1s1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1;
 };
 
@@ -1282,10 +1259,10 @@ pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
 }
 
 
-// partial-sum chunks of the one-pair outputs: 1 + R1S1_NCH from k_r1, one per group from k_r1s2_close
+// partial-sum chunks of the one-pair outputs: one from k_r1, one per group from k_r1s2_close
 inline int r1_chunks(int N) {
-    if (N < 3) return 1 + R1S1_NCH;
-    return 1 + R1S1_NCH + PQ_R1G_N;   // one partial chunk per one-pair two-spectator group
+    if (N < 3) return 1;
+    return 1 + PQ_R1G_N;   // k_r1, then one partial chunk per one-pair two-spectator group
 }
 
 inline size_t r1f_size(int N) {
@@ -1320,6 +1297,7 @@ Carve carve(double* ws, int N) {
     c.part = take((size_t)c.nchunk * NP2 * std::max(np2, (size_t)1));
     c.nch1 = r1_chunks(N);
     c.p1 = take((size_t)c.nch1 * 3 * N);
+    c.p1s1 = take((size_t)r1_lane_chunks() * 3 * N);
     c.p2 = take((size_t)PQ_LANE_NCHUNK * std::max(np2, (size_t)1));
     c.nblkE = (int)((NN + 255) / 256);
     c.epart = take(c.nblkE);
@@ -1336,7 +1314,7 @@ size_t carve_size(int N) {
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
            (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
-           (size_t)PQ_R1G_N * NN;
+           (size_t)PQ_R1G_N * NN + (size_t)r1_lane_chunks() * 3 * N;
 }
 
 View make_view(const double* t, const Carve& c, int N) {
@@ -1460,16 +1438,18 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_R1G_N), dim3(256), 0, s, N, 1,
                            c.F1, c.F1, c.M1, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_r1s2_close, dim3(N, PQ_R1G_N), dim3(64), 0, s, N, c.F1, c.M1, c.p1,
-                           1 + R1S1_NCH, gate);
+        hipLaunchKernelGGL(k_r1s2_close, dim3(N, PQ_R1G_N), dim3(64), 0, s, N, c.F1, c.M1, c.p1, 1,
+                           gate);
         pqph_mark(ctx);
     }
-    hipLaunchKernelGGL(k_r1, dim3(N, 1 + R1S1_NCH), dim3(256), 0, s, N, v, c.p1, gate);
+    hipLaunchKernelGGL(k_r1, dim3(N), dim3(64), 0, s, N, v, c.p1, gate);
+    pqph_mark(ctx);
+    launch_r1_lane(s, N, t, c.t2, c.h1, c.h2, c.p1s1, gate);
     pqph_mark(ctx);
     {
         const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
         hipLaunchKernelGGL(k_final, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N, c.p1,
-                           c.nch1, c.p2, c.part, N > 1 ? c.nchunk : 0, r, gate);
+                           c.nch1, c.p1s1, r1_lane_chunks(), c.p2, c.part, N > 1 ? c.nchunk : 0, r, gate);
     }
 
     pqph_mark(ctx);

@@ -168,10 +168,11 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
 static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2",    "k_spec_w",
                                     "k_spec_lam", "k_dress",   "k_spec_x",       "k_spec_y",
                                     "k_gemm_s1",  "k_r2s2",    "k_r2c",          "k_spec_r1",
-                                    "k_r1s2",     "k_r1s2_close", "k_r1",        "k_final"};
+                                    "k_r1s2",     "k_r1s2_close", "k_r1",        "k_r1c",
+                                    "k_final"};
 
 const char* pq_residual_phase_name(int i) {
-    return (i >= 0 && i < 16) ? kPhaseNames[i] : "";
+    return (i >= 0 && i < 17) ? kPhaseNames[i] : "";
 }
 
 pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const double* eri,

@@ -74,6 +74,12 @@ __device__ inline void decode_pair(long ip, int& P, int& Q) {
 void launch_r2_lane(hipStream_t s, int npair, const double* t, const double* h1, const double* h2K,
                     const double* SK, double* part, const int* gate);
 
+// one-spectator terms of the one-pair outputs (pq_lane.hip): chunk sums
+// part[chunk][k][P]; t2 the mirrored [29][N][N], h2 [key][N][N]
+void launch_r1_lane(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
+                    const double* h2, double* part, const int* gate);
+int r1_lane_chunks();
+
 // PQ residual pieces (pq_residual.hip) --------------------------------------
 size_t pq_ws_doubles(int npair);
 // residual into r on stream s using workspace ws (already large enough); no host sync

@@ -310,6 +310,61 @@ def emit_lane_code(tb, path):
         out.append("    return acc;")
         out.append("}")
         out.append("")
+    # one-pair outputs, one spectator A: lanes over ordered (P, A); staged
+    # t1(P) 0..2, t1(A) 3..5, t2(P,A) 6..34, 1.0 at 35; streamed h1(A), h2(P,A)
+    tab = tb.classes["R1S1"]
+    groups = {}
+    for m in range(3):
+        for i in range(tab.start[m], tab.start[m + 1]):
+            stream, tl = None, []
+            for code in tab.fac[i]:
+                code = int(code)
+                if code == 0:
+                    continue
+                kind, r0, r1, idx = (code >> 28) & 15, (code >> 24) & 15, (code >> 20) & 15, code & 0xFFFF
+                if kind == KIND_T1:
+                    tl.append((0 if r0 == 0 else 3) + idx)
+                elif kind == KIND_T2:
+                    assert (r0, r1) == (0, 1)
+                    tl.append(6 + idx)
+                elif kind == KIND_H1:
+                    assert r0 == 1 and stream is None
+                    stream = ("h1[{i} * N + A]", idx)
+                else:
+                    assert kind == KIND_H2 and (r0, r1) == (0, 1) and stream is None
+                    stream = ("h2[{i} * NN + P * N + A]", idx)
+            groups.setdefault(stream, []).append((m, float(tab.coef[i]), tl))
+    items = sorted(groups.items())
+    nch = 4
+    total = sum(len(v) for _, v in items)
+    chunks, cur, acc_n = [[]], 0, 0
+    for key, terms in items:
+        if acc_n >= total * len(chunks) / nch and len(chunks) < nch:
+            chunks.append([])
+        chunks[-1].append((key, terms))
+        acc_n += len(terms)
+    out.append(f"#define PQ_R1L_NCHUNK {len(chunks)}")
+    out.append("")
+    for c, ch in enumerate(chunks):
+        out.append(f"__device__ __forceinline__ void r1_chunk_{c}(const double* x, double* acc, "
+                   "const double* __restrict__ h1, const double* __restrict__ h2, long N, long NN, "
+                   "long P, long A) {")
+        for (src, idx), terms in ch:
+            out.append(f"    {{ const double sv = {src.format(i=idx)};")
+            for m in range(3):
+                ex = [" * ".join([repr(c0)] + [f"x[{j}]" for j in tl]) for mm, c0, tl in terms if mm == m]
+                if ex:
+                    out.append(f"      acc[{m}] += sv * ({' + '.join(ex)});")
+            out.append("    }")
+        out.append("}")
+        out.append("")
+    out.append("#define PQ_R1L_SWITCH(c, ...) \\")
+    out.append("    switch (c) { \\")
+    for c in range(len(chunks)):
+        out.append(f"        case {c}: r1_chunk_{c}(__VA_ARGS__); break; \\")
+    out.append("        default: break; \\")
+    out.append("    }")
+    out.append("")
     out.append("#define PQ_LANE_SWITCH(c, acc, ...) \\")
     out.append("    switch (c) { \\")
     for c in range(len(V["ch_lo"])):

@@ -55,7 +55,8 @@ def pq_kernel_flops(N: int) -> dict:
             lsum += (len(tb.r2s2_l[bi]) + 2.0) * (N - 2)
     out["k_r2s2"] = lsum * np2
     out["k_r2c"] = (_class_cost(c["R2S0"]) + _class_cost(c["R2S1"])) * np2
-    out["k_r1"] = N * (_class_cost(c["R1S0"]) + (N - 1) * _class_cost(c["R1S1"]))
+    out["k_r1"] = N * _class_cost(c["R1S0"])
+    out["k_r1c"] = N * (N - 1) * _class_cost(c["R1S1"])
     # factorised one-pair two-spectator terms: products X, Y, Z (and Z^T) over
     # ordered label pairs, then per group and output pair one row of a
     # contraction over N labels and a dot per closing product
