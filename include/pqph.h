@@ -156,11 +156,11 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
 /* Diagnostic (per-phase tracing): one pq_residual with a HIP event recorded on
  * the context's stream after every kernel; phase_ms (host, nphase entries)
  * receives the elapsed time of each kernel in launch order and *nphase_out
- * their number (17 for npair >= 3: vertex1, vertex2, unpack_t2, spec_w,
- * spec_lam, dress, spec_x, spec_y, gemm_s1, r2s2, r2c, spec_r1, r1s2,
- * r1s2_close, r1, r1c, final; 14 for npair = 2, without spec_r1, r1s2 and
- * r1s2_close; 4 for npair = 1: vertex1, r1, r1c, final).  Synchronises the stream.  Fails
- * with INVALID_ARG if nphase is too small. */
+ * their number (15 for npair >= 3: vertex1, vertex2, unpack_t2, spec_w,
+ * spec_lam, dress, gemm_s1, r2s2, r2c, spec_r1, r1s2, r1s2_close, r1, r1c,
+ * final; 12 for npair = 2, without spec_r1, r1s2 and r1s2_close; 4 for
+ * npair = 1: vertex1, r1, r1c, final).  Synchronises the stream.  Fails with
+ * INVALID_ARG if nphase is too small. */
 pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h,
                                 const double* eri, const double* t, double* r,
                                 double* phase_ms, int nphase, int* nphase_out);

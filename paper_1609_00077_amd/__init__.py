@@ -100,8 +100,8 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     _check(lib, ctx, lib.pq_residual_profile(ctx, npair, _dev(h, "h", 4 * npair * npair),
                                              _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
                                              _dev(out, "out", na), ms, 24, C.byref(n)))
-    names = [lib.pq_residual_phase_name(i).decode() for i in range(17)]
-    if n.value == 14:      # npair == 2: no one-pair two-spectator terms
+    names = [lib.pq_residual_phase_name(i).decode() for i in range(15)]
+    if n.value == 12:      # npair == 2: no one-pair two-spectator terms
         names = [x for x in names if x not in ("k_spec_r1", "k_r1s2", "k_r1s2_close")]
     elif n.value == 4:     # npair == 1: no two-pair outputs
         names = ["k_vertex1", "k_r1", "k_r1c", "k_final"]

@@ -242,7 +242,57 @@ inline __device__ void tile_of(int t, int nt, int& tP, int& tQ) {
     tQ = tP + t;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict__ X,
+// The factors of one side spec, decoded once: factor f of the product at the
+// ordered label pair (L0, L1) is p[f][L0 * sa[f] + L1 * sb[f]] (an N x N
+// slice read as given or transposed, or a per-label vector), so a staging
+// step issues all its loads at once instead of interpreting codes per element.
+constexpr int SPEC_MAXF = 4;
+struct SpecPtrs {
+    const double* p[SPEC_MAXF];
+    int sa[SPEC_MAXF], sb[SPEC_MAXF];
+    int n;
+};
+
+__device__ __forceinline__ SpecPtrs spec_ptrs(const int* __restrict__ fc, int i0, int i1, const View& v) {
+    SpecPtrs q;
+    q.n = min(i1 - i0, SPEC_MAXF);
+#pragma unroll
+    for (int f = 0; f < SPEC_MAXF; ++f) {
+        q.p[f] = v.t2;
+        q.sa[f] = 0;
+        q.sb[f] = 0;
+        if (f < q.n) {
+            const int code = fc[i0 + f];
+            const int kind = (code >> 28) & 15, r0 = (code >> 24) & 15, r1 = (code >> 20) & 15;
+            const long idx = code & 0xFFFF;
+            if (kind == 1 || kind == 3) {       // per-label vectors t1, h1
+                q.p[f] = (kind == 1 ? v.t1 : v.h1) + idx * v.N;
+                q.sa[f] = r0 == 0;
+                q.sb[f] = r0 == 1;
+            } else {                            // N x N slices t2, h2, W, D
+                q.p[f] = (kind == 2 ? v.t2 : kind == 4 ? v.h2 : kind == 6 ? v.W : v.D) + idx * v.NN;
+                q.sa[f] = (r0 == 0 ? v.N : 0) + (r1 == 0 ? 1 : 0);
+                q.sb[f] = (r0 == 1 ? v.N : 0) + (r1 == 1 ? 1 : 0);
+            }
+        }
+    }
+    return q;
+}
+
+__device__ __forceinline__ double spec_eval(const SpecPtrs& q, int L0, int L1) {
+    double x = 1.0;
+#pragma unroll
+    for (int f = 0; f < SPEC_MAXF; ++f)
+        if (f < q.n) x *= q.p[f][(long)L0 * q.sa[f] + (long)L1 * q.sb[f]];
+    return x;
+}
+
+// FUSED: the sides X_x(P,A) and Y_y(Q,A) are formed while staging, as the
+// products of their factors (amplitudes, vertices, dressed vertices: arrays
+// of at most a few hundred N x N slices that stay in the caches), instead of
+// being read from materialised X and Y (about 1750 slices at 70 pairs)
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_gemm_s1(int N, View v, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
                                                  double* __restrict__ SK, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
@@ -259,8 +309,14 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double* Ts = Ys + NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
     const long NN = (long)N * N;
-    const double* Xp = X + (long)pq_s1pairs[2 * p] * NN;
-    const double* Yp = Y + (long)pq_s1pairs[2 * p + 1] * NN;
+    const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
+    const double* Xp = FUSED ? nullptr : X + (long)xi * NN;
+    const double* Yp = FUSED ? nullptr : Y + (long)yi * NN;
+    SpecPtrs xq, yq;
+    if (FUSED) {
+        xq = spec_ptrs(pq_x_fac, pq_x_start[xi], pq_x_start[xi + 1], v);
+        yq = spec_ptrs(pq_y_fac, pq_y_start[yi], pq_y_start[yi + 1], v);
+    }
     const int i = lane & 15, kq = lane >> 4;
     int tP[S1_TPW], tQ[S1_TPW];
     bool tv[S1_TPW];
@@ -278,8 +334,14 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, const double* __restrict
         for (int e = tid; e < NR * 16; e += 256) {
             const int r = e >> 4, k = e & 15, A = kc + k;
             const bool in = r < N && A < N;
-            Xs[r * S1_PITCH + k] = in ? Xp[(long)r * N + A] : 0.0;
-            Ys[r * S1_PITCH + k] = in ? Yp[(long)r * N + A] : 0.0;
+            if (FUSED) {
+                const bool off = in && r != A;          // zero diagonals keep A != P, Q
+                Xs[r * S1_PITCH + k] = off ? spec_eval(xq, r, A) : 0.0;
+                Ys[r * S1_PITCH + k] = off ? spec_eval(yq, r, A) : 0.0;
+            } else {
+                Xs[r * S1_PITCH + k] = in ? Xp[(long)r * N + A] : 0.0;
+                Ys[r * S1_PITCH + k] = in ? Yp[(long)r * N + A] : 0.0;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -1220,7 +1282,7 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p1s1, *p2, *epart, *scal;
+    double *t2, *h1, *h2, *h2T, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p1s1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1;
 };
 
@@ -1250,8 +1312,11 @@ inline unsigned bgemm_tile_groups(int N) {
 pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     static bool done = false;
     if (done) return PQPH_OK;
-    hipError_t e = hipFuncSetAttribute((const void*)&k_gemm_s1, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)gemm_s1_lds(256));
+    hipError_t e = hipFuncSetAttribute((const void*)&k_gemm_s1<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm_s1_lds(256));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)&k_gemm_s1<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gemm_s1_lds(256));
     if (e != hipSuccess)
         return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
     done = true;
@@ -1285,8 +1350,6 @@ Carve carve(double* ws, int N) {
     c.h1 = take((size_t)PQ_H1_N * N);
     c.h2 = take((size_t)PQ_H2_N * NN);
     c.h2T = take((size_t)PQ_H2_N * std::max(np2, (size_t)1));
-    c.X = take((size_t)PQ_X_N * NN);
-    c.Y = take((size_t)PQ_Y_N * NN);
     c.S = take((size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1));
     c.W = take(2 * (size_t)PQ_W_N * NN);              // W and its transposes
     c.Lam = take((size_t)PQ_LAM_N * NN);
@@ -1311,7 +1374,7 @@ size_t carve_size(int N) {
     s2_chunks(N, nchunk, gchunk);
     const size_t np2m = std::max(np2, (size_t)1);
     return NP2 * NN + (size_t)PQ_H1_N * N +
-           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
+           ((size_t)PQ_H2_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
            (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
            (size_t)PQ_R1G_N * NN + (size_t)r1_lane_chunks() * 3 * N;
@@ -1362,22 +1425,37 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     const unsigned gsq = (unsigned)((N * N + 255) / 256);
+    // Independent branches after the shared vertices and amplitudes: the
+    // one-pair outputs (s2) and the dense two-spectator contraction (s1) run
+    // beside the main chain (dressing, one-spectator GEMM, its epilogue); the
+    // main stream joins both before the final sum.  Serial on s when a gate
+    // is given (batched solves) or per-kernel times are taken.
+    const bool forked = !ctx->profiling && gate == nullptr && s == ctx->stream;
+    hipStream_t s1 = s, s2 = s;
+    if (forked) {
+        if (pqph_status e_ = pqph_ensure_side(ctx)) return e_;
+        s1 = ctx->side[0];
+        s2 = ctx->side[1];
+        PQPH_HIP(ctx, hipEventRecord(ctx->sev[0], s));
+        PQPH_HIP(ctx, hipStreamWaitEvent(s2, ctx->sev[0], 0));
+    }
     if (N > 1) {
         const long np2 = (long)N * (N - 1) / 2;
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, gate);
         pqph_mark(ctx);
         hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, gate);
         pqph_mark(ctx);
+        if (forked) {
+            PQPH_HIP(ctx, hipEventRecord(ctx->sev[1], s));
+            PQPH_HIP(ctx, hipStreamWaitEvent(s1, ctx->sev[1], 0));
+        }
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
         hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
                            c.Lam, c.W, c.D, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, gate);
-        pqph_mark(ctx);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, gate);
-        pqph_mark(ctx);
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
-        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, c.X, c.Y, c.S,
+        hipLaunchKernelGGL(k_gemm_s1<true>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
+                           nullptr, nullptr, c.S,
                            gate);
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
@@ -1399,7 +1477,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +             \
                                                        hipGetErrorString(e_));                  \
         }                                                                                       \
-        hipLaunchKernelGGL(k_r2s2w<NB>, g2, dim3(256), bytes, s, N, v, c.W, c.gchunk, c.part,  \
+        hipLaunchKernelGGL(k_r2s2w<NB>, g2, dim3(256), bytes, s1, N, v, c.W, c.gchunk, c.part,  \
                            gate);                                                       \
     } while (0)
             if (ncb <= 1) PQ_S2W_LAUNCH(1);
@@ -1414,7 +1492,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_ + M2_ROWS * NP2) * sizeof(double);
             };
 #define PQ_S2_LAUNCH(NB)                                                                       \
-    hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s, N, v, c.W, c.gchunk, c.part, \
+    hipLaunchKernelGGL(k_r2s2<NB>, g2, dim3(256), lds(NB), s1, N, v, c.W, c.gchunk, c.part, \
                        gate)
             if (ncb <= 1) PQ_S2_LAUNCH(1);
             else if (ncb <= 2) PQ_S2_LAUNCH(2);
@@ -1429,23 +1507,29 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
 #undef PQ_S2_LAUNCH
         }
         pqph_mark(ctx);
+        if (forked) PQPH_HIP(ctx, hipEventRecord(ctx->sev[2], s1));
         launch_r2_lane(s, N, t, c.h1, c.h2T, c.S, c.p2, gate);
         pqph_mark(ctx);
     }
     if (N >= 3) {
-        hipLaunchKernelGGL(k_spec_r1, dim3(gsq, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, gate);
+        hipLaunchKernelGGL(k_spec_r1, dim3(gsq, PQ_R1F_N), dim3(256), 0, s2, N, v, c.F1, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_R1G_N), dim3(256), 0, s, N, 1,
+        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_R1G_N), dim3(256), 0, s2, N, 1,
                            c.F1, c.F1, c.M1, gate);
         pqph_mark(ctx);
-        hipLaunchKernelGGL(k_r1s2_close, dim3(N, PQ_R1G_N), dim3(64), 0, s, N, c.F1, c.M1, c.p1, 1,
+        hipLaunchKernelGGL(k_r1s2_close, dim3(N, PQ_R1G_N), dim3(64), 0, s2, N, c.F1, c.M1, c.p1, 1,
                            gate);
         pqph_mark(ctx);
     }
-    hipLaunchKernelGGL(k_r1, dim3(N), dim3(64), 0, s, N, v, c.p1, gate);
+    hipLaunchKernelGGL(k_r1, dim3(N), dim3(64), 0, s2, N, v, c.p1, gate);
     pqph_mark(ctx);
-    launch_r1_lane(s, N, t, c.t2, c.h1, c.h2, c.p1s1, gate);
+    launch_r1_lane(s2, N, t, c.t2, c.h1, c.h2, c.p1s1, gate);
     pqph_mark(ctx);
+    if (forked) {
+        PQPH_HIP(ctx, hipEventRecord(ctx->sev[3], s2));
+        PQPH_HIP(ctx, hipStreamWaitEvent(s, ctx->sev[3], 0));
+        if (N > 1) PQPH_HIP(ctx, hipStreamWaitEvent(s, ctx->sev[2], 0));
+    }
     {
         const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
         hipLaunchKernelGGL(k_final, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N, c.p1,
@@ -1484,7 +1568,7 @@ size_t pq_adj_doubles(int N) {
     const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
     return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_DR_N + PQ_LAM_N) * NN +
-           r1f_size(N) + (size_t)PQ_S1PAIRS_N * np2 + 8;
+           r1f_size(N) + (size_t)PQ_S1PAIRS_N * np2 + ((size_t)PQ_X_N + PQ_Y_N) * NN + 8;
 }
 
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
@@ -1512,6 +1596,10 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     a.Wb = Wb;
     a.Db = Db;
     double* Sb = p;
+    // the one-spectator sides, materialised here (the forward residual forms
+    // them while staging): their adjoints need them as operands
+    double* Xf = Sb + (size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1);
+    double* Yf = Xf + (size_t)PQ_X_N * NN;
     const size_t nzero = (size_t)(Sb - aws);
     PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
     const int tb = 64, gx = (N + tb - 1) / tb;
@@ -1522,11 +1610,11 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
         hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
                            c.Lam, c.W, c.D, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, Xf, nullptr);
+        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, Yf, nullptr);
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
-        hipLaunchKernelGGL(k_gemm_s1, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, c.X, c.Y, c.S,
-                           nullptr);
+        hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v, Xf,
+                           Yf, c.S, nullptr);
         {
             const size_t bytes =
                 (size_t)(2 * R2A_PPW * PQ_LOC_N + R2A_PPW * NP2) * sizeof(double);
@@ -1551,7 +1639,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
             hipLaunchKernelGGL(k_r2s2_adj, dim3(rt, (PQ_G_N + gchunk - 1) / gchunk), dim3(256), bytes,
                                s, N, v, c.W, lam, gchunk, a, Wb);
         }
-        hipLaunchKernelGGL(k_gemm_s1_adj, dim3(gx, N, PQ_S1PAIRS_N), dim3(tb), 0, s, N, c.X, c.Y, Sb,
+        hipLaunchKernelGGL(k_gemm_s1_adj, dim3(gx, N, PQ_S1PAIRS_N), dim3(tb), 0, s, N, Xf, Yf, Sb,
                            Xb, Yb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, Xb, a);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, Yb, a);

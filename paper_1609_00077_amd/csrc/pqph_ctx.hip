@@ -72,6 +72,14 @@ int pq_s2_variant(const pqph_ctx* ctx, int npair) {
     return 1;
 }
 
+pqph_status pqph_ensure_side(pqph_ctx* ctx) {
+    for (hipStream_t& st : ctx->side)
+        if (!st) PQPH_HIP(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (hipEvent_t& e : ctx->sev)
+        if (!e) PQPH_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return PQPH_OK;
+}
+
 void pqph_mark(pqph_ctx* ctx) {
     if (!ctx->profiling || ctx->prof_n >= 24) return;
     (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
@@ -131,6 +139,10 @@ void pqph_destroy(pqph_ctx* ctx) {
     for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
     for (hipStream_t st : ctx->bstreams) (void)hipStreamDestroy(st);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    for (hipEvent_t e : ctx->sev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : ctx->side)
+        if (st) (void)hipStreamDestroy(st);
     delete ctx;
 }
 
@@ -165,14 +177,14 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
 }
 
-static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2",    "k_spec_w",
-                                    "k_spec_lam", "k_dress",   "k_spec_x",       "k_spec_y",
-                                    "k_gemm_s1",  "k_r2s2",    "k_r2c",          "k_spec_r1",
-                                    "k_r1s2",     "k_r1s2_close", "k_r1",        "k_r1c",
-                                    "k_final"};
+static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2",  "k_spec_w",
+                                    "k_spec_lam", "k_dress",   "k_gemm_s1",    "k_r2s2",
+                                    "k_r2c",      "k_spec_r1", "k_r1s2",       "k_r1s2_close",
+                                    "k_r1",       "k_r1c",     "k_final"};
+constexpr int kNPhase = (int)(sizeof(kPhaseNames) / sizeof(kPhaseNames[0]));
 
 const char* pq_residual_phase_name(int i) {
-    return (i >= 0 && i < 17) ? kPhaseNames[i] : "";
+    return (i >= 0 && i < kNPhase) ? kPhaseNames[i] : "";
 }
 
 pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h, const double* eri,

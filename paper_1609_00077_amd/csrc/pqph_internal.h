@@ -35,6 +35,10 @@ struct pqph_ctx {
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> bevents;
     hipEvent_t fork = nullptr;
+    // side streams (default priority) and fork/join events of one residual:
+    // its independent branches run concurrently with the main chain
+    hipStream_t side[2] = {};
+    hipEvent_t sev[4] = {};
     // batched solves: 0 = device-resident iterations captured in a HIP graph,
     // 1 = host-driven lockstep (three host synchronisations per iteration)
     int batch_mode = 0;
@@ -59,6 +63,8 @@ pqph_status pqph_fail(pqph_ctx* ctx, pqph_status st, const std::string& msg);
 pqph_status pqph_ensure_ws(pqph_ctx* ctx, size_t bytes);
 pqph_status pqph_ensure_sv(pqph_ctx* ctx, size_t bytes);
 pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n);
+// side streams and events of the residual's concurrent branches (created on first use)
+pqph_status pqph_ensure_side(pqph_ctx* ctx);
 
 // output pair index ip = Q(Q-1)/2 + P (P < Q) -> (P, Q)
 __device__ inline void decode_pair(long ip, int& P, int& Q) {

@@ -40,12 +40,12 @@ def pq_kernel_flops(N: int) -> dict:
     out["k_vertex1"] = 2.0 * nsym1 * N
     out["k_vertex2"] = 2.0 * nsym2 * N * (N - 1)
     out["k_unpack_t2"] = 29.0 * N * (N - 1) / 2          # one sign multiply per mirrored entry
-    out["k_spec_x"] = _spec_cost(tb.r2s1_x) * N * (N - 1)
-    out["k_spec_y"] = _spec_cost(tb.r2s1_y) * N * (N - 1)
     out["k_spec_w"] = _spec_cost(tb.r2s2_w) * N * (N - 1)
     out["k_spec_lam"] = _spec_cost(tb.r2s2_lam) * N * (N - 1)
     out["k_dress"] = 2.0 * len(tb.r2s2_dress) * N * N * N
-    out["k_gemm_s1"] = 2.0 * len(tb.r2s1_pairs) * np2 * max(N - 2, 0)
+    # one-spectator contraction; its sides X, Y are formed while staging
+    out["k_gemm_s1"] = (2.0 * len(tb.r2s1_pairs) * np2 * max(N - 2, 0)
+                        + (_spec_cost(tb.r2s1_x) + _spec_cost(tb.r2s1_y)) * N * (N - 1))
     # two spectators: per output pair and (w, a) group: L_a on N-2 labels, the
     # (N-2)x(N-2) vertex contraction, then per b: L_b and a dot over N-2 labels
     lsum = 0.0

@@ -77,3 +77,16 @@ def test_factorised_one_pair_two_spectator_class(tables, N):
                     ref[:, P] += 0.5 * em.interp(tables.classes["R1S2"], (P, A, B))
     got = em.r1s2_factorised()
     assert np.abs(got - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_one_spectator_sides_fit_the_staged_form(tables):
+    """The one-spectator GEMM forms its sides X_x(P,A), Y_y(Q,A) while
+    staging, from at most four factors each read at (P,A) or (A,P): per-label
+    vectors (t1, h1) or N x N slices (t2, h2, W, dressed D) on roles 0 and 1."""
+    for specs in (tables.r2s1_x, tables.r2s1_y):
+        for spec in specs:
+            assert len(spec) <= 4
+            for code in spec:
+                kind, r0, r1 = (code >> 28) & 15, (code >> 24) & 15, (code >> 20) & 15
+                assert kind in (1, 2, 3, 4, 6, 7)
+                assert r0 in (0, 1) and r1 in (0, 1)

@@ -144,3 +144,22 @@ def test_full_size_properties(pq):
     e1 = pq.pq_solve(f, eri, tol=1e-10).energy
     e2 = pq.pq_solve(f2, eri2, tol=1e-10).energy
     assert abs(e1 - e2) < 1e-9
+
+
+@pytest.mark.parametrize("N", [24, 90])
+def test_two_spectator_variants_agree(pq, N):
+    """The two two-spectator kernel variants (vertex staged in K-chunks,
+    vertex resident in LDS) take different routes through the same sums; at
+    sizes between the oracle-checked ones (1-5 pairs, 70 pairs) their
+    residuals agree to rounding, over several column blocks and a ragged
+    last one."""
+    f, eri = _random_system(N, 300 + N)
+    t = random_amplitudes(N, "pq", seed=400 + N, scale=0.05)
+    outs = {}
+    for variant in (1, 2):
+        pq.set_variant(N, variant)
+        outs[variant] = pq.pq_residual(_d(f), _d(eri), _d(t)).cpu().numpy()
+    pq.set_variant(N, 0)
+    tol = 1e-12 * max(1.0, np.abs(outs[1]).max())
+    assert np.abs(outs[2] - outs[1]).max() <= tol, np.abs(outs[2] - outs[1]).max()
+    assert np.isfinite(outs[1]).all() and np.abs(outs[1]).max() > 0
