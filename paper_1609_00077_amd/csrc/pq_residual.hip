@@ -1032,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_r2_adj(int N, const double* __restrict_
         for (int i = tid; i < PQ_LOC_ONE; i += blockDim.x) {
             const double d = Lb[i];
             if (i >= PQ_LOC_S) {
-                Sb[ip * PQ_S1PAIRS_N + (i - PQ_LOC_S)] = d;
+                Sb[(long)(i - PQ_LOC_S) * np2 + ip] = d;   // p-major: rows of Sbar_p
                 continue;
             }
             if (d == 0.0) continue;
@@ -1046,24 +1046,75 @@ __global__ __launch_bounds__(256) void k_r2_adj(int N, const double* __restrict_
     }
 }
 
-// one-spectator GEMM adjoint: Xb_x(P,A) += sum_{Q>P} Sb_p(P,Q) Y_y(Q,A),
-//                             Yb_y(Q,A) += sum_{P<Q} Sb_p(P,Q) X_x(P,A)
-__global__ void k_gemm_s1_adj(int N, const double* __restrict__ X, const double* __restrict__ Y,
-                              const double* __restrict__ Sb, double* __restrict__ Xb,
-                              double* __restrict__ Yb) {
-    const int A = blockIdx.x * blockDim.x + threadIdx.x;
-    const int L = blockIdx.y, p = blockIdx.z;
-    if (A >= N || A == L) return;
-    const long NN = (long)N * N;
-    const int x = pq_s1pairs[2 * p], y = pq_s1pairs[2 * p + 1];
-    double s = 0.0;
-    for (int Q = L + 1; Q < N; ++Q)
-        s += Sb[((long)Q * (Q - 1) / 2 + L) * PQ_S1PAIRS_N + p] * Y[(long)y * NN + (long)Q * N + A];
-    if (s != 0.0) atomicAdd(&Xb[(long)x * NN + (long)L * N + A], s);
-    s = 0.0;
-    for (int P = 0; P < L; ++P)
-        s += Sb[((long)L * (L - 1) / 2 + P) * PQ_S1PAIRS_N + p] * X[(long)x * NN + (long)P * N + A];
-    if (s != 0.0) atomicAdd(&Yb[(long)y * NN + (long)L * N + A], s);
+// One-spectator GEMM adjoint on the FP64 matrix cores, gathered per side:
+//   SIDE 0: Xbar_x(P,A) += sum_{p = (x,y)} sum_{Q>P} Sbar_p(P,Q) Y_y(Q,A)
+//   SIDE 1: Ybar_y(Q,A) += sum_{p = (x,y)} sum_{P<Q} Sbar_p(P,Q) X_x(P,A)
+// Workgroup: one 64 x 64 tile (rows P or Q, columns A) and one segment of at
+// most 32 pairs sharing x (SIDE 0) or y (SIDE 1); the segment's sum is
+// added with one atomic per element.  Sbar is p-major (pq contiguous), so the
+// staged rows of Sbar_p, for fixed Q and running P, are contiguous.
+constexpr int S1A_T = 64, S1A_KC = 16, S1A_PITCH = S1A_KC + 1;
+
+template <int SIDE>
+__global__ __launch_bounds__(256) void k_s1_adj(int N, const double* __restrict__ X,
+                                                const double* __restrict__ Y,
+                                                const double* __restrict__ Sb, double* __restrict__ out) {
+    __shared__ double Us[S1A_T * S1A_PITCH];     // [row][k]: Sbar (SIDE 0) or Sbar^T (SIDE 1)
+    __shared__ double Os[S1A_KC * S1A_T];        // [k][A]: Y_y or X_x rows
+    const int nAt = (N + S1A_T - 1) / S1A_T;
+    const int R0 = (blockIdx.x / nAt) * S1A_T, A0 = (blockIdx.x % nAt) * S1A_T;
+    const int item = blockIdx.y;
+    const long NN = (long)N * N, np2 = (long)N * (N - 1) / 2;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int j0 = SIDE == 0 ? pq_s1ax_p0[item] : pq_s1ay_i0[item];
+    const int j1 = SIDE == 0 ? pq_s1ax_p0[item + 1] : pq_s1ay_i0[item + 1];
+    const int p0 = SIDE == 0 ? j0 : pq_s1y_perm[j0];
+    const int side = pq_s1pairs[2 * p0 + SIDE];          // x (SIDE 0) or y (SIDE 1)
+    // K runs over Q > P (SIDE 0) or P < Q (SIDE 1): skip chunks that are all zero
+    const int kbeg = SIDE == 0 ? R0 / S1A_KC * S1A_KC : 0;
+    const int kend = SIDE == 0 ? N : min(N, R0 + S1A_T);
+    d4 D[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = j0; j < j1; ++j) {
+        const int p = SIDE == 0 ? j : pq_s1y_perm[j];
+        const double* Sp = Sb + (long)p * np2;
+        const double* other = SIDE == 0 ? Y + (long)pq_s1pairs[2 * p + 1] * NN
+                                        : X + (long)pq_s1pairs[2 * p] * NN;
+        for (int kc = kbeg; kc < kend; kc += S1A_KC) {
+            for (int e = tid; e < S1A_T * S1A_KC; e += 256) {
+                int row, k;
+                if (SIDE == 0) { row = e % S1A_T; k = e / S1A_T; }   // P fastest
+                else { k = e % S1A_KC; row = e / S1A_KC; }            // P fastest
+                const int R = R0 + row, K = kc + k;
+                const int P = SIDE == 0 ? R : K, Q = SIDE == 0 ? K : R;
+                Us[row * S1A_PITCH + k] = (P < Q && Q < N) ? Sp[(long)Q * (Q - 1) / 2 + P] : 0.0;
+            }
+            for (int e = tid; e < S1A_KC * S1A_T; e += 256) {
+                const int k = e / S1A_T, A = A0 + e % S1A_T, K = kc + k;
+                Os[e] = (K < N && A < N) ? other[(long)K * N + A] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < S1A_KC; k4 += 4) {
+                const double av = Us[(wave * 16 + i16) * S1A_PITCH + k4 + kq];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Os[(k4 + kq) * S1A_T + cb * 16 + i16], D[cb],
+                                                                 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+    double* o = out + (long)side * NN;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int R = R0 + wave * 16 + kq + 4 * r, A = A0 + cb * 16 + i16;
+            if (R < N && A < N && R != A && D[cb][r] != 0.0) atomicAdd(&o[(long)R * N + A], D[cb][r]);
+        }
 }
 
 // adjoint of the factor products X, Y, W
@@ -1138,83 +1189,270 @@ __device__ __forceinline__ void link_adj(int s, int P, int Q, int A, double dL, 
     }
 }
 
-// two-spectator adjoint (VALU): per row (pair) and group (w, a) with its b list
-//   V = L_a W,  Vbar(B) = sum_b w_b L_b(B),  Lbar_b = w_b V,  Lbar_a = Vbar W^T,
-//   Wbar += L_a^T Vbar (rows of the workgroup summed, then one atomic per (A,B))
-constexpr int S2A_ROWS = 16;
+// Scatter the adjoint d[r] of link s at (P_r, Q_r, col) for the 4 rows r of
+// this lane (rows wave*16 + kq + 4r of the matrix-core layout) into the
+// amplitude adjoint: factor k receives d times the other factors.  When the
+// wavefront's 16 rows share Q (consecutive output pairs), the Q-side factors
+// are summed over the rows first (registers, then lanes 16 and 32 apart) and
+// added with one atomic per column.  Control flow is wavefront-uniform.
+__device__ __forceinline__ void link_adj4(int s, const int* Pr, const int* Qr, int col, const double* d,
+                                          bool qsame, const View& v, const AdjView& a) {
+    const int n = pq_ld_n[s];
+    const int kq = (threadIdx.x & 63) >> 4;
+    bool ok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ok[r] = Pr[r] >= 0 && col < v.N && col != Pr[r] && col != Qr[r] && d[r] != 0.0;
+    double fv[3][4];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            fv[f][r] = 1.0;
+            if (f < n && ok[r]) {
+                const int who = pq_ld_q[3 * s + f] ? Qr[r] : Pr[r];
+                fv[f][r] = v.t2[(long)pq_ld_m[3 * s + f] * v.NN + (long)who * v.N + col];
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        const int m = pq_ld_m[3 * s + k];
+        const bool isq = pq_ld_q[3 * s + k] != 0;
+        double c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            c[r] = ok[r] ? d[r] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                if (j != k) c[r] *= fv[j][r];
+        }
+        if (isq && qsame) {
+            double t = (c[0] + c[1]) + (c[2] + c[3]);
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            if (kq == 0 && t != 0.0 && col < v.N) atomicAdd(&a.tb2[(long)m * a.NN + (long)Qr[0] * a.N + col], t);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (c[r] != 0.0)
+                    atomicAdd(&a.tb2[(long)m * a.NN + (long)(isq ? Qr[r] : Pr[r]) * a.N + col], c[r]);
+        }
+    }
+}
 
-__global__ __launch_bounds__(256) void k_r2s2_adj(int N, View v, const double* __restrict__ W,
-                                                  const double* __restrict__ lam, int gchunk,
-                                                  AdjView a, double* __restrict__ Wb) {
+// Two-spectator adjoint on the FP64 matrix cores, per block of 64 output
+// pairs (4 wavefronts x 16 rows) and chunk of groups (w, a, {b_i}), with the
+// forward kernel's staging:
+//   V = L_a W                      (MFMA; L_a formed while staging)
+//   Lbar_b_i = c_i lam_i V         (scattered into the amplitude adjoint)
+//   Lbar_a = Vbar W^T,  Vbar = sum_i c_i lam_i L_b_i  (MFMA; Vbar formed while
+//                                   staging, W^T read from the stored transposes)
+// The vertex adjoint Wbar += L_a^T Vbar is k_wbar's.
+template <int NCB>
+__global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* __restrict__ W,
+                                                   const double* __restrict__ lam, int gchunk, AdjView a) {
+    constexpr int NC = 16 * NCB;
     extern __shared__ double sm[];
-    double* La = sm;                        // [S2A_ROWS][N]
-    double* Vb = La + S2A_ROWS * N;         // [S2A_ROWS][N]
-    __shared__ int rowP[S2A_ROWS], rowQ[S2A_ROWS];
-    __shared__ double lamr[S2A_ROWS][NP2];
+    double* Ls = sm;                       // [M2_ROWS][M2_KC]: L_a, then Vbar
+    double* Ws = Ls + M2_ROWS * M2_KC;     // [M2_KC][NC]: W, then W^T
+    __shared__ int rowP[M2_ROWS], rowQ[M2_ROWS];
+    __shared__ double lamr[M2_ROWS][NP2];
     const long np2 = (long)N * (N - 1) / 2;
-    const int tid = threadIdx.x, row = tid / 16, lane = tid % 16;
-    const long ip0 = (long)blockIdx.x * S2A_ROWS;
-    if (tid < S2A_ROWS) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const long ip0 = (long)blockIdx.x * M2_ROWS;
+    if (tid < M2_ROWS) {
         int P = -1, Q = -1;
         if (ip0 + tid < np2) decode_pair(ip0 + tid, P, Q);
         rowP[tid] = P;
         rowQ[tid] = Q;
     }
-    for (int i = tid; i < S2A_ROWS * NP2; i += 256) {
+    for (int i = tid; i < M2_ROWS * NP2; i += 256) {
         const int r = i / NP2, m = i % NP2;
         lamr[r][m] = (ip0 + r < np2) ? lam[3L * N + (long)m * np2 + ip0 + r] : 0.0;
     }
     __syncthreads();
-    const int P = rowP[row], Q = rowQ[row];
+    int Pr[4], Qr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Pr[r] = rowP[wave * 16 + kq + 4 * r];
+        Qr[r] = rowQ[wave * 16 + kq + 4 * r];
+    }
+    // rows are consecutive output pairs (Q non-decreasing; missing rows last)
+    const bool qsame = rowQ[wave * 16 + 15] >= 0 && rowQ[wave * 16] == rowQ[wave * 16 + 15];
+    const int KP = (N + M2_KC - 1) / M2_KC * M2_KC;
     const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
     for (int g = g0; g < g1; ++g) {
         const int w = pq_g_w[g], sa = pq_g_a[g];
-        const double* Wg = W + (long)w * v.NN;
-        __syncthreads();
-        for (int A = lane; A < N; A += 16) {
-            double x = 0.0;
-            if (P >= 0 && A != P && A != Q) {
-                Link L;
-                link_rows(sa, P, Q, v, L);
-                x = link_at(L, A);
-            }
-            La[row * N + A] = x;
-        }
-        __syncthreads();
-        for (int B = lane; B < N; B += 16) {
-            double vb = 0.0;
-            if (P >= 0 && B != P && B != Q) {
-                double Vv = 0.0;
-                for (int A = 0; A < N; ++A) Vv += La[row * N + A] * Wg[(long)A * N + B];
-                for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
-                    const double wb = pq_g_coef[i] * lamr[row][pq_g_mu[i]];
-                    if (wb == 0.0) continue;
-                    Link L;
-                    link_rows(pq_g_b[i], P, Q, v, L);
-                    vb += wb * link_at(L, B);
-                    link_adj(pq_g_b[i], P, Q, B, wb * Vv, v, a);
-                }
-            }
-            Vb[row * N + B] = vb;
-        }
-        __syncthreads();
-        // Lbar_a(A) = sum_B Vb(B) W(A,B)
-        for (int A = lane; A < N; A += 16) {
-            if (P < 0 || A == P || A == Q) continue;
-            double s = 0.0;
-            for (int B = 0; B < N; ++B) s += Vb[row * N + B] * Wg[(long)A * N + B];
-            link_adj(sa, P, Q, A, s, v, a);
-        }
-        // Wbar(A,B) += sum_rows La(row,A) Vb(row,B)
-        for (long ab = tid; ab < (long)N * N; ab += 256) {
-            const int A = (int)(ab / N), B = (int)(ab % N);
-            if (A == B) continue;
-            double s = 0.0;
+        const int wt = w < PQ_W_N ? w + PQ_W_N : w - PQ_W_N;
+        const int ib0 = pq_g_start[g], ib1 = pq_g_start[g + 1];
+        d4 D[NCB];
+        // V = L_a W
 #pragma unroll
-            for (int r = 0; r < S2A_ROWS; ++r) s += La[r * N + A] * Vb[r * N + B];
-            if (s != 0.0) atomicAdd(&Wb[(long)w * v.NN + ab], s);
+        for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kc = 0; kc < KP; kc += M2_KC) {
+            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
+                const int row = i / M2_KC, A = kc + i % M2_KC;
+                const int P = rowP[row], Q = rowQ[row];
+                double x = 0.0;
+                if (P >= 0 && A < N && A != P && A != Q) {
+                    Link L;
+                    link_rows(sa, P, Q, v, L);
+                    x = link_at(L, A);
+                }
+                Ls[i] = x;
+            }
+            const double* Wg = W + (long)w * v.NN;
+            for (int i = tid; i < M2_KC * NC; i += 256) {
+                const int A = kc + i / NC, col = i % NC;
+                Ws[i] = (A < N && col < N) ? Wg[(long)A * N + col] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < M2_KC; k4 += 4) {
+                const double av = Ls[(wave * 16 + i16) * M2_KC + k4 + kq];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[(k4 + kq) * NC + cb * 16 + i16], D[cb],
+                                                                 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // Lbar_b_i = c_i lam_i V
+        for (int ii = ib0; ii < ib1; ++ii) {
+            const int b = pq_g_b[ii], mu = pq_g_mu[ii];
+            const double c = pq_g_coef[ii];
+            double wr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wr[r] = c * lamr[wave * 16 + kq + 4 * r][mu];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                double d[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d[r] = wr[r] * D[cb][r];
+                link_adj4(b, Pr, Qr, cb * 16 + i16, d, qsame, v, a);
+            }
+        }
+        // Lbar_a = Vbar W^T
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kc = 0; kc < KP; kc += M2_KC) {
+            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
+                const int row = i / M2_KC, B = kc + i % M2_KC;
+                const int P = rowP[row], Q = rowQ[row];
+                double x = 0.0;
+                if (P >= 0 && B < N && B != P && B != Q) {
+                    for (int ii = ib0; ii < ib1; ++ii) {
+                        const double wb = pq_g_coef[ii] * lamr[row][pq_g_mu[ii]];
+                        if (wb == 0.0) continue;
+                        Link L;
+                        link_rows(pq_g_b[ii], P, Q, v, L);
+                        x += wb * link_at(L, B);
+                    }
+                }
+                Ls[i] = x;
+            }
+            const double* WTg = W + (long)wt * v.NN;     // W^T(B, A) = W(A, B)
+            for (int i = tid; i < M2_KC * NC; i += 256) {
+                const int B = kc + i / NC, A = i % NC;
+                Ws[i] = (B < N && A < N) ? WTg[(long)B * N + A] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < M2_KC; k4 += 4) {
+                const double av = Ls[(wave * 16 + i16) * M2_KC + k4 + kq];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[(k4 + kq) * NC + cb * 16 + i16], D[cb],
+                                                                 0, 0, 0);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            double d[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] = D[cb][r];
+            link_adj4(sa, Pr, Qr, cb * 16 + i16, d, qsame, v, a);
         }
     }
+}
+
+// Vertex adjoint of the same groups, a contraction over the output pairs:
+//   Wbar_w(A,B) += sum_{P<Q} L_a(P,Q,A) Vbar(P,Q,B),
+//   Vbar(P,Q,B) = sum_i c_i lam(PQ, mu_i) L_b_i(P,Q,B)      (zero at A, B in {P,Q})
+// on the FP64 matrix cores.  Workgroup: one 64 x 64 tile of (A,B), one group
+// and one slice of the pairs; L_a and Vbar are formed per chunk of 16 pairs
+// straight from the amplitudes and lambda (thread = (pair, 16 labels));
+// wavefront w owns rows A = 16w.. of the tile.  The finished tile is added to
+// Wbar with one atomic per element (a few per element over all slices).
+constexpr int WB_T = 64, WB_KC = 16, WB_PITCH = WB_KC + 1;
+
+__global__ __launch_bounds__(256) void k_wbar(int N, View v, const double* __restrict__ lam,
+                                              long per, double* __restrict__ Wb) {
+    __shared__ double Ls[WB_T * WB_PITCH];   // [A local][pair in chunk]
+    __shared__ double Vs[WB_T * WB_PITCH];   // [B local][pair in chunk]
+    const int nBt = (N + WB_T - 1) / WB_T;
+    const int A0 = (blockIdx.x / nBt) * WB_T, B0 = (blockIdx.x % nBt) * WB_T;
+    const int g = blockIdx.y;
+    const long np2 = (long)N * (N - 1) / 2;
+    const long k0 = (long)blockIdx.z * per, k1 = min(np2, k0 + per);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int kk = tid >> 4, l = tid & 15;     // staging: pair kk of the chunk, labels l + 16j
+    const int a = pq_g_a[g], ib0 = pq_g_start[g], ib1 = pq_g_start[g + 1];
+    d4 D[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (long kc = k0; kc < k1; kc += WB_KC) {
+        const long ip = kc + kk;
+        int P = -1, Q = -1;
+        if (ip < k1) decode_pair(ip, P, Q);
+        double la[4], vb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) la[j] = vb[j] = 0.0;
+        if (P >= 0) {
+            Link L;
+            link_rows(a, P, Q, v, L);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int A = A0 + l + 16 * j;
+                if (A < N && A != P && A != Q) la[j] = link_at(L, A);
+            }
+            for (int i = ib0; i < ib1; ++i) {
+                const double wb = pq_g_coef[i] * lam[3L * N + (long)pq_g_mu[i] * np2 + ip];
+                if (wb == 0.0) continue;
+                link_rows(pq_g_b[i], P, Q, v, L);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int B = B0 + l + 16 * j;
+                    if (B < N && B != P && B != Q) vb[j] += wb * link_at(L, B);
+                }
+            }
+        }
+        __syncthreads();                      // previous chunk's operands consumed
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Ls[(l + 16 * j) * WB_PITCH + kk] = la[j];
+            Vs[(l + 16 * j) * WB_PITCH + kk] = vb[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < WB_KC; k4 += 4) {
+            const double av = Ls[(wave * 16 + i16) * WB_PITCH + k4 + kq];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Vs[(cb * 16 + i16) * WB_PITCH + k4 + kq],
+                                                             D[cb], 0, 0, 0);
+        }
+    }
+    double* out = Wb + (long)pq_g_w[g] * v.NN;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int A = A0 + wave * 16 + kq + 4 * r, B = B0 + cb * 16 + i16;
+            if (A < N && B < N && A != B && D[cb][r] != 0.0) atomicAdd(&out[(long)A * N + B], D[cb][r]);
+        }
 }
 
 // packed tbar from the adjoints of t1 and the mirrored t2
@@ -1632,15 +1870,39 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                                bytes, s, N, t, c.h1, c.h2T, c.S, lam, a, Sb);
         }
         {
-            const int rt = (int)((np2 + S2A_ROWS - 1) / S2A_ROWS);
-            const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt, 1)));
+            const int rt2 = s2_rowtiles(N);
+            const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt2, 1)));
             const int gchunk = (PQ_G_N + nchunk - 1) / nchunk;
-            const size_t bytes = (size_t)(2 * S2A_ROWS * N) * sizeof(double);
-            hipLaunchKernelGGL(k_r2s2_adj, dim3(rt, (PQ_G_N + gchunk - 1) / gchunk), dim3(256), bytes,
-                               s, N, v, c.W, lam, gchunk, a, Wb);
+            const dim3 ga(rt2, (PQ_G_N + gchunk - 1) / gchunk);
+            auto ldsa = [](int ncb_) { return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_) * sizeof(double); };
+            const int ncb = (N + 15) / 16;
+#define PQ_S2A_LAUNCH(NB) \
+    hipLaunchKernelGGL(k_r2s2_adjm<NB>, ga, dim3(256), ldsa(NB), s, N, v, c.W, lam, gchunk, a)
+            if (ncb <= 1) PQ_S2A_LAUNCH(1);
+            else if (ncb <= 2) PQ_S2A_LAUNCH(2);
+            else if (ncb <= 3) PQ_S2A_LAUNCH(3);
+            else if (ncb <= 4) PQ_S2A_LAUNCH(4);
+            else if (ncb <= 5) PQ_S2A_LAUNCH(5);
+            else if (ncb <= 6) PQ_S2A_LAUNCH(6);
+            else if (ncb <= 8) PQ_S2A_LAUNCH(8);
+            else if (ncb <= 10) PQ_S2A_LAUNCH(10);
+            else if (ncb <= 13) PQ_S2A_LAUNCH(13);
+            else PQ_S2A_LAUNCH(16);
+#undef PQ_S2A_LAUNCH
+            // vertex adjoint: about 2048 workgroups of (tile, group, pair slice)
+            const int nt64 = (N + WB_T - 1) / WB_T;
+            const long np2l = (long)N * (N - 1) / 2;
+            const int nslice = (int)std::max(1L, std::min((np2l + WB_KC - 1) / WB_KC,
+                                                          2048L / (nt64 * nt64 * PQ_G_N)));
+            const long per = ((np2l + nslice - 1) / nslice + WB_KC - 1) / WB_KC * WB_KC;
+            hipLaunchKernelGGL(k_wbar, dim3(nt64 * nt64, PQ_G_N, (unsigned)((np2l + per - 1) / per)),
+                               dim3(256), 0, s, N, v, lam, per, Wb);
         }
-        hipLaunchKernelGGL(k_gemm_s1_adj, dim3(gx, N, PQ_S1PAIRS_N), dim3(tb), 0, s, N, Xf, Yf, Sb,
-                           Xb, Yb);
+        {
+            const int nAt = (N + S1A_T - 1) / S1A_T;
+            hipLaunchKernelGGL(k_s1_adj<0>, dim3(nAt * nAt, PQ_S1AX_N), dim3(256), 0, s, N, Xf, Yf, Sb, Xb);
+            hipLaunchKernelGGL(k_s1_adj<1>, dim3(nAt * nAt, PQ_S1AY_N), dim3(256), 0, s, N, Xf, Yf, Sb, Yb);
+        }
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_X_N), dim3(tb), 0, s, N, 0, v, Xb, a);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_Y_N), dim3(tb), 0, s, N, 1, v, Yb, a);
         hipLaunchKernelGGL(k_dress_adj, dim3(gx, N, PQ_DR_N), dim3(tb), 0, s, N, c.Lam, c.W, Db, Lamb,

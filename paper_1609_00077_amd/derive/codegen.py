@@ -830,6 +830,26 @@ def emit_pq_header(tb: PQTables, path: str):
     parts.append(_spec_arrays("pq_y", tb.r2s1_y))
     parts.append(_arr("pq_s1pairs", "int", tb.r2s1_pairs.reshape(-1))
                  + f"#define PQ_S1PAIRS_N {len(tb.r2s1_pairs)}\n")
+    # adjoint of the one-spectator GEMM, gathered per side: segments of at
+    # most S1A_SEG pairs sharing x (the pair list is in (x, y) order) and, via
+    # a permutation into (y, x) order, sharing y
+    S1A_SEG = 32
+    pr = [tuple(int(u) for u in q) for q in tb.r2s1_pairs]
+    assert pr == sorted(pr)
+
+    def segments(keys):
+        starts = [0]
+        for i in range(1, len(keys) + 1):
+            if i == len(keys) or keys[i] != keys[starts[-1]] or i - starts[-1] == S1A_SEG:
+                starts.append(i)
+        return starts                       # segment j = [starts[j], starts[j + 1])
+
+    ax = segments([q[0] for q in pr])
+    perm = sorted(range(len(pr)), key=lambda i: (pr[i][1], pr[i][0]))
+    ay = segments([pr[i][1] for i in perm])
+    parts.append(_arr("pq_s1ax_p0", "int", ax) + _arr("pq_s1y_perm", "int", perm)
+                 + _arr("pq_s1ay_i0", "int", ay)
+                 + f"#define PQ_S1AX_N {len(ax) - 1}\n#define PQ_S1AY_N {len(ay) - 1}\n")
     # factorised one-pair two-spectator class: one spec table X | Y | Z
     nx, ny = len(tb.r1s2_x), len(tb.r1s2_y)
     parts.append(_spec_arrays("pq_r1f", tb.r1s2_x + tb.r1s2_y + tb.r1s2_z)
