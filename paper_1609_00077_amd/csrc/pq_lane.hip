@@ -8,8 +8,11 @@
 // four amplitudes of the pair.  The amplitudes are held in registers and the
 // terms are generated straight-line code (pq_lane_code.h, one function per
 // chunk of terms), so a term costs a few multiplies and no table or LDS
-// traffic.  Workgroup: 64 pairs x 4 chunks (one per wavefront); each chunk's
-// sums go to part[chunk][pq] and are combined per output in a fixed order.
+// traffic.  A chunk serves a cluster of up to 8 outputs that share streamed
+// sums S_p, so each S_p is loaded once per cluster rather than once per
+// output.  Workgroup: 64 pairs x 4 chunks (one per wavefront); each chunk's
+// sums go to its output slots part[slot][pq], combined per output in a fixed
+// order.
 #include "pqph_internal.h"
 #include "pq_tables.h"
 #include "pq_lane_code.h"
@@ -38,9 +41,16 @@ __global__ __launch_bounds__(256) void k_r2c(int N, const double* __restrict__ t
 #pragma unroll
     for (int i = PQ_LANE_T2; i < PQ_LANE_ONE; ++i) x[i] = t[3L * N + (long)(i - PQ_LANE_T2) * np2 + ipc];
     x[PQ_LANE_ONE] = 1.0;
-    double acc = 0.0;
-    PQ_LANE_SWITCH(c, acc, x, h1, h2K, SK, (long)N, np2, (long)P, (long)Q, ipc)
-    if (ip < np2) part[(long)c * np2 + ip] = acc;
+    double acc[PQ_LANE_MAXOUT];
+#pragma unroll
+    for (int j = 0; j < PQ_LANE_MAXOUT; ++j) acc[j] = 0.0;
+    PQ_LANE_SWITCH(c, x, acc, h1, h2K, SK, (long)N, np2, (long)P, (long)Q, ipc)
+    const int s0 = pq_lane_ch_slot0[c], ns = pq_lane_ch_slot0[c + 1] - s0;
+    if (ip < np2) {
+#pragma unroll
+        for (int j = 0; j < PQ_LANE_MAXOUT; ++j)
+            if (j < ns) part[(long)(s0 + j) * np2 + ip] = acc[j];
+    }
 }
 
 // One-pair outputs, one spectator: one workgroup per output pair P, one

@@ -736,7 +736,9 @@ __global__ void k_final(int N, const double* __restrict__ p1, int nch1,
         const long g2 = gid - n1;
         const int m = (int)(g2 / np2);
         const long ip = g2 - (long)m * np2;
-        for (int c = pq_lane_m_start[m]; c < pq_lane_m_start[m + 1]; ++c) s += p2[(long)c * np2 + ip];
+#pragma unroll 8
+        for (int k = pq_lane_m_slot_start[m]; k < pq_lane_m_slot_start[m + 1]; ++k)
+            s += p2[(long)pq_lane_m_slots[k] * np2 + ip];
 #pragma unroll 8
         for (int c = 0; c < nchunk; ++c) s += ps2[(long)c * NP2 * np2 + g2];
     }
@@ -1599,7 +1601,7 @@ Carve carve(double* ws, int N) {
     c.nch1 = r1_chunks(N);
     c.p1 = take((size_t)c.nch1 * 3 * N);
     c.p1s1 = take((size_t)r1_lane_chunks() * 3 * N);
-    c.p2 = take((size_t)PQ_LANE_NCHUNK * std::max(np2, (size_t)1));
+    c.p2 = take((size_t)PQ_LANE_NSLOT * std::max(np2, (size_t)1));
     c.nblkE = (int)((NN + 255) / 256);
     c.epart = take(c.nblkE);
     c.scal = take(8);
@@ -1614,7 +1616,7 @@ size_t carve_size(int N) {
     return NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
-           (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NCHUNK * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
+           (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NSLOT * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
            (size_t)PQ_R1G_N * NN + (size_t)r1_lane_chunks() * 3 * N;
 }
 

@@ -213,13 +213,12 @@ LANE_T1P, LANE_T1Q, LANE_T2, LANE_ONE, LANE_NLOC = 0, 3, 6, 35, 36
 STREAM_H1P, STREAM_H1Q, STREAM_H2, STREAM_S = 0, 1, 2, 3
 
 
-def build_r2_lane(tb, target=512):
-    """Terms of R2S0 + R2S1 per output m, grouped by streamed factor into
-    segments, cut into chunks of about `target` terms that never span two
-    outputs.  Returns flat arrays for the constant tables."""
-    per_m = []
+def _lane_terms(tb):
+    """Terms of R2S0 + R2S1 as {(m, stream): {amplitude key: coef}}; every
+    term is one streamed factor (h1 of P or Q, h2 or S_p of the pair) times
+    at most four staged amplitudes of the pair."""
+    terms = {}
     for m in range(29):
-        groups = {}
         for name in ("R2S0", "R2S1"):
             tab = tb.classes[name]
             for i in range(tab.start[m], tab.start[m + 1]):
@@ -246,44 +245,95 @@ def build_r2_lane(tb, target=512):
                             stream = (STREAM_S, idx)
                 assert stream is not None and len(tl) <= 4
                 key = tuple(sorted(tl)) + (LANE_ONE,) * (4 - len(tl))
-                g = groups.setdefault(stream, {})
+                g = terms.setdefault((m, stream), {})
                 g[key] = g.get(key, 0.0) + float(tab.coef[i])
-        per_m.append([(st, [(c, k) for k, c in sorted(g.items()) if c != 0.0])
-                      for st, g in sorted(groups.items())])
-    coef, tidx = [], []
+    return terms
+
+
+def _output_blocks(terms, size):
+    """Outputs clustered (greedy pairwise merging, at most `size` per block) so
+    that the one-spectator sums S_p shared by several outputs are streamed
+    once per block rather than once per output."""
+    use = {}
+    for (m, st), g in terms.items():
+        if st[0] == STREAM_S and any(c != 0.0 for c in g.values()):
+            use.setdefault(st, set()).add(m)
+    uses = list(use.values())
+
+    def reads(blocks):
+        bid = {m: b for b, bl in enumerate(blocks) for m in bl}
+        return sum(len({bid[m] for m in u}) for u in uses)
+
+    blocks = [[m] for m in range(29)]
+    while True:
+        base, best = reads(blocks), None
+        for a in range(len(blocks)):
+            for b in range(a + 1, len(blocks)):
+                if len(blocks[a]) + len(blocks[b]) > size:
+                    continue
+                nb = [bl for k, bl in enumerate(blocks) if k not in (a, b)] + [sorted(blocks[a] + blocks[b])]
+                r = reads(nb)
+                if r < base and (best is None or r < best[0]):
+                    best = (r, nb)
+        if best is None:
+            return sorted(blocks)
+        blocks = best[1]
+
+
+def build_r2_lane(tb, target=400, block=8):
+    """Lane-per-pair local terms of the two-pair outputs, in chunks for the
+    straight-line kernel.  Outputs are clustered into blocks of at most
+    `block` (_output_blocks); within a block the terms are grouped by their
+    streamed factor (one load per segment, terms of several outputs), and the
+    groups are dealt into chunks of about `target` terms, a group never split.
+    A chunk accumulates each of its outputs into one slot; slot s holds
+    output slot_m[s], and output m is the fixed-order sum of its slots
+    m_slots[m_slot_start[m]..m_slot_start[m + 1])."""
+    terms = _lane_terms(tb)
+    coef, tidx, term_m = [], [], []
     seg_kind, seg_idx, seg_lo, seg_hi = [], [], [], []
-    ch_lo, ch_hi, ch_m, m_start = [], [], [], [0]
-    for m, groups in enumerate(per_m):
-        n_m = sum(len(t) for _, t in groups)
-        nch = max(1, -(-n_m // target))
-        per = -(-n_m // nch)
-        cur, open_seg = 0, False
-        ch_lo.append(len(seg_kind))
-        ch_m.append(m)
-        for (kind, idx), terms in groups:
-            for c, k in terms:
-                if cur == per:                         # close the chunk
-                    ch_hi.append(len(seg_kind))
-                    ch_lo.append(len(seg_kind))
-                    ch_m.append(m)
-                    cur = 0
-                    open_seg = False
-                if not open_seg or seg_kind[-1] != kind or seg_idx[-1] != idx:
-                    seg_kind.append(kind)
-                    seg_idx.append(idx)
-                    seg_lo.append(len(coef))
-                    seg_hi.append(len(coef))
-                    open_seg = True
-                coef.append(c)
-                tidx += list(k)
-                seg_hi[-1] = len(coef)
-                cur += 1
-            open_seg = False
-        ch_hi.append(len(seg_kind))
-        m_start.append(len(ch_lo))
-    return {"coef": coef, "tidx": tidx, "seg_kind": seg_kind, "seg_idx": seg_idx,
-            "seg_lo": seg_lo, "seg_hi": seg_hi, "ch_lo": ch_lo, "ch_hi": ch_hi, "ch_m": ch_m,
-            "m_start": m_start}
+    ch_lo, ch_hi, ch_slot0, slot_m = [], [], [0], []
+    for bl in _output_blocks(terms, block):
+        groups = {}
+        for m in bl:
+            for (mm, st), g in terms.items():
+                if mm == m:
+                    for k, c in sorted(g.items()):
+                        if c != 0.0:
+                            groups.setdefault(st, []).append((m, c, k))
+        items = sorted(groups.items())
+        n_b = sum(len(v) for _, v in items)
+        nch = max(1, -(-n_b // target))
+        per = -(-n_b // nch)
+        chunks, cur = [[]], 0
+        for st, tl in items:
+            if cur >= per:
+                chunks.append([])
+                cur = 0
+            chunks[-1].append((st, tl))
+            cur += len(tl)
+        for ch in chunks:
+            ch_lo.append(len(seg_kind))
+            outs = sorted({m for _, tl in ch for m, _, _ in tl})
+            slot_m += outs
+            ch_slot0.append(len(slot_m))
+            for (kind, idx), tl in ch:
+                seg_kind.append(kind)
+                seg_idx.append(idx)
+                seg_lo.append(len(coef))
+                for m, c, k in sorted(tl):
+                    coef.append(c)
+                    tidx += list(k)
+                    term_m.append(m)
+                seg_hi.append(len(coef))
+            ch_hi.append(len(seg_kind))
+    m_slots = [s for m in range(29) for s in range(len(slot_m)) if slot_m[s] == m]
+    m_slot_start = [0]
+    for m in range(29):
+        m_slot_start.append(m_slot_start[-1] + slot_m.count(m))
+    return {"coef": coef, "tidx": tidx, "term_m": term_m, "seg_kind": seg_kind, "seg_idx": seg_idx,
+            "seg_lo": seg_lo, "seg_hi": seg_hi, "ch_lo": ch_lo, "ch_hi": ch_hi, "ch_slot0": ch_slot0,
+            "slot_m": slot_m, "m_slots": m_slots, "m_slot_start": m_slot_start}
 
 
 def emit_lane_code(tb, path):
@@ -296,18 +346,20 @@ def emit_lane_code(tb, path):
            "// One function per chunk of the two-pair outputs' local terms.",
            "#pragma once", ""]
     for c, (lo, hi) in enumerate(zip(V["ch_lo"], V["ch_hi"])):
-        out.append(f"__device__ __forceinline__ double lane_chunk_{c}(const double* x, "
+        slot = {m: j for j, m in enumerate(V["slot_m"][V["ch_slot0"][c]:V["ch_slot0"][c + 1]])}
+        out.append(f"__device__ __forceinline__ void lane_chunk_{c}(const double* x, double* acc, "
                    "const double* __restrict__ h1, const double* __restrict__ h2K, "
                    "const double* __restrict__ SK, long N, long np2, long P, long Q, long ip) {")
-        out.append("    double acc = 0.0;")
         for sg in range(lo, hi):
-            terms = []
+            src = names[V["seg_kind"][sg]].format(i=V["seg_idx"][sg])
+            out.append(f"    {{ const double sv = {src};")
+            per_m = {}
             for i in range(V["seg_lo"][sg], V["seg_hi"][sg]):
                 fac = [f"x[{k}]" for k in V["tidx"][4 * i: 4 * i + 4] if k != LANE_ONE]
-                terms.append(" * ".join([repr(float(V["coef"][i]))] + fac))
-            src = names[V["seg_kind"][sg]].format(i=V["seg_idx"][sg])
-            out.append(f"    acc += {src} * ({' + '.join(terms)});")
-        out.append("    return acc;")
+                per_m.setdefault(V["term_m"][i], []).append(" * ".join([repr(float(V["coef"][i]))] + fac))
+            for m, ex in sorted(per_m.items()):
+                out.append(f"      acc[{slot[m]}] += sv * ({' + '.join(ex)});")
+            out.append("    }")
         out.append("}")
         out.append("")
     # one-pair outputs, one spectator A: lanes over ordered (P, A); staged
@@ -365,10 +417,10 @@ def emit_lane_code(tb, path):
     out.append("        default: break; \\")
     out.append("    }")
     out.append("")
-    out.append("#define PQ_LANE_SWITCH(c, acc, ...) \\")
+    out.append("#define PQ_LANE_SWITCH(c, ...) \\")
     out.append("    switch (c) { \\")
     for c in range(len(V["ch_lo"])):
-        out.append(f"        case {c}: acc = lane_chunk_{c}(__VA_ARGS__); break; \\")
+        out.append(f"        case {c}: lane_chunk_{c}(__VA_ARGS__); break; \\")
     out.append("        default: break; \\")
     out.append("    }")
     with open(path, "w") as fh:
@@ -898,17 +950,13 @@ def emit_pq_header(tb: PQTables, path: str):
                  + _arr("pq_loc_m_start", "int", L["m_start"])
                  + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
                  + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))
+    # lane-per-pair chunks (their terms are generated code): output slots
     V = tb.r2_lane
-    tpack = [V["tidx"][4 * i] | (V["tidx"][4 * i + 1] << 8) | (V["tidx"][4 * i + 2] << 16)
-             | (V["tidx"][4 * i + 3] << 24) for i in range(len(V["coef"]))]
-    parts.append(_arr("pq_lane_coef", "double", V["coef"]) + _arr("pq_lane_tidx", "unsigned", tpack)
-                 + _arr("pq_lane_seg_kind", "int", V["seg_kind"]) + _arr("pq_lane_seg_idx", "int", V["seg_idx"])
-                 + _arr("pq_lane_seg_lo", "int", V["seg_lo"]) + _arr("pq_lane_seg_hi", "int", V["seg_hi"])
-                 + _arr("pq_lane_ch_lo", "int", V["ch_lo"]) + _arr("pq_lane_ch_hi", "int", V["ch_hi"])
-                 + _arr("pq_lane_m_start", "int", V["m_start"])
+    nout = [V["ch_slot0"][c + 1] - V["ch_slot0"][c] for c in range(len(V["ch_lo"]))]
+    parts.append(_arr("pq_lane_ch_slot0", "int", V["ch_slot0"]) + _arr("pq_lane_m_slots", "int", V["m_slots"])
+                 + _arr("pq_lane_m_slot_start", "int", V["m_slot_start"])
                  + f"#define PQ_LANE_NCHUNK {len(V['ch_lo'])}\n#define PQ_LANE_NLOC {LANE_NLOC}\n"
-                 + f"#define PQ_LANE_MAXS {max(h - l for l, h in zip(V['ch_lo'], V['ch_hi']))}\n"
-                 + f"#define PQ_LANE_MAXT {max(V['seg_hi'][h - 1] - V['seg_lo'][l] for l, h in zip(V['ch_lo'], V['ch_hi']))}\n"
+                 + f"#define PQ_LANE_NSLOT {len(V['slot_m'])}\n#define PQ_LANE_MAXOUT {max(nout)}\n"
                  + f"#define PQ_LANE_ONE {LANE_ONE}\n#define PQ_LANE_T2 {LANE_T2}\n")
     # link specs of the two-spectator sums, decoded: every factor is
     # t2[m][P or Q][spectator]; up to 3 factors

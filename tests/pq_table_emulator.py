@@ -112,18 +112,23 @@ class Emu:
         loc[3:6] = self.t1[:, Q]
         loc[6:35] = self.t2[:, P, Q]
         loc[35] = 1.0
+        # per chunk, one accumulator per output slot; then each output sums
+        # its slots in the kernels' order
+        slot = np.zeros(len(V["slot_m"]))
+        for c in range(len(V["ch_lo"])):
+            base = V["ch_slot0"][c]
+            local = {m: base + j for j, m in enumerate(V["slot_m"][base:V["ch_slot0"][c + 1]])}
+            for sg in range(V["ch_lo"][c], V["ch_hi"][c]):
+                kind, idx = V["seg_kind"][sg], V["seg_idx"][sg]
+                sv = (self.h1[idx, P] if kind == 0 else self.h1[idx, Q] if kind == 1
+                      else self.h2[idx, P, Q] if kind == 2 else Spairs[idx, P, Q])
+                for i in range(V["seg_lo"][sg], V["seg_hi"][sg]):
+                    k = V["tidx"][4 * i: 4 * i + 4]
+                    slot[local[V["term_m"][i]]] += sv * V["coef"][i] * loc[k[0]] * loc[k[1]] * loc[k[2]] * loc[k[3]]
         out = np.zeros(29)
         for m in range(29):
-            for c in range(V["m_start"][m], V["m_start"][m + 1]):
-                for sg in range(V["ch_lo"][c], V["ch_hi"][c]):
-                    kind, idx = V["seg_kind"][sg], V["seg_idx"][sg]
-                    sv = (self.h1[idx, P] if kind == 0 else self.h1[idx, Q] if kind == 1
-                          else self.h2[idx, P, Q] if kind == 2 else Spairs[idx, P, Q])
-                    s = 0.0
-                    for i in range(V["seg_lo"][sg], V["seg_hi"][sg]):
-                        k = V["tidx"][4 * i: 4 * i + 4]
-                        s += V["coef"][i] * loc[k[0]] * loc[k[1]] * loc[k[2]] * loc[k[3]]
-                    out[m] += sv * s
+            for k in range(V["m_slot_start"][m], V["m_slot_start"][m + 1]):
+                out[m] += slot[V["m_slots"][k]]
         return out
 
     def r1s2_factorised(self):
