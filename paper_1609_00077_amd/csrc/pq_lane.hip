@@ -95,6 +95,53 @@ __global__ __launch_bounds__(256) void k_r1c(int N, const double* __restrict__ t
     }
 }
 
+// Adjoint of the one-pair one-spectator terms: thread (P, A), lam-weighted
+// generated code (r1_adj_code).  Targets only this thread touches -- the
+// adjoints of t2(P,A) and of h2(P,A) -- are plain read-modify-writes (kernels
+// on one stream run in order); those of the per-label vectors are atomics,
+// the P ones after a wavefront reduction.
+__global__ __launch_bounds__(64) void k_r1c_adj(int N, const double* __restrict__ t,
+                                                const double* __restrict__ t2,
+                                                const double* __restrict__ h1,
+                                                const double* __restrict__ h2,
+                                                const double* __restrict__ lam, double* __restrict__ tb1,
+                                                double* __restrict__ tb2, double* __restrict__ hb1,
+                                                double* __restrict__ hb2) {
+    const long NN = (long)N * N;
+    const int P = blockIdx.x, lane = threadIdx.x;
+    const int A = blockIdx.y * 64 + lane;
+    const bool ok = A < N && A != P;
+    const int Ac = ok ? A : (P == 0 ? 1 : 0);          // a valid label for the idle lanes' loads
+    double x[36], gx[36];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        x[i] = t[(long)i * N + P];
+        x[3 + i] = t[(long)i * N + Ac];
+    }
+    const long e = (long)P * N + Ac;
+#pragma unroll
+    for (int m = 0; m < 29; ++m) x[6 + m] = t2[(long)m * NN + e];
+    x[35] = 1.0;
+#pragma unroll
+    for (int i = 0; i < 36; ++i) gx[i] = 0.0;
+    const double l[3] = {lam[P], lam[N + P], lam[2L * N + P]};
+    if (ok) r1_adj_code(x, l, gx, h1, h2, hb1, hb2, (long)N, NN, (long)P, (long)A);
+    if (ok) {
+#pragma unroll
+        for (int m = 0; m < 29; ++m)
+            if (gx[6 + m] != 0.0) tb2[(long)m * NN + e] += gx[6 + m];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (gx[3 + i] != 0.0) atomicAdd(&tb1[(long)i * N + A], gx[3 + i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double g = gx[i];
+        for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+        if (lane == 0 && g != 0.0) atomicAdd(&tb1[(long)i * N + P], g);
+    }
+}
+
 }  // namespace
 
 void launch_r1_lane(hipStream_t s, int N, const double* t, const double* t2, const double* h1,
@@ -103,6 +150,14 @@ void launch_r1_lane(hipStream_t s, int N, const double* t, const double* t2, con
 }
 
 int r1_lane_chunks() { return PQ_R1L_NCHUNK; }
+
+void launch_r1_lane_adj(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
+                        const double* h2, const double* lam, double* tb1, double* tb2, double* hb1,
+                        double* hb2) {
+    if (npair < 2) return;
+    hipLaunchKernelGGL(k_r1c_adj, dim3(npair, (npair + 63) / 64), dim3(64), 0, s, npair, t, t2, h1, h2, lam,
+                       tb1, tb2, hb1, hb2);
+}
 
 void launch_r2_lane(hipStream_t s, int N, const double* t, const double* h1, const double* h2K,
                     const double* SK, double* part, const int* gate) {

@@ -864,8 +864,9 @@ __device__ __forceinline__ void class_adj(const int* start, const double* coef, 
     for (int i = start[m]; i < start[m + 1]; ++i) term_adj(fac + 5 * i, w * coef[i], L0, L1, L2, L3, v, a);
 }
 
-// one-pair outputs: weights lam1[k][P]
-__global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __restrict__ lam,
+// one-pair outputs without spectators: weights lam1[k][P] (the one-spectator
+// terms are k_r1c_adj's generated code)
+__global__ __launch_bounds__(64) void k_r1_adj(int N, View v, const double* __restrict__ lam,
                                                 AdjView a) {
     const int P = blockIdx.x, tid = threadIdx.x;
     const double l0 = lam[P], l1 = lam[N + P], l2 = lam[2 * N + P];
@@ -873,12 +874,6 @@ __global__ __launch_bounds__(256) void k_r1_adj(int N, View v, const double* __r
         class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 0, l0, P, 0, 0, 0, v, a);
         class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 1, l1, P, 0, 0, 0, v, a);
         class_adj(pq_r1s0_start, pq_r1s0_coef, pq_r1s0_fac, 2, l2, P, 0, 0, 0, v, a);
-    }
-    for (int A = tid; A < N; A += blockDim.x) {
-        if (A == P) continue;
-        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 0, l0, P, A, 0, 0, v, a);
-        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 1, l1, P, A, 0, 0, v, a);
-        class_adj(pq_r1s1_start, pq_r1s1_coef, pq_r1s1_fac, 2, l2, P, A, 0, 0, v, a);
     }
 }
 
@@ -1913,7 +1908,8 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
         hipLaunchKernelGGL(k_fold_wt, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, Wb);
         hipLaunchKernelGGL(k_spec_adj, dim3(gx, N, PQ_W_N), dim3(tb), 0, s, N, 2, v, Wb, a);
     }
-    hipLaunchKernelGGL(k_r1_adj, dim3(N), dim3(256), 0, s, N, v, lam, a);
+    hipLaunchKernelGGL(k_r1_adj, dim3(N), dim3(64), 0, s, N, v, lam, a);
+    launch_r1_lane_adj(s, N, t, c.t2, c.h1, c.h2, lam, a.tb1, a.tb2, a.hb1, a.hb2);
     if (N >= 3) {
         const unsigned gsq3 = (unsigned)((N * N + 255) / 256);
         hipLaunchKernelGGL(k_spec_r1, dim3(gsq3, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, nullptr);

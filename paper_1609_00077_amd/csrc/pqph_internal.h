@@ -85,6 +85,10 @@ void launch_r2_lane(hipStream_t s, int npair, const double* t, const double* h1,
 void launch_r1_lane(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
                     const double* h2, double* part, const int* gate);
 int r1_lane_chunks();
+// adjoint of those terms, lam-weighted, into the amplitude and vertex adjoints
+void launch_r1_lane_adj(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
+                        const double* h2, const double* lam, double* tb1, double* tb2, double* hb1,
+                        double* hb2);
 
 // PQ residual pieces (pq_residual.hip) --------------------------------------
 size_t pq_ws_doubles(int npair);

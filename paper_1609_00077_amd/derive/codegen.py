@@ -410,6 +410,30 @@ def emit_lane_code(tb, path):
             out.append("    }")
         out.append("}")
         out.append("")
+    # adjoint of the same terms (lam-weighted): per streamed factor one sum
+    # for its own adjoint, and the adjoints of the staged amplitudes in gx
+    # (each occurrence of a factor gets the product of the others)
+    out.append("__device__ __forceinline__ void r1_adj_code(const double* x, const double* l, double* gx, "
+               "const double* __restrict__ h1, const double* __restrict__ h2, double* __restrict__ hb1, "
+               "double* __restrict__ hb2, long N, long NN, long P, long A) {")
+    for (src, idx), terms in items:
+        out.append(f"    {{ const double sv = {src.format(i=idx)};")
+        out.append("      double gs = 0.0;")
+        for m, c0, tl in terms:
+            out.append(f"      {{ const double w = l[{m}] * {c0!r};")
+            prod = " * ".join([f"x[{j}]" for j in tl]) if tl else "1.0"
+            out.append(f"        gs += w * {prod};")
+            for pos, j in enumerate(tl):
+                rest = [f"x[{k}]" for q, k in enumerate(tl) if q != pos]
+                out.append(f"        gx[{j}] += " + " * ".join(["w", "sv"] + rest) + ";")
+            out.append("      }")
+        if src.startswith("h1"):
+            out.append(f"      if (gs != 0.0) atomicAdd(&hb1[{idx} * N + A], gs);")
+        else:
+            out.append(f"      hb2[{idx} * NN + P * N + A] += gs;")
+        out.append("    }")
+    out.append("}")
+    out.append("")
     out.append("#define PQ_R1L_SWITCH(c, ...) \\")
     out.append("    switch (c) { \\")
     for c in range(len(chunks)):
