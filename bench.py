@@ -180,7 +180,8 @@ def source_hash() -> str:
     for sub in ("paper_1609_00077_amd/csrc", "paper_1609_00077_amd/derive"):
         d = os.path.join(ROOT, sub)
         for name in sorted(os.listdir(d)):
-            if name.endswith((".hip", ".h", ".py")) and not name.startswith(("pq_tables", "pq_lane_code")):
+            generated = name.startswith(("pq_tables", "pq_lane_code", "pq_lane_adj_code"))
+            if name.endswith((".hip", ".h", ".py")) and not generated:
                 with open(os.path.join(d, name), "rb") as fh:
                     h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]

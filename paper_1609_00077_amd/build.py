@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpqph.so")
-SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "pq_lane.hip", "integrals.hip",
-           "batched.hip"]
+SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "pq_lane.hip", "pq_lane_adj.hip",
+           "integrals.hip", "batched.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (wrong results seen on this part)
@@ -26,6 +26,7 @@ def generate_tables() -> None:
     tb = codegen.build_pq_tables()
     codegen.emit_pq_header(tb, os.path.join(CSRC, "pq_tables.h"))
     codegen.emit_lane_code(tb, os.path.join(CSRC, "pq_lane_code.h"))
+    codegen.emit_lane_adj_code(tb, os.path.join(CSRC, "pq_lane_adj_code.h"))
 
 
 def build(verbose: bool = False) -> str:

@@ -950,99 +950,6 @@ __global__ void k_energy_adj(int N, View v, double ew, AdjView a) {
         class_adj(pq_e2_start, pq_e2_coef, pq_e2_fac, 0, 0.5 * ew, P, Q, 0, 0, v, a);
 }
 
-// pair-local adjoint of the no-spectator terms and the one-spectator epilogue
-constexpr int R2A_PPW = 2;
-
-__global__ __launch_bounds__(256) void k_r2_adj(int N, const double* __restrict__ t,
-                                                const double* __restrict__ h1,
-                                                const double* __restrict__ h2T,
-                                                const double* __restrict__ ST,
-                                                const double* __restrict__ lam, AdjView a,
-                                                double* __restrict__ Sb) {
-    extern __shared__ double sm[];
-    double* loc = sm;                                  // [R2A_PPW][PQ_LOC_N]
-    double* locb = sm + R2A_PPW * PQ_LOC_N;            // [R2A_PPW][PQ_LOC_N]
-    double* laml = locb + R2A_PPW * PQ_LOC_N;          // [R2A_PPW][29]
-    const long np2 = (long)N * (N - 1) / 2;
-    const long ip0 = (long)blockIdx.x * R2A_PPW;
-    const int tid = threadIdx.x;
-    int PP[R2A_PPW], QQ[R2A_PPW];
-    for (int p = 0; p < R2A_PPW; ++p) {
-        const long ip = ip0 + p;
-        const bool ok = ip < np2;
-        int P = 0, Q = 1;
-        if (ok) decode_pair(ip, P, Q);
-        PP[p] = ok ? P : -1;
-        QQ[p] = Q;
-        double* L = loc + p * PQ_LOC_N;
-        for (int i = tid; i < PQ_LOC_N; i += blockDim.x) {
-            double val = 0.0;
-            if (i == PQ_LOC_ONE)
-                val = 1.0;
-            else if (ok) {
-                if (i < PQ_LOC_T1Q) val = t[(long)(i - PQ_LOC_T1P) * N + P];
-                else if (i < PQ_LOC_T2) val = t[(long)(i - PQ_LOC_T1Q) * N + Q];
-                else if (i < PQ_LOC_H1P) val = t[3L * N + (long)(i - PQ_LOC_T2) * np2 + ip];
-                else if (i < PQ_LOC_H1Q) val = h1[(long)(i - PQ_LOC_H1P) * N + P];
-                else if (i < PQ_LOC_H2) val = h1[(long)(i - PQ_LOC_H1Q) * N + Q];
-                else if (i < PQ_LOC_S) val = h2T[(long)(i - PQ_LOC_H2) * np2 + ip];
-                else val = ST[(long)(i - PQ_LOC_S) * np2 + ip];
-            }
-            L[i] = val;
-            locb[p * PQ_LOC_N + i] = 0.0;
-        }
-        if (tid < NP2) laml[p * NP2 + tid] = ok ? lam[3L * N + (long)tid * np2 + ip] : 0.0;
-    }
-    __syncthreads();
-    for (int c = tid; c < PQ_LOC_NCHUNK; c += blockDim.x) {
-        const int m = pq_loc_ch_m[c];
-        const int hi = pq_loc_ch_hi[c];
-        for (int i = pq_loc_ch_lo[c]; i < hi; ++i) {
-            const double cf = pq_loc_coef[i];
-            const unsigned short* ix = pq_loc_idx + 5 * i;
-#pragma unroll
-            for (int p = 0; p < R2A_PPW; ++p) {
-                const double w = cf * laml[p * NP2 + m];
-                if (w == 0.0) continue;
-                const double* L = loc + p * PQ_LOC_N;
-                double fv[5];
-#pragma unroll
-                for (int j = 0; j < 5; ++j) fv[j] = L[ix[j]];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    if (ix[k] == PQ_LOC_ONE) continue;
-                    double d = w;
-#pragma unroll
-                    for (int j = 0; j < 5; ++j)
-                        if (j != k) d *= fv[j];
-                    atomicAdd(&locb[p * PQ_LOC_N + ix[k]], d);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int p = 0; p < R2A_PPW; ++p) {
-        const int P = PP[p], Q = QQ[p];
-        if (P < 0) continue;
-        const long ip = ip0 + p;
-        const double* Lb = locb + p * PQ_LOC_N;
-        for (int i = tid; i < PQ_LOC_ONE; i += blockDim.x) {
-            const double d = Lb[i];
-            if (i >= PQ_LOC_S) {
-                Sb[(long)(i - PQ_LOC_S) * np2 + ip] = d;   // p-major: rows of Sbar_p
-                continue;
-            }
-            if (d == 0.0) continue;
-            if (i < PQ_LOC_T1Q) atomicAdd(&a.tb1[(long)(i - PQ_LOC_T1P) * N + P], d);
-            else if (i < PQ_LOC_T2) atomicAdd(&a.tb1[(long)(i - PQ_LOC_T1Q) * N + Q], d);
-            else if (i < PQ_LOC_H1P) atomicAdd(&a.tb2[(long)(i - PQ_LOC_T2) * a.NN + (long)P * N + Q], d);
-            else if (i < PQ_LOC_H1Q) atomicAdd(&a.hb1[(long)(i - PQ_LOC_H1P) * N + P], d);
-            else if (i < PQ_LOC_H2) atomicAdd(&a.hb1[(long)(i - PQ_LOC_H1Q) * N + Q], d);
-            else atomicAdd(&a.hb2[(long)(i - PQ_LOC_H2) * a.NN + (long)P * N + Q], d);
-        }
-    }
-}
-
 // One-spectator GEMM adjoint on the FP64 matrix cores, gathered per side:
 //   SIDE 0: Xbar_x(P,A) += sum_{p = (x,y)} sum_{Q>P} Sbar_p(P,Q) Y_y(Q,A)
 //   SIDE 1: Ybar_y(Q,A) += sum_{p = (x,y)} sum_{P<Q} Sbar_p(P,Q) X_x(P,A)
@@ -1851,20 +1758,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
         hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v, Xf,
                            Yf, c.S, nullptr);
         {
-            const size_t bytes =
-                (size_t)(2 * R2A_PPW * PQ_LOC_N + R2A_PPW * NP2) * sizeof(double);
-            static bool attr = false;
-            if (!attr) {
-                hipError_t e_ = hipFuncSetAttribute((const void*)&k_r2_adj,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                    (int)bytes);
-                if (e_ != hipSuccess)
-                    return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") +
-                                                           hipGetErrorString(e_));
-                attr = true;
-            }
-            hipLaunchKernelGGL(k_r2_adj, dim3((unsigned)((np2 + R2A_PPW - 1) / R2A_PPW)), dim3(256),
-                               bytes, s, N, t, c.h1, c.h2T, c.S, lam, a, Sb);
+            launch_r2_lane_adj(s, N, t, c.h1, c.h2T, c.S, lam, a.tb1, a.tb2, a.hb1, a.hb2, Sb);
         }
         {
             const int rt2 = s2_rowtiles(N);

@@ -85,6 +85,11 @@ void launch_r2_lane(hipStream_t s, int npair, const double* t, const double* h1,
 void launch_r1_lane(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
                     const double* h2, double* part, const int* gate);
 int r1_lane_chunks();
+// adjoint of the two-pair local terms (pq_lane_adj.hip): Sbar_p (p-major) and
+// h2bar(P,Q) written by their owning lane, the rest added atomically
+void launch_r2_lane_adj(hipStream_t s, int npair, const double* t, const double* h1, const double* h2K,
+                        const double* SK, const double* lam, double* tb1, double* tb2, double* hb1,
+                        double* hb2, double* SbK);
 // adjoint of those terms, lam-weighted, into the amplitude and vertex adjoints
 void launch_r1_lane_adj(hipStream_t s, int npair, const double* t, const double* t2, const double* h1,
                         const double* h2, const double* lam, double* tb1, double* tb2, double* hb1,

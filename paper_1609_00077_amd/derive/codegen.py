@@ -71,7 +71,6 @@ class PQTables:
     r2s2_groups: list = None       # per (w, a): list of (b, coef, mu)
     r2s2_lam: list = None          # one-sided link products, roles 0 (P or Q), 1 (B)
     r2s2_dress: list = None        # (lam index or -1 for 1, vertex): D(s,A) = sum_B lam(s,B) W(A,B)
-    r2_local: dict = None          # R2S0 + R2S1 terms on pair-local staging offsets
     r2_lane: dict = None           # the same terms grouped by their streamed factor
 
 
@@ -123,85 +122,6 @@ def _interp_rows(tables, terms, nout):
         codes += [_slot_code(rho, p, ident) for rho, p in t.slots]
         rows.append((m, float(t.sign), codes))
     return rows
-
-
-# Pair-local staging of the two-pair classes: every factor of a no- or
-# one-spectator term with outputs (P, Q) is one of the pair's own values,
-# staged contiguously: t1(P) t1(Q) t2(P,Q) h1(P) h1(Q) h2(P,Q) S(P,Q) 1.0
-LOC_T1P, LOC_T1Q, LOC_T2, LOC_H1P = 0, 3, 6, 35
-
-
-def local_offsets(n_h1, n_h2, n_s):
-    off = {"t1P": 0, "t1Q": 3, "t2": 6, "h1P": 35}
-    off["h1Q"] = off["h1P"] + n_h1
-    off["h2"] = off["h1Q"] + n_h1
-    off["S"] = off["h2"] + n_h2
-    off["one"] = off["S"] + n_s
-    off["n"] = off["one"] + 1
-    return off
-
-
-def _balanced_chunk(counts, threads=256, max_chunks=1024):
-    """Chunk length that minimises the per-thread work ceil(#chunks/threads)
-    * length when each output's rows are cut into chunks (longest wins ties)."""
-    best = None
-    for ch in range(16, 257):
-        n = sum(-(-c // ch) for c in counts)
-        if n > max_chunks:
-            continue
-        key = (-(-n // threads) * ch, -ch)
-        if best is None or key < best[0]:
-            best = (key, ch)
-    return best[1]
-
-
-def build_r2_local(tb, chunk=None):
-    off = local_offsets(len(tb.h1_keys), len(tb.h2_keys), len(tb.r2s1_pairs))
-
-    def loc(code):
-        if code == 0:
-            return off["one"]
-        kind = (code >> 28) & 15
-        r0, r1 = (code >> 24) & 15, (code >> 20) & 15
-        idx = code & 0xFFFF
-        if kind == KIND_T1:
-            return (off["t1P"] if r0 == 0 else off["t1Q"]) + idx
-        if kind == KIND_T2:
-            assert (r0, r1) == (0, 1)
-            return off["t2"] + idx
-        if kind == KIND_H1:
-            return (off["h1P"] if r0 == 0 else off["h1Q"]) + idx
-        if kind == KIND_H2:
-            assert (r0, r1) == (0, 1)
-            return off["h2"] + idx
-        if kind == KIND_S:
-            return off["S"] + idx
-        raise ValueError(kind)
-
-    if chunk is None:
-        # k_r2: 1024 threads, one chunk each at best; the staging of 4 pairs
-        # and 4 partial sums per chunk must fit 160 KB of LDS
-        counts = [sum(tb.classes[nm].start[m + 1] - tb.classes[nm].start[m] for nm in ("R2S0", "R2S1"))
-                  for m in range(29)]
-        max_chunks = (160 * 1024 // 8 - 4 * (off["one"] + 1)) // 4 - 16
-        chunk = _balanced_chunk(counts, threads=1024, max_chunks=max_chunks)
-    coef, idx, ch_m, ch_lo, ch_hi, m_start = [], [], [], [], [], [0]
-    for m in range(29):
-        rows = []
-        for name in ("R2S0", "R2S1"):
-            tab = tb.classes[name]
-            for i in range(tab.start[m], tab.start[m + 1]):
-                rows.append((tab.coef[i], [loc(int(c)) for c in tab.fac[i]]))
-        for a in range(0, len(rows), chunk):
-            ch_m.append(m)
-            ch_lo.append(len(coef) + a)
-            ch_hi.append(len(coef) + min(len(rows), a + chunk))
-        for c, ix in rows:
-            coef.append(c)
-            idx += ix
-        m_start.append(len(ch_m))
-    return {"off": off, "coef": coef, "idx": idx, "ch_m": ch_m, "ch_lo": ch_lo,
-            "ch_hi": ch_hi, "m_start": m_start}
 
 
 # Lane-per-pair evaluation of the two-pair outputs' local terms: every term is
@@ -451,6 +371,75 @@ def emit_lane_code(tb, path):
         fh.write("\n".join(out) + "\n")
 
 
+def emit_lane_adj_code(tb, path, target=400):
+    """Adjoint of the lane-per-pair local terms of the two-pair outputs, as
+    straight-line code: the terms are grouped by streamed factor over all
+    outputs (each stream in exactly one chunk), so a chunk computes the whole
+    adjoint of each of its streams -- stored once, no atomics -- and adds to
+    the adjoints of the pair's staged amplitudes gx.  Term weights are
+    lam_m(P,Q) times the coefficient."""
+    terms = _lane_terms(tb)
+    groups = {}
+    for (m, st), g in sorted(terms.items()):
+        for k, c in sorted(g.items()):
+            if c != 0.0:
+                groups.setdefault(st, []).append((m, c, k))
+    s_streams = {st[1] for st in groups if st[0] == STREAM_S}
+    assert s_streams == set(range(len(tb.r2s1_pairs))), "every S_p must get its adjoint written"
+    items = sorted(groups.items())
+    total = sum(len(v) for _, v in items)
+    nch = max(1, -(-total // target))
+    per = -(-total // nch)
+    chunks, cur = [[]], 0
+    for st, tl in items:
+        if cur >= per:
+            chunks.append([])
+            cur = 0
+        chunks[-1].append((st, tl))
+        cur += len(tl)
+    src = {STREAM_H1P: "h1[{i} * N + P]", STREAM_H1Q: "h1[{i} * N + Q]", STREAM_H2: "h2K[{i} * np2 + ip]",
+           STREAM_S: "SK[{i} * np2 + ip]"}
+    dst = {STREAM_H1P: "atomicAdd(&hb1[{i} * N + P], gs);", STREAM_H1Q: "atomicAdd(&hb1[{i} * N + Q], gs);",
+           STREAM_H2: "hb2[{i} * NN + P * N + Q] += gs;", STREAM_S: "SbK[{i} * np2 + ip] = gs;"}
+    out = ["// Generated by paper_1609_00077_amd/derive/codegen.py -- do not edit.",
+           "// Adjoint of the two-pair outputs' local terms, one function per chunk.",
+           "#pragma once", "", f"#define PQ_LANEA_NCHUNK {len(chunks)}", ""]
+    for c, ch in enumerate(chunks):
+        out.append(f"__device__ __forceinline__ void lane_adj_chunk_{c}(const double* x, double* gx, "
+                   "const double* __restrict__ lam, const double* __restrict__ h1, "
+                   "const double* __restrict__ h2K, const double* __restrict__ SK, double* __restrict__ hb1, "
+                   "double* __restrict__ hb2, double* __restrict__ SbK, long N, long NN, long np2, long P, "
+                   "long Q, long ip) {")
+        used = sorted({m for _, tl in ch for m, _, _ in tl})
+        for m in used:
+            out.append(f"    const double l{m} = lam[3 * N + {m} * np2 + ip];")
+        for (kind, idx), tl in ch:
+            out.append(f"    {{ const double sv = {src[kind].format(i=idx)};")
+            out.append("      double gs = 0.0;")
+            for m, c0, k in tl:
+                fac = [j for j in k if j != LANE_ONE]
+                prod = " * ".join(f"x[{j}]" for j in fac) if fac else "1.0"
+                out.append(f"      {{ const double w = l{m} * {c0!r}; gs += w * ({prod});")
+                if fac:
+                    out.append("        const double ws = w * sv;")
+                    for pos, j in enumerate(fac):
+                        rest = [f"x[{q}]" for n, q in enumerate(fac) if n != pos]
+                        out.append(f"        gx[{j}] += " + " * ".join(["ws"] + rest) + ";")
+                out.append("      }")
+            out.append(f"      {dst[kind].format(i=idx)}")
+            out.append("    }")
+        out.append("}")
+        out.append("")
+    out.append("#define PQ_LANEA_SWITCH(c, ...) \\")
+    out.append("    switch (c) { \\")
+    for c in range(len(chunks)):
+        out.append(f"        case {c}: lane_adj_chunk_{c}(__VA_ARGS__); break; \\")
+    out.append("        default: break; \\")
+    out.append("    }")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 def eri_quads(size):
     """Stored quadruples of the packed integral layout (include/pqph.h)."""
     norb = 2 * size
@@ -661,7 +650,6 @@ def build_pq_tables() -> PQTables:
                     for code in codes]) for m, c, codes in rows]
     tb.r2s1_pairs = np.array(order, dtype=np.int32).reshape(-1, 2)
     tb.classes["R2S1"] = _table(29, rows)
-    tb.r2_local = build_r2_local(tb)
     tb.r2_lane = build_r2_lane(tb)
     return tb
 
@@ -913,10 +901,10 @@ def emit_pq_header(tb: PQTables, path: str):
     pr = [tuple(int(u) for u in q) for q in tb.r2s1_pairs]
     assert pr == sorted(pr)
 
-    def segments(keys):
+    def segments(keys, size=S1A_SEG):
         starts = [0]
         for i in range(1, len(keys) + 1):
-            if i == len(keys) or keys[i] != keys[starts[-1]] or i - starts[-1] == S1A_SEG:
+            if i == len(keys) or keys[i] != keys[starts[-1]] or i - starts[-1] == size:
                 starts.append(i)
         return starts                       # segment j = [starts[j], starts[j + 1])
 
@@ -967,13 +955,6 @@ def emit_pq_header(tb: PQTables, path: str):
     parts.append(_arr("pq_g_w", "int", gw) + _arr("pq_g_a", "int", ga) + _arr("pq_g_start", "int", gs)
                  + _arr("pq_g_b", "int", gb) + _arr("pq_g_coef", "double", gc) + _arr("pq_g_mu", "int", gm)
                  + f"#define PQ_G_N {len(gw)}\n")
-    L = tb.r2_local
-    parts.append(_arr("pq_loc_coef", "double", L["coef"]) + _arr("pq_loc_idx", "unsigned short", L["idx"])
-                 + _arr("pq_loc_ch_lo", "int", L["ch_lo"]) + _arr("pq_loc_ch_hi", "int", L["ch_hi"])
-                 + _arr("pq_loc_ch_m", "int", L["ch_m"])
-                 + _arr("pq_loc_m_start", "int", L["m_start"])
-                 + f"#define PQ_LOC_N {L['off']['n']}\n#define PQ_LOC_NCHUNK {len(L['ch_lo'])}\n"
-                 + "".join(f"#define PQ_LOC_{k.upper()} {v}\n" for k, v in L["off"].items() if k != "n"))
     # lane-per-pair chunks (their terms are generated code): output slots
     V = tb.r2_lane
     nout = [V["ch_slot0"][c + 1] - V["ch_slot0"][c] for c in range(len(V["ch_lo"]))]
