@@ -300,7 +300,7 @@ def main():
                                f"U={args.U}, seed {args.seed}) from t=0 to ||R||<={args.tol:g}, "
                                "integral transform included", "sites": args.sites, "pairs": N,
                    "iterations_per_solve": res.iterations, "energy": res.energy,
-                   "s2_variant": variant},
+                   "s2_variant": variant, "s1_mode": pq.tuning(N)["s1_mode"]},
         "roofline": {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom,
                      "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": hbm_traffic(dom),

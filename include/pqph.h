@@ -156,11 +156,13 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
 /* Diagnostic (per-phase tracing): one pq_residual with a HIP event recorded on
  * the context's stream after every kernel; phase_ms (host, nphase entries)
  * receives the elapsed time of each kernel in launch order and *nphase_out
- * their number (15 for npair >= 3: vertex1, vertex2, unpack_t2, spec_w,
- * spec_lam, dress, gemm_s1, r2s2, r2c, spec_r1, r1s2, r1s2_close, r1, r1c,
- * final; 12 for npair = 2, without spec_r1, r1s2 and r1s2_close; 4 for
- * npair = 1: vertex1, r1, r1c, final).  Synchronises the stream.  Fails with
- * INVALID_ARG if nphase is too small. */
+ * their number (16 for npair >= 3: vertex1, vertex2, unpack_t2, spec_w,
+ * spec_lam, dress, spec_xy (the materialised one-spectator sides; empty
+ * unless that mode is in effect), gemm_s1, r2s2, r2c, spec_r1, r1s2,
+ * r1s2_close, r1, r1c, final; 13 for npair = 2, without spec_r1, r1s2 and
+ * r1s2_close; 4 for npair = 1: vertex1, r1, r1c, final).  The kernels run
+ * serially on the context's stream here.  Synchronises the stream.  Fails
+ * with INVALID_ARG if nphase is too small. */
 pqph_status pq_residual_profile(pqph_ctx* ctx, int npair, const double* h,
                                 const double* eri, const double* t, double* r,
                                 double* phase_ms, int nphase, int* nphase_out);
@@ -173,8 +175,10 @@ const char* pq_residual_phase_name(int i);
  * contraction for this npair on the given inputs (three residuals each, after
  * a warm-up; r receives the last residual) and keep the fastest for every
  * later call on this context.  *choice (host, may be NULL) = 1 (K-chunked
- * staging of the vertex) or 2 (vertex resident in LDS, npair <= 96).
- * Synchronises the stream.  Without tuning, variant 1 is used. */
+ * staging of the vertex) or 2 (vertex resident in LDS, npair <= 96).  The
+ * one-spectator mode (pqph_set_s1_mode) is tuned jointly, over every pair of
+ * choices.  Synchronises the stream.  Without tuning, variant 1 and the
+ * size-based mode are used. */
 pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h,
                           const double* eri, const double* t, double* r,
                           int* choice);
@@ -182,6 +186,20 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h,
 /* Force the two-spectator variant for npair on this context (0 = default,
  * 1, or 2 when npair <= 96); INVALID_ARG otherwise.  For tests and tuning. */
 pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
+
+/* Force how the one-spectator GEMM (Sec. II one-spectator terms, S_p(P,Q) =
+ * sum_A X_x(P,A) Y_y(Q,A)) obtains its sides for npair on this context:
+ * 0 = default (by size, or as tuned by pqph_autotune), 1 = each side formed
+ * from its factors while staging, 2 = X and Y materialised first and read by
+ * the GEMM, 3 = as 1 with the next chunk's loads overlapping the current
+ * chunk's matrix-core steps (npair <= 128).  All give the same residual up to
+ * rounding order.  INVALID_ARG for another mode.  For tests and tuning. */
+pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
+
+/* The choices in effect for npair on this context (host outputs, each may be
+ * NULL): the two-spectator variant (1 or 2) and the one-spectator mode (1, 2
+ * or 3). */
+pqph_status pqph_tuning(pqph_ctx* ctx, int npair, int* s2_variant, int* s1_mode);
 
 /* Batched PQ solves (many Hamiltonians of uneven pair counts, solved
  * together; each chain runs its own Jacobi + DIIS exactly as pq_solve and

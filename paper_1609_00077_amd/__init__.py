@@ -100,8 +100,8 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     _check(lib, ctx, lib.pq_residual_profile(ctx, npair, _dev(h, "h", 4 * npair * npair),
                                              _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
                                              _dev(out, "out", na), ms, 24, C.byref(n)))
-    names = [lib.pq_residual_phase_name(i).decode() for i in range(15)]
-    if n.value == 12:      # npair == 2: no one-pair two-spectator terms
+    names = [lib.pq_residual_phase_name(i).decode() for i in range(16)]
+    if n.value == 13:      # npair == 2: no one-pair two-spectator terms
         names = [x for x in names if x not in ("k_spec_r1", "k_r1s2", "k_r1s2_close")]
     elif n.value == 4:     # npair == 1: no two-pair outputs
         names = ["k_vertex1", "k_r1", "k_r1c", "k_final"]
@@ -127,6 +127,24 @@ def set_variant(npair: int, variant: int, device: str | torch.device = "cuda:0")
     on the context of the current stream."""
     lib, ctx = _ctx(torch.device(device))
     _check(lib, ctx, lib.pqph_set_variant(ctx, npair, variant))
+
+
+def set_s1_mode(npair: int, mode: int, device: str | torch.device = "cuda:0") -> None:
+    """Force how the one-spectator GEMM gets its sides for npair (1 formed
+    while staging, 2 materialised, 3 formed while staging with the loads
+    pipelined, npair <= 128; 0 = default) on the context of the current
+    stream."""
+    lib, ctx = _ctx(torch.device(device))
+    _check(lib, ctx, lib.pqph_set_s1_mode(ctx, npair, mode))
+
+
+def tuning(npair: int, device: str | torch.device = "cuda:0") -> dict:
+    """The kernel choices in effect for npair: two-spectator variant and
+    one-spectator mode."""
+    lib, ctx = _ctx(torch.device(device))
+    v, m = C.c_int(), C.c_int()
+    _check(lib, ctx, lib.pqph_tuning(ctx, npair, C.byref(v), C.byref(m)))
+    return {"s2_variant": v.value, "s1_mode": m.value}
 
 
 def pq_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:

@@ -48,6 +48,8 @@ SIGNATURES = {
     "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
     "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
     "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
+    "pqph_set_s1_mode": (C.c_int, [P, C.c_int, C.c_int]),
+    "pqph_tuning": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pqph_set_batch_mode": (C.c_int, [P, C.c_int]),
     "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),
     "pq_energy_grad": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),

@@ -283,7 +283,7 @@ __device__ __forceinline__ double spec_eval(const SpecPtrs& q, int L0, int L1) {
     double x = 1.0;
 #pragma unroll
     for (int f = 0; f < SPEC_MAXF; ++f)
-        if (f < q.n) x *= q.p[f][(long)L0 * q.sa[f] + (long)L1 * q.sb[f]];
+        if (f < q.n) x *= q.p[f][L0 * q.sa[f] + L1 * q.sb[f]];   // < 2^16: 32-bit offsets
     return x;
 }
 
@@ -360,6 +360,109 @@ __global__ __launch_bounds__(256) void k_gemm_s1(int N, View v, const double* __
     for (int u = 0; u < S1_TPW; ++u) {
         if (!tv[u]) continue;
         // D[u][r] = S(P = tP*16 + kq + 4r, Q = tQ*16 + i): stage as Ts[Ql][Pl]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ts[i * S1_PITCH + kq + 4 * r] = D[u][r];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int e = lane; e < 256; e += 64) {
+            const int ql = e >> 4, pl = e & 15;
+            const int P = tP[u] * 16 + pl, Q = tQ[u] * 16 + ql;
+            if (P < Q && Q < N) out[(long)Q * (Q - 1) / 2 + P] = Ts[ql * S1_PITCH + pl];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// Mode 3 of the same contraction: the fused staging software-pipelined.  The
+// raw factors of K-chunk k+1 are loaded into registers before the matrix-core
+// steps of chunk k are issued, and multiplied into the other of two LDS
+// buffers after them, so the loads overlap the MFMAs of the same wavefront;
+// one barrier per chunk.  NT = row tiles (N <= 16 NT); thread element j of a
+// chunk is e = tid + 256 j (row e/16, column e%16).
+template <int NT>
+__global__ __launch_bounds__(256) void k_gemm_s1p(int N, View v, double* __restrict__ SK,
+                                                  const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    extern __shared__ double sm[];
+    constexpr int NR = NT * 16, ntile = NT * (NT + 1) / 2;
+    constexpr int ngrp = (ntile + S1_TPG - 1) / S1_TPG;
+    const long nitem = (long)ngrp * PQ_S1PAIRS_N;
+    const long per = gridDim.x / 8;
+    const long w = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= nitem) return;
+    const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
+    double* Xs = sm;                          // [2][NR][S1_PITCH]
+    double* Ys = Xs + 2 * NR * S1_PITCH;      // [2][NR][S1_PITCH]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double* Ts = Ys + 2 * NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
+    const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
+    const SpecPtrs xq = spec_ptrs(pq_x_fac, pq_x_start[xi], pq_x_start[xi + 1], v);
+    const SpecPtrs yq = spec_ptrs(pq_y_fac, pq_y_start[yi], pq_y_start[yi + 1], v);
+    const int i = lane & 15, kq = lane >> 4;
+    int tP[S1_TPW], tQ[S1_TPW];
+    bool tv[S1_TPW];
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) {
+        const int t = tg * S1_TPG + wave + 4 * u;
+        tv[u] = t < ntile;
+        tile_of(tv[u] ? t : 0, NT, tP[u], tQ[u]);
+    }
+    d4 D[S1_TPW];
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) D[u] = d4{0.0, 0.0, 0.0, 0.0};
+    // raw factors of this thread's NT elements of one chunk, both sides
+    double fx[NT][SPEC_MAXF], fy[NT][SPEC_MAXF];
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int e = tid + 256 * j, r = e >> 4, A = kc + (e & 15);
+            const bool off = r < N && A < N && r != A;     // zero diagonals keep A != P, Q
+#pragma unroll
+            for (int f = 0; f < SPEC_MAXF; ++f) {
+                fx[j][f] = (off && f < xq.n) ? xq.p[f][r * xq.sa[f] + A * xq.sb[f]] : (off ? 1.0 : 0.0);
+                fy[j][f] = (off && f < yq.n) ? yq.p[f][r * yq.sa[f] + A * yq.sb[f]] : (off ? 1.0 : 0.0);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int e = tid + 256 * j, r = e >> 4, k = e & 15;
+            double x = 1.0, y = 1.0;
+#pragma unroll
+            for (int f = 0; f < SPEC_MAXF; ++f) {
+                x *= fx[j][f];
+                y *= fy[j][f];
+            }
+            Xs[(buf * NR + r) * S1_PITCH + k] = x;
+            Ys[(buf * NR + r) * S1_PITCH + k] = y;
+        }
+    };
+    const int nch = (N + 15) / 16;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) load((c + 1) * 16);
+#pragma unroll
+        for (int u = 0; u < S1_TPW; ++u) {
+            if (!tv[u]) continue;
+            const double* xa = Xs + (buf * NR + tP[u] * 16 + i) * S1_PITCH + kq;
+            const double* yb = Ys + (buf * NR + tQ[u] * 16 + i) * S1_PITCH + kq;
+#pragma unroll
+            for (int k4 = 0; k4 < 16; k4 += 4)
+                D[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k4], yb[k4], D[u], 0, 0, 0);
+        }
+        if (c + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+    const long np2 = (long)N * (N - 1) / 2;
+    double* out = SK + (long)p * np2;
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) {
+        if (!tv[u]) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) Ts[i * S1_PITCH + kq + 4 * r] = D[u][r];
         __builtin_amdgcn_wave_barrier();
@@ -1424,7 +1527,7 @@ __global__ void k_vertex2_adj(int N, const double* __restrict__ hb2, double* __r
 }
 
 struct Carve {
-    double *t2, *h1, *h2, *h2T, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p1s1, *p2, *epart, *scal;
+    double *t2, *h1, *h2, *h2T, *X, *Y, *S, *W, *Lam, *D, *F1, *M1, *part, *p1, *p1s1, *p2, *epart, *scal;
     int nchunk, gchunk, nblkE, nch1;
 };
 
@@ -1445,6 +1548,12 @@ inline size_t gemm_s1_lds(int N) {
     return (size_t)(2 * NR * S1_PITCH + 4 * 16 * S1_PITCH) * sizeof(double);
 }
 
+// the pipelined form (mode 3): two LDS buffers per side, N <= 128
+inline size_t gemm_s1p_lds(int N) {
+    const int NR = (N + 15) / 16 * 16;
+    return (size_t)(4 * NR * S1_PITCH + 4 * 16 * S1_PITCH) * sizeof(double);
+}
+
 inline unsigned bgemm_tile_groups(int N) {
     const int nt = (N + 15) / 16;
     return (unsigned)(nt * ((nt + 3) / 4));
@@ -1459,6 +1568,13 @@ pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)&k_gemm_s1<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)gemm_s1_lds(256));
+    const void* pipelined[] = {(const void*)&k_gemm_s1p<1>, (const void*)&k_gemm_s1p<2>,
+                               (const void*)&k_gemm_s1p<3>, (const void*)&k_gemm_s1p<4>,
+                               (const void*)&k_gemm_s1p<5>, (const void*)&k_gemm_s1p<6>,
+                               (const void*)&k_gemm_s1p<7>, (const void*)&k_gemm_s1p<8>};
+    for (int nt = 1; nt <= 8 && e == hipSuccess; ++nt)
+        e = hipFuncSetAttribute(pipelined[nt - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gemm_s1p_lds(nt * 16));
     if (e != hipSuccess)
         return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
     done = true;
@@ -1492,6 +1608,8 @@ Carve carve(double* ws, int N) {
     c.h1 = take((size_t)PQ_H1_N * N);
     c.h2 = take((size_t)PQ_H2_N * NN);
     c.h2T = take((size_t)PQ_H2_N * std::max(np2, (size_t)1));
+    c.X = take((size_t)PQ_X_N * NN);                  // materialised sides (mode 2, adjoint)
+    c.Y = take((size_t)PQ_Y_N * NN);
     c.S = take((size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1));
     c.W = take(2 * (size_t)PQ_W_N * NN);              // W and its transposes
     c.Lam = take((size_t)PQ_LAM_N * NN);
@@ -1516,7 +1634,7 @@ size_t carve_size(int N) {
     s2_chunks(N, nchunk, gchunk);
     const size_t np2m = std::max(np2, (size_t)1);
     return NP2 * NN + (size_t)PQ_H1_N * N +
-           ((size_t)PQ_H2_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
+           ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_LAM_N + PQ_DR_N) * NN +
            ((size_t)PQ_H2_N + PQ_S1PAIRS_N) * np2m + (size_t)nchunk * NP2 * np2m +
            (size_t)r1_chunks(N) * 3 * N + (size_t)PQ_LANE_NSLOT * np2m + (NN + 255) / 256 + 8 + r1f_size(N) +
            (size_t)PQ_R1G_N * NN + (size_t)r1_lane_chunks() * 3 * N;
@@ -1596,9 +1714,32 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                            c.Lam, c.W, c.D, gate);
         pqph_mark(ctx);
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
-        hipLaunchKernelGGL(k_gemm_s1<true>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
-                           nullptr, nullptr, c.S,
-                           gate);
+        const int s1m = pq_s1_mode(ctx, N);
+        if (s1m == 2) {        // materialised sides (an empty phase in the other modes)
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, gate);
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, gate);
+        }
+        pqph_mark(ctx);
+        if (s1m == 3 && (N + 15) / 16 <= 8) {
+            const dim3 gg(gemm_s1_grid(N));
+            const size_t lb = gemm_s1p_lds(N);
+            switch ((N + 15) / 16) {
+                case 1: hipLaunchKernelGGL(k_gemm_s1p<1>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 2: hipLaunchKernelGGL(k_gemm_s1p<2>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 3: hipLaunchKernelGGL(k_gemm_s1p<3>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 4: hipLaunchKernelGGL(k_gemm_s1p<4>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 5: hipLaunchKernelGGL(k_gemm_s1p<5>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 6: hipLaunchKernelGGL(k_gemm_s1p<6>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                case 7: hipLaunchKernelGGL(k_gemm_s1p<7>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+                default: hipLaunchKernelGGL(k_gemm_s1p<8>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
+            }
+        } else if (s1m == 2) {
+            hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
+                               c.X, c.Y, c.S, gate);
+        } else {
+            hipLaunchKernelGGL(k_gemm_s1<true>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
+                               nullptr, nullptr, c.S, gate);
+        }
         pqph_mark(ctx);
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
@@ -1710,15 +1851,17 @@ size_t pq_adj_doubles(int N) {
     const size_t NN = (size_t)N * N, np2 = std::max((size_t)N * (N - 1) / 2, (size_t)1);
     return 3 * (size_t)N + NP2 * NN + (size_t)PQ_H1_N * N +
            ((size_t)PQ_H2_N + PQ_X_N + PQ_Y_N + 2 * PQ_W_N + PQ_DR_N + PQ_LAM_N) * NN +
-           r1f_size(N) + (size_t)PQ_S1PAIRS_N * np2 + ((size_t)PQ_X_N + PQ_Y_N) * NN + 8;
+           r1f_size(N) + (size_t)PQ_S1PAIRS_N * np2 + 8;
 }
 
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
                       const double* t, const double* lam, double ew, double* tbar, double* hbar,
-                      double* eribar, double* ws, double* aws) {
+                      double* eribar, double* ws, double* aws, bool fwd_ready) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
-    if (st) return st;
+    if (!fwd_ready) {
+        pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
+        if (st) return st;
+    }
     View v = make_view(t, c, N);
     const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
     AdjView a;
@@ -1738,28 +1881,26 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     a.Wb = Wb;
     a.Db = Db;
     double* Sb = p;
-    // the one-spectator sides, materialised here (the forward residual forms
-    // them while staging): their adjoints need them as operands
-    double* Xf = Sb + (size_t)PQ_S1PAIRS_N * std::max(np2, (size_t)1);
-    double* Yf = Xf + (size_t)PQ_X_N * NN;
+    // the one-spectator sides, materialised (their adjoints need them as operands)
+    double* Xf = c.X;
+    double* Yf = c.Y;
     const size_t nzero = (size_t)(Sb - aws);
     PQPH_HIP(ctx, hipMemsetAsync(aws, 0, nzero * sizeof(double), s));
     const int tb = 64, gx = (N + tb - 1) / tb;
     const unsigned gsq = (unsigned)((N * N + 255) / 256);
     if (N > 1) {
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, nullptr);
-        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
-        hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
-                           c.Lam, c.W, c.D, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, Xf, nullptr);
-        hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, Yf, nullptr);
-        if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
-        hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v, Xf,
-                           Yf, c.S, nullptr);
-        {
-            launch_r2_lane_adj(s, N, t, c.h1, c.h2T, c.S, lam, a.tb1, a.tb2, a.hb1, a.hb2, Sb);
+        if (!fwd_ready) {      // the forward intermediates the adjoint reads (functions of h, v, t)
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_W_N), dim3(256), 0, s, N, 2, v, c.W, nullptr);
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_LAM_N), dim3(256), 0, s, N, 4, v, c.Lam, nullptr);
+            if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
+            hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
+                               c.Lam, c.W, c.D, nullptr);
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, Xf, nullptr);
+            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, Yf, nullptr);
+            hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
+                               Xf, Yf, c.S, nullptr);
         }
+        launch_r2_lane_adj(s, N, t, c.h1, c.h2T, c.S, lam, a.tb1, a.tb2, a.hb1, a.hb2, Sb);
         {
             const int rt2 = s2_rowtiles(N);
             const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt2, 1)));
@@ -1806,7 +1947,8 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
     launch_r1_lane_adj(s, N, t, c.t2, c.h1, c.h2, lam, a.tb1, a.tb2, a.hb1, a.hb2);
     if (N >= 3) {
         const unsigned gsq3 = (unsigned)((N * N + 255) / 256);
-        hipLaunchKernelGGL(k_spec_r1, dim3(gsq3, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, nullptr);
+        if (!fwd_ready)
+            hipLaunchKernelGGL(k_spec_r1, dim3(gsq3, PQ_R1F_N), dim3(256), 0, s, N, v, c.F1, nullptr);
         hipLaunchKernelGGL(k_r1s2_adj, dim3((N + R1A_PB - 1) / R1A_PB, PQ_R1G_N), dim3(256),
                            (size_t)2 * R1A_PB * N * sizeof(double), s, N, c.F1, lam, F1b);
         hipLaunchKernelGGL(k_fold_r1z, dim3(gx, N, PQ_R1F_N - PQ_R1F_Z0), dim3(tb), 0, s, N, F1b);

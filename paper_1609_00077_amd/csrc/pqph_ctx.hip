@@ -80,6 +80,14 @@ pqph_status pqph_ensure_side(pqph_ctx* ctx) {
     return PQPH_OK;
 }
 
+int pq_s1_mode(const pqph_ctx* ctx, int npair) {
+    if (npair >= 0 && npair <= 256 && ctx->s1_mode[npair]) return ctx->s1_mode[npair];
+    // untuned: forming the sides while staging wins at small N (no 1750 N x N
+    // arrays written and re-read); the materialised sides win once N^2 slices
+    // no longer sit in the caches
+    return npair >= 100 ? 2 : 1;
+}
+
 void pqph_mark(pqph_ctx* ctx) {
     if (!ctx->profiling || ctx->prof_n >= 24) return;
     (void)hipEventRecord(ctx->prof[ctx->prof_n++], ctx->stream);
@@ -177,10 +185,10 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
 }
 
-static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2",  "k_spec_w",
-                                    "k_spec_lam", "k_dress",   "k_gemm_s1",    "k_r2s2",
-                                    "k_r2c",      "k_spec_r1", "k_r1s2",       "k_r1s2_close",
-                                    "k_r1",       "k_r1c",     "k_final"};
+static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2", "k_spec_w",
+                                    "k_spec_lam", "k_dress",   "k_spec_xy",   "k_gemm_s1",
+                                    "k_r2s2",     "k_r2c",     "k_spec_r1",   "k_r1s2",
+                                    "k_r1s2_close", "k_r1",    "k_r1c",       "k_final"};
 constexpr int kNPhase = (int)(sizeof(kPhaseNames) / sizeof(kPhaseNames[0]));
 
 const char* pq_residual_phase_name(int i) {
@@ -225,6 +233,23 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant) {
     return PQPH_OK;
 }
 
+pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (mode < 0 || mode > 3 || (mode == 3 && npair > 128))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, or 3 (3 needs npair <= 128)");
+    ctx->s1_mode[npair] = mode;
+    return PQPH_OK;
+}
+
+pqph_status pqph_tuning(pqph_ctx* ctx, int npair, int* s2_variant, int* s1_mode) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (s2_variant) *s2_variant = pq_s2_variant(ctx, npair);
+    if (s1_mode) *s1_mode = pq_s1_mode(ctx, npair);
+    return PQPH_OK;
+}
+
 pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const double* eri,
                           const double* t, double* r, int* choice) {
     pqph_status st = check_pq(ctx, npair);
@@ -234,9 +259,12 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
     if (st) return st;
     const int nvar = (npair + 15) / 16 <= 6 ? 2 : 1;
     float best = 1e30f;
-    int bestv = 1;
-    for (int var = 1; var <= nvar; ++var) {
+    int bestv = 1, bestm = 1;
+    const int nmode = npair <= 128 ? 3 : 2;
+    for (int combo = 0; combo < nmode * nvar; ++combo) {
+        const int var = 1 + combo % nvar, mode = 1 + combo / nvar;
         ctx->s2_variant[npair] = var;
+        ctx->s1_mode[npair] = mode;
         for (int rep = 0; rep < 2; ++rep) {      // first run warms up
             PQPH_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
             for (int k = 0; k < 3; ++k) {
@@ -250,10 +278,12 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
             if (rep == 1 && ms < best) {
                 best = ms;
                 bestv = var;
+                bestm = mode;
             }
         }
     }
     ctx->s2_variant[npair] = bestv;
+    ctx->s1_mode[npair] = bestm;
     if (choice) *choice = bestv;
     return PQPH_OK;
 }
@@ -517,11 +547,18 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     *energy = ctx->host[32];
     // lambda equations: J^T lambda + dE/dt = 0, solved like the amplitudes
     PQPH_HIP(ctx, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+    // t is fixed from here on: the forward intermediates the adjoint reads are
+    // computed by the first VJP and reused by the later ones (only the VJPs
+    // write ws and aws during the lambda solve)
+    bool fwd_ready = false;
     auto lres = [&](const double* x, double* r) {
-        return pq_vjp_ws(ctx, s, npair, h, eri, t, x, 1.0, r, nullptr, nullptr, ctx->ws, aws);
+        pqph_status e = pq_vjp_ws(ctx, s, npair, h, eri, t, x, 1.0, r, nullptr, nullptr, ctx->ws, aws,
+                                  fwd_ready);
+        fwd_ready = fwd_ready || e == PQPH_OK;
+        return e;
     };
     if ((st = jacobi_diis(ctx, n, D, lam, o, lres, bufs, iters, rn, result))) return st;
-    if ((st = pq_vjp_ws(ctx, s, npair, h, eri, t, lam, 1.0, tbar, dE_dh, dE_deri, ctx->ws, aws)))
+    if ((st = pq_vjp_ws(ctx, s, npair, h, eri, t, lam, 1.0, tbar, dE_dh, dE_deri, ctx->ws, aws, fwd_ready)))
         return st;
     if (lambda_out)
         PQPH_HIP(ctx, hipMemcpyAsync(lambda_out, lam, n * sizeof(double), hipMemcpyDeviceToDevice, s));

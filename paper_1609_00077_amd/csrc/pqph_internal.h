@@ -31,6 +31,10 @@ struct pqph_ctx {
     // autotuned kernel variants per npair (two-spectator contraction):
     // 1 = K-chunked staging, 2 = vertex resident in LDS; 0 = not tuned
     int s2_variant[257] = {};
+    // one-spectator GEMM sides per npair: 1 = formed while staging (fused),
+    // 2 = materialised X, Y read by the GEMM, 3 = fused with the staging
+    // software-pipelined (npair <= 128); 0 = not tuned
+    int s1_mode[257] = {};
     // streams and events of batched solves (default priority), created on first use
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> bevents;
@@ -46,6 +50,8 @@ struct pqph_ctx {
 
 // variant of the two-spectator contraction for this npair (tuned or default)
 int pq_s2_variant(const pqph_ctx* ctx, int npair);
+// one-spectator side formation for this npair (tuned, forced, or by size)
+int pq_s1_mode(const pqph_ctx* ctx, int npair);
 
 // records an event after a launch when the context is profiling
 void pqph_mark(pqph_ctx* ctx);
@@ -110,11 +116,13 @@ pqph_status pq_denominators_dev(pqph_ctx* ctx, hipStream_t s, int npair, const d
 
 // adjoint (pq_residual.hip): tbar = lam . dR/dt + ew dE/dt and, when hbar and
 // eribar are given, the same pulled back to f and the packed integrals.
-// aws: pq_adj_doubles(npair) doubles of adjoint workspace.
+// aws: pq_adj_doubles(npair) doubles of adjoint workspace.  fwd_ready: ws and
+// aws still hold the forward intermediates of a previous call with the same
+// h, eri and t (nothing else wrote them since), so they are not recomputed.
 size_t pq_adj_doubles(int npair);
 pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h, const double* eri,
                       const double* t, const double* lam, double ew, double* tbar, double* hbar,
-                      double* eribar, double* ws, double* aws);
+                      double* eribar, double* ws, double* aws, bool fwd_ready = false);
 
 // streaming kernels of the solver (solver_kernels.hip) ---------------------
 int stream_blocks(size_t n);

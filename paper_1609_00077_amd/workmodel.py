@@ -43,9 +43,10 @@ def pq_kernel_flops(N: int) -> dict:
     out["k_spec_w"] = _spec_cost(tb.r2s2_w) * N * (N - 1)
     out["k_spec_lam"] = _spec_cost(tb.r2s2_lam) * N * (N - 1)
     out["k_dress"] = 2.0 * len(tb.r2s2_dress) * N * N * N
-    # one-spectator contraction; its sides X, Y are formed while staging
-    out["k_gemm_s1"] = (2.0 * len(tb.r2s1_pairs) * np2 * max(N - 2, 0)
-                        + (_spec_cost(tb.r2s1_x) + _spec_cost(tb.r2s1_y)) * N * (N - 1))
+    # one-spectator contraction over A != P, Q; its sides X, Y (products of
+    # factors) are materialised (k_spec_xy) or formed while staging
+    out["k_spec_xy"] = (_spec_cost(tb.r2s1_x) + _spec_cost(tb.r2s1_y)) * N * (N - 1)
+    out["k_gemm_s1"] = 2.0 * len(tb.r2s1_pairs) * np2 * max(N - 2, 0)
     # two spectators: per output pair and (w, a) group: L_a on N-2 labels, the
     # (N-2)x(N-2) vertex contraction, then per b: L_b and a dot over N-2 labels
     lsum = 0.0

@@ -105,19 +105,23 @@ def _golden(name):
         return json.load(fh)
 
 
+@pytest.mark.parametrize("s1_mode", [1, 2, 3])
 @pytest.mark.parametrize("variant", [1, 2])
-def test_full_size_pq140_sampled_blocks(pq, variant):
-    """140-site chain (70 pairs, the bench workload), seeded amplitudes: the
-    sampled output blocks and the energy equal the oracle's sub-cluster values
-    stored by tests/golden/make_golden.py."""
+def test_full_size_pq140_sampled_blocks(pq, variant, s1_mode):
+    """140-site chain (70 pairs, the bench workload), seeded amplitudes, every
+    kernel choice the autotuner can make: the sampled output blocks and the
+    energy equal the oracle's sub-cluster values stored by
+    tests/golden/make_golden.py."""
     g = _golden("pq140_blocks")
     prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
     N = prob.npair
     f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
     t = random_amplitudes(N, "pq", seed=g["amp_seed"], scale=g["amp_scale"])
     pq.set_variant(N, variant)
+    pq.set_s1_mode(N, s1_mode)
     R = pq.pq_residual(f, eri, _d(t)).cpu().numpy()
     pq.set_variant(N, 0)
+    pq.set_s1_mode(N, 0)
     for _, vals in g["blocks"].items():
         ref = np.array(list(vals.values()))
         got = R[[int(s) for s in vals]]
@@ -163,3 +167,26 @@ def test_two_spectator_variants_agree(pq, N):
     tol = 1e-12 * max(1.0, np.abs(outs[1]).max())
     assert np.abs(outs[2] - outs[1]).max() <= tol, np.abs(outs[2] - outs[1]).max()
     assert np.isfinite(outs[1]).all() and np.abs(outs[1]).max() > 0
+
+
+@pytest.mark.parametrize("N", [3, 24, 90])
+def test_one_spectator_modes_agree(pq, N):
+    """The one-spectator GEMM with its sides formed while staging (mode 1),
+    from materialised X, Y (mode 2) and formed while staging with pipelined
+    loads (mode 3) give the same residual; at N = 3 they match the
+    definitional oracle."""
+    f, eri = _random_system(N, 500 + N)
+    t = random_amplitudes(N, "pq", seed=600 + N, scale=0.05)
+    outs = {}
+    for mode in (1, 2, 3):
+        pq.set_s1_mode(N, mode)
+        assert pq.tuning(N)["s1_mode"] == mode
+        outs[mode] = pq.pq_residual(_d(f), _d(eri), _d(t)).cpu().numpy()
+    pq.set_s1_mode(N, 0)
+    tol = 1e-12 * max(1.0, np.abs(outs[1]).max())
+    for mode in (2, 3):
+        assert np.abs(outs[mode] - outs[1]).max() <= tol, mode
+    if N == 3:
+        RA, _ = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
+        for mode in (1, 2, 3):
+            assert np.abs(outs[mode] - RA).max() <= 1e-12 * max(1.0, np.abs(RA).max()), mode
