@@ -392,9 +392,9 @@ pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
 }
 
 // one iteration of every chain, enqueued on the batch streams (captured)
-pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo, const std::vector<int>& chains) {
+pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
     pqph_status st;
-    for (int c : chains) {
+    for (int c : b.order) {
         Chain& x = b.ch[c];
         hipStream_t s = ctx->bstreams[x.stream];
         DevChain* d = b.dst + c;
@@ -419,29 +419,24 @@ pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo, const st
     return PQPH_OK;
 }
 
-// longest-processing-time assignment of chains (in order of decreasing N) to
-// the batch streams; every stream's workspace fits the largest chain
-void assign_streams(Batch& b, const std::vector<int>& chains) {
-    std::vector<double> load(b.ns, 0.0);
-    for (int c : chains) {
-        const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        const double N = b.ch[c].N;
-        load[s] += N * N * N * N;
-        b.ch[c].stream = s;
-    }
-}
-
-// one iteration of the given chains captured from the batch streams into a
-// graph (forked from and joined back into stream 0) and instantiated
-pqph_status capture_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo, const std::vector<int>& chains,
-                              hipGraphExec_t* exec) {
-    const int ns = b.ns;
+pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
+    const int ns = b.ns, nb = b.nb;
+    BOpts bo{b.o.max_iter, b.o.diis_dim, b.o.diis_start, b.o.stall_window, b.o.tol,
+             b.o.diverge_factor};
     hipStream_t s0 = ctx->bstreams[0];
+    pqph_status st;
+    hipLaunchKernelGGL(k_b_init, dim3((nb + 63) / 64), dim3(64), 0, ctx->stream, b.dst, nb);
+    PQPH_HIP(ctx, hipGetLastError());
+    // s0 starts after everything already on the context stream
+    PQPH_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
+    PQPH_HIP(ctx, hipStreamWaitEvent(s0, ctx->fork, 0));
     PQPH_HIP(ctx, hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
+    // fork the other streams from s0, enqueue, join them back into s0
+    bool capturing = true;
     auto body = [&]() -> pqph_status {
         PQPH_HIP(ctx, hipEventRecord(ctx->fork, s0));
         for (int i = 1; i < ns; ++i) PQPH_HIP(ctx, hipStreamWaitEvent(ctx->bstreams[i], ctx->fork, 0));
-        pqph_status e = enqueue_iteration(ctx, b, bo, chains);
+        pqph_status e = enqueue_iteration(ctx, b, bo);
         if (e) return e;
         for (int i = 1; i < ns; ++i) {
             PQPH_HIP(ctx, hipEventRecord(ctx->bevents[i], ctx->bstreams[i]));
@@ -449,47 +444,29 @@ pqph_status capture_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo, const st
         }
         return PQPH_OK;
     };
-    const pqph_status st = body();
+    st = body();
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(s0, &graph);
+    capturing = false;
+    (void)capturing;
     if (st) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
     }
     if (ec != hipSuccess || !graph)
         return pqph_fail(ctx, PQPH_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-    ec = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ec != hipSuccess)
         return pqph_fail(ctx, PQPH_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ec));
-    return PQPH_OK;
-}
-
-pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
-    const int nb = b.nb;
-    BOpts bo{b.o.max_iter, b.o.diis_dim, b.o.diis_start, b.o.stall_window, b.o.tol,
-             b.o.diverge_factor};
-    hipStream_t s0 = ctx->bstreams[0];
-    hipLaunchKernelGGL(k_b_init, dim3((nb + 63) / 64), dim3(64), 0, ctx->stream, b.dst, nb);
-    PQPH_HIP(ctx, hipGetLastError());
-    // s0 starts after everything already on the context stream
-    PQPH_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
-    PQPH_HIP(ctx, hipStreamWaitEvent(s0, ctx->fork, 0));
-    // the replayed graph holds the chains still active when it was captured;
-    // once half of them have finished it is captured again without them (a
-    // finished chain's kernels only return at their gate, but each still costs
-    // a launch), their streams re-balanced
-    std::vector<int> active = b.order;
-    hipGraphExec_t exec = nullptr;
-    if (pqph_status e = capture_iteration(ctx, b, bo, active, &exec)) return e;
-    size_t captured = active.size();
     // replay; poll the gate flags after a few replays, then every other one
     int* flags = reinterpret_cast<int*>(ctx->host);
     pqph_status result = PQPH_OK;
     int launched = 0;
     int next_poll = std::min(b.o.max_iter, 8);
     while (launched < b.o.max_iter) {
-        hipError_t ec = hipGraphLaunch(exec, s0);
+        ec = hipGraphLaunch(exec, s0);
         if (ec != hipSuccess) {
             result = pqph_fail(ctx, PQPH_DEVICE, std::string("graph launch: ") + hipGetErrorString(ec));
             break;
@@ -503,21 +480,12 @@ pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
             result = pqph_fail(ctx, PQPH_DEVICE, std::string("poll: ") + hipGetErrorString(ec));
             break;
         }
-        std::vector<int> still;
-        for (int c : active)
-            if (flags[c]) still.push_back(c);
-        if (still.empty()) break;
+        int any = 0;
+        for (int c = 0; c < nb; ++c) any |= flags[c];
+        if (!any) break;
         next_poll = launched + 2;
-        if (2 * still.size() <= captured) {
-            (void)hipGraphExecDestroy(exec);
-            exec = nullptr;
-            active.swap(still);
-            assign_streams(b, active);
-            if ((result = capture_iteration(ctx, b, bo, active, &exec))) break;
-            captured = active.size();
-        }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphExecDestroy(exec);
     if (result) return result;
     PQPH_HIP(ctx, hipEventRecord(ctx->bevents[0], s0));
     PQPH_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->bevents[0], 0));
@@ -586,10 +554,6 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     // device memory: per-stream residual workspace, per-chain solver state,
     // the batch-wide arrays of norms, Gram rows, coefficients, energies, and
     // the device-resident chain states
-    // every stream's workspace fits the largest chain: the graph mode re-balances
-    // the chains still active over the streams
-    const size_t ws_max = *std::max_element(ws_need.begin(), ws_need.end());
-    for (int s = 0; s < ns; ++s) ws_need[s] = ws_max;
     size_t total = 0;
     for (int s = 0; s < ns; ++s) total += ws_need[s];
     for (auto& x : ch) total += x.n * (4 + 2 * (size_t)m) + (size_t)x.nblk * (m + 1);
