@@ -187,6 +187,20 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_variant(phase: str, N: int, tuning: dict) -> str:
+    """The kernel a residual phase launches under the tuning in effect (the
+    counters are keyed by it: variants move different bytes)."""
+    ncb = (N + 15) // 16
+    if phase == "k_gemm_s1":
+        return {1: "k_gemm_s1<true>", 2: "k_gemm_s1<false>", 3: f"k_gemm_s1p<{ncb}>"}[tuning["s1_mode"]]
+    if phase == "k_r2s2":
+        if tuning["s2_variant"] == 2:
+            return f"k_r2s2w<{ncb}>"
+        nb = next(b for b in (1, 2, 3, 4, 5, 6, 8, 10, 13, 16) if ncb <= b)
+        return f"k_r2s2<{nb}>"
+    return phase
+
+
 def hbm_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
     WRITE_SIZE counter runs, each scaled by the same counter's reading for a
@@ -208,8 +222,16 @@ def counter_run(args, pq, torch, dev):
     f, eri = pq.integrals(d(prob.F_site), d(prob.V), d(prob.C), k=2)
     t = d(random_amplitudes(prob.npair, "pq", seed=1400, scale=0.05))
     r = torch.empty_like(t)
-    for _ in range(args.counter_run):
-        pq.pq_residual(f, eri, t, out=r)
+    N = prob.npair
+    # every kernel choice the autotuner can make, counter_run residuals each
+    for variant in ((1, 2) if (N + 15) // 16 <= 6 else (1,)):
+        for mode in ((1, 2, 3) if N <= 128 else (1, 2)):
+            pq.set_variant(N, variant)
+            pq.set_s1_mode(N, mode)
+            for _ in range(args.counter_run):
+                pq.pq_residual(f, eri, t, out=r)
+    pq.set_variant(N, 0)
+    pq.set_s1_mode(N, 0)
     torch.cuda.synchronize()
     a = torch.full((32 * 1024 * 1024,), 1.0, dtype=torch.float64, device=dev)   # 256 MiB
     b = torch.empty_like(a)
@@ -301,9 +323,10 @@ def main():
                                "integral transform included", "sites": args.sites, "pairs": N,
                    "iterations_per_solve": res.iterations, "energy": res.energy,
                    "s2_variant": variant, "s1_mode": pq.tuning(N)["s1_mode"]},
-        "roofline": {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom,
+        "roofline": {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": kernel_variant(dom, N, pq.tuning(N)),
                      "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": hbm_traffic(dom),
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": hbm_traffic(kernel_variant(dom, N, pq.tuning(N))),
                      "flops_per_launch": flops[dom], "ms_per_launch": acc[dom]},
         "residual_ms": resid_ms,
         "residual_evals_per_s_back_to_back": 1e3 / resid_ms,

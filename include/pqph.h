@@ -177,7 +177,8 @@ const char* pq_residual_phase_name(int i);
  * later call on this context.  *choice (host, may be NULL) = 1 (K-chunked
  * staging of the vertex) or 2 (vertex resident in LDS, npair <= 96).  The
  * one-spectator mode (pqph_set_s1_mode) is tuned jointly, over every pair of
- * choices.  Synchronises the stream.  Without tuning, variant 1 and the
+ * choices; a non-default pair must be 3 % faster to be kept, so near-ties
+ * keep the defaults.  Synchronises the stream.  Without tuning, variant 1 and the
  * size-based mode are used. */
 pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h,
                           const double* eri, const double* t, double* r,

@@ -275,7 +275,9 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
             PQPH_HIP(ctx, hipEventSynchronize(ctx->ev1));
             float ms = 0.f;
             PQPH_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-            if (rep == 1 && ms < best) {
+            // a later (non-default) choice must win by 3 %: near-ties keep the
+            // default, so the choice is stable from run to run
+            if (rep == 1 && (combo == 0 || ms < 0.97f * best)) {
                 best = ms;
                 bestv = var;
                 bestm = mode;
