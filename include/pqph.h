@@ -250,7 +250,7 @@ pqph_status pq_vjp(pqph_ctx* ctx, int npair, const double* h, const double* eri,
 /* PQ energy and its gradient with respect to the Hamiltonian.  If t is NULL
  * the amplitudes are solved here from zero (opts); otherwise t must hold
  * converged amplitudes.  lambda then solves J^T lambda = -dE/dt (J = dR/dt) by
- * the same Jacobi + DIIS (opts) and
+ * the same Jacobi + DIIS (opts), starting from lambda = t, and
  *     dE/dh = dE_c/dh + lambda . dR/dh,  dE/deri = dE_c/deri + lambda . dR/deri
  * (raw partials: dE = sum dE_dh . dh + sum dE_deri . deri over the stored
  * elements).  energy: host; dE_dh: 2N x 2N device; dE_deri: packed device;

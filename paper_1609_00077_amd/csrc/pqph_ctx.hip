@@ -548,7 +548,9 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     PQPH_HIP(ctx, hipStreamSynchronize(s));
     *energy = ctx->host[32];
     // lambda equations: J^T lambda + dE/dt = 0, solved like the amplitudes
-    PQPH_HIP(ctx, hipMemsetAsync(lam, 0, n * sizeof(double), s));
+    // start from lambda = t, its first-order value (both solve equations with
+    // the same leading part D); the converged lambda does not depend on it
+    PQPH_HIP(ctx, hipMemcpyAsync(lam, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     // t is fixed from here on: the forward intermediates the adjoint reads are
     // computed by the first VJP and reused by the later ones (only the VJPs
     // write ws and aws during the lambda solve)
