@@ -1675,9 +1675,11 @@ pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const 
 
 size_t pq_ws_doubles(int npair) { return carve_size(npair); }
 
+pqph_status pq_residual_prepare(pqph_ctx* ctx) { return gemm_s1_prepare(ctx); }
+
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate) {
+                           const int* gate, int fork) {
     Carve c = carve(ws, N);
     pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate);
     if (st) return st;
@@ -1690,7 +1692,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     // beside the main chain (dressing, one-spectator GEMM, its epilogue); the
     // main stream joins both before the final sum.  Serial on s when a gate
     // is given (batched solves) or per-kernel times are taken.
-    const bool forked = !ctx->profiling && gate == nullptr && s == ctx->stream;
+    const bool forked = fork > 0 || (fork < 0 && !ctx->profiling && gate == nullptr && s == ctx->stream);
     hipStream_t s1 = s, s2 = s;
     if (forked) {
         if (pqph_status e_ = pqph_ensure_side(ctx)) return e_;

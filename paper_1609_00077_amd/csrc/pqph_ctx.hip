@@ -72,6 +72,53 @@ int pq_s2_variant(const pqph_ctx* ctx, int npair) {
     return 1;
 }
 
+pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const double* eri,
+                              const double* t, double* r, double* ws) {
+    if (ctx->profiling) return pq_residual_ws(ctx, ctx->stream, N, h, eri, t, r, ws);
+    const int s1 = pq_s1_mode(ctx, N), s2 = pq_s2_variant(ctx, N);
+    const bool same = ctx->rexec && ctx->rN == N && ctx->rh == h && ctx->reri == eri && ctx->rt == t &&
+                      ctx->rr == r && ctx->rws == ws && ctx->rs1 == s1 && ctx->rs2 == s2;
+    if (!same) {
+        if (ctx->rexec) {
+            PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));    // the old graph may still run
+            (void)hipGraphExecDestroy(ctx->rexec);
+            ctx->rexec = nullptr;
+        }
+        // capture on a stream of our own (the context's may be the legacy default
+        // stream, which cannot be captured), forked to the side streams, then
+        // replay on the context's stream
+        if (pqph_status e = pq_residual_prepare(ctx)) return e;
+        if (pqph_status e = pqph_ensure_side(ctx)) return e;
+        if (!ctx->cap) PQPH_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        PQPH_HIP(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
+        const pqph_status st = pq_residual_ws(ctx, ctx->cap, N, h, eri, t, r, ws, nullptr, 1);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
+        if (st) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess || !graph)
+            return pqph_fail(ctx, PQPH_DEVICE, std::string("residual capture: ") + hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&ctx->rexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            ctx->rexec = nullptr;
+            return pqph_fail(ctx, PQPH_DEVICE, std::string("residual instantiate: ") + hipGetErrorString(ei));
+        }
+        ctx->rN = N;
+        ctx->rh = h;
+        ctx->reri = eri;
+        ctx->rt = t;
+        ctx->rr = r;
+        ctx->rws = ws;
+        ctx->rs1 = s1;
+        ctx->rs2 = s2;
+    }
+    PQPH_HIP(ctx, hipGraphLaunch(ctx->rexec, ctx->stream));
+    return PQPH_OK;
+}
+
 pqph_status pqph_ensure_side(pqph_ctx* ctx) {
     for (hipStream_t& st : ctx->side)
         if (!st) PQPH_HIP(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -147,6 +194,8 @@ void pqph_destroy(pqph_ctx* ctx) {
     for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
     for (hipStream_t st : ctx->bstreams) (void)hipStreamDestroy(st);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->rexec) (void)hipGraphExecDestroy(ctx->rexec);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (hipEvent_t e : ctx->sev)
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t st : ctx->side)
@@ -182,7 +231,7 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
     st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
     if (st) return st;
-    return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
+    return pq_residual_graph(ctx, npair, h, eri, t, r, ctx->ws);
 }
 
 static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2", "k_spec_w",
@@ -321,7 +370,7 @@ pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, 
 // ------------------------------------------------------ Jacobi/DIIS driver
 // x <- x - r/D with DIIS on the last m iterates (Sec. III; Table IV), where
 // resid(x, r) enqueues r = F(x) on the context stream.  bufs holds
-// n*(3 + 2m) + nblk*(m+1) + 64 doubles.  Host syncs: two per iteration.
+// n*(3 + 2m) + nblk*(m+1) + 64 doubles.  One host sync per iteration.
 namespace {
 size_t driver_doubles(size_t n, int m) {
     return n * (3 + 2 * (size_t)m) + (size_t)stream_blocks(n) * (m + 1) + 64;
@@ -348,11 +397,31 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     std::vector<double> best;      // best[i]: smallest norm up to iteration i + 1
     rn = INFINITY;
     result = PQPH_NOT_CONVERGED;
+    // One host synchronisation per iteration: the Jacobi step, the history
+    // copies and the DIIS Gram row are enqueued right behind the residual norm
+    // (if the iteration turns out to be the last they are simply unused), and
+    // the norm and the Gram row come back together.  The DIIS coefficients go
+    // to the device from their own pinned slot (hst + 32), which the host
+    // rewrites only after the next synchronisation.
+    const bool diis = o.diis_dim > 0;
     for (it = 1; it <= o.max_iter; ++it) {
         pqph_status st = resid(x, r);
         if (st) return st;
         launch_norm2(s, r, n, part, nblk, scal);
-        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        const bool step = it < o.max_iter;
+        const int slot = next;
+        if (step) {
+            launch_jacobi(s, x, r, D, n, xn, e);
+            if (diis) {
+                PQPH_HIP(ctx, hipMemcpyAsync(xh + (size_t)slot * n, xn, n * sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
+                PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
+                launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal + 1);
+            }
+        }
+        const int nread = 1 + (step && diis ? m : 0);
+        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, nread * sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
         rn = std::sqrt(hst[0]);
         if (!std::isfinite(rn)) {
@@ -377,36 +446,26 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
             pqph_fail(ctx, result, "residual norm diverged at iteration " + std::to_string(it));
             break;
         }
-        if (it == o.max_iter) break;
-        launch_jacobi(s, x, r, D, n, xn, e);
-        if (o.diis_dim == 0) {
+        if (!step) break;
+        if (!diis) {
             PQPH_HIP(ctx, hipMemcpyAsync(x, xn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             continue;
         }
-        const int slot = next;
         next = (next + 1) % m;
         stored = std::min(stored + 1, m);
-        PQPH_HIP(ctx, hipMemcpyAsync(xh + (size_t)slot * n, xn, n * sizeof(double),
-                                     hipMemcpyDeviceToDevice, s));
-        PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
-                                     hipMemcpyDeviceToDevice, s));
-        launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal);
-        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, m * sizeof(double), hipMemcpyDeviceToHost, s));
-        PQPH_HIP(ctx, hipStreamSynchronize(s));
         for (int j = 0; j < m; ++j) {
-            B[(size_t)slot * 16 + j] = hst[j];
-            B[(size_t)j * 16 + slot] = hst[j];
+            B[(size_t)slot * 16 + j] = hst[1 + j];
+            B[(size_t)j * 16 + slot] = hst[1 + j];
         }
         if (it >= o.diis_start && stored >= 2) {
             std::vector<double> Bs(16 * 16, 0.0);
             for (int a = 0; a < stored; ++a)
                 for (int b = 0; b < stored; ++b) Bs[(size_t)a * 16 + b] = B[(size_t)a * 16 + b];
             if (diis_solve(Bs, stored, c)) {
-                for (int j = 0; j < m; ++j) hst[8 + j] = j < stored ? c[j] : 0.0;
-                PQPH_HIP(ctx, hipMemcpyAsync(scal + 16, hst + 8, m * sizeof(double),
+                for (int j = 0; j < m; ++j) hst[32 + j] = j < stored ? c[j] : 0.0;
+                PQPH_HIP(ctx, hipMemcpyAsync(scal + 32, hst + 32, m * sizeof(double),
                                              hipMemcpyHostToDevice, s));
-                launch_combine(s, xh, scal + 16, stored, n, x);   // only written slots
-                PQPH_HIP(ctx, hipStreamSynchronize(s));   // pinned staging reused next iteration
+                launch_combine(s, xh, scal + 32, stored, n, x);   // only written slots
                 continue;
             }
         }
@@ -464,7 +523,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     double rn = 0.0;
     pqph_status result = PQPH_OK;
     auto resid = [&](const double* x, double* r) {
-        return pq_residual_ws(ctx, s, npair, h, eri, x, r, ctx->ws);
+        return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
     };
     if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
     double* edst = ctx->ws + wsd;
@@ -536,7 +595,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     if (!t) {
         PQPH_HIP(ctx, hipMemsetAsync(tl, 0, n * sizeof(double), s));
         auto resid = [&](const double* x, double* r) {
-            return pq_residual_ws(ctx, s, npair, h, eri, x, r, ctx->ws);
+            return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
         };
         if ((st = jacobi_diis(ctx, n, D, tl, o, resid, bufs, iters, rn, result))) return st;
         if (result != PQPH_OK) return result;

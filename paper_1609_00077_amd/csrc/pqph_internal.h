@@ -43,6 +43,12 @@ struct pqph_ctx {
     // its independent branches run concurrently with the main chain
     hipStream_t side[2] = {};
     hipEvent_t sev[4] = {};
+    // the residual captured as a HIP graph, with what it was captured for
+    hipStream_t cap = nullptr;
+    hipGraphExec_t rexec = nullptr;
+    int rN = 0, rs1 = 0, rs2 = 0;
+    const double *rh = nullptr, *reri = nullptr, *rt = nullptr;
+    double *rr = nullptr, *rws = nullptr;
     // batched solves: 0 = device-resident iterations captured in a HIP graph,
     // 1 = host-driven lockstep (three host synchronisations per iteration)
     int batch_mode = 0;
@@ -105,9 +111,18 @@ void launch_r1_lane_adj(hipStream_t s, int npair, const double* t, const double*
 size_t pq_ws_doubles(int npair);
 // residual into r on stream s using workspace ws (already large enough); no host sync
 // gate: device flag; when it reads 0 every kernel returns at once (NULL: always run)
+// fork: 1 = run the independent branches on the context's side streams, 0 =
+// serially on s, -1 = fork when s is the context's stream, no gate is given
+// and no per-kernel timing is taken
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate = nullptr);
+                           const int* gate = nullptr, int fork = -1);
+// one-time kernel attributes of the residual (outside any stream capture)
+pqph_status pq_residual_prepare(pqph_ctx* ctx);
+// the residual on the context's stream replayed from a HIP graph captured for
+// these arguments and kernel choices (captured again when they change)
+pqph_status pq_residual_graph(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                              const double* t, double* r, double* ws);
 // energy: writes one double to dst (device) on stream s, no sync
 pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                          const double* eri, const double* t, double* dst, double* ws);

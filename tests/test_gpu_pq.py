@@ -190,3 +190,18 @@ def test_one_spectator_modes_agree(pq, N):
         RA, _ = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
         for mode in (1, 2, 3):
             assert np.abs(outs[mode] - RA).max() <= 1e-12 * max(1.0, np.abs(RA).max()), mode
+
+
+@pytest.mark.parametrize("N", [3, 70])
+def test_concurrent_branches_bitwise_equal_serial(pq, N):
+    """pq_residual runs the residual's independent branches on side streams;
+    the per-kernel profile runs the same kernels serially on one stream. Every
+    output is a fixed-order sum either way, so the two agree bitwise, and so
+    do repeated concurrent evaluations."""
+    f, eri = _random_system(N, 700 + N)
+    t = _d(random_amplitudes(N, "pq", seed=800 + N, scale=0.05))
+    fd, ed = _d(f), _d(eri)
+    R1 = pq.pq_residual(fd, ed, t)
+    R2, _ = pq.pq_residual_profile(fd, ed, t)
+    R3 = pq.pq_residual(fd, ed, t)
+    assert torch.equal(R1, R2) and torch.equal(R1, R3)
