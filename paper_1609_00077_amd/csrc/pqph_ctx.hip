@@ -410,15 +410,11 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
         launch_norm2(s, r, n, part, nblk, scal);
         const bool step = it < o.max_iter;
         const int slot = next;
-        if (step) {
+        if (step && diis) {      // the step and its error vector go straight into the history slot
+            launch_jacobi(s, x, r, D, n, xh + (size_t)slot * n, eh + (size_t)slot * n);
+            launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal + 1);
+        } else if (step) {
             launch_jacobi(s, x, r, D, n, xn, e);
-            if (diis) {
-                PQPH_HIP(ctx, hipMemcpyAsync(xh + (size_t)slot * n, xn, n * sizeof(double),
-                                             hipMemcpyDeviceToDevice, s));
-                PQPH_HIP(ctx, hipMemcpyAsync(eh + (size_t)slot * n, e, n * sizeof(double),
-                                             hipMemcpyDeviceToDevice, s));
-                launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal + 1);
-            }
         }
         const int nread = 1 + (step && diis ? m : 0);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, nread * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -469,7 +465,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
                 continue;
             }
         }
-        PQPH_HIP(ctx, hipMemcpyAsync(x, xn, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        PQPH_HIP(ctx, hipMemcpyAsync(x, xh + (size_t)slot * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     iters = std::min(it, o.max_iter);
     if (result == PQPH_NOT_CONVERGED)
