@@ -407,14 +407,13 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     for (it = 1; it <= o.max_iter; ++it) {
         pqph_status st = resid(x, r);
         if (st) return st;
-        launch_norm2(s, r, n, part, nblk, scal);
         const bool step = it < o.max_iter;
         const int slot = next;
-        if (step && diis) {      // the step and its error vector go straight into the history slot
-            launch_jacobi(s, x, r, D, n, xh + (size_t)slot * n, eh + (size_t)slot * n);
-            launch_gram(s, eh, m, eh + (size_t)slot * n, n, part, nblk, scal + 1);
-        } else if (step) {
-            launch_jacobi(s, x, r, D, n, xn, e);
+        if (step && diis) {      // norm, step and Gram row in one pass, into the history slot
+            launch_step(s, x, r, D, n, xh + (size_t)slot * n, eh, m, slot, part, nblk, scal);
+        } else {
+            launch_norm2(s, r, n, part, nblk, scal);
+            if (step) launch_jacobi(s, x, r, D, n, xn, e);
         }
         const int nread = 1 + (step && diis ? m : 0);
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, nread * sizeof(double), hipMemcpyDeviceToHost, s));

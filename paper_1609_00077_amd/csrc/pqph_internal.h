@@ -153,5 +153,9 @@ void launch_gram(hipStream_t s, const double* eh, int m, const double* enew, siz
                  int nblk, double* out);
 // out[0] = min |a_i|
 void launch_absmin(hipStream_t s, const double* a, size_t n, double* part, int nblk, double* out);
+// one Jacobi/DIIS step: tn = t - r/D, eh[slot] = -r/D; out[0] = ||r||^2 and
+// out[1 + j] = eh[j] . eh[slot] for j < m (m <= 16; part holds (m+1)*nblk)
+void launch_step(hipStream_t s, const double* t, const double* r, const double* D, size_t n, double* tn,
+                 double* eh, int m, int slot, double* part, int nblk, double* out);
 // t = sum_j c[j] th[j]
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);

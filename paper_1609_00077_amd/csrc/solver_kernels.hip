@@ -51,6 +51,42 @@ __global__ void k_jacobi(const double* __restrict__ t, const double* __restrict_
     }
 }
 
+// One Jacobi/DIIS step in one pass: e = -r/D into the new history slot
+// eh[slot], tn = t + e, and the block partials of ||r||^2 (row 0) and of
+// e . eh[j] for the m history vectors (rows 1..m; the new slot from the
+// register value).  Same grid-stride order and tree reductions as
+// k_dot_partial / k_dots_partial, so the sums are the same.
+__global__ void k_step(const double* __restrict__ t, const double* __restrict__ r,
+                       const double* __restrict__ D, size_t n, double* __restrict__ tn,
+                       double* __restrict__ eh, int m, int slot, double* __restrict__ partial) {
+    __shared__ double red[256];
+    double sr = 0.0, sg[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sg[j] = 0.0;
+    double* es = eh + (size_t)slot * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double ri = r[i];
+        const double d = -ri / D[i];
+        es[i] = d;
+        tn[i] = t[i] + d;
+        sr += ri * ri;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < m) sg[j] += (j == slot ? d : eh[(size_t)j * n + i]) * d;
+    }
+    for (int row = 0; row <= m; ++row) {
+        red[threadIdx.x] = row == 0 ? sr : sg[row - 1];
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(size_t)row * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
 // t = sum_i c[i] * hist[slot_i]
 __global__ void k_combine(const double* __restrict__ hist, const double* __restrict__ c, int m,
                           size_t n, double* __restrict__ t) {
@@ -175,6 +211,12 @@ void launch_gram(hipStream_t s, const double* eh, int m, const double* enew, siz
                  int nblk, double* out) {
     hipLaunchKernelGGL(k_dots_partial, dim3(nblk, m), dim3(256), 0, s, eh, m, enew, n, nblk, part);
     hipLaunchKernelGGL(k_sum_rows, dim3(m), dim3(256), 0, s, part, nblk, out);
+}
+
+void launch_step(hipStream_t s, const double* t, const double* r, const double* D, size_t n, double* tn,
+                 double* eh, int m, int slot, double* part, int nblk, double* out) {
+    hipLaunchKernelGGL(k_step, dim3(nblk), dim3(256), 0, s, t, r, D, n, tn, eh, m, slot, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(m + 1), dim3(256), 0, s, part, nblk, out);
 }
 
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t) {
