@@ -1253,11 +1253,15 @@ __device__ __forceinline__ void link_adj4(int s, const int* Pr, const int* Qr, i
 //   Lbar_b_i = c_i lam_i V         (scattered into the amplitude adjoint)
 //   Lbar_a = Vbar W^T,  Vbar = sum_i c_i lam_i L_b_i  (MFMA; Vbar formed while
 //                                   staging, W^T read from the stored transposes)
-// The vertex adjoint Wbar += L_a^T Vbar is k_wbar's.
+// The vertex adjoint Wbar += L_a^T Vbar is k_wbar's.  Above 128 pairs the
+// output columns (B of V, A of Lbar_a) are split over grid.z, which halves the
+// accumulators (one more wavefront per SIMD) at the price of staging L_a and
+// Vbar twice.
 template <int NCB>
 __global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* __restrict__ W,
                                                    const double* __restrict__ lam, int gchunk, AdjView a) {
     constexpr int NC = 16 * NCB;
+    const int c0 = blockIdx.z * NC;        // this workgroup's output columns c0 .. c0 + NC - 1
     extern __shared__ double sm[];
     double* Ls = sm;                       // [M2_ROWS][M2_KC]: L_a, then Vbar
     double* Ws = Ls + M2_ROWS * M2_KC;     // [M2_KC][NC]: W, then W^T
@@ -1310,7 +1314,7 @@ __global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* 
             }
             const double* Wg = W + (long)w * v.NN;
             for (int i = tid; i < M2_KC * NC; i += 256) {
-                const int A = kc + i / NC, col = i % NC;
+                const int A = kc + i / NC, col = c0 + i % NC;
                 Ws[i] = (A < N && col < N) ? Wg[(long)A * N + col] : 0.0;
             }
             __syncthreads();
@@ -1336,7 +1340,7 @@ __global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* 
                 double d[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) d[r] = wr[r] * D[cb][r];
-                link_adj4(b, Pr, Qr, cb * 16 + i16, d, qsame, v, a);
+                link_adj4(b, Pr, Qr, c0 + cb * 16 + i16, d, qsame, v, a);
             }
         }
         // Lbar_a = Vbar W^T
@@ -1360,7 +1364,7 @@ __global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* 
             }
             const double* WTg = W + (long)wt * v.NN;     // W^T(B, A) = W(A, B)
             for (int i = tid; i < M2_KC * NC; i += 256) {
-                const int B = kc + i / NC, A = i % NC;
+                const int B = kc + i / NC, A = c0 + i % NC;
                 Ws[i] = (B < N && A < N) ? WTg[(long)B * N + A] : 0.0;
             }
             __syncthreads();
@@ -1379,7 +1383,7 @@ __global__ __launch_bounds__(256) void k_r2s2_adjm(int N, View v, const double* 
             double d[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[r] = D[cb][r];
-            link_adj4(sa, Pr, Qr, cb * 16 + i16, d, qsame, v, a);
+            link_adj4(sa, Pr, Qr, c0 + cb * 16 + i16, d, qsame, v, a);
         }
     }
 }
@@ -1907,21 +1911,23 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
             const int rt2 = s2_rowtiles(N);
             const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt2, 1)));
             const int gchunk = (PQ_G_N + nchunk - 1) / nchunk;
-            const dim3 ga(rt2, (PQ_G_N + gchunk - 1) / gchunk);
             auto ldsa = [](int ncb_) { return (size_t)(M2_ROWS * M2_KC + M2_KC * 16 * ncb_) * sizeof(double); };
             const int ncb = (N + 15) / 16;
+            const int nsplit = ncb > 8 ? 2 : 1;          // column halves above 128 pairs
+            const int nbh = (ncb + nsplit - 1) / nsplit;
+            const dim3 ga(rt2, (PQ_G_N + gchunk - 1) / gchunk, nsplit);
 #define PQ_S2A_LAUNCH(NB) \
     hipLaunchKernelGGL(k_r2s2_adjm<NB>, ga, dim3(256), ldsa(NB), s, N, v, c.W, lam, gchunk, a)
-            if (ncb <= 1) PQ_S2A_LAUNCH(1);
-            else if (ncb <= 2) PQ_S2A_LAUNCH(2);
-            else if (ncb <= 3) PQ_S2A_LAUNCH(3);
-            else if (ncb <= 4) PQ_S2A_LAUNCH(4);
-            else if (ncb <= 5) PQ_S2A_LAUNCH(5);
-            else if (ncb <= 6) PQ_S2A_LAUNCH(6);
-            else if (ncb <= 8) PQ_S2A_LAUNCH(8);
-            else if (ncb <= 10) PQ_S2A_LAUNCH(10);
-            else if (ncb <= 13) PQ_S2A_LAUNCH(13);
-            else PQ_S2A_LAUNCH(16);
+            switch (nbh) {
+                case 1: PQ_S2A_LAUNCH(1); break;
+                case 2: PQ_S2A_LAUNCH(2); break;
+                case 3: PQ_S2A_LAUNCH(3); break;
+                case 4: PQ_S2A_LAUNCH(4); break;
+                case 5: PQ_S2A_LAUNCH(5); break;
+                case 6: PQ_S2A_LAUNCH(6); break;
+                case 7: PQ_S2A_LAUNCH(7); break;
+                default: PQ_S2A_LAUNCH(8); break;
+            }
 #undef PQ_S2A_LAUNCH
             // vertex adjoint: about 2048 workgroups of (tile, group, pair slice)
             const int nt64 = (N + WB_T - 1) / WB_T;

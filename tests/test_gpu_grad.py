@@ -193,3 +193,24 @@ def test_autograd_function(pq):
     assert abs(E.item() - g.energy) < 1e-12
     _close(h.grad.cpu().numpy(), 3.0 * g.dE_dh.cpu().numpy(), 1e-10)
     _close(e.grad.cpu().numpy(), 3.0 * g.dE_deri.cpu().numpy(), 1e-10)
+
+
+def test_vjp_dot_product_above_128_pairs(pq):
+    """Above 128 pairs the two-spectator adjoint splits its output columns
+    over workgroups.  Property that holds at any size: <lam, J dt>, with J dt
+    from central differences of the residual (parity-checked against the
+    oracle), equals <J^T lam, dt> from the VJP.  R is quartic in t, so the
+    difference error is O(eps^2)."""
+    N = 136
+    f, eri = _system(N, 901)
+    t = random_amplitudes(N, "pq", seed=902, scale=0.02)
+    lam = random_vector(len(t), seed=903)
+    dt = random_vector(len(t), seed=904)
+    eps = 1e-4
+    fd, ed = _d(f), _d(eri)
+    rp = pq.pq_residual(fd, ed, _d(t + eps * dt)).cpu().numpy()
+    rm = pq.pq_residual(fd, ed, _d(t - eps * dt)).cpu().numpy()
+    lhs = float(lam @ ((rp - rm) / (2 * eps)))
+    tb, _, _ = pq.pq_vjp(fd, ed, _d(t), _d(lam), 0.0, with_hamiltonian=False)
+    rhs = float(tb.cpu().numpy() @ dt)
+    assert abs(lhs - rhs) <= 1e-6 * max(1.0, abs(lhs)), (lhs, rhs)
