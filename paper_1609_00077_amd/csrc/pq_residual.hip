@@ -291,8 +291,10 @@ __device__ __forceinline__ double spec_eval(const SpecPtrs& q, int L0, int L1) {
 // products of their factors (amplitudes, vertices, dressed vertices: arrays
 // of at most a few hundred N x N slices that stay in the caches), instead of
 // being read from materialised X and Y (about 1750 slices at 70 pairs)
+// (five wavefronts per SIMD, as many workgroups as the LDS allows: at 96
+// VGPRs a few values spill, which costs less than the lost occupancy)
 template <bool FUSED>
-__global__ __launch_bounds__(256) void k_gemm_s1(int N, View v, const double* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gemm_s1(int N, View v, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
                                                  double* __restrict__ SK, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
