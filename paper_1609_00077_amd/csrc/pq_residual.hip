@@ -630,7 +630,8 @@ constexpr int M2_KC = 16;
 // (amdgpu_waves_per_eu) than their register use would give by default: the
 // MFMA accumulators otherwise take AGPRs that halve the occupancy, and the
 // latency of their staging loads is hidden by other wavefronts (measured:
-// k_r2s2 20-37 % faster, k_r2s2_adjm 14 %, even where a few registers spill).
+// k_r2s2 20-37 % faster, k_r2s2_adjm 14 %, k_s1_adj up to 19 %, even where a
+// few registers spill).
 
 template <int NCB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_r2s2(int N, View v, const double* __restrict__ W,
@@ -1070,7 +1071,7 @@ __global__ void k_energy_adj(int N, View v, double ew, AdjView a) {
 constexpr int S1A_T = 64, S1A_KC = 16, S1A_PITCH = S1A_KC + 1;
 
 template <int SIDE>
-__global__ __launch_bounds__(256) void k_s1_adj(int N, const double* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_s1_adj(int N, const double* __restrict__ X,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ Sb, double* __restrict__ out) {
     __shared__ double Us[S1A_T * S1A_PITCH];     // [row][k]: Sbar (SIDE 0) or Sbar^T (SIDE 1)
