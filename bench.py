@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ph", action="store_true", help="skip the PH (three-pair) leg")
+    ap.add_argument("--ph-sites", type=int, default=10, help="sites of the PH leg's chain")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--counter-run", type=int, default=0,
@@ -90,6 +92,39 @@ def cpu_baseline(prob, seconds: float):
                        "(%.3g s per residual)" % ("/".join(str(nsamp[s]) for s in (1, 2, 3, 4)),
                                                   total)),
             "seconds_per_subcluster": {str(s): per[s] for s in per}}
+
+
+def ph_leg(args, pq, torch, dev):
+    """PH (three-pair) model on a small chain: one solve from t = 0 (integral
+    transform included) and back-to-back residuals at the converged
+    amplitudes, timed with HIP events on the library's stream."""
+    from inputs import chain_problem
+    prob = chain_problem(args.ph_sites, U=args.U, seed=args.seed)
+    d = lambda x: torch.as_tensor(x, device=dev).contiguous()
+    F, V, Cm = d(prob.F_site), d(prob.V), d(prob.C)
+    f, eri = pq.integrals(F, V, Cm, k=3)
+    pq.ph_residual(f, eri, torch.zeros(pq.amp_len(prob.npair, "ph"), dtype=torch.float64,
+                                       device=dev))          # loads the term tables
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, eri = pq.integrals(F, V, Cm, k=3)
+    res = pq.ph_solve(f, eri, tol=args.tol)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    r = torch.empty_like(res.t)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 5
+    ev0.record()
+    for _ in range(nrep):
+        pq.ph_residual(f, eri, res.t, out=r)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / nrep
+    return {"workload": f"PH solve of a {args.ph_sites}-site PPP chain ({prob.npair} pairs, "
+                        f"U={args.U}, seed {args.seed}) from t=0 to ||R||<={args.tol:g}",
+            "solve_s": ts, "iterations": res.iterations, "energy": res.energy,
+            "status": res.status, "residual_ms": ms, "residual_evals_per_s": 1e3 / ms,
+            "amplitudes": pq.amp_len(prob.npair, "ph")}
 
 
 def batch_leg(args, pq, torch, dev):
@@ -339,6 +374,8 @@ def main():
         line["energy_gradient"] = grad_leg(args, pq, torch, dev)
     if not args.no_batch:
         line["batched"] = batch_leg(args, pq, torch, dev)
+    if not args.no_ph:
+        line["ph"] = ph_leg(args, pq, torch, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(line), flush=True)

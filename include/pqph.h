@@ -153,6 +153,32 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
                      const double* eri, const pqph_solve_opts* opts,
                      double* t_inout, double* energy, pqph_solve_info* info);
 
+/* PH residual r(t) = <mu| e^{-T} H_N e^{T} |0> for every packed slot of the
+ * three-pair model (Sec. II with k = 3: amplitudes and integrals on at most
+ * three pairs).  t and r: ph_amp_len(npair) doubles; eri: ph_eri_len(npair);
+ * h: (2N)^2.  Stream-ordered, no host sync after the first call.  The terms
+ * are the derived PH term tables, read on the context's first PH call from
+ * ph_terms.bin beside the library (or the file named by the environment
+ * variable PQPH_PH_TERMS) and kept in device memory until pqph_destroy; a
+ * missing or damaged file is PQPH_INVALID_ARG.  The kernel interprets the
+ * tables (one wavefront per output slot), so its cost grows as
+ * C(N,3) N^3 times the term count: meant for small active spaces.
+ * npair in [1, 256]. */
+pqph_status ph_residual(pqph_ctx* ctx, int npair, const double* h,
+                        const double* eri, const double* t, double* r);
+
+/* PH correlation energy <0| H_N e^T |0> at amplitudes t (Eqs. (2)-(3), with
+ * the doubles and integrals of up to three pairs); energy is a host pointer;
+ * the call synchronises the stream. */
+pqph_status ph_energy(pqph_ctx* ctx, int npair, const double* h,
+                      const double* eri, const double* t, double* energy);
+
+/* PH amplitude solve: pq_solve's Jacobi + DIIS loop on ph_residual, with the
+ * same options, outputs and status codes; t_inout holds ph_amp_len doubles. */
+pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h,
+                     const double* eri, const pqph_solve_opts* opts,
+                     double* t_inout, double* energy, pqph_solve_info* info);
+
 /* Diagnostic (per-phase tracing): one pq_residual with a HIP event recorded on
  * the context's stream after every kernel; phase_ms (host, nphase entries)
  * receives the elapsed time of each kernel in launch order and *nphase_out

@@ -248,6 +248,50 @@ def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None,
                        info.solve_ms)
 
 
+def ph_residual(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, out: torch.Tensor | None = None):
+    """Packed PH (three-pair) residual r(t) (no host sync)."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair, "ph")
+    if out is None:
+        out = torch.empty(na, dtype=torch.float64, device=h.device)
+    _check(lib, ctx, lib.ph_residual(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                     _dev(eri, "eri", eri_len(npair, "ph")), _dev(t, "t", na),
+                                     _dev(out, "out", na)))
+    return out
+
+
+def ph_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    e = C.c_double()
+    _check(lib, ctx, lib.ph_energy(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                   _dev(eri, "eri", eri_len(npair, "ph")),
+                                   _dev(t, "t", amp_len(npair, "ph")), C.byref(e)))
+    return e.value
+
+
+def ph_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
+             tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
+             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+             raise_on_failure: bool = True) -> SolveResult:
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair, "ph")
+    t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
+                          stall_window)
+    info = _lib.SolveInfo()
+    e = C.c_double()
+    st = lib.ph_solve(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                      _dev(eri, "eri", eri_len(npair, "ph")), C.byref(opts), _dev(t, "t", na),
+                      C.byref(e), C.byref(info))
+    if st != 0 and raise_on_failure:
+        _check(lib, ctx, st)
+    return SolveResult(t, e.value, info.iterations, info.rnorm, _lib.STATUS.get(st, str(st)),
+                       info.solve_ms)
+
+
 def pq_vjp(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, lam: torch.Tensor,
            energy_weight: float = 0.0, with_hamiltonian: bool = True):
     """Transposed residual contraction (no host sync): returns (tbar, hbar,

@@ -39,8 +39,12 @@ SIGNATURES = {
     "ph_eri_len": (C.c_size_t, [C.c_int]),
     "pqph_integrals": (C.c_int, [P, C.c_int, C.c_int, P, P, P, P, P]),
     "pq_residual": (C.c_int, [P, C.c_int, P, P, P, P]),
+    "ph_residual": (C.c_int, [P, C.c_int, P, P, P, P]),
+    "ph_energy": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(C.c_double)]),
     "pq_energy": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(C.c_double)]),
     "pq_solve": (C.c_int, [P, C.c_int, P, P, C.POINTER(SolveOpts), P, C.POINTER(C.c_double),
+                           C.POINTER(SolveInfo)]),
+    "ph_solve": (C.c_int, [P, C.c_int, P, P, C.POINTER(SolveOpts), P, C.POINTER(C.c_double),
                            C.POINTER(SolveInfo)]),
     "pqph_denominators": (C.c_int, [P, C.c_int, C.c_int, P, C.c_double, P]),
     "pq_residual_profile": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_double), C.c_int,

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpqph.so")
 SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "pq_lane.hip", "pq_lane_adj.hip",
-           "integrals.hip", "batched.hip"]
+           "integrals.hip", "batched.hip", "ph_residual.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (wrong results seen on this part)
@@ -29,10 +29,43 @@ def generate_tables() -> None:
     codegen.emit_lane_adj_code(tb, os.path.join(CSRC, "pq_lane_adj_code.h"))
 
 
+PH_TERMS = os.path.join(HERE, "ph_terms.bin")
+PH_INPUTS = [os.path.join(HERE, "derive", f) for f in ("algebra.py", "terms.py", "codegen.py",
+                                                       "ph_tables.py")]
+
+
+def _ph_key() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for path in PH_INPUTS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def ensure_ph_terms() -> str:
+    """The PH term tables (ph_terms.bin beside the library), regenerated when
+    the derivation sources changed since they were written.  Enumerating the
+    three-pair classes takes several CPU-minutes on 8 cores, so a current
+    file is kept."""
+    key = _ph_key()
+    keyfile = PH_TERMS + ".key"
+    if os.path.exists(PH_TERMS) and os.path.exists(keyfile):
+        with open(keyfile) as fh:
+            if fh.read().strip() == key:
+                return PH_TERMS
+    from .derive import ph_tables
+    ph_tables.main([PH_TERMS])
+    with open(keyfile, "w") as fh:
+        fh.write(key + "\n")
+    return PH_TERMS
+
+
 def build(verbose: bool = False) -> str:
     """Regenerate the tables, compile every source to an object in parallel
     (the generated straight-line kernel dominates), link the shared library."""
     generate_tables()
+    ensure_ph_terms()
     os.makedirs(OBJDIR, exist_ok=True)
     procs = []
     for src in SOURCES:
@@ -51,7 +84,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     if failed:
         raise RuntimeError("hipcc failed on " + ", ".join(failed))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", LIB + ".tmp"] + objs + ["-ldl", "-lz"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

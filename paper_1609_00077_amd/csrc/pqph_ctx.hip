@@ -200,6 +200,7 @@ void pqph_destroy(pqph_ctx* ctx) {
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t st : ctx->side)
         if (st) (void)hipStreamDestroy(st);
+    ph_tables_free(ctx);
     delete ctx;
 }
 
@@ -360,8 +361,9 @@ pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, 
                               double* D) {
     pqph_status st = check_pq(ctx, npair);
     if (st) return st;
-    if (k != 2) return pqph_fail(ctx, PQPH_INVALID_ARG, "only k = 2 is built");
+    if (k != 2 && k != 3) return pqph_fail(ctx, PQPH_INVALID_ARG, "k must be 2 (PQ) or 3 (PH)");
     if (!h || !D) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    if (k == 3) return ph_denominators_dev(ctx, ctx->stream, npair, h, shift, D);
     return pq_denominators_dev(ctx, ctx->stream, npair, h, shift, D);
 }
 
@@ -523,6 +525,78 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));
+    PQPH_HIP(ctx, hipStreamSynchronize(s));
+    *energy = ctx->host[0];
+    if (info) {
+        info->iterations = iters;
+        info->rnorm = rn;
+        info->status = result;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        info->solve_ms = ms;
+    }
+    if (result == PQPH_OK && !std::isfinite(*energy)) {
+        result = PQPH_NONFINITE;
+        pqph_fail(ctx, result, "non-finite energy");
+    }
+    return result;
+}
+
+pqph_status ph_residual(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                        const double* t, double* r) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    return ph_residual_dev(ctx, ctx->stream, npair, h, eri, t, r);
+}
+
+pqph_status ph_energy(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                      const double* t, double* energy) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    const size_t wsd = ph_energy_ws_doubles();
+    if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
+    if ((st = ph_energy_dev(ctx, ctx->stream, npair, h, eri, t, ctx->ws + wsd, ctx->ws))) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(energy, ctx->ws + wsd, sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(*energy)) return pqph_fail(ctx, PQPH_NONFINITE, "non-finite energy");
+    return PQPH_OK;
+}
+
+pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                     const pqph_solve_opts* opts_in, double* t, double* energy,
+                     pqph_solve_info* info) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !energy) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    pqph_solve_opts o;
+    if ((st = read_opts(ctx, opts_in, o))) return st;
+    if ((st = ph_tables_load(ctx))) return st;
+    const size_t n = ph_amp_len(npair);
+    const int m = std::max(o.diis_dim, 1);
+    if ((st = pqph_ensure_sv(ctx, (n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    const size_t wsd = ph_energy_ws_doubles();
+    if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_host(ctx, 64))) return st;
+    double* D = ctx->sv;
+    double* bufs = D + n;
+    hipStream_t s = ctx->stream;
+    PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
+    if ((st = ph_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
+    if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    int iters = 0;
+    double rn = 0.0;
+    pqph_status result = PQPH_OK;
+    auto resid = [&](const double* x, double* r) {
+        return ph_residual_dev(ctx, s, npair, h, eri, x, r);
+    };
+    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
+    double* edst = ctx->ws + wsd;
+    if ((st = ph_energy_dev(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
     PQPH_HIP(ctx, hipEventRecord(ctx->ev1, s));
     PQPH_HIP(ctx, hipStreamSynchronize(s));

@@ -52,7 +52,20 @@ struct pqph_ctx {
     // batched solves: 0 = device-resident iterations captured in a HIP graph,
     // 1 = host-driven lockstep (three host synchronisations per iteration)
     int batch_mode = 0;
+    // PH term tables in device memory, read from file on first PH call
+    struct PhTables* ph = nullptr;
 };
+
+// PH (k = 3) path: term tables, residual, energy, denominators on stream s
+pqph_status ph_tables_load(pqph_ctx* ctx);
+void ph_tables_free(pqph_ctx* ctx);
+pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                            const double* eri, const double* t, double* r);
+size_t ph_energy_ws_doubles();
+pqph_status ph_energy_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
+                          const double* t, double* out, double* ws);
+pqph_status ph_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h, double shift,
+                                double* D);
 
 // variant of the two-spectator contraction for this npair (tuned or default)
 int pq_s2_variant(const pqph_ctx* ctx, int npair);

@@ -32,9 +32,45 @@ def all_slots(roles, k):
     return out
 
 
-def enumerate_class(k: int, nout: int, nspec: int, energy: bool = False):
+def _mask(gens):
+    m = 0
+    for g in gens:
+        m |= 1 << g
+    return m
+
+
+def _disjoint_products(cands, I):
+    """The combinations of itertools.product(*cands), in the same order,
+    whose remaining generators repeat neither each other nor those of I; the
+    others multiply to zero (a generator squares to zero), so skipping them
+    early changes no term."""
+    masks = [[_mask(c[3]) for c in cl] for cl in cands]
+    out = []
+    pick = [None] * len(cands)
+
+    def rec(i, used):
+        if i == len(cands):
+            out.append(tuple(pick))
+            return
+        for c, m in zip(cands[i], masks[i]):
+            if used & m:
+                continue
+            pick[i] = c
+            rec(i + 1, used | m)
+
+    i0 = _mask(I)
+    if len(set(I)) == len(I):
+        rec(0, i0)
+    return out
+
+
+def enumerate_class(k: int, nout: int, nspec: int, energy: bool = False, only_hroles=None,
+                    part=(0, 1)):
     """All terms of the output block with roles 0..nout-1 and spectators
-    nout..nout+nspec-1.  With energy=True (nout=0) it gives E_c terms."""
+    nout..nout+nspec-1.  With energy=True (nout=0) it gives E_c terms.
+    only_hroles restricts the Hamiltonian term to those role sets and
+    part = (i, n) to every n-th of their terms from the i-th, so that the
+    enumeration can run in pieces."""
     out_roles = tuple(range(nout))
     spec_roles = tuple(range(nout, nout + nspec))
     allroles = out_roles + spec_roles
@@ -45,7 +81,11 @@ def enumerate_class(k: int, nout: int, nspec: int, energy: bool = False):
         for hroles in itertools.combinations(allroles, hsize):
             if not spec_set <= set(hroles):
                 continue
-            for (I, J), _coef in hamiltonian_terms(hroles, k).items():
+            if only_hroles is not None and hroles not in only_hroles:
+                continue
+            for ih, ((I, J), _coef) in enumerate(hamiltonian_terms(hroles, k).items()):
+                if ih % part[1] != part[0]:
+                    continue
                 if any(g // 4 in spec_set for g in I):
                     continue
                 for psign, blocks in partition_products(J):
@@ -61,7 +101,7 @@ def enumerate_class(k: int, nout: int, nspec: int, energy: bool = False):
                             break
                         cands.append(c)
                     else:
-                        for combo in itertools.product(*cands):
+                        for combo in _disjoint_products(cands, I):
                             seq = list(I)
                             sg = psign
                             for _, _, s, rem in combo:

@@ -20,7 +20,8 @@ def declared():
 
 def test_header_declares_the_path():
     names = declared()
-    for n in ("pq_residual", "pq_solve", "pq_energy", "pqph_integrals", "pqph_create"):
+    for n in ("pq_residual", "pq_solve", "pq_energy", "pqph_integrals", "pqph_create",
+              "ph_residual", "ph_energy", "ph_solve"):
         assert n in names
 
 
