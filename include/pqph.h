@@ -161,7 +161,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
  * ph_terms.bin beside the library (or the file named by the environment
  * variable PQPH_PH_TERMS) and kept in device memory until pqph_destroy; a
  * missing or damaged file is PQPH_INVALID_ARG.  The kernel interprets the
- * tables (one wavefront per output slot), so its cost grows as
+ * tables (one workgroup per output slot), so its cost grows as
  * C(N,3) N^3 times the term count: meant for small active spaces.
  * npair in [1, 256]. */
 pqph_status ph_residual(pqph_ctx* ctx, int npair, const double* h,

@@ -7,10 +7,10 @@
 // The derived terms (one table per output block size and spectator count,
 // grouped by output pattern) are read from a binary file written by the
 // package's PH table generator and kept in device memory per context.  One
-// wavefront owns one output slot: its lanes run over (term, ordered spectator
-// tuple) pairs, evaluate the Hamiltonian symbol sum and the amplitude factors
-// from the packed arrays, and the wave sums them in a fixed order, so results
-// are deterministic.  This is a generic interpreter: its cost grows as
+// workgroup owns one output slot: its threads run over (term, ordered
+// spectator tuple) pairs, evaluate the Hamiltonian symbol sum and the amplitude factors
+// from the packed arrays, and the sums are combined in a fixed order, so
+// results are deterministic.  This is a generic interpreter: its cost grows as
 // C(N,3) x N^3 x terms, far from a factorised kernel.
 #include <dlfcn.h>
 #include <zlib.h>
@@ -217,14 +217,21 @@ __device__ __forceinline__ void decode_slot(long s, int N, int& n, int& m, int* 
     L[0] = (int)(si - (long)Q * (Q - 1) / 2);
 }
 
-__global__ __launch_bounds__(256) void k_ph_residual(int N, long namp, PhArgs a,
-                                                     const double* __restrict__ f,
-                                                     const double* __restrict__ eri,
-                                                     const double* __restrict__ t,
-                                                     double* __restrict__ r) {
-    const long slot = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (slot >= namp) return;
+// One workgroup of PH_WAVES wavefronts per output slot; its threads take the
+// slot's (term, spectator tuple) pairs in a fixed round robin (the pair index
+// advances by the block size without a division), then the waves' sums are
+// added in a fixed order, so the result is deterministic.
+constexpr int PH_WAVES = 8;
+constexpr int PH_BLOCK = 64 * PH_WAVES;
+
+__global__ __launch_bounds__(PH_BLOCK) void k_ph_residual(int N, PhArgs a,
+                                                          const double* __restrict__ f,
+                                                          const double* __restrict__ eri,
+                                                          const double* __restrict__ t,
+                                                          double* __restrict__ r) {
+    __shared__ double red[PH_WAVES];
+    const long slot = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     int n, m, L[3] = {0, 0, 0};
     decode_slot(slot, N, n, m, L);
     // terms are stored for the canonical reordering of the output tuple: its
@@ -239,16 +246,31 @@ __global__ __launch_bounds__(256) void k_ph_residual(int N, long namp, PhArgs a,
         if (k.nout != n || k.nspec > N - n) continue;
         const int* st = a.starts + k.soff;
         const long t0 = k.off + st[mc], nt = st[mc + 1] - st[mc];
-        const long np = nperm(N - n, k.nspec), tot = nt * np;
+        const int np = (int)nperm(N - n, k.nspec);
+        const long tot = nt * np;
+        const int dq = PH_BLOCK / np, dp = PH_BLOCK % np;
+        long q = tid / np;
+        int p = tid % np;
         double part = 0.0;
-        for (long i = lane; i < tot; i += 64) {
-            const long q = i / np;
-            part += term_value(a, N, Lr, L, n, k.nspec, t0 + q, i - q * np, f, eri, t);
+        for (long i = tid; i < tot; i += PH_BLOCK) {
+            part += term_value(a, N, Lr, L, n, k.nspec, t0 + q, p, f, eri, t);
+            q += dq;
+            p += dp;
+            if (p >= np) {
+                p -= np;
+                ++q;
+            }
         }
         acc += inv_fact(k.nspec) * part;
     }
     acc = wave_sum(acc);
-    if (lane == 0) r[slot] = (cn >> 15) & 1 ? -acc : acc;
+    if (lane == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < PH_WAVES; ++w) sum += red[w];
+        r[slot] = (cn >> 15) & 1 ? -sum : sum;
+    }
 }
 
 // E_c = <0| H_3 e^T |0>: the energy classes (no output labels) over ordered
@@ -557,7 +579,7 @@ pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h
     pqph_status st = ph_tables_load(ctx);
     if (st) return st;
     const long namp = (long)ph_amp_len(N);
-    hipLaunchKernelGGL(k_ph_residual, dim3((unsigned)((namp + 3) / 4)), dim3(256), 0, s, N, namp,
+    hipLaunchKernelGGL(k_ph_residual, dim3((unsigned)namp), dim3(PH_BLOCK), 0, s, N,
                        ctx->ph->args, h, eri, t, r);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
