@@ -101,6 +101,35 @@ def make_vjp(name):
         json.dump(out, fh, indent=1)
 
 
+PH_FIXTURES = {
+    # name: (sites, U, chain seed, amplitude seed, amplitude scale)
+    # 6 pairs: the first size where outputs on three pairs have three
+    # spectators, so every PH class contributes
+    "ph12_full": (12, 4.0, 12, 1200, 0.05),
+}
+
+
+def make_ph_full(name):
+    from oracle import tier_a
+    n, U, seed, aseed, scale = PH_FIXTURES[name]
+    prob = chain_problem(n, U=U, seed=seed)
+    N = prob.npair
+    f, eri = integrals.chain_integrals(prob, 3)
+    t = random_amplitudes(N, "ph", seed=aseed, scale=scale)
+    t0 = time.time()
+    R, E = tier_a.TierA(N, 3).residual(f, layout.unpack_eri(eri, N, 3), t)
+    out = {"sites": n, "U": U, "seed": seed, "amp_seed": aseed, "amp_scale": scale,
+           "citation": "R_mu = <mu|e^-T H_3 e^T|0> on the three-pair manifold (Sec. II); "
+                       "definitional oracle (determinant space), every packed slot",
+           "energy": float(E), "residual": [float(x) for x in R]}
+    print(name, f"{time.time() - t0:.1f}s", flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump(out, fh)
+
+
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(FIXTURES) + list(VJP_FIXTURES)):
-        (make_vjp if nm in VJP_FIXTURES else make)(nm)
+    for nm in (sys.argv[1:] or list(FIXTURES) + list(VJP_FIXTURES) + list(PH_FIXTURES)):
+        if nm in PH_FIXTURES:
+            make_ph_full(nm)
+        else:
+            (make_vjp if nm in VJP_FIXTURES else make)(nm)

@@ -2,7 +2,8 @@
 
 The oracle's PH residual is the definition itself (Tier A: e^{-T} H e^{T}
 applied in the determinant space of the active orbitals, k = 3), so these
-checks reach N = 5 pairs.  Above that, the PH residual restricted to
+checks reach N = 5 pairs, and N = 6 (every class active) through values it
+stored in tests/golden.  Above that, the PH residual restricted to
 amplitudes and integrals of at most two pairs must equal the PQ residual on
 the PQ slots (both are the projection of the same transformed Hamiltonian),
 which checks the PH kernel against the oracle-checked PQ path at any size.
@@ -102,6 +103,27 @@ def test_ph_solve_8_sites_matches_oracle_solve(pq):
     assert ref.converged
     assert abs(res.energy - ref.energy) < 1e-10
     assert np.abs(res.t.cpu().numpy() - ref.t).max() < 1e-8
+
+
+def test_ph_residual_12_sites_every_slot(pq):
+    """6 pairs (12-site chain), the first size where three-pair outputs have
+    three spectators: every slot and the energy against the definitional
+    oracle's values stored by tests/golden/make_golden.py."""
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "ph12_full.json")
+    if not os.path.exists(p):
+        pytest.skip("golden fixture ph12_full not generated (tests/golden/make_golden.py)")
+    with open(p) as fh:
+        g = json.load(fh)
+    prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
+    N = prob.npair
+    f, eri = (_d(x) for x in oint.chain_integrals(prob, 3))
+    t = _d(random_amplitudes(N, "ph", seed=g["amp_seed"], scale=g["amp_scale"]))
+    R = pq.ph_residual(f, eri, t).cpu().numpy()
+    ref = np.array(g["residual"])
+    assert np.abs(R - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert abs(pq.ph_energy(f, eri, t) - g["energy"]) < 1e-12
 
 
 def test_ph_residual_is_deterministic(pq):
