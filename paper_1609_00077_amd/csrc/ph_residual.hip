@@ -146,14 +146,11 @@ __device__ __forceinline__ int outside(int j, const int* L, int n) {
     return j;
 }
 
-// one term over one ordered spectator tuple (number perm of n_o (n_o - 1) ...);
-// output role i sits at label Lr[i], L is the same set in ascending order
-__device__ __forceinline__ double term_value(const PhArgs& a, int N, const int* Lr, const int* L,
-                                             int nout, int nspec, long q, long perm,
-                                             const double* __restrict__ f,
-                                             const double* __restrict__ eri,
-                                             const double* __restrict__ t) {
-    int lab[6];
+// labels of an output slot's roles and of one ordered spectator tuple (number
+// perm of n_o (n_o - 1) ...); output role i sits at label Lr[i], L is the
+// same set in ascending order
+__device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, int nout,
+                                            int nspec, long perm, int* lab) {
     for (int i = 0; i < nout; ++i) lab[i] = Lr[i];
     const int no = N - nout;
     int j[3] = {0, 0, 0};
@@ -169,13 +166,31 @@ __device__ __forceinline__ double term_value(const PhArgs& a, int N, const int* 
         if (j[2] >= hi) ++j[2];
     }
     for (int i = 0; i < nspec; ++i) lab[nout + i] = outside(j[i], L, nout);
-    double v = hval(a, lab, a.th[q], N, f, eri);
-    if (v == 0.0) return 0.0;
-    const int cw = a.cw_dict[a.tcw[q]];
-    const int nf = cw >> 16;
-    v *= (double)((cw & 0xffff) - 32768);
-    for (int i = 0; i < nf && v != 0.0; ++i) v *= amp(a, lab, a.slot_dict[a.ts[i * a.nterm + q]], N, t);
-    return v;
+}
+
+// the terms q0 .. q1-1 at one label assignment; consecutive terms of one
+// Hamiltonian term (the tables keep them together) reuse its value
+__device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int* lab, long q0,
+                                              long q1, const double* __restrict__ f,
+                                              const double* __restrict__ eri,
+                                              const double* __restrict__ t) {
+    double sum = 0.0, hv = 0.0;
+    int hprev = -1;
+    for (long q = q0; q < q1; ++q) {
+        const int h = a.th[q];
+        if (h != hprev) {
+            hv = hval(a, lab, h, N, f, eri);
+            hprev = h;
+        }
+        if (hv == 0.0) continue;
+        const int cw = a.cw_dict[a.tcw[q]];
+        const int nf = cw >> 16;
+        double v = hv * (double)((cw & 0xffff) - 32768);
+        for (int i = 0; i < nf && v != 0.0; ++i)
+            v *= amp(a, lab, a.slot_dict[a.ts[i * a.nterm + q]], N, t);
+        sum += v;
+    }
+    return sum;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -217,12 +232,15 @@ __device__ __forceinline__ void decode_slot(long s, int N, int& n, int& m, int* 
     L[0] = (int)(si - (long)Q * (Q - 1) / 2);
 }
 
-// One workgroup of PH_WAVES wavefronts per output slot; its threads take the
-// slot's (term, spectator tuple) pairs in a fixed round robin (the pair index
-// advances by the block size without a division), then the waves' sums are
-// added in a fixed order, so the result is deterministic.
+// One workgroup of PH_WAVES wavefronts per output slot.  Its work items are
+// (chunk of PH_CHUNK consecutive terms, ordered spectator tuple), spectator
+// tuple fastest, so the lanes of a wave walk the same terms at different
+// spectators; items go round robin over the threads (the item index advances
+// by the block size without a division), and the waves' sums are added in a
+// fixed order, so the result is deterministic.
 constexpr int PH_WAVES = 8;
 constexpr int PH_BLOCK = 64 * PH_WAVES;
+constexpr int PH_CHUNK = 16;
 
 __global__ __launch_bounds__(PH_BLOCK) void k_ph_residual(int N, PhArgs a,
                                                           const double* __restrict__ f,
@@ -245,20 +263,23 @@ __global__ __launch_bounds__(PH_BLOCK) void k_ph_residual(int N, PhArgs a,
         const PhClass& k = a.cls[c];
         if (k.nout != n || k.nspec > N - n) continue;
         const int* st = a.starts + k.soff;
-        const long t0 = k.off + st[mc], nt = st[mc + 1] - st[mc];
+        const long t0 = k.off + st[mc], t1 = k.off + st[mc + 1];
         const int np = (int)nperm(N - n, k.nspec);
-        const long tot = nt * np;
+        const long items = (t1 - t0 + PH_CHUNK - 1) / PH_CHUNK * np;
         const int dq = PH_BLOCK / np, dp = PH_BLOCK % np;
-        long q = tid / np;
+        long ch = tid / np;
         int p = tid % np;
         double part = 0.0;
-        for (long i = tid; i < tot; i += PH_BLOCK) {
-            part += term_value(a, N, Lr, L, n, k.nspec, t0 + q, p, f, eri, t);
-            q += dq;
+        for (long i = tid; i < items; i += PH_BLOCK) {
+            int lab[6];
+            role_labels(N, Lr, L, n, k.nspec, p, lab);
+            const long q0 = t0 + ch * PH_CHUNK;
+            part += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
+            ch += dq;
             p += dp;
             if (p >= np) {
                 p -= np;
-                ++q;
+                ++ch;
             }
         }
         acc += inv_fact(k.nspec) * part;
@@ -290,7 +311,9 @@ __global__ __launch_bounds__(256) void k_ph_energy(int N, PhArgs a, const double
         double s = 0.0;
         for (long i = g; i < tot; i += G) {
             const long q = i / np;
-            s += term_value(a, N, L, L, 0, k.nspec, k.off + q, i - q * np, f, eri, t);
+            int lab[6];
+            role_labels(N, L, L, 0, k.nspec, i - q * np, lab);
+            s += chunk_value(a, N, lab, k.off + q, k.off + q + 1, f, eri, t);
         }
         acc += inv_fact(k.nspec) * s;
     }
