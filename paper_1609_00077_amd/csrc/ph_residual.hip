@@ -15,6 +15,7 @@
 #include <dlfcn.h>
 #include <zlib.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -72,17 +73,18 @@ __device__ __forceinline__ long eri_off(int N, int n) {
     return n == 1 ? 0 : n == 2 ? 6L * N : 6L * N + 43 * ncomb(N, 2);
 }
 
-// amplitude of one factor: the labels of its roles, put in ascending order
-// (swapping two odd patterns flips the sign), looked up in the packed t
-__device__ __forceinline__ double amp(const PhArgs& a, const int* lab, int code, int N,
-                                      const double* __restrict__ t) {
+// packed position of one amplitude factor: the labels of its roles, put in
+// ascending order (swapping two odd patterns flips the sign); -1 for no
+// factor (code 0) or a pattern tuple the layout does not store
+__device__ __forceinline__ long amp_pos(const PhArgs& a, const int* lab, int code, int N,
+                                        double& sg) {
     const int n = code & 3;
-    int l[3] = {0, 0, 0}, p[3] = {0, 0, 0};
-    for (int i = 0; i < n; ++i) {
-        l[i] = lab[(code >> (2 + 3 * i)) & 7];
-        p[i] = (code >> (11 + 4 * i)) & 15;
+    int l[3], p[3];
+    for (int i = 0; i < 3; ++i) {
+        l[i] = i < n ? lab[(code >> (2 + 3 * i)) & 7] : 0;
+        p[i] = i < n ? (code >> (11 + 4 * i)) & 15 : 0;
     }
-    double sg = 1.0;
+    sg = 1.0;
     auto sw = [&](int i) {
         if (l[i] > l[i + 1]) {
             if ((__popc(p[i]) & 1) && (__popc(p[i + 1]) & 1)) sg = -sg;
@@ -92,10 +94,11 @@ __device__ __forceinline__ double amp(const PhArgs& a, const int* lab, int code,
     };
     if (n == 2) sw(0);
     if (n == 3) { sw(0); sw(1); sw(0); }
+    if (n == 0) return -1;
     const int base = n == 1 ? 0 : n == 2 ? 16 : 272;
     const int m = a.pat2m[base + (p[0] | p[1] << 4 | p[2] << 8)];
-    if (m < 0) return 0.0;
-    return sg * t[amp_off(N, n) + m * ncomb(N, n) + set_index(l, n)];
+    if (m < 0) return -1;
+    return amp_off(N, n) + m * ncomb(N, n) + set_index(l, n);
 }
 
 // Hamiltonian factor: sum of weighted f and chemists' (pq|rs) symbols, local
@@ -185,9 +188,15 @@ __device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int*
         if (hv == 0.0) continue;
         const int cw = a.cw_dict[a.tcw[q]];
         const int nf = cw >> 16;
+        // the factors are independent: all their loads can be in flight at once
+        int code[4];
+        for (int i = 0; i < 4; ++i) code[i] = i < nf ? a.slot_dict[a.ts[i * a.nterm + q]] : 0;
+        long pos[4];
+        double sg[4];
+        for (int i = 0; i < 4; ++i) pos[i] = amp_pos(a, lab, code[i], N, sg[i]);
         double v = hv * (double)((cw & 0xffff) - 32768);
-        for (int i = 0; i < nf && v != 0.0; ++i)
-            v *= amp(a, lab, a.slot_dict[a.ts[i * a.nterm + q]], N, t);
+        for (int i = 0; i < 4; ++i)
+            if (i < nf) v *= pos[i] >= 0 ? sg[i] * t[pos[i]] : 0.0;
         sum += v;
     }
     return sum;
@@ -206,6 +215,24 @@ __device__ __forceinline__ long nperm(int no, int nspec) {
 
 // 1 / nspec!: the terms are summed over ordered spectator tuples
 __device__ __forceinline__ double inv_fact(int n) { return n == 2 ? 0.5 : n == 3 ? 1.0 / 6.0 : 1.0; }
+
+// ascending labels of set number si among the label sets of size n
+__device__ __forceinline__ void decode_set(long si, int n, int* L) {
+    if (n == 1) {
+        L[0] = (int)si;
+        return;
+    }
+    if (n == 3) {
+        int R = 2;
+        while ((long)(R + 1) * R * (R - 1) / 6 <= si) ++R;
+        L[2] = R;
+        si -= (long)R * (R - 1) * (R - 2) / 6;
+    }
+    int Q = 1;
+    while ((long)(Q + 1) * Q / 2 <= si) ++Q;
+    L[1] = Q;
+    L[0] = (int)(si - (long)Q * (Q - 1) / 2);
+}
 
 // decode a packed slot into (block size, pattern number, ascending labels)
 __device__ __forceinline__ void decode_slot(long s, int N, int& n, int& m, int* L) {
@@ -232,57 +259,62 @@ __device__ __forceinline__ void decode_slot(long s, int N, int& n, int& m, int* 
     L[0] = (int)(si - (long)Q * (Q - 1) / 2);
 }
 
-// One workgroup of PH_WAVES wavefronts per output slot.  Its work items are
+// The residual runs as balanced work units.  A unit is a range of one
+// class's work items for one output pattern m of block size n; items are
 // (chunk of PH_CHUNK consecutive terms, ordered spectator tuple), spectator
 // tuple fastest, so the lanes of a wave walk the same terms at different
-// spectators; items go round robin over the threads (the item index advances
-// by the block size without a division), and the waves' sums are added in a
-// fixed order, so the result is deterministic.
+// spectators.  k_ph_part runs one workgroup per (label set, unit) and writes
+// the unit's sum; k_ph_gather adds a slot's units in their fixed order (the
+// result is deterministic).  Splitting matters: the term count of the
+// three-pair output patterns ranges over a factor of 20.
 constexpr int PH_WAVES = 8;
 constexpr int PH_BLOCK = 64 * PH_WAVES;
 constexpr int PH_CHUNK = 16;
 
-__global__ __launch_bounds__(PH_BLOCK) void k_ph_residual(int N, PhArgs a,
-                                                          const double* __restrict__ f,
-                                                          const double* __restrict__ eri,
-                                                          const double* __restrict__ t,
-                                                          double* __restrict__ r) {
+struct PhUnits {
+    const int* m;          // per unit: output pattern
+    const int* cls;        // class
+    const long* i0;        // item range
+    const long* i1;
+};
+
+__global__ __launch_bounds__(PH_BLOCK) void k_ph_part(int N, int n, PhArgs a, PhUnits u,
+                                                      const double* __restrict__ f,
+                                                      const double* __restrict__ eri,
+                                                      const double* __restrict__ t,
+                                                      double* __restrict__ part) {
     __shared__ double red[PH_WAVES];
-    const long slot = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63;
-    int n, m, L[3] = {0, 0, 0};
-    decode_slot(slot, N, n, m, L);
+    const long si = blockIdx.x, nsets = gridDim.x;
+    const int un = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+    int L[3] = {0, 0, 0};
+    decode_set(si, n, L);
+    const int m = u.m[un];
     // terms are stored for the canonical reordering of the output tuple: its
-    // role i sits at label L[p_i], and the operator reorders with a sign
+    // role i sits at label L[p_i]
     const int cn = a.canon[(n == 1 ? 0 : n == 2 ? 3 : 32) + m];
     const int mc = cn & 511;
     int Lr[3];
     for (int i = 0; i < 3; ++i) Lr[i] = L[(cn >> (9 + 2 * i)) & 3];
+    const PhClass& k = a.cls[u.cls[un]];
+    const int* st = a.starts + k.soff;
+    const long t0 = k.off + st[mc], t1 = k.off + st[mc + 1];
+    const int np = (int)nperm(N - n, k.nspec);
+    const long i0 = u.i0[un], i1 = u.i1[un];
+    const int dq = PH_BLOCK / np, dp = PH_BLOCK % np;
+    long ch = (i0 + tid) / np;
+    int p = (int)((i0 + tid) % np);
     double acc = 0.0;
-    for (int c = 0; c < a.nclass; ++c) {
-        const PhClass& k = a.cls[c];
-        if (k.nout != n || k.nspec > N - n) continue;
-        const int* st = a.starts + k.soff;
-        const long t0 = k.off + st[mc], t1 = k.off + st[mc + 1];
-        const int np = (int)nperm(N - n, k.nspec);
-        const long items = (t1 - t0 + PH_CHUNK - 1) / PH_CHUNK * np;
-        const int dq = PH_BLOCK / np, dp = PH_BLOCK % np;
-        long ch = tid / np;
-        int p = tid % np;
-        double part = 0.0;
-        for (long i = tid; i < items; i += PH_BLOCK) {
-            int lab[6];
-            role_labels(N, Lr, L, n, k.nspec, p, lab);
-            const long q0 = t0 + ch * PH_CHUNK;
-            part += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
-            ch += dq;
-            p += dp;
-            if (p >= np) {
-                p -= np;
-                ++ch;
-            }
+    for (long i = i0 + tid; i < i1; i += PH_BLOCK) {
+        int lab[6];
+        role_labels(N, Lr, L, n, k.nspec, p, lab);
+        const long q0 = t0 + ch * PH_CHUNK;
+        acc += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
+        ch += dq;
+        p += dp;
+        if (p >= np) {
+            p -= np;
+            ++ch;
         }
-        acc += inv_fact(k.nspec) * part;
     }
     acc = wave_sum(acc);
     if (lane == 0) red[tid >> 6] = acc;
@@ -290,8 +322,25 @@ __global__ __launch_bounds__(PH_BLOCK) void k_ph_residual(int N, PhArgs a,
     if (tid == 0) {
         double sum = 0.0;
         for (int w = 0; w < PH_WAVES; ++w) sum += red[w];
-        r[slot] = (cn >> 15) & 1 ? -sum : sum;
+        part[(long)un * nsets + si] = inv_fact(k.nspec) * sum;
     }
+}
+
+// r(slot) = sign * (sum of the slot's unit sums, in unit order)
+__global__ void k_ph_gather(int N, long namp, PhArgs a, const int* __restrict__ ustart,
+                            const double* __restrict__ part1, const double* __restrict__ part2,
+                            const double* __restrict__ part3, double* __restrict__ r) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= namp) return;
+    int n, m, L[3];
+    decode_slot(s, N, n, m, L);
+    const long nsets = ncomb(N, n), si = set_index(L, n);
+    const int* us = ustart + (n == 1 ? 0 : n == 2 ? 4 : 34);
+    const double* part = n == 1 ? part1 : n == 2 ? part2 : part3;
+    double sum = 0.0;
+    for (int un = us[m]; un < us[m + 1]; ++un) sum += part[(long)un * nsets + si];
+    const int cn = a.canon[(n == 1 ? 0 : n == 2 ? 3 : 32) + m];
+    r[s] = (cn >> 15) & 1 ? -sum : sum;
 }
 
 // E_c = <0| H_3 e^T |0>: the energy classes (no output labels) over ordered
@@ -353,10 +402,23 @@ __global__ void k_ph_denom(int N, long namp, PhArgs a, const double* __restrict_
 }  // namespace
 
 // ------------------------------------------------------------ table loading
+// work units of one pair count: per block size n, a list of (pattern m,
+// class, item range), grouped by m (ustart: 4 + 30 + 304 offsets)
+struct PhSched {
+    void* dev = nullptr;
+    PhUnits units[4] = {};
+    const int* ustart = nullptr;
+    int nunit[4] = {};
+    size_t part_off[4] = {};      // partial sums of size n start here (doubles)
+    size_t part_doubles = 0;
+};
+
 struct PhTables {
     PhArgs args{};
     void* dev = nullptr;
     int nh = 0;
+    std::vector<int> starts_h, canon_h;     // host copies for scheduling
+    std::vector<PhSched*> sched = std::vector<PhSched*>(257, nullptr);
 };
 
 namespace {
@@ -526,6 +588,8 @@ pqph_status ph_parse(pqph_ctx* ctx, const std::vector<char>& buf, PhTables& tb,
         }
     }
     tb.nh = nh;
+    tb.starts_h = starts;
+    tb.canon_h.assign(canon, canon + 3 + 29 + 303);
     return PQPH_OK;
 }
 
@@ -592,18 +656,136 @@ pqph_status ph_tables_load(pqph_ctx* ctx) {
 
 void ph_tables_free(pqph_ctx* ctx) {
     if (!ctx->ph) return;
+    for (PhSched* sc : ctx->ph->sched)
+        if (sc) {
+            if (sc->dev) (void)hipFree(sc->dev);
+            delete sc;
+        }
     if (ctx->ph->dev) (void)hipFree(ctx->ph->dev);
     delete ctx->ph;
     ctx->ph = nullptr;
 }
 
-pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
-                            const double* eri, const double* t, double* r) {
+namespace {
+
+long host_nperm(int no, int k) {
+    long p = 1;
+    for (int i = 0; i < k; ++i) p *= no - i;
+    return p;
+}
+
+long host_ncomb(int N, int k) {
+    return k == 1 ? N : k == 2 ? (long)N * (N - 1) / 2 : (long)N * (N - 1) * (N - 2) / 6;
+}
+
+// units of at most U items, U chosen so that no block size has more than
+// 60000 units (the grid's second dimension)
+pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
+    PhTables& tb = *ctx->ph;
+    if ((out = tb.sched[N])) return PQPH_OK;
+    const PhArgs& a = tb.args;
+    auto items = [&](int n, int m, int c) -> long {
+        const PhClass& k = a.cls[c];
+        if (k.nout != n || k.nspec > N - n) return 0;
+        const int mc = tb.canon_h[(n == 1 ? 0 : n == 2 ? 3 : 32) + m] & 511;
+        const long nt = tb.starts_h[k.soff + mc + 1] - tb.starts_h[k.soff + mc];
+        return (nt + PH_CHUNK - 1) / PH_CHUNK * host_nperm(N - n, k.nspec);
+    };
+    long U = 4096;
+    for (int n = 1; n <= 3 && n <= N; ++n) {
+        const int npat = n == 1 ? 3 : n == 2 ? 29 : 303;
+        long tot = 0;
+        for (int m = 0; m < npat; ++m)
+            for (int c = 0; c < a.nclass; ++c) tot += items(n, m, c);
+        // units of size n <= tot / U + (patterns x classes)
+        U = std::max(U, tot / (60000 - npat * kMaxClass) + 1);
+    }
+    std::vector<int> um, uc, ustart;
+    std::vector<long> ui0, ui1;
+    PhSched* sc = new PhSched();
+    size_t first[4] = {};
+    for (int n = 1; n <= 3; ++n) {
+        const int npat = n == 1 ? 3 : n == 2 ? 29 : 303;
+        first[n] = um.size();
+        int cnt = 0;
+        for (int m = 0; m < npat; ++m) {
+            ustart.push_back(cnt);
+            if (n > N) continue;
+            for (int c = 0; c < a.nclass; ++c) {
+                const long it = items(n, m, c);
+                for (long i0 = 0; i0 < it; i0 += U) {
+                    um.push_back(m);
+                    uc.push_back(c);
+                    ui0.push_back(i0);
+                    ui1.push_back(std::min(i0 + U, it));
+                    ++cnt;
+                }
+            }
+        }
+        ustart.push_back(cnt);
+        sc->nunit[n] = cnt;
+        sc->part_off[n] = sc->part_doubles;
+        if (n <= N) sc->part_doubles += (size_t)cnt * host_ncomb(N, n);
+    }
+    const size_t nu = um.size();
+    const size_t bytes = nu * 24 + ustart.size() * 4 + 64;
+    if (hipMalloc(&sc->dev, bytes) != hipSuccess) {
+        delete sc;
+        return pqph_fail(ctx, PQPH_OOM, "PH schedule: device allocation failed");
+    }
+    std::vector<char> blob(bytes, 0);
+    char* p = blob.data();
+    const size_t o_i0 = 0, o_i1 = nu * 8, o_m = nu * 16, o_c = nu * 20, o_us = nu * 24;
+    memcpy(p + o_i0, ui0.data(), nu * 8);
+    memcpy(p + o_i1, ui1.data(), nu * 8);
+    memcpy(p + o_m, um.data(), nu * 4);
+    memcpy(p + o_c, uc.data(), nu * 4);
+    memcpy(p + o_us, ustart.data(), ustart.size() * 4);
+    if (hipMemcpy(sc->dev, blob.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(sc->dev);
+        delete sc;
+        return pqph_fail(ctx, PQPH_DEVICE, "PH schedule: upload failed");
+    }
+    const char* d = static_cast<const char*>(sc->dev);
+    for (int n = 1; n <= 3; ++n) {
+        sc->units[n].i0 = reinterpret_cast<const long*>(d + o_i0) + first[n];
+        sc->units[n].i1 = reinterpret_cast<const long*>(d + o_i1) + first[n];
+        sc->units[n].m = reinterpret_cast<const int*>(d + o_m) + first[n];
+        sc->units[n].cls = reinterpret_cast<const int*>(d + o_c) + first[n];
+    }
+    sc->ustart = reinterpret_cast<const int*>(d + o_us);
+    tb.sched[N] = out = sc;
+    return PQPH_OK;
+}
+
+}  // namespace
+
+pqph_status ph_residual_ws_doubles(pqph_ctx* ctx, int N, size_t* out) {
     pqph_status st = ph_tables_load(ctx);
     if (st) return st;
+    PhSched* sc = nullptr;
+    if ((st = ph_schedule(ctx, N, sc))) return st;
+    *out = sc->part_doubles;
+    return PQPH_OK;
+}
+
+pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                            const double* eri, const double* t, double* r, double* ws) {
+    pqph_status st = ph_tables_load(ctx);
+    if (st) return st;
+    PhSched* sc = nullptr;
+    if ((st = ph_schedule(ctx, N, sc))) return st;
+    for (int n = 1; n <= 3 && n <= N; ++n) {
+        if (sc->nunit[n] == 0) continue;
+        hipLaunchKernelGGL(k_ph_part, dim3((unsigned)host_ncomb(N, n), (unsigned)sc->nunit[n]),
+                           dim3(PH_BLOCK), 0, s, N, n, ctx->ph->args, sc->units[n], h, eri, t,
+                           ws + sc->part_off[n]);
+        PQPH_HIP(ctx, hipGetLastError());
+    }
     const long namp = (long)ph_amp_len(N);
-    hipLaunchKernelGGL(k_ph_residual, dim3((unsigned)namp), dim3(PH_BLOCK), 0, s, N,
-                       ctx->ph->args, h, eri, t, r);
+    hipLaunchKernelGGL(k_ph_gather, dim3((unsigned)((namp + 255) / 256)), dim3(256), 0, s, N, namp,
+                       ctx->ph->args, sc->ustart, ws + sc->part_off[1], ws + sc->part_off[2],
+                       ws + sc->part_off[3], r);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
 }

@@ -549,7 +549,10 @@ pqph_status ph_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     pqph_status st = check_pq(ctx, npair);
     if (st) return st;
     if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
-    return ph_residual_dev(ctx, ctx->stream, npair, h, eri, t, r);
+    size_t wsd = 0;
+    if ((st = ph_residual_ws_doubles(ctx, npair, &wsd))) return st;
+    if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
+    return ph_residual_dev(ctx, ctx->stream, npair, h, eri, t, r, ctx->ws);
 }
 
 pqph_status ph_energy(pqph_ctx* ctx, int npair, const double* h, const double* eri,
@@ -580,7 +583,9 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     const int m = std::max(o.diis_dim, 1);
     if ((st = pqph_ensure_sv(ctx, (n + driver_doubles(n, m)) * sizeof(double)))) return st;
     const size_t wsd = ph_energy_ws_doubles();
-    if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
+    size_t rwsd = 0;      // the residual's partial sums share the workspace (same stream)
+    if ((st = ph_residual_ws_doubles(ctx, npair, &rwsd))) return st;
+    if ((st = pqph_ensure_ws(ctx, (std::max(wsd, rwsd) + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
     double* D = ctx->sv;
     double* bufs = D + n;
@@ -592,7 +597,7 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     double rn = 0.0;
     pqph_status result = PQPH_OK;
     auto resid = [&](const double* x, double* r) {
-        return ph_residual_dev(ctx, s, npair, h, eri, x, r);
+        return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws);
     };
     if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
     double* edst = ctx->ws + wsd;

@@ -59,8 +59,10 @@ struct pqph_ctx {
 // PH (k = 3) path: term tables, residual, energy, denominators on stream s
 pqph_status ph_tables_load(pqph_ctx* ctx);
 void ph_tables_free(pqph_ctx* ctx);
+// ws: ph_residual_ws_doubles (the work units' partial sums)
+pqph_status ph_residual_ws_doubles(pqph_ctx* ctx, int N, size_t* out);
 pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
-                            const double* eri, const double* t, double* r);
+                            const double* eri, const double* t, double* r, double* ws);
 size_t ph_energy_ws_doubles();
 pqph_status ph_energy_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
                           const double* t, double* out, double* ws);
