@@ -160,10 +160,13 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
  * are the derived PH term tables, read on the context's first PH call from
  * ph_terms.bin beside the library (or the file named by the environment
  * variable PQPH_PH_TERMS) and kept in device memory until pqph_destroy; a
- * missing or damaged file is PQPH_INVALID_ARG.  The kernel interprets the
- * tables (one workgroup per output slot), so its cost grows as
- * C(N,3) N^3 times the term count: meant for small active spaces.
- * npair in [1, 256]. */
+ * missing or damaged file is PQPH_INVALID_ARG.  The kernels interpret the
+ * tables in balanced work units (a host schedule built once per npair), so
+ * the cost grows as C(N,3) N^3 times the term count: meant for small active
+ * spaces (about 0.3 s at 8 pairs, 34 s at 16).  The context's workspace
+ * grows to hold one partial sum per (label set, work unit): at most 60000
+ * units per block size, so up to 60000 C(N,3) doubles.  npair in [1, 256];
+ * a workspace that cannot be allocated is PQPH_OOM. */
 pqph_status ph_residual(pqph_ctx* ctx, int npair, const double* h,
                         const double* eri, const double* t, double* r);
 
