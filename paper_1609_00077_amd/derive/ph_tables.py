@@ -33,7 +33,9 @@ File layout (int32 unless marked; the whole file is zlib-compressed):
 Slot code of an amplitude factor: nlab | r0 << 2 | r1 << 5 | r2 << 8 |
 p0 << 11 | p1 << 15 | p2 << 19, roles and patterns in the term's role order.
 A term contributes coef / nspec! * h * prod(t) for every ordered choice of
-distinct spectator labels outside the output set.
+distinct spectator labels outside the output set.  Terms are kept for the
+canonical output tuples only, and once per orbit under renamings of the
+spectator roles, with coef summed over the orbit.
 """
 from __future__ import annotations
 
@@ -81,6 +83,79 @@ def reorder_sign(mu, p):
     return -1 if inv % 2 else 1
 
 
+def _odd(e):
+    return bin(e).count("1") % 2
+
+
+def _relabel(t, pi, h_sign_cache):
+    """The term t with its roles renamed by pi, written in the stored form
+    (roles of every factor ascending, Hamiltonian key sorted), and the sign
+    that rewriting costs; None if the renamed Hamiltonian key does not exist."""
+    sign = t.sign
+    slots = []
+    for rho, pats in t.slots:
+        items = sorted(zip((pi[r] for r in rho), pats))
+        order = sorted(range(len(rho)), key=lambda i: pi[rho[i]])
+        inv = sum(1 for i in range(len(order)) for j in range(i + 1, len(order))
+                  if order[i] > order[j] and _odd(pats[order[i]]) and _odd(pats[order[j]]))
+        sign *= -1 if inv % 2 else 1
+        slots.append((tuple(r for r, _ in items), tuple(p for _, p in items)))
+    hroles = tuple(sorted(pi[r] for r in t.hroles))
+    key = (t.hroles, t.hkey, tuple(sorted(pi.items())))
+    if key not in h_sign_cache:
+        I, J = t.hkey
+        sI, I2 = algebra.sort_sign([4 * pi[g // 4] + g % 4 for g in I])
+        sJ, J2 = algebra.sort_sign([4 * pi[g // 4] + g % 4 for g in J])
+        new = algebra.hamiltonian_terms(hroles, K).get((I2, J2))
+        hs = None
+        if new is not None and sI and sJ:
+            old = algebra.hamiltonian_terms(tuple(t.hroles), K)[t.hkey]
+            mx = lambda x: 2 * pi[x // 2] + x % 2
+            ratios = set()
+            for sym, w in old.items():
+                if sym[0] == "f":
+                    img = ("f", mx(sym[1]), mx(sym[2]))
+                else:
+                    img = ("v",) + algebra.eri_canon(*(mx(x) for x in sym[1:]))
+                wn = new.get(img)
+                ratios.add(None if wn is None else round(wn / w, 9))
+            if len(ratios) == 1 and len(new) == len(old) and next(iter(ratios)) in (1.0, -1.0):
+                hs = int(next(iter(ratios)))
+        h_sign_cache[key] = None if hs is None else ((I2, J2), hs)
+    hk = h_sign_cache[key]
+    if hk is None:
+        return None
+    return t._replace(sign=sign * hk[1], hroles=hroles, hkey=hk[0], slots=tuple(slots))
+
+
+def spectator_canonical(terms, nout, nspec):
+    """One representative per orbit of the terms under renamings of the
+    spectator roles, its coefficient summed over the orbit.  The kernels sum
+    every term over ordered spectator tuples, and renaming the spectator roles
+    of a term equals reordering the tuple, so an orbit contributes |orbit|
+    times its representative."""
+    if nspec < 2:
+        return terms
+    cache = {}
+    out = []
+    spec = list(range(nout, nout + nspec))
+    perms = []
+    for p in itertools.permutations(spec):
+        pi = {r: r for r in range(nout)}
+        pi.update(dict(zip(spec, p)))
+        perms.append(pi)
+    for t in terms:
+        best = None
+        for pi in perms:
+            img = _relabel(t, pi, cache)
+            assert img is not None
+            k = (img.hroles, img.hkey, tuple(sorted(img.slots)))
+            if best is None or k < best[0]:
+                best = (k, img)
+        out.append(best[1])
+    return out
+
+
 def _unit(args):
     """Terms of one piece, for the canonical output tuples only: the terms of
     a reordered tuple are the same terms with the output roles relabelled
@@ -90,7 +165,7 @@ def _unit(args):
     terms = enumerate_class(K, nout, nspec, energy=(nout == 0), only_hroles={hroles}, part=part)
     if nout >= 2:
         terms = [t for t in terms if canonical(t.mu)[0] == t.mu]
-    return (nout, nspec), merge_terms(terms)
+    return (nout, nspec), merge_terms(spectator_canonical(terms, nout, nspec))
 
 
 def _units():
@@ -107,15 +182,20 @@ def _units():
 
 
 def enumerate_all(procs=None):
-    """{(nout, nspec): merged terms} for every PH class.  Pieces never share a
-    Hamiltonian term, so merging each piece merges the class; they are
-    joined in a fixed order, so the tables do not depend on scheduling."""
+    """{(nout, nspec): merged terms} for every PH class.  Pieces are merged
+    as they come and joined in a fixed order (the tables do not depend on
+    scheduling); the orbit representatives of one class can come from
+    several pieces, so classes with two or more spectators are merged once
+    more."""
     raw = {c: [] for c in CLASSES}
     units = _units()
     with mp.Pool(procs or min(8, os.cpu_count() or 1)) as pool:
         for i, (cls, terms) in enumerate(pool.imap(_unit, units)):
             raw[cls].extend(terms)
             print(f"piece {i + 1}/{len(units)} {units[i][:3]}: {len(terms)} terms", flush=True)
+    for cls in raw:
+        if cls[1] >= 2:
+            raw[cls] = merge_terms(raw[cls])
     return raw
 
 

@@ -178,3 +178,13 @@ def test_tables_reproduce_oracle_three_pair_outputs(tb):
     rng = np.random.default_rng(5)
     sample = set((base + rng.choice(303, 10, replace=False)).tolist())
     _check(tb, 3, 1, sample=sample)
+
+
+def test_tables_reproduce_oracle_four_pairs_sampled(tb):
+    """N = 4: one-pair outputs with up to three spectators and sampled
+    two-pair outputs with up to two spectators (the terms are stored once per
+    orbit under renamings of the spectator roles, weighted by its size)."""
+    base = 3 * 4
+    rng = np.random.default_rng(7)
+    sample = set((base + rng.choice(29 * 6, 4, replace=False)).tolist())
+    _check(tb, 4, 1, sample=sample)
