@@ -278,7 +278,7 @@ struct PhUnits {
     const long* i1;
 };
 
-__global__ __launch_bounds__(PH_BLOCK) void k_ph_part(int N, int n, PhArgs a, PhUnits u,
+__global__ __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ph_part(int N, int n, PhArgs a, PhUnits u,
                                                       const double* __restrict__ f,
                                                       const double* __restrict__ eri,
                                                       const double* __restrict__ t,
