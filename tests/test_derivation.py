@@ -90,3 +90,23 @@ def test_one_spectator_sides_fit_the_staged_form(tables):
                 kind, r0, r1 = (code >> 28) & 15, (code >> 24) & 15, (code >> 20) & 15
                 assert kind in (1, 2, 3, 4, 6, 7)
                 assert r0 in (0, 1) and r1 in (0, 1)
+
+
+def test_ph_canonical_reordering_sign():
+    """The PH tables keep terms for the canonical reordering of each output
+    pattern tuple; the kernel maps another tuple to it with a sign.  That sign
+    must equal the anticommutation sign of writing the generators in the
+    reordered label order (computed here with the derivation's own operator
+    sort), for every two- and three-pair tuple."""
+    from paper_1609_00077_amd.derive import algebra
+    from paper_1609_00077_amd.derive.ph_tables import canonical, reorder_sign
+    for size in (2, 3):
+        tuples = algebra.pattern_tuples(size)
+        for mu in tuples:
+            c, order = canonical(mu)
+            assert c == tuple(mu[i] for i in order) and c in tuples
+            seq = []
+            for i in order:
+                seq += list(algebra.pattern_gens(i, mu[i]))
+            s, _ = algebra.sort_sign(seq)
+            assert s == reorder_sign(mu, order), (mu, order)
