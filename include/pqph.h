@@ -163,7 +163,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h,
  * missing or damaged file is PQPH_INVALID_ARG.  The kernels interpret the
  * tables in balanced work units (a host schedule built once per npair), so
  * the cost grows as C(N,3) N^3 times the term count: meant for small active
- * spaces (about 0.17 s at 8 pairs, 10 s at 16, 39 s at 20).  The context's workspace
+ * spaces (about 0.16 s at 8 pairs, 10 s at 16, 37 s at 20).  The context's workspace
  * grows to hold one partial sum per (label set, work unit): at most 60000
  * units per block size, so up to 60000 C(N,3) doubles.  npair in [1, 256];
  * a workspace that cannot be allocated is PQPH_OOM. */
