@@ -120,11 +120,44 @@ def ph_leg(args, pq, torch, dev):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / nrep
+    nev = ph_term_evals(prob.npair)
     return {"workload": f"PH solve of a {args.ph_sites}-site PPP chain ({prob.npair} pairs, "
                         f"U={args.U}, seed {args.seed}) from t=0 to ||R||<={args.tol:g}",
             "solve_s": ts, "iterations": res.iterations, "energy": res.energy,
             "status": res.status, "residual_ms": ms, "residual_evals_per_s": 1e3 / ms,
-            "amplitudes": pq.amp_len(prob.npair, "ph")}
+            "amplitudes": pq.amp_len(prob.npair, "ph"),
+            "term_evals_per_residual": nev, "term_evals_per_s": nev / (ms * 1e-3)}
+
+
+def ph_term_evals(N):
+    """(term, ordered spectator tuple) evaluations of one PH residual: the
+    work the interpreted kernels do, counted from the term-table file."""
+    from math import comb, perm
+
+    import numpy as np
+
+    from paper_1609_00077_amd.derive import ph_tables
+    raw = ph_tables.read(os.path.join(ROOT, "paper_1609_00077_amd", "ph_terms.bin"))
+    a = np.frombuffer(raw, dtype="<i4")
+    nclass = int(a[2])
+    pos, classes = 8, []
+    for _ in range(nclass):
+        nout, nspec, nt, off, npat = (int(x) for x in a[pos:pos + 5])
+        classes.append((nout, nspec, a[pos + 5:pos + 6 + npat]))
+        pos += 6 + npat
+    # the canonical map sits just before the integral map at the end of the file
+    canon = a[len(a) - 3 * 1296 - 335:len(a) - 3 * 1296]
+    tot = 0
+    for n in (1, 2, 3):
+        if n > N:
+            continue
+        base = (0, 3, 32)[n - 1]
+        for m in range((3, 29, 303)[n - 1]):
+            mc = int(canon[base + m]) & 511
+            for nout, nspec, start in classes:
+                if nout == n and nspec <= N - n:
+                    tot += int(start[mc + 1] - start[mc]) * perm(N - n, nspec) * comb(N, n)
+    return tot
 
 
 def batch_leg(args, pq, torch, dev):
