@@ -89,3 +89,30 @@ def hn_on_reference(npair: int, f: np.ndarray, eri: np.ndarray) -> dict:
             if v != 0.0:
                 add(apply_string(ref, [(True, a), (True, b), (False, j), (False, i)]), 0.25 * v)
     return out
+
+
+def diagonal_one_body(det, f: np.ndarray) -> float:
+    """<det| sum_p f_pp a+_p a_p |det> for a determinant of spin orbitals."""
+    return float(sum(f[x // 2, x // 2] for x in det))
+
+
+def pair_label(spatial: int, npair: int) -> int:
+    """Pair of a spatial orbital in the mirror numbering (o_P = P, v_P = N+P)."""
+    return spatial if spatial < npair else spatial - npair
+
+
+def restricted_mp2(npair: int, k: int, f: np.ndarray, eri: np.ndarray) -> float:
+    """-sum_{i<j, a<b} |<ij||ab>|^2 / (f_aa + f_bb - f_ii - f_jj) over the
+    spin-orbital doubles whose four orbitals lie in at most k pairs."""
+    occ = [so(p, s) for p in range(npair) for s in (0, 1)]
+    vir = [so(npair + p, s) for p in range(npair) for s in (0, 1)]
+    e = 0.0
+    for i, j in itertools.combinations(occ, 2):
+        for a, b in itertools.combinations(vir, 2):
+            labels = {pair_label(x // 2, npair) for x in (i, j, a, b)}
+            if len(labels) > k:
+                continue
+            v = antisym(eri, i, j, a, b)
+            d = f[a // 2, a // 2] + f[b // 2, b // 2] - f[i // 2, i // 2] - f[j // 2, j // 2]
+            e -= v * v / d
+    return e

@@ -302,3 +302,94 @@ def test_packed_integrals_match_dense():
     # 8-fold symmetry of the site-basis transformation
     assert np.abs(eri - eri.transpose(1, 0, 2, 3)).max() < 1e-13
     assert np.abs(eri - eri.transpose(2, 3, 0, 1)).max() < 1e-13
+
+
+# ------------------------------------------------ denominators (Table IV)
+@pytest.mark.parametrize("N,k", [(2, 2), (3, 3)])
+def test_denominators_from_diagonal_fock_operator(N, k):
+    """D_mu is the change of <F_d> = sum_p f_pp <a+_p a_p> from the reference to
+    the excited determinant tau_mu|0>, found by applying the slot's operator
+    string with the separate fermion code (a wrong orbital, spin or sign in
+    the oracle's bit-pattern sum fails it).  A non-symmetric diagonal pattern
+    is used so that occupied and virtual entries cannot be confused."""
+    rng = np.random.default_rng(51 + N)
+    f = random_fock(N, seed=51)
+    f[np.diag_indices(2 * N)] = rng.uniform(-3.0, 3.0, 2 * N)
+    D = solver.denominators(f, N, k)
+    ref = fr.reference(N)
+    e0 = fr.diagonal_one_body(next(iter(ref)), f)
+    for pos, labels, tup in layout.iter_amp_slots(N, k):
+        (det, _), = fr.apply_string(ref, fr.slot_ops(N, labels, tup)).items()
+        assert abs(D[pos] - (fr.diagonal_one_body(det, f) - e0)) < 1e-13
+    # closed form for the pair double o_P(alpha beta) -> v_P(alpha beta)
+    m = layout.pattern_tuples(1).index((15,))
+    for P in range(N):
+        assert abs(D[layout.amp_slot(N, (P,), m)] - 2 * (f[N + P, N + P] - f[P, P])) < 1e-13
+    # the level shift adds to every slot
+    assert np.abs(solver.denominators(f, N, k, shift=0.25) - D - 0.25).max() < 1e-15
+
+
+# ------------------------------------------------ weak coupling (Sec. II)
+@pytest.mark.parametrize("N,k", [(3, 2), (3, 3), (4, 2)])
+def test_first_jacobi_step_gives_pair_restricted_mp2(N, k):
+    """With a diagonal f, one Jacobi step from t = 0 gives t = -<ab||ij>/D on
+    the doubles of the manifold, and its energy is the MP2 energy restricted to
+    the doubles whose orbitals lie in at most k pairs, summed here over spin
+    orbitals with the untruncated integrals."""
+    f = np.diag(np.diag(random_fock(N, seed=61 + N)))
+    B = random_bfactors(N, seed=62 + N, scale=0.2)
+    eri_full = integrals.eri_dense_from_b(B)
+    packed = integrals.eri_packed_from_b(B, N, k)
+    eri_t = layout.unpack_eri(packed, N, k)
+    ta = tier_a.TierA(N, k)
+    R0, _ = ta.residual(f, eri_t, np.zeros(layout.amp_count(N, k)))
+    t1 = -R0 / solver.denominators(f, N, k)
+    e1 = ta.energy(f, eri_t, t1)
+    emp2 = fr.restricted_mp2(N, k, f, eri_full)
+    assert emp2 < -1e-4
+    assert abs(e1 - emp2) < 1e-13 * max(1.0, abs(emp2))
+    # PQ keeps fewer doubles than PH: the restriction is really applied
+    if k == 3:
+        assert fr.restricted_mp2(N, 2, f, eri_full) > emp2 + 1e-6
+
+
+def test_weak_coupling_limit_of_solved_energy():
+    """U -> 0 on the 8-site chain: E_c / E_MP2(pair-restricted) -> 1 with an
+    error of first order in U (the third-order energy over the second)."""
+    devs = []
+    for U in (0.02, 0.01):
+        prob = chain_problem(8, U=U, seed=8)
+        f = integrals.mo_fock(prob.F_site, prob.C)
+        eri = integrals.eri_dense_zdo(prob.C, prob.V)
+        res = _solve_tier_a(4, 2, f, layout.pack_eri(eri, 4, 2))
+        emp2 = fr.restricted_mp2(4, 2, np.diag(np.diag(f)), eri)
+        devs.append(abs(res.energy / emp2 - 1.0))
+    assert devs[0] < 0.1
+    assert 1.6 < devs[0] / devs[1] < 2.4
+
+
+# ------------------------------------------------ size consistency, PH (Sec. II)
+def test_size_consistency_ph():
+    """Two non-interacting 4-site chains (2 pairs each) with fragment-local
+    pairs at k = 3: the three-pair amplitudes that span both fragments must
+    vanish and E_PH(A+B) = E(A) + E(B), each exact (FCI) for two pairs."""
+    pa = chain_problem(4, U=4.5, seed=33)
+    pb = chain_problem(4, U=2.5, seed=34)
+    fa, fb = (integrals.mo_fock(p.F_site, p.C) for p in (pa, pb))
+    ea, eb = (integrals.eri_dense_zdo(p.C, p.V) for p in (pa, pb))
+    oa = [0, 1, 4, 5]
+    ob = [2, 3, 6, 7]
+    f = np.zeros((8, 8))
+    f[np.ix_(oa, oa)] = fa
+    f[np.ix_(ob, ob)] = fb
+    eri = np.zeros((8,) * 4)
+    eri[np.ix_(oa, oa, oa, oa)] = ea
+    eri[np.ix_(ob, ob, ob, ob)] = eb
+    res = _solve_tier_a(4, 3, f, layout.pack_eri(eri, 4, 3))
+    efa = tier_a.TierA(2, 2).fci(fa, ea)[0]
+    efb = tier_a.TierA(2, 2).fci(fb, eb)[0]
+    assert abs(res.energy - efa - efb) < 1e-10
+    # amplitudes on label sets mixing the fragments vanish
+    for pos, labels, _ in layout.iter_amp_slots(4, 3):
+        if {0, 1} & set(labels) and {2, 3} & set(labels):
+            assert abs(res.t[pos]) < 1e-9
