@@ -84,7 +84,18 @@ class TierB:
         self._cache.clear()
 
     # ---------------------------------------------------------------- results
-    def residual_block(self, L, t):
+    def prefetch(self, subs, t, workers: int):
+        """Evaluate the sub-systems subs (sorted tuples) over a process pool into
+        the cache; the sums below then read them from there."""
+        todo = [Y for Y in subs if Y not in self._cache]
+        global _POOL_STATE
+        _POOL_STATE = (self, t)
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            for Y, (gmap, RY, _, E) in zip(todo, pool.imap(_sub_residual_arrays, todo, chunksize=4)):
+                self._cache[Y] = (dict(zip(gmap.tolist(), RY.tolist())), E)
+
+    def residual_block(self, L, t, workers: int = 1):
         """R for every slot whose label set is exactly L (sorted tuple).
 
         Returns {global slot: value}.
@@ -92,6 +103,9 @@ class TierB:
         L = tuple(sorted(L))
         N, k = self.N, self.k
         others = [x for x in range(N) if x not in L]
+        if workers > 1:
+            self.prefetch([tuple(sorted(L + add)) for extra in range(k + 1)
+                           for add in itertools.combinations(others, extra)], t, workers)
         slots = [layout.amp_slot(N, L, m) for m in range(len(layout.pattern_tuples(len(L))))]
         total = {s: 0 for s in slots}
         for extra in range(0, k + 1):
@@ -121,6 +135,42 @@ class TierB:
                 total += d
         return total
 
+    def mobius_weight(self, nlab: int, nsub: int) -> int:
+        """sum over X >= Y, |X| <= nlab + k, of (-1)^{|X|-|Y|} for |Y| = nsub:
+        the coefficient with which R^{(Y)} enters every output block on a
+        label set L <= Y of size nlab once the two sums above are swapped."""
+        return sum((-1) ** m * comb(self.N - nsub, m) for m in range(nlab + self.k - nsub + 1))
+
+    def residual_all(self, t, workers: int = 1):
+        """The full packed residual with every sub-system evaluated once.
+
+        Swapping the sums of residual_block gives R_mu = sum over Y >= labels(mu),
+        |Y| <= |labels(mu)| + k, of mobius_weight(|labels(mu)|, |Y|) R^{(Y)}_mu.
+        The sub-systems (all label sets of at most 2k pairs) are independent, so
+        they are spread over a process pool."""
+        N, k = self.N, self.k
+        subs = [Y for n in range(1, min(N, 2 * k) + 1) for Y in itertools.combinations(range(N), n)]
+        R = np.zeros(layout.amp_count(N, k), dtype=np.result_type(self.f, self.eri, t))
+        global _POOL_STATE
+        _POOL_STATE = (self, t)
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                parts = pool.imap(_sub_residual_arrays, subs, chunksize=16)
+                self._accumulate(R, subs, parts)
+        else:
+            self._accumulate(R, subs, map(_sub_residual_arrays, subs))
+        return R
+
+    def _accumulate(self, R, subs, parts):
+        for Y, (gmap, RY, nlab, _) in zip(subs, parts):
+            for size in range(1, self.k + 1):
+                if len(Y) - size > self.k:
+                    continue
+                w = self.mobius_weight(size, len(Y))
+                sel = nlab == size
+                np.add.at(R, gmap[sel], w * RY[sel])
+
     def residual(self, t):
         """The full packed residual (only for small N: every block is evaluated)."""
         R = np.zeros(layout.amp_count(self.N, self.k), dtype=np.result_type(self.f, self.eri, t))
@@ -129,3 +179,16 @@ class TierB:
                 for s, v in self.residual_block(L, t).items():
                     R[s] = v
         return R
+
+
+_POOL_STATE = None
+
+
+def _sub_residual_arrays(Y):
+    """(global slots, R^{(Y)} on them, label-set size of each slot, E^{(Y)}) of
+    one sub-system."""
+    tb, t = _POOL_STATE
+    f_sub, eri_sub, t_sub, gmap = tb.sub_inputs(tuple(Y), t)
+    R, E = tb.engine(len(Y)).residual(f_sub, eri_sub, t_sub)
+    nlab = np.array([len(loc) for _, loc, _ in layout.iter_amp_slots(len(Y), tb.k)])
+    return gmap, R, nlab, E

@@ -22,9 +22,19 @@ from oracle import gradient, integrals, layout, tier_b  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+WORKERS = min(8, os.cpu_count() or 1)
+
 FIXTURES = {
     # name: (sites, U, chain seed, k, amplitude seed, amplitude scale, blocks)
     "pq140_blocks": (140, 4.0, 140, 2, 1400, 0.05, [(0,), (69,), (0, 1), (17, 52)]),
+    # the same amplitudes; blocks at the ragged edges of the 16-wide pair tiles
+    # (labels 64..69) and of the last 64-row block of pair indices (2368..2414)
+    "pq140_edges": (140, 4.0, 140, 2, 1400, 0.05,
+                    [(63,), (64,), (15, 16), (63, 64), (64, 65), (68, 69), (0, 69), (3, 68),
+                     (64, 69)]),
+    # 40-site chain, three-pair model: one- and two-pair output blocks (their
+    # sub-systems have at most four and five pairs)
+    "ph40_blocks": (40, 4.0, 40, 3, 4000, 0.05, [(0,), (7,), (19,), (0, 19), (18, 19)]),
 }
 
 
@@ -41,7 +51,7 @@ def make(name):
     t0 = time.time()
     out["energy"] = tb.energy(t)
     for L in blocks:
-        vals = tb.residual_block(L, t)
+        vals = tb.residual_block(L, t, workers=WORKERS)
         out["blocks"][",".join(map(str, L))] = {str(s): v for s, v in sorted(vals.items())}
         tb.clear()
         print(name, L, f"{time.time() - t0:.1f}s", flush=True)
@@ -101,6 +111,32 @@ def make_vjp(name):
         json.dump(out, fh, indent=1)
 
 
+FULL_FIXTURES = {
+    # name: (sites, U, chain seed, amplitude seed, amplitude scale)
+    # 33 pairs: three 16-wide pair tiles with a ragged last one, and 528 pairs
+    # of labels = eight full 64-row blocks and a ragged ninth
+    "pq66_full": (66, 4.0, 66, 660, 0.05),
+}
+
+
+def make_full(name):
+    n, U, seed, aseed, scale = FULL_FIXTURES[name]
+    prob = chain_problem(n, U=U, seed=seed)
+    N = prob.npair
+    f, eri = integrals.chain_integrals(prob, 2)
+    t = random_amplitudes(N, "pq", seed=aseed, scale=scale)
+    tb = tier_b.TierB(N, 2, f, eri)
+    t0 = time.time()
+    R = tb.residual_all(t, workers=WORKERS)
+    out = {"sites": n, "U": U, "seed": seed, "amp_seed": aseed, "amp_scale": scale,
+           "citation": "R_mu = <mu|e^-T H_2 e^T|0> (Sec. II, Eq. (1)); every packed slot by "
+                       "sub-cluster inclusion-exclusion of the oracle",
+           "energy": tb.energy(t), "residual": [float(x) for x in R]}
+    print(name, f"{time.time() - t0:.1f}s", flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump(out, fh)
+
+
 PH_FIXTURES = {
     # name: (sites, U, chain seed, amplitude seed, amplitude scale)
     # 6 pairs: the first size where outputs on three pairs have three
@@ -128,8 +164,11 @@ def make_ph_full(name):
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or list(FIXTURES) + list(VJP_FIXTURES) + list(PH_FIXTURES)):
+    for nm in (sys.argv[1:] or list(FIXTURES) + list(VJP_FIXTURES) + list(PH_FIXTURES)
+               + list(FULL_FIXTURES)):
         if nm in PH_FIXTURES:
             make_ph_full(nm)
+        elif nm in FULL_FIXTURES:
+            make_full(nm)
         else:
             (make_vjp if nm in VJP_FIXTURES else make)(nm)

@@ -58,7 +58,7 @@ def test_ph_denominators_match_oracle(pq, N):
     assert np.abs(D - (solver.denominators(f, N, 3) + 0.25)).max() < 1e-13
 
 
-@pytest.mark.parametrize("N", [6, 9])
+@pytest.mark.parametrize("N", [6, 9, 20])
 def test_ph_restricted_to_two_pairs_is_pq(pq, N):
     """With three-pair amplitudes and integrals zero, the PH residual on the
     PQ slots is the PQ residual and its three-pair slots are the projection
@@ -132,3 +132,29 @@ def test_ph_residual_is_deterministic(pq):
     R1 = pq.ph_residual(_d(f), _d(eri), t)
     R2 = pq.ph_residual(_d(f), _d(eri), t)
     assert torch.equal(R1, R2)
+
+
+def test_ph_40_sites_sampled_blocks(pq):
+    """The PH configuration's chain (40 sites, 20 pairs) at seeded amplitudes:
+    one-pair output blocks (sub-systems of up to four pairs) and two-pair
+    output blocks (up to five pairs), including the last labels, and the
+    energy against the oracle's sub-cluster sums stored by
+    tests/golden/make_golden.py."""
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "ph40_blocks.json")
+    if not os.path.exists(p):
+        pytest.skip("golden fixture ph40_blocks not generated (tests/golden/make_golden.py)")
+    with open(p) as fh:
+        g = json.load(fh)
+    prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
+    N = prob.npair
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=3)
+    t = _d(random_amplitudes(N, "ph", seed=g["amp_seed"], scale=g["amp_scale"]))
+    print(f"ph_residual N={N} (40 sites)", flush=True)
+    R = pq.ph_residual(f, eri, t).cpu().numpy()
+    for key, vals in g["blocks"].items():
+        ref = np.array(list(vals.values()))
+        got = R[[int(s) for s in vals]]
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), key
+    assert abs(pq.ph_energy(f, eri, t) - g["energy"]) < 1e-10

@@ -205,3 +205,52 @@ def test_concurrent_branches_bitwise_equal_serial(pq, N):
     R2, _ = pq.pq_residual_profile(fd, ed, t)
     R3 = pq.pq_residual(fd, ed, t)
     assert torch.equal(R1, R2) and torch.equal(R1, R3)
+
+
+@pytest.mark.parametrize("s1_mode", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_every_slot_pq66(pq, variant, s1_mode):
+    """66-site chain (33 pairs): three 16-wide pair tiles with a ragged last
+    one and 528 output pairs, eight full 64-row blocks of the two-spectator
+    contraction and a ragged ninth.  Every packed slot and the energy against
+    the oracle's sub-cluster sums (stored by tests/golden/make_golden.py),
+    under every kernel choice the autotuner can make."""
+    g = _golden("pq66_full")
+    prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
+    N = prob.npair
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    t = random_amplitudes(N, "pq", seed=g["amp_seed"], scale=g["amp_scale"])
+    ref = np.array(g["residual"])
+    pq.set_variant(N, variant)
+    pq.set_s1_mode(N, s1_mode)
+    R = pq.pq_residual(f, eri, _d(t)).cpu().numpy()
+    pq.set_variant(N, 0)
+    pq.set_s1_mode(N, 0)
+    assert R.shape == ref.shape
+    err = np.abs(R - ref)
+    assert err.max() <= 1e-12 * max(1.0, np.abs(ref).max()), (err.argmax(), err.max())
+    assert abs(pq.pq_energy(f, eri, _d(t)) - g["energy"]) < 1e-10
+
+
+@pytest.mark.parametrize("s1_mode", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_full_size_pq140_edge_blocks(pq, variant, s1_mode):
+    """140-site chain: output blocks inside the ragged last 16-wide pair tile
+    (labels 64..69) and in the last, ragged 64-row block of pair indices
+    (2368..2414), against the oracle's sub-cluster sums."""
+    g = _golden("pq140_edges")
+    prob = chain_problem(g["sites"], U=g["U"], seed=g["seed"])
+    N = prob.npair
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    t = random_amplitudes(N, "pq", seed=g["amp_seed"], scale=g["amp_scale"])
+    pq.set_variant(N, variant)
+    pq.set_s1_mode(N, s1_mode)
+    R = pq.pq_residual(f, eri, _d(t)).cpu().numpy()
+    pq.set_variant(N, 0)
+    pq.set_s1_mode(N, 0)
+    assert {(68, 69), (0, 69), (64, 69)} <= {tuple(int(x) for x in k.split(",")) for k in g["blocks"]}
+    for key, vals in g["blocks"].items():
+        ref = np.array(list(vals.values()))
+        got = R[[int(s) for s in vals]]
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), key
+    assert abs(pq.pq_energy(f, eri, _d(t)) - g["energy"]) < 1e-10
