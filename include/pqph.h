@@ -140,6 +140,22 @@ pqph_status pqph_integrals(pqph_ctx* ctx, int npair, int k, const double* F,
 pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h,
                         const double* eri, const double* t, double* r);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * residual as pq_residual, computed by the same kernels serially on the
+ * context's stream, with its workspace taken from a static device array of
+ * 48 MiB that each GPU holds from library load until the process ends (its
+ * device address is looked up once per device in pqph_create).  No device
+ * memory is allocated or freed and the stream is not synchronised; no
+ * memset is issued either (every workspace value is written before it is
+ * read).  The caller passes inputs and outputs as for pq_residual.  npair in
+ * [1, 32]; a larger npair is PQPH_INVALID_ARG.  Every call on one GPU shares
+ * that GPU's array and it keeps the last call's contents: calls that overlap
+ * on one GPU (other streams, other contexts, other threads) race and must be
+ * serialised by the caller. */
+pqph_status pq_residual_noalloc(pqph_ctx* ctx, int npair, const double* h,
+                                const double* eri, const double* t, double* r);
+
 /* PQ correlation energy at amplitudes t (Eqs. (2)-(3)); energy is a host
  * pointer; the call synchronises the stream. */
 pqph_status pq_energy(pqph_ctx* ctx, int npair, const double* h,

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["pq_residual", "pq_energy", "pq_solve", "pq_solve_batched", "pq_vjp",
+__all__ = ["pq_residual", "pq_residual_noalloc", "pq_energy", "pq_solve", "pq_solve_batched", "pq_vjp",
            "pq_energy_grad", "PQEnergy", "pq_energy_autograd", "integrals", "denominators",
            "amp_len", "eri_len", "SolveResult", "GradResult", "BatchResult", "PQPHError"]
 
@@ -86,6 +86,19 @@ def pq_residual(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, out: torch.
     _check(lib, ctx, lib.pq_residual(ctx, npair, _dev(h, "h", 4 * npair * npair),
                                      _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
                                      _dev(out, "out", na)))
+    return out
+
+
+def pq_residual_noalloc(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor, out: torch.Tensor):
+    """Packed PQ residual into out with no device allocation by the library
+    (its workspace is a static per-GPU array; npair <= 32; calls on one GPU
+    must not overlap).  out must be given."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na = amp_len(npair)
+    _check(lib, ctx, lib.pq_residual_noalloc(ctx, npair, _dev(h, "h", 4 * npair * npair),
+                                             _dev(eri, "eri", eri_len(npair)), _dev(t, "t", na),
+                                             _dev(out, "out", na)))
     return out
 
 

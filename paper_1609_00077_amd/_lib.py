@@ -40,6 +40,7 @@ SIGNATURES = {
     "pqph_integrals": (C.c_int, [P, C.c_int, C.c_int, P, P, P, P, P]),
     "pq_residual": (C.c_int, [P, C.c_int, P, P, P, P]),
     "ph_residual": (C.c_int, [P, C.c_int, P, P, P, P]),
+    "pq_residual_noalloc": (C.c_int, [P, C.c_int, P, P, P, P]),
     "ph_energy": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(C.c_double)]),
     "pq_energy": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(C.c_double)]),
     "pq_solve": (C.c_int, [P, C.c_int, P, P, C.POINTER(SolveOpts), P, C.POINTER(C.c_double),

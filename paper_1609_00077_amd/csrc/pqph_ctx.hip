@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -13,6 +14,38 @@ namespace {
 thread_local std::string g_no_ctx_error;
 
 }  // namespace
+
+// ------------------------------------------- scratch of pq_residual_noalloc
+// A file-scope device array: every GPU the library runs on holds its own
+// copy from module load until the process ends.  Host code never uses the
+// array's name as an address; the device address of each GPU's copy is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and kept in g_scratch_dev.  48 MiB holds the carved residual workspace up
+// to 32 pairs.
+constexpr size_t kScratchDoubles = (size_t)6 << 20;
+constexpr int kScratchMaxPairs = 32;
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kScratchMaxDevices] = {};
+
+// Called with ctx->device current.
+static pqph_status scratch_lookup(pqph_ctx* ctx) {
+    if (ctx->device >= kScratchMaxDevices) return PQPH_OK;   // the entry point reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[ctx->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return pqph_fail(ctx, PQPH_DEVICE, std::string("scratch symbol lookup: ") +
+                                                   hipGetErrorString(e));
+        }
+        g_scratch_dev[ctx->device] = (double*)p;
+    }
+    ctx->scratch = g_scratch_dev[ctx->device];
+    return PQPH_OK;
+}
 
 // ----------------------------------------------------------------- helpers
 pqph_status pqph_fail(pqph_ctx* ctx, pqph_status st, const std::string& msg) {
@@ -176,6 +209,11 @@ pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return pqph_fail(nullptr, PQPH_DEVICE, "device setup failed");
     }
+    if (scratch_lookup(ctx) != PQPH_OK || pq_residual_prepare(ctx) != PQPH_OK) {
+        const std::string msg = ctx->err;
+        pqph_destroy(ctx);
+        return pqph_fail(nullptr, PQPH_DEVICE, msg);
+    }
     *out = ctx;
     return PQPH_OK;
 }
@@ -233,6 +271,25 @@ pqph_status pq_residual(pqph_ctx* ctx, int npair, const double* h, const double*
     st = pqph_ensure_ws(ctx, pq_ws_doubles(npair) * sizeof(double));
     if (st) return st;
     return pq_residual_graph(ctx, npair, h, eri, t, r, ctx->ws);
+}
+
+pqph_status pq_residual_noalloc(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                                const double* t, double* r) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!h || !eri || !t || !r) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    if (npair > kScratchMaxPairs || pq_ws_doubles(npair) > kScratchDoubles)
+        return pqph_fail(ctx, PQPH_INVALID_ARG,
+                         "npair above the allocation-free limit of " +
+                             std::to_string(kScratchMaxPairs) + " pairs");
+    if (!ctx->scratch)
+        return pqph_fail(ctx, PQPH_DEVICE, "no scratch array on this device");
+    if ((st = pq_residual_prepare(ctx))) return st;
+    // the same kernels as pq_residual, serially on the context's stream, with
+    // the workspace carved from this GPU's scratch array; every workspace
+    // value a kernel reads is written earlier in the same call, so nothing
+    // needs clearing between calls
+    return pq_residual_ws(ctx, ctx->stream, npair, h, eri, t, r, ctx->scratch, nullptr, 0);
 }
 
 static const char* kPhaseNames[] = {"k_vertex1",  "k_vertex2", "k_unpack_t2", "k_spec_w",
@@ -711,6 +768,5 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     }
     return result;
 }
-
 
 }  // extern "C"

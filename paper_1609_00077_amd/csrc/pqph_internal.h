@@ -54,6 +54,9 @@ struct pqph_ctx {
     int batch_mode = 0;
     // PH term tables in device memory, read from file on first PH call
     struct PhTables* ph = nullptr;
+    // device address of this GPU's static scratch array (allocation-free
+    // residual), looked up once per device at pqph_create
+    double* scratch = nullptr;
 };
 
 // PH (k = 3) path: term tables, residual, energy, denominators on stream s
