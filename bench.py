@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--counter-run", type=int, default=0,
                     help="only run this many 140-site residuals and a 256 MiB copy (for rocprofv3 --pmc)")
     ap.add_argument("--grad-sites", type=int, default=400)
+    ap.add_argument("--integrals-run", type=int, default=0,
+                    help="only run this many integral transforms at --sites (for rocprofv3)")
     return ap.parse_args()
 
 
@@ -283,6 +285,33 @@ def hbm_traffic(kernel: str):
     return 1024.0 * (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"])
 
 
+def integrals_leg(pq, torch, dev, sites, reps=10):
+    """Integral transformation into pair blocks at one chain size: HIP-event
+    time per transform on the current stream and its MFMA roofline.  Work:
+    Y = V X over every orbital pair (2 n^2 n(n+1)/2 flop) and f = C^T F C
+    (2 x 2 n^3), both on the FP64 matrix cores; the packing dots are
+    2 n per stored integral."""
+    from inputs import chain_problem
+    from paper_1609_00077_amd import workmodel
+    prob = chain_problem(sites, U=4.0, seed=sites)
+    d = lambda x: torch.as_tensor(x, device=dev).contiguous()
+    F, V, Cm = d(prob.F_site), d(prob.V), d(prob.C)
+    for _ in range(2):
+        pq.integrals(F, V, Cm, k=2)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        pq.integrals(F, V, Cm, k=2)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    fl = workmodel.integral_flops(prob.npair)
+    ach = fl / (ms * 1e-3) / 1e12
+    return {"sites": sites, "ms": ms, "flops": fl,
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": workmodel.PEAK_FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / workmodel.PEAK_FP64_VECTOR_TFLOPS}}
+
+
 def counter_run(args, pq, torch, dev):
     from inputs import chain_problem, random_amplitudes
     prob = chain_problem(args.sites, U=args.U, seed=args.seed)
@@ -323,6 +352,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.counter_run:
         return counter_run(args, pq, torch, dev)
+    if args.integrals_run:
+        print(json.dumps(integrals_leg(pq, torch, dev, args.sites, args.integrals_run)), flush=True)
+        return
     prob = chain_problem(args.sites, U=args.U, seed=args.seed)
     N = prob.npair
     F = torch.as_tensor(prob.F_site, device=dev).contiguous()

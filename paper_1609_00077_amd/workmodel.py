@@ -76,6 +76,16 @@ def pq_compulsory_bytes(N: int) -> float:
     return 8.0 * (2 * amps + eri + 4 * N * N)
 
 
+def integral_flops(N: int, k: int = 2) -> float:
+    """Integral transformation of a chain of n = 2N sites: Y over every orbital
+    pair (2 n^2 n(n+1)/2), f = C^T (F C) (2 x 2 n^3) and one dot of length n
+    per stored integral (2 n each)."""
+    n = 2 * N
+    npq = n * (n + 1) // 2
+    stored = 6 * N + 43 * comb(N, 2) + (84 * comb(N, 3) if k == 3 else 0)
+    return 2.0 * n * n * npq + 4.0 * n ** 3 + 2.0 * n * stored
+
+
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
