@@ -307,6 +307,27 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h,
                            double* dE_dh, double* dE_deri, double* lambda_out,
                            pqph_solve_info* info);
 
+/* Unrelaxed one- and two-particle densities of the PQ Lagrangian and the
+ * natural occupation numbers (Table IV caption: the densities are formed after
+ * the lambda solve; Sec. IV.B and Fig. 7 report natural occupations).  Solves
+ * (or takes) t and lambda exactly as pq_energy_grad, then
+ *     gamma[p][q] = <E_pq> = 2 delta_pq [p < npair] + dE/dh[p][q]
+ *                   (2N x 2N device, spin-summed, E_pq = sum_s p_s+ q_s; the
+ *                   first npair orbitals are occupied in the reference; not
+ *                   symmetric in general), its trace is the electron count 2N;
+ *     Gamma = dE/deri, the two-body density conjugate to each stored integral
+ *             (packed device, the integral layout);
+ *     noons (host, 2N, may be NULL) = eigenvalues of (gamma + gamma^T)/2 in
+ *             descending order, by cyclic Jacobi rotations on the host.
+ * energy: host; info (host, may be NULL) as for pq_energy_grad.  Returns the
+ * lambda solve's status; the densities are written for OK and NOT_CONVERGED.
+ * Synchronises the stream. */
+pqph_status pq_densities(pqph_ctx* ctx, int npair, const double* h,
+                         const double* eri, const double* t,
+                         const pqph_solve_opts* opts, double* energy,
+                         double* gamma, double* Gamma, double* noons,
+                         pqph_solve_info* info);
+
 /* Orbital-energy denominators of the packed slots (length pq_amp_len or
  * ph_amp_len by k): D = sum of f_aa over particles - sum of f_ii over holes
  * + shift.  Exposed for callers that run their own update. */

@@ -101,3 +101,20 @@ def directional_vjp_blocks(N: int, k: int, f, eri_packed, t, lam_blocks: dict,
         if not keep_cache:
             tb.clear()
     return float(np.imag(total) / H)
+
+
+def densities(N: int, k: int, f: np.ndarray, eri_packed: np.ndarray, t: np.ndarray):
+    """Unrelaxed response densities of the Lagrangian at converged t (Table IV
+    caption: the densities follow the lambda solve; Sec. IV.B and Fig. 7 use
+    the natural occupation numbers).
+
+    gamma_pq = <E_pq> = 2 delta_pq [p occupied] + dE_c/df_pq (f multiplies the
+    spin-summed E_pq in H; the reference part of the energy carries the
+    2 delta_pq), Gamma = dE_c/d(packed eri), and the natural occupation
+    numbers, the eigenvalues of (gamma + gamma^T)/2 in descending order.
+    Returns (gamma, Gamma, noons)."""
+    gf, ge, _ = lagrangian_gradient(N, k, f, eri_packed, t)
+    gamma = gf.copy()
+    gamma[np.arange(N), np.arange(N)] += 2.0
+    noons = np.sort(np.linalg.eigvalsh(0.5 * (gamma + gamma.T)))[::-1]
+    return gamma, ge, noons

@@ -16,7 +16,7 @@ import torch
 from . import _lib
 
 __all__ = ["pq_residual", "pq_residual_noalloc", "pq_energy", "pq_solve", "pq_solve_batched", "pq_vjp",
-           "pq_energy_grad", "PQEnergy", "pq_energy_autograd", "integrals", "denominators",
+           "pq_energy_grad", "pq_densities", "PQEnergy", "pq_energy_autograd", "integrals", "denominators",
            "amp_len", "eri_len", "SolveResult", "GradResult", "BatchResult", "PQPHError"]
 
 PQPHError = _lib.PQPHError
@@ -362,6 +362,43 @@ def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = 
         _check(lib, ctx, st)
     return GradResult(e.value, gh, ge, lam, info.iterations, info.rnorm,
                       _lib.STATUS.get(st, str(st)), info.solve_ms)
+
+
+@dataclass
+class DensityResult:
+    energy: float
+    gamma: torch.Tensor        # 2N x 2N, <E_pq>: reference occupation + dE/dh
+    Gamma: torch.Tensor        # packed integral layout, dE/d(eri)
+    noons: list                # natural occupation numbers, descending
+    iterations: int            # lambda iterations
+    rnorm: float
+    status: str
+    solve_ms: float
+
+
+def pq_densities(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
+                 tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
+                 level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+                 raise_on_failure: bool = True) -> DensityResult:
+    """Unrelaxed densities gamma, Gamma of the PQ Lagrangian and the natural
+    occupation numbers; t: converged amplitudes, or None to solve them here."""
+    npair = h.shape[0] // 2
+    lib, ctx = _ctx(h.device)
+    na, ne = amp_len(npair), eri_len(npair)
+    g1 = torch.empty_like(h)
+    g2 = torch.empty(ne, dtype=torch.float64, device=h.device)
+    noons = (C.c_double * (2 * npair))()
+    opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
+                          stall_window)
+    info = _lib.SolveInfo()
+    e = C.c_double()
+    st = lib.pq_densities(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),
+                          None if t is None else _dev(t, "t", na), C.byref(opts), C.byref(e),
+                          _dev(g1, "gamma"), _dev(g2, "Gamma"), noons, C.byref(info))
+    if st != 0 and raise_on_failure:
+        _check(lib, ctx, st)
+    return DensityResult(e.value, g1, g2, [noons[i] for i in range(2 * npair)], info.iterations,
+                         info.rnorm, _lib.STATUS.get(st, str(st)), info.solve_ms)
 
 
 class PQEnergy(torch.autograd.Function):

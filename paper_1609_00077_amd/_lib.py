@@ -59,6 +59,8 @@ SIGNATURES = {
     "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),
     "pq_energy_grad": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),
                                  P, P, P, C.POINTER(SolveInfo)]),
+    "pq_densities": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),
+                               P, P, C.POINTER(C.c_double), C.POINTER(SolveInfo)]),
     "pq_solve_batched": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64), P, P,
                                    C.POINTER(SolveOpts), P, C.POINTER(C.c_double),

@@ -531,6 +531,46 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     return PQPH_OK;
 }
 
+// Eigenvalues of the symmetric n x n matrix A (row-major, overwritten) by
+// cyclic Jacobi rotations (the symmetric Schur decomposition): each rotation
+// zeroes one off-diagonal pair; sweeps stop once the off-diagonal Frobenius
+// norm is below 1e-15 of the whole norm.  Host code for the small natural
+// occupation problem (n = 2N <= 512).
+void symmetric_eigenvalues(std::vector<double>& A, int n, std::vector<double>& w) {
+    auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+    double total = 0.0;
+    for (double x : A) total += x * x;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2.0 * at(p, q) * at(p, q);
+        if (off <= 1e-30 * total || off == 0.0) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = at(p, q);
+                if (apq == 0.0) continue;
+                // rotation angle: tan(2 theta) = 2 a_pq / (a_qq - a_pp), smaller root
+                const double tau = (at(q, q) - at(p, p)) / (2.0 * apq);
+                const double tn = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + tn * tn), sn = tn * c;
+                for (int k = 0; k < n; ++k) {      // columns p, q
+                    const double akp = at(k, p), akq = at(k, q);
+                    at(k, p) = c * akp - sn * akq;
+                    at(k, q) = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {      // rows p, q
+                    const double apk = at(p, k), aqk = at(q, k);
+                    at(p, k) = c * apk - sn * aqk;
+                    at(q, k) = sn * apk + c * aqk;
+                }
+                at(p, q) = at(q, p) = 0.0;
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = at(i, i);
+    std::sort(w.begin(), w.end(), [](double a, double b) { return a > b; });
+}
+
 pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts& o) {
     pqph_default_opts(&o);
     if (in) o = *in;
@@ -768,5 +808,35 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     }
     return result;
 }
+
+pqph_status pq_densities(pqph_ctx* ctx, int npair, const double* h, const double* eri,
+                         const double* t, const pqph_solve_opts* opts, double* energy, double* gamma,
+                         double* Gamma, double* noons, pqph_solve_info* info) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (!gamma || !Gamma) return pqph_fail(ctx, PQPH_INVALID_ARG, "null array");
+    if (npair > 256) return pqph_fail(ctx, PQPH_INVALID_ARG, "npair must be in [1, 256]");
+    const pqph_status res = pq_energy_grad(ctx, npair, h, eri, t, opts, energy, gamma, Gamma, nullptr, info);
+    if (res != PQPH_OK && res != PQPH_NOT_CONVERGED) return res;
+    launch_add_reference_occupation(ctx->stream, gamma, npair);
+    PQPH_HIP(ctx, hipGetLastError());
+    if (noons) {
+        const int n = 2 * npair;
+        if ((st = pqph_ensure_host(ctx, (size_t)n * n))) return st;
+        PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, gamma, (size_t)n * n * sizeof(double),
+                                     hipMemcpyDeviceToHost, ctx->stream));
+        PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        std::vector<double> A((size_t)n * n), w;
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q)
+                A[(size_t)p * n + q] = 0.5 * (ctx->host[(size_t)p * n + q] + ctx->host[(size_t)q * n + p]);
+        symmetric_eigenvalues(A, n, w);
+        std::copy(w.begin(), w.end(), noons);
+    } else {
+        PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return res;
+}
+
 
 }  // extern "C"

@@ -177,3 +177,5 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
                  double* eh, int m, int slot, double* part, int nblk, double* out);
 // t = sum_j c[j] th[j]
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
+// gamma (2N x 2N) += 2 on the occupied diagonal (p < npair)
+void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair);

@@ -222,3 +222,15 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t) {
     hipLaunchKernelGGL(k_combine, dim3(stream_blocks(n)), dim3(256), 0, s, th, c, m, n, t);
 }
+
+// gamma_pp += 2 for the occupied orbitals p < npair: the reference part of
+// the one-particle density (the correlation part is dE/df)
+__global__ void k_add_reference_occupation(double* __restrict__ gamma, int npair) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npair) gamma[(size_t)p * 2 * npair + p] += 2.0;
+}
+
+void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair) {
+    hipLaunchKernelGGL(k_add_reference_occupation, dim3((npair + 255) / 256), dim3(256), 0, s, gamma,
+                       npair);
+}

@@ -94,3 +94,46 @@ def test_subcluster_directional_vjp_matches_determinant_space():
     d = gradient.directional_vjp_blocks(N, k, f, eri, t, blocks, w, dt, df, de, keep_cache=True)
     an = tbar @ dt + np.sum(hbar * df) + eribar @ de
     assert abs(d - an) < 1e-10 * max(1.0, abs(an))
+
+
+def test_densities_equal_fci_density_where_the_model_is_exact():
+    """PQ is exact for two pairs, so its response density equals the FCI
+    one-particle density <Psi|E_pq|Psi> of the ground state (Hellmann-Feynman),
+    built here from the FCI eigenvector in the determinant space; the trace is
+    the electron count and the natural occupations lie in [0, 2]."""
+    from oracle.tier_a import TierA
+    N, k = 2, 2
+    f = random_fock(N, seed=131, offdiag=0.05)
+    B = random_bfactors(N, seed=132, scale=0.3)
+    eri_full = integrals.eri_dense_from_b(B)
+    eri = integrals.eri_packed_from_b(B, N, k)
+    res = _solve(N, k, f, eri)
+    gamma, Gamma, noons = gradient.densities(N, k, f, eri, res.t)
+    ta = TierA(N, k)
+    hb = ta.bare_onebody(f, eri_full)
+    ns = ta.shape[0] * ta.shape[1]
+    Hm = np.zeros((ns, ns))
+    e = np.zeros(ta.shape)
+    for i in range(ns):
+        e.flat[i] = 1.0
+        Hm[:, i] = ta.sigma(hb, eri_full, e).reshape(-1)
+        e.flat[i] = 0.0
+    w, v = np.linalg.eigh(0.5 * (Hm + Hm.T))
+    psi = v[:, 0].reshape(ta.shape)
+    n = 2 * N
+    g_fci = np.array([[np.sum(psi * ta._e(p, q, psi)) for q in range(n)] for p in range(n)])
+    assert np.abs(gamma - g_fci).max() < 1e-9
+    assert abs(np.trace(gamma) - 2 * N) < 1e-10
+    assert noons.min() > -1e-12 and noons.max() < 2 + 1e-12
+    assert abs(noons.sum() - 2 * N) < 1e-10
+
+
+def test_density_trace_and_occupations_pq_three_pairs():
+    N, k = 3, 2
+    f = random_fock(N, seed=141, offdiag=0.05)
+    eri = integrals.eri_packed_from_b(random_bfactors(N, seed=142, scale=0.2), N, k)
+    res = _solve(N, k, f, eri)
+    gamma, _, noons = gradient.densities(N, k, f, eri, res.t)
+    assert abs(np.trace(gamma) - 2 * N) < 1e-10
+    # strongly occupied and weakly occupied halves
+    assert noons[:N].min() > 1.0 > noons[N:].max()
