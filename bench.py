@@ -52,15 +52,54 @@ def parse():
     return ap.parse_args()
 
 
+def _time_subclusters(tb, t, N, seconds, rng_seed):
+    """Mean seconds per sub-cluster evaluation of each size (1..4 pairs),
+    timed over random sub-clusters for a share of `seconds`."""
+    import numpy as np
+    rng = np.random.default_rng(rng_seed)
+    per, nsamp = {}, {}
+    budget = {1: 0.05, 2: 0.1, 3: 0.25, 4: 0.6}
+    for s in (1, 2, 3, 4):
+        tb.engine(s)                       # build the template outside timing
+        n, t0 = 0, time.perf_counter()
+        while True:
+            Y = tuple(sorted(rng.choice(N, s, replace=False).tolist()))
+            tb.clear()
+            tb.sub_residual(Y, t)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget[s] * seconds or n >= 100000:
+                break
+        per[s] = el / n
+        nsamp[s] = n
+    return per, nsamp
+
+
+def _pool_worker(args):
+    from threadpoolctl import threadpool_limits
+    seconds, seed = args
+    with threadpool_limits(limits=1):
+        per, nsamp = _time_subclusters(_POOL["tb"], _POOL["t"], _POOL["N"], seconds, seed)
+    return per, nsamp
+
+
+_POOL = {}
+
+
 def cpu_baseline(prob, seconds: float):
     """The oracle as it stands (sub-cluster inclusion-exclusion over the
-    definitional determinant-space evaluation), timed on a bounded sample.
+    definitional determinant-space evaluation), timed on a bounded sample,
+    on one core and on every core of the process's affinity set.
 
-    A full residual needs every sub-cluster of at most 4 pairs once (with the
-    oracle's cache): C(N,s) evaluations of size s.  The sample times a number
-    of random sub-clusters of each size and scales by those counts.
+    A full residual needs every sub-cluster of at most 4 pairs once (the
+    oracle evaluates each once): C(N,s) evaluations of size s.  The sample
+    times random sub-clusters of each size and scales by those counts; with
+    all cores, one worker process per core times its own sample and the rate
+    is the sum of the workers' rates.
     """
-    import numpy as np
+    import multiprocessing as mp
+    import platform
+
     from threadpoolctl import threadpool_limits
 
     from inputs import random_amplitudes
@@ -70,29 +109,31 @@ def cpu_baseline(prob, seconds: float):
     f, eri = integrals.chain_integrals(prob, 2)
     t = random_amplitudes(N, "pq", seed=1400, scale=0.05)
     tb = tier_b.TierB(N, 2, f, eri)
-    rng = np.random.default_rng(0)
-    per, nsamp = {}, {}
-    budget = {1: 0.05, 2: 0.1, 3: 0.25, 4: 0.6}
     with threadpool_limits(limits=1):
-        for s in (1, 2, 3, 4):
-            tb.engine(s)                       # build the template outside timing
-            n, t0 = 0, time.perf_counter()
-            while True:
-                Y = tuple(sorted(rng.choice(N, s, replace=False).tolist()))
-                tb.clear()
-                tb.sub_residual(Y, t)
-                n += 1
-                el = time.perf_counter() - t0
-                if el >= budget[s] * seconds or n >= 100000:
-                    break
-            per[s] = el / n
-            nsamp[s] = n
+        per, nsamp = _time_subclusters(tb, t, N, seconds, 0)
     total = sum(comb(N, s) * per[s] for s in per)
-    return {"value": 1.0 / total, "unit": "residual evals/s", "cores": 1, "kind": "oracle",
-            "sample": ("timed %s random sub-clusters of 1/2/3/4 pairs of the same chain and "
-                       "amplitudes; one residual = C(70,s) sub-clusters of each size s "
-                       "(%.3g s per residual)" % ("/".join(str(nsamp[s]) for s in (1, 2, 3, 4)),
-                                                  total)),
+    cores = min(16, len(os.sched_getaffinity(0)))     # the process's CPU share
+    _POOL.update(tb=tb, t=t, N=N)
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_pool_worker, [(seconds, 1 + w) for w in range(cores)])
+    rate_all = sum(1.0 / sum(comb(N, s) * p[s] for s in p) for p, _ in res)
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": rate_all, "unit": "residual evals/s", "cores": cores, "kind": "oracle",
+            "sample": ("timed random sub-clusters of 1/2/3/4 pairs of the same chain and "
+                       "amplitudes (%s on one core); one residual = C(70,s) sub-clusters of each "
+                       "size s; all cores: %d worker processes, each timing its own sample of "
+                       "~%.0f s, rates summed" % ("/".join(str(nsamp[s]) for s in (1, 2, 3, 4)),
+                                                  cores, seconds)),
+            "single_core_value": 1.0 / total, "single_core_seconds_per_residual": total,
+            "cpu_model": model, "affinity_cores": cores,
             "seconds_per_subcluster": {str(s): per[s] for s in per}}
 
 
@@ -196,7 +237,17 @@ def batch_leg(args, pq, torch, dev):
     tb, res = out["graph"]
     tl, resl = out["lockstep"]
     ok = [i for i, s in enumerate(res.statuses) if s == "OK"]
+    from paper_1609_00077_amd import workmodel
+    fl = sum(sum(workmodel.pq_kernel_flops(p.npair).values()) * it
+             for p, it in zip(probs, res.iterations))
+    ach = fl / tb / 1e12
     return {"batched_solves_per_s": len(hs) / tb, "lockstep_solves_per_s": len(hs) / tl,
+            "batched_converged_solves_per_s": len(ok) / tb,
+            "sequential_converged_solves_per_s":
+                sum(1 for r in seq if r.status == "OK") / ts,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": workmodel.PEAK_FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / workmodel.PEAK_FP64_VECTOR_TFLOPS,
+                         "note": "residual flops of every chain's iterations over the batched wall time"},
             "sequential_solves_per_s": len(hs) / ts, "batched_speedup": ts / tb,
             "batch_size": len(hs), "batch_statuses": dict(Counter(res.statuses)),
             "sequential_statuses": dict(Counter(r.status for r in seq)),
@@ -229,7 +280,18 @@ def grad_leg(args, pq, torch, dev):
     g = pq.pq_energy_grad(f, eri, tol=args.tol)
     torch.cuda.synchronize()
     tg = time.perf_counter() - t0
+    from paper_1609_00077_amd import workmodel
+    F = sum(workmodel.pq_kernel_flops(prob.npair).values())
+    # t iterations: one residual each; lambda iterations: one transposed
+    # contraction each, counted as twice the forward flops (the reverse of a
+    # contraction forms both operand adjoints); the final VJP with the
+    # Hamiltonian adjoints likewise, plus the forward it recomputes once
+    fl = F * res.iterations + 2.0 * F * (g.iterations + 1) + F
+    ach = fl / tg / 1e12
     return {"sites": args.grad_sites, "pairs": prob.npair, "energy": res.energy,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": workmodel.PEAK_FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / workmodel.PEAK_FP64_VECTOR_TFLOPS,
+                         "note": "energy + gradient: counted residual and adjoint flops over its wall time"},
             "energy_s": te, "energy_grad_s": tg, "grad_energy_ratio": tg / te,
             "t_iterations": res.iterations, "lambda_iterations": g.iterations,
             "grad_status": g.status,
@@ -283,6 +345,25 @@ def hbm_traffic(kernel: str):
         return None
     k = c["kernels"][kernel]
     return 1024.0 * (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"])
+
+
+def densities_leg(pq, torch, dev, sites):
+    """Densities and natural occupations of the benchmark chain: one
+    pq_densities call from t = 0 (solve, lambda, densities) after a warm-up."""
+    from inputs import chain_problem
+    prob = chain_problem(sites, U=4.0, seed=sites)
+    d = lambda x: torch.as_tensor(x, device=dev).contiguous()
+    f, eri = pq.integrals(d(prob.F_site), d(prob.V), d(prob.C), k=2)
+    pq.pq_densities(f, eri, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = pq.pq_densities(f, eri, tol=1e-8)
+    torch.cuda.synchronize()
+    N = prob.npair
+    return {"sites": sites, "seconds": time.perf_counter() - t0, "status": r.status,
+            "trace_gamma": float(torch.trace(r.gamma)),
+            "noons_around_gap": [round(x, 6) for x in r.noons[N - 4:N + 4]],
+            "noon_min_max": [min(r.noons), max(r.noons)]}
 
 
 def integrals_leg(pq, torch, dev, sites, reps=10):
@@ -435,8 +516,13 @@ def main():
         "residual_compulsory_bytes": workmodel.pq_compulsory_bytes(N),
         "kernel_ms": acc,
     }
+    line["integrals"] = {str(n): integrals_leg(pq, torch, dev, n) for n in (args.sites, args.grad_sites)}
+    ceil = pq.measure_ceilings()
+    line["ceilings_measured"] = ceil
+    line["roofline"]["frac_of_measured_peak"] = achieved / ceil["fp64_mfma_TFLOPs"]
     if not args.no_grad:
         line["energy_gradient"] = grad_leg(args, pq, torch, dev)
+        line["densities"] = densities_leg(pq, torch, dev, args.sites)
     if not args.no_batch:
         line["batched"] = batch_leg(args, pq, torch, dev)
     if not args.no_ph:

@@ -247,6 +247,13 @@ pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
  * or 3). */
 pqph_status pqph_tuning(pqph_ctx* ctx, int npair, int* s2_variant, int* s1_mode);
 
+/* Diagnostic: the device's measured ceilings for roofline fractions, host
+ * out[4] = { STREAM copy GB/s, STREAM triad GB/s (1 GiB arrays, counting the
+ * bytes read and written), FP64 vector FMA TFLOP/s, FP64 matrix-core
+ * (v_mfma_f64_16x16x4f64) TFLOP/s }.  Uses 3 GiB of the context's workspace;
+ * synchronises the stream. */
+pqph_status pqph_measure_ceilings(pqph_ctx* ctx, double* out);
+
 /* Batched PQ solves (many Hamiltonians of uneven pair counts, solved
  * together; each chain runs its own Jacobi + DIIS exactly as pq_solve and
  * converges on its own).  Chain c has npair[c] pairs (host array) and reads

@@ -121,6 +121,16 @@ def pq_residual_profile(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor):
     return out, list(zip(names, [ms[i] for i in range(n.value)]))
 
 
+def measure_ceilings(device: str | torch.device = "cuda:0") -> dict:
+    """Measured HBM bandwidth (STREAM copy, triad), FP64 FMA and FP64 MFMA
+    rates of the device (diagnostic for roofline fractions)."""
+    lib, ctx = _ctx(torch.device(device))
+    out = (C.c_double * 4)()
+    _check(lib, ctx, lib.pqph_measure_ceilings(ctx, out))
+    return {"stream_copy_GBs": out[0], "stream_triad_GBs": out[1], "fp64_fma_TFLOPs": out[2],
+            "fp64_mfma_TFLOPs": out[3]}
+
+
 def autotune(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> int:
     """Pick the fastest two-spectator kernel variant for this size (kept on
     the context of the current stream); returns the variant number."""

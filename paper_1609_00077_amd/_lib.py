@@ -51,6 +51,7 @@ SIGNATURES = {
     "pq_residual_profile": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_double), C.c_int,
                                       C.POINTER(C.c_int)]),
     "pq_residual_phase_name": (C.c_char_p, [C.c_int]),
+    "pqph_measure_ceilings": (C.c_int, [P, C.POINTER(C.c_double)]),
     "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
     "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
     "pqph_set_s1_mode": (C.c_int, [P, C.c_int, C.c_int]),
