@@ -93,6 +93,13 @@ typedef struct {
     int stall_window;      /* default 40: stop (NOT_CONVERGED) once the best
                               ||R|| has not halved over this many
                               iterations; 0 = never                      */
+    int max_rank;          /* default 0 = every excitation of the model; r in
+                              1..6 keeps only the excitations of at most r
+                              holes (Sec. V: PH restricted to singles and
+                              doubles, r = 2, or up to quadruples, r = 4):
+                              the others have t = 0 and their residuals are
+                              not solved for (left out of the norm and DIIS).
+                              Not supported by pq_solve_batched.          */
 } pqph_solve_opts;
 
 /* Per-solve report (host struct). */
@@ -268,7 +275,8 @@ pqph_status pqph_measure_ceilings(pqph_ctx* ctx, double* out);
  * 4.3 KB of solver state per chain.  By default the iterations run entirely
  * on the device: one iteration of the whole batch is captured into a HIP graph
  * and replayed, and the host only polls the chains' finished flags every few
- * replays (opts->stall_window must be below 257 here).  The t_inout values are
+ * replays (opts->stall_window must be below 257 here; opts->max_rank must
+ * be 0).  The t_inout values are
  * the starting amplitudes; iterates of converged chains stop changing.
  * Enqueued on the context's stream order (internal streams wait for it, and
  * it waits for them); the call returns after the results are on the host. */

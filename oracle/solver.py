@@ -6,6 +6,10 @@ sum of f_ii over its holes (optionally plus a level shift); DIIS (Pulay)
 extrapolates the amplitudes from the last m iterates with error vectors
 Delta t = -R/D, starting once two iterates exist.  The iteration stops when
 the 2-norm of R over the packed (unique) amplitudes is at most tol.
+
+An excitation-rank limit (Sec. V: PH with only singles and doubles, or up to
+quadruples) keeps t = 0 on the excitations of more than max_rank holes and
+solves R = 0 on the others only.
 """
 from __future__ import annotations
 
@@ -33,6 +37,14 @@ def denominators(f: np.ndarray, npair: int, k: int, shift: float = 0.0) -> np.nd
     return D
 
 
+def slot_ranks(npair: int, k: int) -> np.ndarray:
+    """Number of holes (occupied spin orbitals removed) of every packed slot."""
+    rk = np.zeros(layout.amp_count(npair, k), dtype=np.int64)
+    for pos, _, tup in layout.iter_amp_slots(npair, k):
+        rk[pos] = sum(bin(e & 3).count("1") for e in tup)
+    return rk
+
+
 @dataclass
 class SolveResult:
     t: np.ndarray
@@ -45,12 +57,17 @@ class SolveResult:
 
 def solve(residual_fn, energy_fn, D: np.ndarray, t0: np.ndarray | None = None,
           tol: float = 1e-10, max_iter: int = 200, diis_dim: int = 8,
-          diis_start: int = 2) -> SolveResult:
-    """residual_fn(t) -> R; energy_fn(t) -> E_c."""
+          diis_start: int = 2, keep: np.ndarray | None = None) -> SolveResult:
+    """residual_fn(t) -> R; energy_fn(t) -> E_c.  keep (boolean per slot, or
+    None for all): the slots that are solved for; the others stay zero."""
     t = np.zeros_like(D) if t0 is None else t0.copy()
+    if keep is not None:
+        t[~keep] = 0.0
     ts, es, hist = [], [], []
     for it in range(1, max_iter + 1):
         R = residual_fn(t)
+        if keep is not None:
+            R = np.where(keep, R, 0.0)
         rn = float(np.linalg.norm(R))
         hist.append(rn)
         if not np.isfinite(rn):
@@ -79,4 +96,6 @@ def solve(residual_fn, energy_fn, D: np.ndarray, t0: np.ndarray | None = None,
                 pass
         t = tn
     R = residual_fn(t)
+    if keep is not None:
+        R = np.where(keep, R, 0.0)
     return SolveResult(t, energy_fn(t), float(np.linalg.norm(R)), max_iter, False, hist)

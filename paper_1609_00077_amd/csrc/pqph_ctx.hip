@@ -193,6 +193,7 @@ void pqph_default_opts(pqph_solve_opts* o) {
     o->level_shift = 0.0;
     o->diverge_factor = 1e4;
     o->stall_window = 40;
+    o->max_rank = 0;
 }
 
 pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
@@ -438,7 +439,8 @@ size_t driver_doubles(size_t n, int m) {
 pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
                         const pqph_solve_opts& o,
                         const std::function<pqph_status(const double*, double*)>& resid,
-                        double* bufs, int& iters, double& rn, pqph_status& result) {
+                        double* bufs, int& iters, double& rn, pqph_status& result,
+                        const double* rank = nullptr) {
     const int m = std::max(o.diis_dim, 1);
     const int nblk = stream_blocks(n);
     double* r = bufs;
@@ -463,9 +465,13 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     // to the device from their own pinned slot (hst + 32), which the host
     // rewrites only after the next synchronisation.
     const bool diis = o.diis_dim > 0;
+    // excitations above max_rank: t stays zero, their residuals are not solved for
+    const bool masked = rank != nullptr && o.max_rank > 0;
+    if (masked) launch_rank_mask(s, x, rank, o.max_rank, n);
     for (it = 1; it <= o.max_iter; ++it) {
         pqph_status st = resid(x, r);
         if (st) return st;
+        if (masked) launch_rank_mask(s, r, rank, o.max_rank, n);
         const bool step = it < o.max_iter;
         const int slot = next;
         if (step && diis) {      // norm, step and Gram row in one pass, into the history slot
@@ -571,11 +577,26 @@ void symmetric_eigenvalues(std::vector<double>& A, int n, std::vector<double>& w
     std::sort(w.begin(), w.end(), [](double a, double b) { return a > b; });
 }
 
+// Excitation rank (number of holes) of every packed slot, through the
+// denominator kernels with f = diag(-1 occupied, 0 virtual); fs holds 4N^2
+// doubles of scratch.  Only when o.max_rank truncates the manifold.
+pqph_status slot_ranks(pqph_ctx* ctx, const pqph_solve_opts& o, int npair, int k, double* fs,
+                       double* rank, const double*& out) {
+    out = nullptr;
+    if (o.max_rank <= 0) return PQPH_OK;
+    launch_rank_fock(ctx->stream, fs, npair);
+    pqph_status st = k == 3 ? ph_denominators_dev(ctx, ctx->stream, npair, fs, 0.0, rank)
+                            : pq_denominators_dev(ctx, ctx->stream, npair, fs, 0.0, rank);
+    if (st) return st;
+    out = rank;
+    return PQPH_OK;
+}
+
 pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts& o) {
     pqph_default_opts(&o);
     if (in) o = *in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0) || o.stall_window < 0)
+        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.max_rank < 0 || o.max_rank > 6)
         return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
     return PQPH_OK;
 }
@@ -603,23 +624,26 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     if ((st = read_opts(ctx, opts_in, o))) return st;
     const size_t n = pq_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
-    if ((st = pqph_ensure_sv(ctx, (n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
+    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
     double* D = ctx->sv;
-    double* bufs = D + n;
+    double* bufs = D + nr;
+    const double* rank = nullptr;
     hipStream_t s = ctx->stream;
     PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
     if ((st = pq_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
     if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    if ((st = slot_ranks(ctx, o, npair, 2, D + 2 * n, D + n, rank))) return st;
     int iters = 0;
     double rn = 0.0;
     pqph_status result = PQPH_OK;
     auto resid = [&](const double* x, double* r) {
         return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
+    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -678,25 +702,28 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     if ((st = ph_tables_load(ctx))) return st;
     const size_t n = ph_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
-    if ((st = pqph_ensure_sv(ctx, (n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
+    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
     const size_t wsd = ph_energy_ws_doubles();
     size_t rwsd = 0;      // the residual's partial sums share the workspace (same stream)
     if ((st = ph_residual_ws_doubles(ctx, npair, &rwsd))) return st;
     if ((st = pqph_ensure_ws(ctx, (std::max(wsd, rwsd) + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
     double* D = ctx->sv;
-    double* bufs = D + n;
+    double* bufs = D + nr;
+    const double* rank = nullptr;
     hipStream_t s = ctx->stream;
     PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
     if ((st = ph_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
     if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    if ((st = slot_ranks(ctx, o, npair, 3, D + 2 * n, D + n, rank))) return st;
     int iters = 0;
     double rn = 0.0;
     pqph_status result = PQPH_OK;
     auto resid = [&](const double* x, double* r) {
         return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result))) return st;
+    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = ph_energy_dev(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -744,8 +771,10 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     if ((st = read_opts(ctx, opts_in, o))) return st;
     const size_t n = pq_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
-    // solver memory: D, t (when solved here), lambda, tbar scratch, driver buffers
-    if ((st = pqph_ensure_sv(ctx, (4 * n + driver_doubles(n, m)) * sizeof(double)))) return st;
+    // solver memory: D, t (when solved here), lambda, tbar scratch, ranks, the
+    // rank Fock matrix, driver buffers
+    const size_t nr = 5 * n + 4 * (size_t)npair * npair;
+    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair), ad = pq_adj_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + ad + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
@@ -753,12 +782,15 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     double* tl = D + n;
     double* lam = tl + n;
     double* tbar = lam + n;
-    double* bufs = tbar + n;
+    double* rankv = tbar + n;
+    double* bufs = D + nr;
+    const double* rank = nullptr;
     double* aws = ctx->ws + wsd;
     hipStream_t s = ctx->stream;
     PQPH_HIP(ctx, hipEventRecord(ctx->ev0, s));
     if ((st = pq_denominators_dev(ctx, s, npair, h, o.level_shift, D))) return st;
     if ((st = check_denominators(ctx, D, n, bufs))) return st;
+    if ((st = slot_ranks(ctx, o, npair, 2, rankv + n, rankv, rank))) return st;
     int iters = 0;
     double rn = 0.0;
     pqph_status result = PQPH_OK;
@@ -768,7 +800,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
         auto resid = [&](const double* x, double* r) {
             return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
         };
-        if ((st = jacobi_diis(ctx, n, D, tl, o, resid, bufs, iters, rn, result))) return st;
+        if ((st = jacobi_diis(ctx, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
         if (result != PQPH_OK) return result;
         t = tl;
     }
@@ -791,7 +823,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
         fwd_ready = fwd_ready || e == PQPH_OK;
         return e;
     };
-    if ((st = jacobi_diis(ctx, n, D, lam, o, lres, bufs, iters, rn, result))) return st;
+    if ((st = jacobi_diis(ctx, n, D, lam, o, lres, bufs, iters, rn, result, rank))) return st;
     if ((st = pq_vjp_ws(ctx, s, npair, h, eri, t, lam, 1.0, tbar, dE_dh, dE_deri, ctx->ws, aws, fwd_ready)))
         return st;
     if (lambda_out)

@@ -177,5 +177,9 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
                  double* eh, int m, int slot, double* part, int nblk, double* out);
 // t = sum_j c[j] th[j]
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
+// f = diag(-1 occupied, 0 virtual): through the denominator kernels, the slot ranks
+void launch_rank_fock(hipStream_t s, double* f, int npair);
+// r[i] = 0 where rank[i] > max_rank
+void launch_rank_mask(hipStream_t s, double* r, const double* rank, int max_rank, size_t n);
 // gamma (2N x 2N) += 2 on the occupied diagonal (p < npair)
 void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair);

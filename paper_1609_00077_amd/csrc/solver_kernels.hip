@@ -234,3 +234,30 @@ void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair) {
     hipLaunchKernelGGL(k_add_reference_occupation, dim3((npair + 255) / 256), dim3(256), 0, s, gamma,
                        npair);
 }
+
+// f = diag(-1 on the occupied orbitals p < npair, 0 elsewhere): with it the
+// denominator kernels give D = (number of holes) = the excitation rank
+__global__ void k_rank_fock(double* __restrict__ f, int npair) {
+    const long n = 2L * npair;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    const long p = i / n, q = i % n;
+    f[i] = (p == q && p < npair) ? -1.0 : 0.0;
+}
+
+// r[s] = 0 where rank[s] > max_rank (excitations outside the kept ranks)
+__global__ void k_rank_mask(double* __restrict__ r, const double* __restrict__ rank, int max_rank,
+                            size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (rank[i] > max_rank + 0.5) r[i] = 0.0;
+}
+
+void launch_rank_fock(hipStream_t s, double* f, int npair) {
+    const long n2 = 4L * npair * npair;
+    hipLaunchKernelGGL(k_rank_fock, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, f, npair);
+}
+
+void launch_rank_mask(hipStream_t s, double* r, const double* rank, int max_rank, size_t n) {
+    const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_rank_mask, dim3(g), dim3(256), 0, s, r, rank, max_rank, n);
+}

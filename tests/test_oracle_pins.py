@@ -411,3 +411,67 @@ def test_size_consistency_ph():
     for pos, labels, _ in layout.iter_amp_slots(4, 3):
         if {0, 1} & set(labels) and {2, 3} & set(labels):
             assert abs(res.t[pos]) < 1e-9
+
+
+# ------------------------------------------------ excitation-rank limits (Sec. V)
+def test_rank_limit_counts():
+    rk = solver.slot_ranks(3, 3)
+    assert rk.max() == 6 and rk.min() == 1
+    # per pair: 2 singles (o -> v alpha, beta) and 1 double; per pair of pairs
+    # 4 singles, 16 doubles, 8 triples, 1 quadruple (Table II's rank columns)
+    r2 = solver.slot_ranks(2, 2)
+    assert np.bincount(r2).tolist() == [0, 2 * 2 + 4, 2 + 16, 8, 1]
+
+
+def test_rank_two_is_exact_for_two_electron_fragments():
+    """Two non-interacting 2-site chains (one pair, two electrons each):
+    coupled cluster with singles and doubles only is exact for two
+    electrons and size-extensive, so the rank-2 limit of PQ on the union is
+    FCI(A) + FCI(B), while rank 1 is not."""
+    pa = chain_problem(2, U=4.0, seed=35)
+    pb = chain_problem(2, U=2.5, seed=36)
+    fa, fb = (integrals.mo_fock(p.F_site, p.C) for p in (pa, pb))
+    ea, eb = (integrals.eri_dense_zdo(p.C, p.V) for p in (pa, pb))
+    oa, ob = [0, 2], [1, 3]
+    f = np.zeros((4, 4))
+    f[np.ix_(oa, oa)] = fa
+    f[np.ix_(ob, ob)] = fb
+    eri = np.zeros((4,) * 4)
+    eri[np.ix_(oa, oa, oa, oa)] = ea
+    eri[np.ix_(ob, ob, ob, ob)] = eb
+    N, k = 2, 2
+    packed = layout.pack_eri(eri, N, k)
+    ta = tier_a.TierA(N, k)
+    et = layout.unpack_eri(packed, N, k)
+    D = solver.denominators(f, N, k)
+    rk = solver.slot_ranks(N, k)
+    exact = tier_a.TierA(1, 1).fci(fa, ea)[0] + tier_a.TierA(1, 1).fci(fb, eb)[0]
+    res = solver.solve(lambda t: ta.residual(f, et, t)[0], lambda t: ta.energy(f, et, t), D,
+                       tol=1e-12, max_iter=300, keep=rk <= 2)
+    assert res.converged and abs(res.energy - exact) < 1e-10
+    assert np.abs(res.t[rk > 2]).max() == 0.0
+    r1 = solver.solve(lambda t: ta.residual(f, et, t)[0], lambda t: ta.energy(f, et, t), D,
+                      tol=1e-12, max_iter=300, keep=rk <= 1)
+    assert abs(r1.energy - exact) > 1e-4
+
+
+def test_rank_limit_changes_ph_energy():
+    """PH restricted to doubles (local CCSD on three-pair clusters) differs
+    from PH-SDTQ and the full PH; SDTQ on three pairs misses only the rank-5
+    and rank-6 excitations, so it lies closest to PH."""
+    prob = chain_problem(6, U=4.0, seed=6)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = layout.pack_eri(integrals.eri_dense_zdo(prob.C, prob.V), 3, 3)
+    N, k = 3, 3
+    ta = tier_a.TierA(N, k)
+    et = layout.unpack_eri(eri, N, k)
+    D = solver.denominators(f, N, k)
+    rk = solver.slot_ranks(N, k)
+    e = {}
+    for r in (2, 4, 6):
+        res = solver.solve(lambda t: ta.residual(f, et, t)[0], lambda t: ta.energy(f, et, t), D,
+                           tol=1e-11, max_iter=300, keep=rk <= r)
+        assert res.converged
+        e[r] = res.energy
+    assert abs(e[6] - e[4]) < abs(e[6] - e[2])
+    assert abs(e[4] - e[2]) > 1e-5
