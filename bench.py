@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-ph", action="store_true", help="skip the PH (three-pair) leg")
     ap.add_argument("--ph-sites", type=int, default=10, help="sites of the PH leg's chain")
+    ap.add_argument("--ph-reps", type=int, default=5, help="back-to-back PH residuals timed")
+    ap.add_argument("--ph-only", action="store_true", help="run only the PH leg")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--counter-run", type=int, default=0,
@@ -142,12 +144,12 @@ def ph_leg(args, pq, torch, dev):
     transform included) and back-to-back residuals at the converged
     amplitudes, timed with HIP events on the library's stream."""
     from inputs import chain_problem
-    prob = chain_problem(args.ph_sites, U=args.U, seed=args.seed)
+    prob = chain_problem(args.ph_sites, U=args.U, seed=args.ph_sites)
     d = lambda x: torch.as_tensor(x, device=dev).contiguous()
     F, V, Cm = d(prob.F_site), d(prob.V), d(prob.C)
-    f, eri = pq.integrals(F, V, Cm, k=3)
-    pq.ph_residual(f, eri, torch.zeros(pq.amp_len(prob.npair, "ph"), dtype=torch.float64,
-                                       device=dev))          # loads the term tables
+    small = chain_problem(6, U=args.U, seed=6)                  # loads the term tables
+    fs, es = pq.integrals(d(small.F_site), d(small.V), d(small.C), k=3)
+    pq.ph_residual(fs, es, torch.zeros(pq.amp_len(3, "ph"), dtype=torch.float64, device=dev))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     f, eri = pq.integrals(F, V, Cm, k=3)
@@ -156,7 +158,7 @@ def ph_leg(args, pq, torch, dev):
     ts = time.perf_counter() - t0
     r = torch.empty_like(res.t)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    nrep = 5
+    nrep = args.ph_reps
     ev0.record()
     for _ in range(nrep):
         pq.ph_residual(f, eri, res.t, out=r)
@@ -165,7 +167,7 @@ def ph_leg(args, pq, torch, dev):
     ms = ev0.elapsed_time(ev1) / nrep
     nev = ph_term_evals(prob.npair)
     return {"workload": f"PH solve of a {args.ph_sites}-site PPP chain ({prob.npair} pairs, "
-                        f"U={args.U}, seed {args.seed}) from t=0 to ||R||<={args.tol:g}",
+                        f"U={args.U}, seed {args.ph_sites}) from t=0 to ||R||<={args.tol:g}",
             "solve_s": ts, "iterations": res.iterations, "energy": res.energy,
             "status": res.status, "residual_ms": ms, "residual_evals_per_s": 1e3 / ms,
             "amplitudes": pq.amp_len(prob.npair, "ph"),
@@ -435,6 +437,9 @@ def main():
         return counter_run(args, pq, torch, dev)
     if args.integrals_run:
         print(json.dumps(integrals_leg(pq, torch, dev, args.sites, args.integrals_run)), flush=True)
+        return
+    if args.ph_only:
+        print(json.dumps({"ph": ph_leg(args, pq, torch, dev)}), flush=True)
         return
     prob = chain_problem(args.sites, U=args.U, seed=args.seed)
     N = prob.npair

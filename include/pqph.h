@@ -82,7 +82,10 @@ typedef struct pqph_ctx pqph_ctx;
  * application), accelerated by DIIS (Sec. III) on the last diis_dim iterates
  * once iteration diis_start is reached (0 disables DIIS).  Convergence: 2-norm
  * of r over the packed unique slots <= tol.  Divergence: the norm exceeds
- * diverge_factor times the smallest norm seen, or 1e3 in absolute value. */
+ * diverge_factor times the smallest norm seen, or 1e3 in absolute value.
+ * With the environment variable PQPH_VERBOSE set to a nonzero value, every
+ * solve prints one line per iteration (residual norm, elapsed time) to
+ * stderr. */
 typedef struct {
     int max_iter;          /* default 200                                */
     double tol;            /* default 1e-8                               */
@@ -100,6 +103,18 @@ typedef struct {
                               the others have t = 0 and their residuals are
                               not solved for (left out of the norm and DIIS).
                               Not supported by pq_solve_batched.          */
+    int solver;            /* default 0 = Jacobi/DIIS as above; 1 = inexact
+                              Newton-Krylov (GMRES on J dx = -R,
+                              preconditioned by D, J v by central
+                              differences of R, backtracking on ||R||)
+                              from t_inout; 2 = Jacobi/DIIS, then
+                              Newton-Krylov from its iterate of smallest
+                              ||R|| when it stalls, diverges or reaches
+                              max_iter (Sec. IV.B: the iterations fail at
+                              strong correlation).  The iteration count
+                              reported is then residual evaluations.  In
+                              pq_energy_grad it applies to the amplitude
+                              solve; lambda uses Jacobi/DIIS.              */
 } pqph_solve_opts;
 
 /* Per-solve report (host struct). */
@@ -276,7 +291,10 @@ pqph_status pqph_measure_ceilings(pqph_ctx* ctx, double* out);
  * on the device: one iteration of the whole batch is captured into a HIP graph
  * and replayed, and the host only polls the chains' finished flags every few
  * replays (opts->stall_window must be below 257 here; opts->max_rank must
- * be 0).  The t_inout values are
+ * be 0).  With opts->solver = 2, every chain that ends NOT_CONVERGED or
+ * DIVERGED is solved again afterwards, alone, by pq_solve with solver 2 from
+ * zero amplitudes (its energy, report and amplitudes replaced); solver 1 is
+ * not accepted here.  The t_inout values are
  * the starting amplitudes; iterates of converged chains stop changing.
  * Enqueued on the context's stream order (internal streams wait for it, and
  * it waits for them); the call returns after the results are on the host. */

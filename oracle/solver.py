@@ -99,3 +99,31 @@ def solve(residual_fn, energy_fn, D: np.ndarray, t0: np.ndarray | None = None,
     if keep is not None:
         R = np.where(keep, R, 0.0)
     return SolveResult(t, energy_fn(t), float(np.linalg.norm(R)), max_iter, False, hist)
+
+
+def newton(residual_fn, jacobian_fn, energy_fn, t0: np.ndarray, tol: float = 1e-10,
+           max_steps: int = 50) -> SolveResult:
+    """Newton's method on R(t) = 0 with the dense Jacobian J = dR/dt (small
+    systems), backtracking the step until ||R|| decreases.  The same fixed
+    point as the Jacobi/DIIS iteration, reached where that iteration stalls or
+    diverges (Sec. IV.B)."""
+    t = t0.copy()
+    hist = []
+    for it in range(1, max_steps + 1):
+        R = residual_fn(t)
+        rn = float(np.linalg.norm(R))
+        hist.append(rn)
+        if not np.isfinite(rn):
+            return SolveResult(t, float("nan"), rn, it, False, hist)
+        if rn <= tol:
+            return SolveResult(t, energy_fn(t), rn, it, True, hist)
+        dt = np.linalg.solve(jacobian_fn(t), -R)
+        lam = 1.0
+        while lam > 1e-4:
+            tn = t + lam * dt
+            if np.linalg.norm(residual_fn(tn)) < (1.0 - 1e-4 * lam) * rn:
+                break
+            lam *= 0.5
+        t = tn
+    R = residual_fn(t)
+    return SolveResult(t, energy_fn(t), float(np.linalg.norm(R)), max_steps, False, hist)

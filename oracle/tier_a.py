@@ -130,6 +130,17 @@ class TierA:
         e = chi[self.ref, self.ref]
         return R, (e if np.iscomplexobj(e) else float(e))
 
+    def jacobian(self, f, eri_trunc, t, h: float = 1e-30) -> np.ndarray:
+        """J = dR/dt by complex-step derivatives (exact to rounding: R is a
+        polynomial in t)."""
+        fc, ec = f.astype(complex), eri_trunc.astype(complex)
+        J = np.zeros((len(t), len(t)))
+        for j in range(len(t)):
+            tc = t.astype(complex)
+            tc[j] += 1j * h
+            J[:, j] = self.residual(fc, ec, tc)[0].imag / h
+        return J
+
     def energy(self, f, eri_trunc, t) -> float:
         """E_c = <0| (H_k - E_ref) e^T |0>."""
         hb = self.bare_onebody(f, eri_trunc)

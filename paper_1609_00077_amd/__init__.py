@@ -202,7 +202,8 @@ class BatchResult:
 
 def pq_solve_batched(hs, eris, *, tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8,
                      diis_start: int = 2, level_shift: float = 0.0,
-                     diverge_factor: float = 1e4, stall_window: int = 40, max_rank: int = 0,
+                     diverge_factor: float = 1e4, stall_window: int = 40,
+                     max_rank: int = 0, solver: int = 0,
                      mode: str = "graph") -> BatchResult:
     """Solve many PQ problems together.  hs, eris: lists of per-chain Fock
     matrices and packed integrals (device tensors), packed here into one
@@ -226,7 +227,7 @@ def pq_solve_batched(hs, eris, *, tol: float = 1e-8, max_iter: int = 200, diis_d
         a += h.numel(); b += e.numel(); c += amp_len(n)
     t = torch.zeros(c, dtype=torch.float64, device=dev)
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank)
+                          stall_window, max_rank, solver)
     infos = (_lib.SolveInfo * nb)()
     en = (C.c_double * nb)()
     st = lib.pq_solve_batched(ctx, nb, (C.c_int * nb)(*npairs), (C.c_int64 * nb)(*h_off),
@@ -253,14 +254,15 @@ class SolveResult:
 
 def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
              tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40, max_rank: int = 0,
+             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+             max_rank: int = 0, solver: int = 0,
              raise_on_failure: bool = True) -> SolveResult:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)
     na = amp_len(npair)
     t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank)
+                          stall_window, max_rank, solver)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_solve(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", eri_len(npair)),
@@ -296,14 +298,15 @@ def ph_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
 
 def ph_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
              tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40, max_rank: int = 0,
+             level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+             max_rank: int = 0, solver: int = 0,
              raise_on_failure: bool = True) -> SolveResult:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)
     na = amp_len(npair, "ph")
     t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank)
+                          stall_window, max_rank, solver)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.ph_solve(ctx, npair, _dev(h, "h", 4 * npair * npair),
@@ -350,7 +353,8 @@ class GradResult:
 
 def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
                    tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-                   level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40, max_rank: int = 0,
+                   level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+                   max_rank: int = 0, solver: int = 0,
                    raise_on_failure: bool = True) -> GradResult:
     """PQ correlation energy and dE/dh, dE/d(packed eri) through the lambda
     equations; t: converged amplitudes, or None to solve them here."""
@@ -361,7 +365,7 @@ def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = 
     ge = torch.empty(ne, dtype=torch.float64, device=h.device)
     lam = torch.empty(na, dtype=torch.float64, device=h.device)
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank)
+                          stall_window, max_rank, solver)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_energy_grad(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),
@@ -388,7 +392,8 @@ class DensityResult:
 
 def pq_densities(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
                  tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
-                 level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40, max_rank: int = 0,
+                 level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
+                 max_rank: int = 0, solver: int = 0,
                  raise_on_failure: bool = True) -> DensityResult:
     """Unrelaxed densities gamma, Gamma of the PQ Lagrangian and the natural
     occupation numbers; t: converged amplitudes, or None to solve them here."""
@@ -399,7 +404,7 @@ def pq_densities(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = No
     g2 = torch.empty(ne, dtype=torch.float64, device=h.device)
     noons = (C.c_double * (2 * npair))()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank)
+                          stall_window, max_rank, solver)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_densities(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),

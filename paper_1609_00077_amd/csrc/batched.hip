@@ -518,9 +518,10 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     pqph_default_opts(&o);
     if (opts_in) o = *opts_in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kRing || o.max_rank != 0)
+        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kRing || o.max_rank != 0 ||
+        (o.solver != 0 && o.solver != 2))
         return pqph_fail(ctx, PQPH_INVALID_ARG,
-                         "invalid solver options (batched: stall_window < 257, max_rank 0)");
+                         "invalid solver options (batched: stall_window < 257, max_rank 0, solver 0 or 2)");
     PQPH_HIP(ctx, hipSetDevice(ctx->device));
     const int m = b.m = std::max(o.diis_dim, 1);
     const int ns = b.ns = std::min(kMaxStreams, nbatch);
@@ -630,10 +631,32 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    std::vector<double> en(hst, hst + nbatch);
+    // solver 2: chains the batched Jacobi/DIIS left unconverged are solved
+    // again alone (Jacobi/DIIS, then Newton-Krylov from its best iterate); the
+    // batch's device state is no longer needed, so pq_solve may reuse it
+    if (o.solver == 2) {
+        pqph_solve_opts o2 = o;
+        for (int c = 0; c < nbatch; ++c) {
+            if (ch[c].st != PQPH_NOT_CONVERGED && ch[c].st != PQPH_DIVERGED) continue;
+            Chain& x = ch[c];
+            PQPH_HIP(ctx, hipMemsetAsync(x.t, 0, x.n * sizeof(double), ctx->stream));
+            pqph_solve_info inf{};
+            double e = 0.0;
+            const pqph_status sc = pq_solve(ctx, x.N, x.h, x.eri, &o2, x.t, &e, &inf);
+            if (sc != PQPH_OK && sc != PQPH_NOT_CONVERGED && sc != PQPH_DIVERGED && sc != PQPH_NONFINITE)
+                return sc;
+            x.st = sc;
+            x.iters += inf.iterations;
+            x.rn = inf.rnorm;
+            en[c] = e;
+            ms += (float)inf.solve_ms;      // pq_solve times itself on the context stream
+        }
+    }
     pqph_status worst = PQPH_OK;
     for (int c = 0; c < nbatch; ++c) {
-        energies[c] = hst[c];
-        if (ch[c].st == PQPH_OK && !std::isfinite(hst[c])) ch[c].st = PQPH_NONFINITE;
+        energies[c] = en[c];
+        if (ch[c].st == PQPH_OK && !std::isfinite(en[c])) ch[c].st = PQPH_NONFINITE;
         if (infos) {
             infos[c].iterations = ch[c].iters;
             infos[c].rnorm = ch[c].rn;

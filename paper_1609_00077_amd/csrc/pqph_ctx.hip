@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -194,6 +196,7 @@ void pqph_default_opts(pqph_solve_opts* o) {
     o->diverge_factor = 1e4;
     o->stall_window = 40;
     o->max_rank = 0;
+    o->solver = 0;
 }
 
 pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
@@ -440,7 +443,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
                         const pqph_solve_opts& o,
                         const std::function<pqph_status(const double*, double*)>& resid,
                         double* bufs, int& iters, double& rn, pqph_status& result,
-                        const double* rank = nullptr) {
+                        const double* rank = nullptr, double* best = nullptr) {
     const int m = std::max(o.diis_dim, 1);
     const int nblk = stream_blocks(n);
     double* r = bufs;
@@ -455,7 +458,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     std::vector<double> B(16 * 16, 0.0), c;
     int stored = 0, next = 0, it = 0;
     double rmin = INFINITY;
-    std::vector<double> best;      // best[i]: smallest norm up to iteration i + 1
+    std::vector<double> hist_min;  // hist_min[i]: smallest norm up to iteration i + 1
     rn = INFINITY;
     result = PQPH_NOT_CONVERGED;
     // One host synchronisation per iteration: the Jacobi step, the history
@@ -465,6 +468,10 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     // to the device from their own pinned slot (hst + 32), which the host
     // rewrites only after the next synchronisation.
     const bool diis = o.diis_dim > 0;
+    // PQPH_VERBOSE=1: one line per iteration on stderr (long solves report progress)
+    const char* venv = getenv("PQPH_VERBOSE");
+    const bool verbose = venv && venv[0] && venv[0] != '0';
+    const auto t_start = std::chrono::steady_clock::now();
     // excitations above max_rank: t stays zero, their residuals are not solved for
     const bool masked = rank != nullptr && o.max_rank > 0;
     if (masked) launch_rank_mask(s, x, rank, o.max_rank, n);
@@ -484,18 +491,23 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
         PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, nread * sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
         rn = std::sqrt(hst[0]);
+        if (verbose)
+            fprintf(stderr, "pqph: iteration %d  ||R|| = %.3e  (%.1f s)\n", it, rn,
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
         if (!std::isfinite(rn)) {
             result = PQPH_NONFINITE;
             pqph_fail(ctx, result, "non-finite residual at iteration " + std::to_string(it));
             break;
         }
+        if (best && rn < rmin)      // keep the iterate of smallest ||R|| (x is unchanged so far)
+            PQPH_HIP(ctx, hipMemcpyAsync(best, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         rmin = std::min(rmin, rn);
-        best.push_back(rmin);
+        hist_min.push_back(rmin);
         if (rn <= o.tol) {
             result = PQPH_OK;
             break;
         }
-        if (o.stall_window > 0 && it > o.stall_window && rmin > 0.5 * best[it - 1 - o.stall_window]) {
+        if (o.stall_window > 0 && it > o.stall_window && rmin > 0.5 * hist_min[it - 1 - o.stall_window]) {
             pqph_fail(ctx, result, "stalled: ||R|| did not halve in " + std::to_string(o.stall_window) +
                                        " iterations (iteration " + std::to_string(it) + ")");
             iters = it;
@@ -535,6 +547,204 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     if (result == PQPH_NOT_CONVERGED)
         pqph_fail(ctx, result, "not converged in " + std::to_string(o.max_iter) + " iterations");
     return PQPH_OK;
+}
+
+// Inexact Newton-Krylov solve of R(x) = 0, the same fixed point as the
+// Jacobi/DIIS iteration, for the systems where that iteration stalls or
+// diverges (Sec. IV.B: strongly correlated geometries; the paper suggests a
+// better preconditioner).  Each Newton step solves J dx = -R by GMRES with up
+// to KRYLOV Arnoldi vectors (no restart), right-preconditioned by the orbital-energy
+// denominators (J M^-1 y = -R, dx = M^-1 y, M = diag(D)); J v comes from
+// central differences of the residual, R(x + e v) - R(x - e v) = 2 e J v +
+// O(e^3) (R is a quartic polynomial in t); classical Gram-Schmidt with one
+// reorthogonalisation; the step is backtracked until ||R|| decreases.
+// Every residual is evaluated on the same two buffers (xin -> rout), so a
+// captured residual graph is reused.  iters counts residual evaluations.
+constexpr int KRYLOV = 100;       // 30 vectors stalled near the root on strongly correlated chains
+constexpr int NEWTON_MAX_STEPS = 60;
+
+size_t newton_doubles(size_t n) {
+    return n * (5 + KRYLOV + 1) + (size_t)stream_blocks(n) * (KRYLOV + 1) + KRYLOV + 64;
+}
+
+pqph_status newton_krylov(pqph_ctx* ctx, size_t n, const double* D, double* x,
+                          const pqph_solve_opts& o,
+                          const std::function<pqph_status(const double*, double*)>& resid,
+                          double* nbuf, int& iters, double& rn, pqph_status& result,
+                          const double* rank) {
+    const int nblk = stream_blocks(n);
+    double* r = nbuf;
+    double* xin = r + n;
+    double* rout = xin + n;
+    double* w = rout + n;
+    double* z = w + n;
+    double* V = z + n;                                   // KRYLOV + 1 vectors
+    double* part = V + (size_t)(KRYLOV + 1) * n;
+    double* scal = part + (size_t)nblk * (KRYLOV + 1);
+    hipStream_t s = ctx->stream;
+    // host staging: Gram rows (KRYLOV + 1) and, apart, the Krylov coefficients
+    PQPH_HIP(ctx, hipStreamSynchronize(s));      // no copy from the old buffer is pending
+    if (pqph_status e = pqph_ensure_host(ctx, 2 * KRYLOV + 64)) return e;
+    double* hst = ctx->host;
+    double* hy = hst + KRYLOV + 32;
+    const bool masked = rank != nullptr && o.max_rank > 0;
+    const char* venv = getenv("PQPH_VERBOSE");
+    const bool verbose = venv && venv[0] && venv[0] != '0';
+    auto R = [&]() -> pqph_status {                      // rout = R(xin), masked
+        if (pqph_status e = resid(xin, rout)) return e;
+        if (masked) launch_rank_mask(s, rout, rank, o.max_rank, n);
+        ++iters;
+        return PQPH_OK;
+    };
+    auto fetch = [&](int cnt) -> pqph_status {           // scal[0..cnt) -> hst
+        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        PQPH_HIP(ctx, hipStreamSynchronize(s));
+        return PQPH_OK;
+    };
+    auto norm = [&](const double* v, double& out) -> pqph_status {
+        launch_norm2(s, v, n, part, nblk, scal);
+        if (pqph_status e = fetch(1)) return e;
+        out = std::sqrt(hst[0]);
+        return PQPH_OK;
+    };
+    pqph_status st;
+    result = PQPH_NOT_CONVERGED;
+    if (masked) launch_rank_mask(s, x, rank, o.max_rank, n);
+    PQPH_HIP(ctx, hipMemcpyAsync(xin, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if ((st = R())) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(r, rout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double beta = 0.0;
+    for (int step = 0; step < NEWTON_MAX_STEPS; ++step) {
+        if ((st = norm(r, beta))) return st;
+        rn = beta;
+        if (verbose) fprintf(stderr, "pqph: Newton step %d  ||R|| = %.3e\n", step, beta);
+        if (!std::isfinite(beta)) {
+            result = PQPH_NONFINITE;
+            pqph_fail(ctx, result, "non-finite residual in the Newton-Krylov solve");
+            return PQPH_OK;
+        }
+        if (beta <= o.tol) {
+            result = PQPH_OK;
+            return PQPH_OK;
+        }
+        double xnorm = 0.0;
+        if ((st = norm(x, xnorm))) return st;
+        launch_axpby(s, V, -1.0 / beta, r, 0.0, nullptr, nullptr, n);      // V_0 = -R / beta
+        std::vector<double> H((size_t)(KRYLOV + 1) * KRYLOV, 0.0), g(KRYLOV + 1, 0.0), cs(KRYLOV),
+            sn(KRYLOV);
+        auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * KRYLOV + j]; };
+        g[0] = beta;
+        const double eta = std::min(0.1, std::sqrt(beta));                 // forcing term
+        int k = 0;
+        for (int j = 0; j < KRYLOV; ++j) {
+            const double* Vj = V + (size_t)j * n;
+            launch_axpby(s, z, 0.0, Vj, 1.0, Vj, D, n);                     // z = M^-1 V_j
+            double zn = 0.0;
+            if ((st = norm(z, zn))) return st;
+            if (!(zn > 0.0)) break;
+            const double e = 1e-5 * (1.0 + xnorm) / zn;
+            launch_axpby(s, xin, 1.0, x, e, z, nullptr, n);
+            if ((st = R())) return st;
+            PQPH_HIP(ctx, hipMemcpyAsync(w, rout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            launch_axpby(s, xin, 1.0, x, -e, z, nullptr, n);
+            if ((st = R())) return st;
+            launch_axpby(s, w, 0.5 / e, w, -0.5 / e, rout, nullptr, n);    // w = J z
+            for (int pass = 0; pass < 2; ++pass) {                           // CGS2
+                launch_gram(s, V, j + 1, w, n, part, nblk, scal);
+                launch_sub_combine(s, w, V, scal, j + 1, n);
+                if ((st = fetch(j + 1))) return st;
+                for (int i = 0; i <= j; ++i) Hat(i, j) += hst[i];
+            }
+            double hn = 0.0;
+            if ((st = norm(w, hn))) return st;
+            Hat(j + 1, j) = hn;
+            if (hn > 0.0) launch_axpby(s, V + (size_t)(j + 1) * n, 1.0 / hn, w, 0.0, nullptr, nullptr, n);
+            for (int i = 0; i < j; ++i) {                                    // earlier rotations
+                const double a = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+                Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+                Hat(i, j) = a;
+            }
+            const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
+            if (!(den > 0.0)) break;
+            cs[j] = Hat(j, j) / den;
+            sn[j] = Hat(j + 1, j) / den;
+            Hat(j, j) = den;
+            Hat(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= eta * beta || !(hn > 0.0)) break;
+        }
+        if (k == 0) {
+            pqph_fail(ctx, result, "Newton-Krylov: no Krylov direction");
+            return PQPH_OK;
+        }
+        std::vector<double> y(k, 0.0);                                       // H y = g
+        for (int i = k - 1; i >= 0; --i) {
+            double a = g[i];
+            for (int l = i + 1; l < k; ++l) a -= Hat(i, l) * y[l];
+            y[i] = a / Hat(i, i);
+        }
+        for (int i = 0; i < k; ++i) hy[i] = y[i];
+        PQPH_HIP(ctx, hipMemcpyAsync(scal, hy, k * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_combine(s, V, scal, k, n, w);                                 // w = sum y_i V_i
+        launch_axpby(s, z, 0.0, w, 1.0, w, D, n);                            // dx = M^-1 w
+        // the host rewrites hy only after the copy above has completed
+        PQPH_HIP(ctx, hipStreamSynchronize(s));
+        bool moved = false;
+        double lam = 1.0;
+        for (int ls = 0; ls < 12 && !moved; ++ls, lam *= 0.5) {
+            launch_axpby(s, xin, 1.0, x, lam, z, nullptr, n);
+            if ((st = R())) return st;
+            double rt = 0.0;
+            if ((st = norm(rout, rt))) return st;
+            if (std::isfinite(rt) && rt < (1.0 - 1e-4 * lam) * beta) {
+                PQPH_HIP(ctx, hipMemcpyAsync(x, xin, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                PQPH_HIP(ctx, hipMemcpyAsync(r, rout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                moved = true;
+            }
+        }
+        if (!moved) {
+            pqph_fail(ctx, result, "Newton-Krylov: the line search found no decrease of ||R||");
+            return PQPH_OK;
+        }
+    }
+    if ((st = norm(r, beta))) return st;
+    rn = beta;
+    if (beta <= o.tol)
+        result = PQPH_OK;
+    else
+        pqph_fail(ctx, result, "Newton-Krylov: not converged in " + std::to_string(NEWTON_MAX_STEPS) +
+                                   " steps");
+    return PQPH_OK;
+}
+
+// The amplitude solve of pq_solve / ph_solve / pq_energy_grad by opts.solver:
+// 0 Jacobi/DIIS; 1 Newton-Krylov from x; 2 Jacobi/DIIS, then Newton-Krylov
+// from its iterate of smallest ||R|| when it stalls, diverges or runs out of
+// iterations.  sbuf: solver_doubles(n, m, solver) doubles.
+size_t solver_doubles(size_t n, int m, int solver) {
+    size_t d = driver_doubles(n, m);
+    if (solver >= 1) d = std::max(d, newton_doubles(n));
+    if (solver == 2) d += n;                             // the best Jacobi/DIIS iterate
+    return d;
+}
+
+pqph_status amplitude_solve(pqph_ctx* ctx, size_t n, const double* D, double* x,
+                            const pqph_solve_opts& o,
+                            const std::function<pqph_status(const double*, double*)>& resid,
+                            double* sbuf, int& iters, double& rn, pqph_status& result,
+                            const double* rank) {
+    iters = 0;
+    if (o.solver == 1) return newton_krylov(ctx, n, D, x, o, resid, sbuf, iters, rn, result, rank);
+    double* best = o.solver == 2 ? sbuf + solver_doubles(n, std::max(o.diis_dim, 1), 1) : nullptr;
+    pqph_status st = jacobi_diis(ctx, n, D, x, o, resid, sbuf, iters, rn, result, rank, best);
+    if (st || o.solver != 2 || (result != PQPH_NOT_CONVERGED && result != PQPH_DIVERGED)) return st;
+    PQPH_HIP(ctx, hipMemcpyAsync(x, best, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    int it2 = 0;
+    st = newton_krylov(ctx, n, D, x, o, resid, sbuf, it2, rn, result, rank);
+    iters += it2;
+    return st;
 }
 
 // Eigenvalues of the symmetric n x n matrix A (row-major, overwritten) by
@@ -596,7 +806,8 @@ pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts&
     pqph_default_opts(&o);
     if (in) o = *in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.max_rank < 0 || o.max_rank > 6)
+        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.max_rank < 0 || o.max_rank > 6 ||
+        o.solver < 0 || o.solver > 2)
         return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
     return PQPH_OK;
 }
@@ -625,7 +836,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     const size_t n = pq_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
     const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
-    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
@@ -643,7 +854,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     auto resid = [&](const double* x, double* r) {
         return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
+    if ((st = amplitude_solve(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -703,7 +914,7 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     const size_t n = ph_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
     const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
-    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
     const size_t wsd = ph_energy_ws_doubles();
     size_t rwsd = 0;      // the residual's partial sums share the workspace (same stream)
     if ((st = ph_residual_ws_doubles(ctx, npair, &rwsd))) return st;
@@ -723,7 +934,7 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     auto resid = [&](const double* x, double* r) {
         return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = jacobi_diis(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
+    if ((st = amplitude_solve(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = ph_energy_dev(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -774,7 +985,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     // solver memory: D, t (when solved here), lambda, tbar scratch, ranks, the
     // rank Fock matrix, driver buffers
     const size_t nr = 5 * n + 4 * (size_t)npair * npair;
-    if ((st = pqph_ensure_sv(ctx, (nr + driver_doubles(n, m)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair), ad = pq_adj_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + ad + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
@@ -800,7 +1011,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
         auto resid = [&](const double* x, double* r) {
             return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
         };
-        if ((st = jacobi_diis(ctx, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
+        if ((st = amplitude_solve(ctx, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
         if (result != PQPH_OK) return result;
         t = tl;
     }

@@ -181,5 +181,10 @@ void launch_combine(hipStream_t s, const double* th, const double* c, int m, siz
 void launch_rank_fock(hipStream_t s, double* f, int npair);
 // r[i] = 0 where rank[i] > max_rank
 void launch_rank_mask(hipStream_t s, double* r, const double* rank, int max_rank, size_t n);
+// out = a x + b y (y may be null; with D, y is divided elementwise by D)
+void launch_axpby(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
+                  const double* D, size_t n);
+// y -= sum_j c[j] V[j] (c on the device)
+void launch_sub_combine(hipStream_t s, double* y, const double* V, const double* c, int m, size_t n);
 // gamma (2N x 2N) += 2 on the occupied diagonal (p < npair)
 void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair);

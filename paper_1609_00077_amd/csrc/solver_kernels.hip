@@ -261,3 +261,32 @@ void launch_rank_mask(hipStream_t s, double* r, const double* rank, int max_rank
     const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_rank_mask, dim3(g), dim3(256), 0, s, r, rank, max_rank, n);
 }
+
+// out = a x + b y (y may be null), optionally with y divided elementwise by D
+__global__ void k_axpby(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, const double* __restrict__ D, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double v = a * x[i];
+        if (y) v += b * (D ? y[i] / D[i] : y[i]);
+        out[i] = v;
+    }
+}
+
+// y -= sum_j c[j] V[j] (c in device memory, m vectors of length n)
+__global__ void k_sub_combine(double* __restrict__ y, const double* __restrict__ V,
+                              const double* __restrict__ c, int m, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += c[j] * V[(size_t)j * n + i];
+        y[i] -= s;
+    }
+}
+
+void launch_axpby(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
+                  const double* D, size_t n) {
+    hipLaunchKernelGGL(k_axpby, dim3(stream_blocks(n)), dim3(256), 0, s, out, a, x, b, y, D, n);
+}
+
+void launch_sub_combine(hipStream_t s, double* y, const double* V, const double* c, int m, size_t n) {
+    hipLaunchKernelGGL(k_sub_combine, dim3(stream_blocks(n)), dim3(256), 0, s, y, V, c, m, n);
+}

@@ -475,3 +475,40 @@ def test_rank_limit_changes_ph_energy():
         e[r] = res.energy
     assert abs(e[6] - e[4]) < abs(e[6] - e[2])
     assert abs(e[4] - e[2]) > 1e-5
+
+
+# ------------------------------------------------ Newton's method (Sec. IV.B)
+def test_newton_reaches_the_jacobi_diis_fixed_point():
+    """Where Jacobi/DIIS converges (6-site chain, U = 4), Newton's method with
+    the complex-step Jacobian finds the same amplitudes and energy; two
+    different iterations agree on the root of the definitional residual."""
+    prob = chain_problem(6, U=4.0, seed=6)
+    f, eri = integrals.chain_integrals(prob, 2)
+    ta = tier_a.TierA(3, 2)
+    et = layout.unpack_eri(eri, 3, 2)
+    R = lambda t: ta.residual(f, et, t)[0]
+    E = lambda t: ta.energy(f, et, t)
+    D = solver.denominators(f, 3, 2)
+    ref = solver.solve(R, E, D, tol=1e-12, max_iter=300)
+    nw = solver.newton(R, lambda t: ta.jacobian(f, et, t), E, np.zeros_like(D), tol=1e-12)
+    assert ref.converged and nw.converged and nw.iterations < 10
+    assert abs(nw.energy - ref.energy) < 1e-11
+    assert np.abs(nw.t - ref.t).max() < 1e-9
+
+
+def test_newton_solves_a_chain_where_jacobi_diis_stalls():
+    """8-site chain at U = 10: Jacobi/DIIS is still far from converged after
+    60 iterations (and after 1000, ||R|| ~ 0.09); Newton from its last iterate
+    reaches ||R|| <= 1e-11 in a few steps."""
+    prob = chain_problem(8, U=10.0, seed=8)
+    f, eri = integrals.chain_integrals(prob, 2)
+    ta = tier_a.TierA(4, 2)
+    et = layout.unpack_eri(eri, 4, 2)
+    R = lambda t: ta.residual(f, et, t)[0]
+    E = lambda t: ta.energy(f, et, t)
+    D = solver.denominators(f, 4, 2)
+    jd = solver.solve(R, E, D, tol=1e-8, max_iter=60)
+    assert not jd.converged and jd.rnorm > 1e-2
+    nw = solver.newton(R, lambda t: ta.jacobian(f, et, t), E, jd.t, tol=1e-11)
+    assert nw.converged and nw.iterations <= 6
+    assert np.linalg.norm(R(nw.t)) <= 1e-11
