@@ -41,8 +41,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-ph", action="store_true", help="skip the PH (three-pair) leg")
-    ap.add_argument("--ph-sites", type=int, default=10, help="sites of the PH leg's chain")
-    ap.add_argument("--ph-reps", type=int, default=5, help="back-to-back PH residuals timed")
+    ap.add_argument("--ph-sites", type=int, default=40,
+                    help="sites of the PH configuration's chain (one timed residual)")
+    ap.add_argument("--ph-reps", type=int, default=1, help="PH residuals timed back to back")
+    ap.add_argument("--ph-solve-sites", type=int, default=12,
+                    help="sites of the chain the PH leg solves from t = 0")
+    ap.add_argument("--ph-solve", action="store_true",
+                    help="solve the --ph-sites chain itself (15 minutes at 40 sites)")
     ap.add_argument("--ph-only", action="store_true", help="run only the PH leg")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-grad", action="store_true")
@@ -140,43 +145,63 @@ def cpu_baseline(prob, seconds: float):
 
 
 def ph_leg(args, pq, torch, dev):
-    """PH (three-pair) model on a small chain: one solve from t = 0 (integral
-    transform included) and back-to-back residuals at the converged
-    amplitudes, timed with HIP events on the library's stream."""
-    from inputs import chain_problem
-    prob = chain_problem(args.ph_sites, U=args.U, seed=args.ph_sites)
+    """PH (three-pair) model.  The configuration's chain (--ph-sites, 40
+    sites = 20 pairs): one residual at seeded amplitudes (scale 0.05), timed
+    with HIP events on the library's stream (a solve of this chain takes ~25
+    residuals, 15 minutes: it is run on its own with --ph-only --ph-solve).
+    And a full solve from t = 0 of a smaller chain (--ph-solve-sites, integral
+    transform included)."""
+    from inputs import chain_problem, random_amplitudes
     d = lambda x: torch.as_tensor(x, device=dev).contiguous()
-    F, V, Cm = d(prob.F_site), d(prob.V), d(prob.C)
     small = chain_problem(6, U=args.U, seed=6)                  # loads the term tables
     fs, es = pq.integrals(d(small.F_site), d(small.V), d(small.C), k=3)
     pq.ph_residual(fs, es, torch.zeros(pq.amp_len(3, "ph"), dtype=torch.float64, device=dev))
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f, eri = pq.integrals(F, V, Cm, k=3)
-    res = pq.ph_solve(f, eri, tol=args.tol)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    r = torch.empty_like(res.t)
+    out = {}
+    prob = chain_problem(args.ph_sites, U=args.U, seed=args.ph_sites)
+    N = prob.npair
+    f, eri = pq.integrals(d(prob.F_site), d(prob.V), d(prob.C), k=3)
+    t = d(random_amplitudes(N, "ph", seed=100 * args.ph_sites, scale=0.05))
+    r = torch.empty_like(t)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    nrep = args.ph_reps
     ev0.record()
-    for _ in range(nrep):
-        pq.ph_residual(f, eri, res.t, out=r)
+    for _ in range(args.ph_reps):
+        pq.ph_residual(f, eri, t, out=r)
     ev1.record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / nrep
-    nev = ph_term_evals(prob.npair)
-    return {"workload": f"PH solve of a {args.ph_sites}-site PPP chain ({prob.npair} pairs, "
-                        f"U={args.U}, seed {args.ph_sites}) from t=0 to ||R||<={args.tol:g}",
-            "solve_s": ts, "iterations": res.iterations, "energy": res.energy,
-            "status": res.status, "residual_ms": ms, "residual_evals_per_s": 1e3 / ms,
-            "amplitudes": pq.amp_len(prob.npair, "ph"),
-            "term_evals_per_residual": nev, "term_evals_per_s": nev / (ms * 1e-3)}
+    ms = ev0.elapsed_time(ev1) / args.ph_reps
+    nev, nfl = ph_term_evals(N)
+    ach = nfl / (ms * 1e-3) / 1e12
+    out["residual"] = {
+        "workload": f"one PH residual of the {args.ph_sites}-site PPP chain ({N} pairs, U={args.U}, "
+                    f"seed {args.ph_sites}) at seeded amplitudes", "amplitudes": pq.amp_len(N, "ph"),
+        "residual_ms": ms, "residual_evals_per_s": 1e3 / ms,
+        "term_evals_per_residual": nev, "term_evals_per_s": nev / (ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "k_ph_part", "achieved": ach,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": ach / 78.6,
+                     "flops_per_launch": nfl,
+                     "note": "interpreted work: one multiply per factor and one add per evaluated "
+                             "term; the kernel is bound by its dependent table gathers"}}
+    if args.ph_solve or args.ph_solve_sites != args.ph_sites:
+        sites = args.ph_sites if args.ph_solve else args.ph_solve_sites
+        sp = chain_problem(sites, U=args.U, seed=sites)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, eri = pq.integrals(d(sp.F_site), d(sp.V), d(sp.C), k=3)
+        res = pq.ph_solve(f, eri, tol=args.tol)
+        torch.cuda.synchronize()
+        out["solve"] = {"workload": f"PH solve of a {sites}-site PPP chain ({sp.npair} pairs, "
+                                    f"U={args.U}, seed {sites}) from t=0 to ||R||<={args.tol:g}, "
+                                    "integral transform included",
+                        "solve_s": time.perf_counter() - t0, "iterations": res.iterations,
+                        "energy": res.energy, "status": res.status}
+    return out
 
 
 def ph_term_evals(N):
-    """(term, ordered spectator tuple) evaluations of one PH residual: the
-    work the interpreted kernels do, counted from the term-table file."""
+    """(term, ordered spectator tuple) evaluations of one PH residual, the
+    work the interpreted kernels do, and its flops (one multiply per factor
+    and one add per evaluation), counted from the term-table file."""
     from math import comb, perm
 
     import numpy as np
@@ -184,25 +209,34 @@ def ph_term_evals(N):
     from paper_1609_00077_amd.derive import ph_tables
     raw = ph_tables.read(os.path.join(ROOT, "paper_1609_00077_amd", "ph_terms.bin"))
     a = np.frombuffer(raw, dtype="<i4")
-    nclass = int(a[2])
+    nclass, nterm, ncw = int(a[2]), int(a[5]), int(a[6])
     pos, classes = 8, []
     for _ in range(nclass):
         nout, nspec, nt, off, npat = (int(x) for x in a[pos:pos + 5])
-        classes.append((nout, nspec, a[pos + 5:pos + 6 + npat]))
+        classes.append((nout, nspec, off, a[pos + 5:pos + 6 + npat]))
         pos += 6 + npat
+    cw_dict = a[pos:pos + ncw]
+    nslot = int(a[7])
+    byte = 4 * (pos + ncw + nslot) + (2 * nterm + 3) // 4 * 4      # past slot_dict and h
+    cw = cw_dict[np.frombuffer(raw, dtype="<u1", count=nterm, offset=byte)]
+    fl_term = (cw >> 16) + 1                                     # factors + 1 per evaluation
+    cum = np.concatenate([[0], np.cumsum(fl_term, dtype=np.int64)])
     # the canonical map sits just before the integral map at the end of the file
     canon = a[len(a) - 3 * 1296 - 335:len(a) - 3 * 1296]
-    tot = 0
+    tot = fl = 0
     for n in (1, 2, 3):
         if n > N:
             continue
         base = (0, 3, 32)[n - 1]
         for m in range((3, 29, 303)[n - 1]):
             mc = int(canon[base + m]) & 511
-            for nout, nspec, start in classes:
+            for nout, nspec, off, start in classes:
                 if nout == n and nspec <= N - n:
-                    tot += int(start[mc + 1] - start[mc]) * perm(N - n, nspec) * comb(N, n)
-    return tot
+                    mult = perm(N - n, nspec) * comb(N, n)
+                    q0, q1 = off + int(start[mc]), off + int(start[mc + 1])
+                    tot += (q1 - q0) * mult
+                    fl += int(cum[q1] - cum[q0]) * mult
+    return tot, float(fl)
 
 
 def batch_leg(args, pq, torch, dev):
