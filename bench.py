@@ -559,6 +559,20 @@ def main():
     ceil = pq.measure_ceilings()
     line["ceilings_measured"] = ceil
     line["roofline"]["frac_of_measured_peak"] = achieved / ceil["fp64_mfma_TFLOPs"]
+    # the two-pair-intermediate variant (doubly-mixed two-spectator terms left out)
+    pq.set_pq_intermediates(N, 2)
+    for _ in range(3):
+        pq.pq_residual(f, eri, t_conv, out=r)
+    ev0.record()
+    for _ in range(nrep):
+        pq.pq_residual(f, eri, t_conv, out=r)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms2 = ev0.elapsed_time(ev1) / nrep
+    e2 = pq.pq_solve(f, eri, tol=args.tol).energy
+    pq.set_pq_intermediates(N, 3)
+    line["pq_two_pair_intermediates"] = {"residual_ms": ms2, "residual_evals_per_s": 1e3 / ms2,
+                                         "energy": e2, "energy_exact_model": res.energy}
     if not args.no_grad:
         line["energy_gradient"] = grad_leg(args, pq, torch, dev)
         line["densities"] = densities_leg(pq, torch, dev, args.sites)

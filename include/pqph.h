@@ -264,6 +264,17 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
  * rounding order.  INVALID_ARG for another mode.  For tests and tuning. */
 pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
 
+/* The PQ model variant with two-pair intermediates (Sec. III: the paper
+ * builds PQ with intermediates of up to three pairs and notes that truncating
+ * them to two pairs, O(N^3), costs accuracy).  labels = 3 (the default) is
+ * the exact projection; labels = 2 leaves out the two-spectator terms of the
+ * two-pair outputs in which both spectators are linked to both output pairs
+ * (the doubly-mixed terms), the only PQ terms whose contraction needs an
+ * intermediate over three labels.  Applies to pq_residual, the solves, the
+ * batched solve, pq_vjp and pq_energy_grad for npair on this context.
+ * INVALID_ARG for other values. */
+pqph_status pqph_set_pq_intermediates(pqph_ctx* ctx, int npair, int labels);
+
 /* The choices in effect for npair on this context (host outputs, each may be
  * NULL): the two-spectator variant (1 or 2) and the one-spectator mode (1, 2
  * or 3). */

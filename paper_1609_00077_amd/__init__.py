@@ -161,6 +161,14 @@ def set_s1_mode(npair: int, mode: int, device: str | torch.device = "cuda:0") ->
     _check(lib, ctx, lib.pqph_set_s1_mode(ctx, npair, mode))
 
 
+def set_pq_intermediates(npair: int, labels: int, device: str | torch.device = "cuda:0") -> None:
+    """PQ model for npair on the context of the current stream: labels = 3
+    (exact projection, the default) or 2 (two-pair intermediates: the
+    doubly-mixed two-spectator terms left out)."""
+    lib, ctx = _ctx(torch.device(device))
+    _check(lib, ctx, lib.pqph_set_pq_intermediates(ctx, npair, labels))
+
+
 def tuning(npair: int, device: str | torch.device = "cuda:0") -> dict:
     """The kernel choices in effect for npair: two-spectator variant and
     one-spectator mode."""

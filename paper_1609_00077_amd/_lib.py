@@ -56,6 +56,7 @@ SIGNATURES = {
     "pqph_autotune": (C.c_int, [P, C.c_int, P, P, P, P, C.POINTER(C.c_int)]),
     "pqph_set_variant": (C.c_int, [P, C.c_int, C.c_int]),
     "pqph_set_s1_mode": (C.c_int, [P, C.c_int, C.c_int]),
+    "pqph_set_pq_intermediates": (C.c_int, [P, C.c_int, C.c_int]),
     "pqph_tuning": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pqph_set_batch_mode": (C.c_int, [P, C.c_int]),
     "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),

@@ -1696,6 +1696,8 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate);
     if (st) return st;
     View v = make_view(t, c, N);
+    // the doubly-mixed two-spectator contraction (three-label intermediates)
+    const bool mixed = pq_intermediates(ctx, N) == 3;
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     const unsigned gsq = (unsigned)((N * N + 255) / 256);
@@ -1758,7 +1760,9 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         dim3 g2(s2_rowtiles(N), c.nchunk);
         const int ncb = (N + 15) / 16;
         const int variant = pq_s2_variant(ctx, N);
-        if (variant == 2 && ncb <= 6) {
+        if (!mixed) {
+            // two-pair-intermediate model: the doubly-mixed terms are left out
+        } else if (variant == 2 && ncb <= 6) {
             const int KP = (N + 3) / 4 * 4;
             auto ldsw = [&](int ncb_) {
                 return (size_t)(KP * 16 * ncb_ + M2_ROWS * KP + M2_ROWS * NP2) * sizeof(double);
@@ -1830,7 +1834,8 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     {
         const long ntot = 3L * N + (long)NP2 * N * (N - 1) / 2;
         hipLaunchKernelGGL(k_final, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, N, c.p1,
-                           c.nch1, c.p1s1, r1_lane_chunks(), c.p2, c.part, N > 1 ? c.nchunk : 0, r, gate);
+                           c.nch1, c.p1s1, r1_lane_chunks(), c.p2, c.part, (N > 1 && mixed) ? c.nchunk : 0, r,
+                           gate);
     }
 
     pqph_mark(ctx);
@@ -1915,7 +1920,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                                Xf, Yf, c.S, nullptr);
         }
         launch_r2_lane_adj(s, N, t, c.h1, c.h2T, c.S, lam, a.tb1, a.tb2, a.hb1, a.hb2, Sb);
-        {
+        if (pq_intermediates(ctx, N) == 3) {      // adjoint of the doubly-mixed terms
             const int rt2 = s2_rowtiles(N);
             const int nchunk = std::max(1, std::min(PQ_G_N, 2048 / std::max(rt2, 1)));
             const int gchunk = (PQ_G_N + nchunk - 1) / nchunk;

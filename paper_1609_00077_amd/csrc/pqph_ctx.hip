@@ -102,6 +102,10 @@ pqph_status pqph_ensure_host(pqph_ctx* ctx, size_t n) {
     return PQPH_OK;
 }
 
+int pq_intermediates(const pqph_ctx* ctx, int npair) {
+    return (npair >= 0 && npair <= 256 && ctx->pq_int[npair] == 2) ? 2 : 3;
+}
+
 int pq_s2_variant(const pqph_ctx* ctx, int npair) {
     if (npair >= 0 && npair <= 256 && ctx->s2_variant[npair]) return ctx->s2_variant[npair];
     return 1;
@@ -110,9 +114,10 @@ int pq_s2_variant(const pqph_ctx* ctx, int npair) {
 pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const double* eri,
                               const double* t, double* r, double* ws) {
     if (ctx->profiling) return pq_residual_ws(ctx, ctx->stream, N, h, eri, t, r, ws);
-    const int s1 = pq_s1_mode(ctx, N), s2 = pq_s2_variant(ctx, N);
+    const int s1 = pq_s1_mode(ctx, N), s2 = pq_s2_variant(ctx, N), li = pq_intermediates(ctx, N);
     const bool same = ctx->rexec && ctx->rN == N && ctx->rh == h && ctx->reri == eri && ctx->rt == t &&
-                      ctx->rr == r && ctx->rws == ws && ctx->rs1 == s1 && ctx->rs2 == s2;
+                      ctx->rr == r && ctx->rws == ws && ctx->rs1 == s1 && ctx->rs2 == s2 &&
+                      ctx->rint == li;
     if (!same) {
         if (ctx->rexec) {
             PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));    // the old graph may still run
@@ -149,6 +154,7 @@ pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const doubl
         ctx->rws = ws;
         ctx->rs1 = s1;
         ctx->rs2 = s2;
+        ctx->rint = li;
     }
     PQPH_HIP(ctx, hipGraphLaunch(ctx->rexec, ctx->stream));
     return PQPH_OK;
@@ -350,6 +356,15 @@ pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode) {
     if (mode < 0 || mode > 3 || (mode == 3 && npair > 128))
         return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, or 3 (3 needs npair <= 128)");
     ctx->s1_mode[npair] = mode;
+    return PQPH_OK;
+}
+
+pqph_status pqph_set_pq_intermediates(pqph_ctx* ctx, int npair, int labels) {
+    pqph_status st = check_pq(ctx, npair);
+    if (st) return st;
+    if (labels != 2 && labels != 3)
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "intermediates must span 2 or 3 pairs");
+    ctx->pq_int[npair] = labels;
     return PQPH_OK;
 }
 

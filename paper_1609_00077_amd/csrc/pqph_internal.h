@@ -35,6 +35,10 @@ struct pqph_ctx {
     // 2 = materialised X, Y read by the GEMM, 3 = fused with the staging
     // software-pipelined (npair <= 128); 0 = not tuned
     int s1_mode[257] = {};
+    // PQ intermediates per npair: 3 (0 = default) = the exact projection; 2 =
+    // the two-pair-intermediate model without the doubly-mixed two-spectator
+    // terms (the only ones whose contraction needs a three-label intermediate)
+    int pq_int[257] = {};
     // streams and events of batched solves (default priority), created on first use
     std::vector<hipStream_t> bstreams;
     std::vector<hipEvent_t> bevents;
@@ -46,7 +50,7 @@ struct pqph_ctx {
     // the residual captured as a HIP graph, with what it was captured for
     hipStream_t cap = nullptr;
     hipGraphExec_t rexec = nullptr;
-    int rN = 0, rs1 = 0, rs2 = 0;
+    int rN = 0, rs1 = 0, rs2 = 0, rint = 0;
     const double *rh = nullptr, *reri = nullptr, *rt = nullptr;
     double *rr = nullptr, *rws = nullptr;
     // batched solves: 0 = device-resident iterations captured in a HIP graph,
@@ -74,6 +78,8 @@ pqph_status ph_denominators_dev(pqph_ctx* ctx, hipStream_t s, int N, const doubl
 
 // variant of the two-spectator contraction for this npair (tuned or default)
 int pq_s2_variant(const pqph_ctx* ctx, int npair);
+// labels of the largest PQ intermediate for this npair: 3 (exact) or 2
+int pq_intermediates(const pqph_ctx* ctx, int npair);
 // one-spectator side formation for this npair (tuned, forced, or by size)
 int pq_s1_mode(const pqph_ctx* ctx, int npair);
 

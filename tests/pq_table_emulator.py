@@ -17,9 +17,10 @@ def unpack_factor(code):
 
 
 class Emu:
-    def __init__(self, tb, N, f, eri, lane=False):
+    def __init__(self, tb, N, f, eri, lane=False, mixed=True):
         self.tb, self.N, self.f, self.eri = tb, N, f, eri
         self.lane = lane          # evaluate the two-pair local terms through the lane tables
+        self.mixed = mixed        # include the doubly-mixed two-spectator terms
         self.np2 = comb(N, 2)
         self.h1 = np.zeros((len(tb.h1_keys), N))
         self.h2 = np.zeros((len(tb.h2_keys), N, N))
@@ -214,7 +215,7 @@ class Emu:
                     Lv[li] = np.array([self.spec(sp, (P, Q, A)) if A not in (P, Q) else 0.0
                                        for A in range(N)])
                 Wall = self.Wall                                   # vertices nw + w: transposed
-                for (wi, ai), lst in tb.r2s2_groups:
+                for (wi, ai), lst in (tb.r2s2_groups if self.mixed else []):
                     V = Lv[ai] @ Wall[wi]       # V[B] = sum_A L_a(A) W(A,B) (or transposed)
                     for bi, c, m in lst:
                         acc[m] += c * np.dot(V, Lv[bi])

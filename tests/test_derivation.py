@@ -110,3 +110,21 @@ def test_ph_canonical_reordering_sign():
                 seq += list(algebra.pattern_gens(i, mu[i]))
             s, _ = algebra.sort_sign(seq)
             assert s == reorder_sign(mu, order), (mu, order)
+
+
+def test_two_pair_intermediate_model_differs_only_from_four_pairs(tables):
+    """The two-pair-intermediate PQ variant leaves out the doubly-mixed
+    two-spectator terms.  Below four pairs a two-pair output has at most one
+    spectator, so the variant equals the definitional residual; from four
+    pairs on it differs (in the two-pair outputs only)."""
+    from pq_table_emulator import Emu
+    for N in (3, 4):
+        f, eri = _system(N, 720 + N)
+        t = random_amplitudes(N, "pq", seed=820 + N, scale=0.1)
+        RA, _ = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
+        R2 = Emu(tables, N, f, eri, mixed=False).residual(t)
+        if N == 3:
+            assert np.abs(R2 - RA).max() < 1e-13
+        else:
+            d = np.abs(R2 - RA)
+            assert d[:3 * N].max() < 1e-13 and d.max() > 1e-6
