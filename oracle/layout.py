@@ -203,3 +203,32 @@ def eri_slot_multiplicity(npair: int, k: int) -> np.ndarray:
                     (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)}
             out[off + u * nsets: off + (u + 1) * nsets] = len(imgs)
     return out
+
+
+def spin_flip(e: int) -> int:
+    """The pattern with alpha and beta exchanged (bits 0 <-> 1, 2 <-> 3)."""
+    return ((e & 1) << 1) | ((e >> 1) & 1) | ((e & 4) << 1) | ((e >> 1) & 4)
+
+
+def spin_flip_sign(e: int) -> int:
+    """Sign of writing the spin-exchanged generators of g^e (taken in the
+    order of g^e) in ascending bit order."""
+    fl = [b ^ 1 for b in range(4) if e >> b & 1]
+    inv = sum(1 for i in range(len(fl)) for j in range(i + 1, len(fl)) if fl[i] > fl[j])
+    return -1 if inv % 2 else 1
+
+
+def spin_partner(npair: int, k: int):
+    """(partner slot, sign) of every packed slot: the excitation with alpha
+    and beta exchanged on every pair, and the product over its pairs of the
+    reordering signs.  A closed-shell (spin-free) problem keeps
+    t[partner] = sign * t and R[partner] = sign * R."""
+    n = amp_count(npair, k)
+    partner = np.zeros(n, dtype=np.int64)
+    sign = np.zeros(n)
+    for pos, labels, tup in iter_amp_slots(npair, k):
+        ft = tuple(spin_flip(e) for e in tup)
+        m = pattern_tuples(len(labels)).index(ft)
+        partner[pos] = amp_slot(npair, labels, m)
+        sign[pos] = np.prod([spin_flip_sign(e) for e in tup])
+    return partner, sign

@@ -512,3 +512,28 @@ def test_newton_solves_a_chain_where_jacobi_diis_stalls():
     nw = solver.newton(R, lambda t: ta.jacobian(f, et, t), E, jd.t, tol=1e-11)
     assert nw.converged and nw.iterations <= 6
     assert np.linalg.norm(R(nw.t)) <= 1e-11
+
+
+# ------------------------------------------------ closed-shell spin symmetry (Sec. V)
+@pytest.mark.parametrize("N,k", [(4, 2), (3, 3)])
+def test_spin_symmetry_of_closed_shell_solutions(N, k):
+    """With a spin-free Hamiltonian and the closed-shell reference the
+    residual maps spin-symmetric amplitudes (t[partner] = sign t) to a
+    spin-symmetric residual, and the solved amplitudes are spin-symmetric;
+    amplitudes breaking the symmetry give a residual that breaks it."""
+    f, _, packed = _random_system(N, k, 57)
+    et = layout.unpack_eri(packed, N, k)
+    ta = tier_a.TierA(N, k)
+    partner, sign = layout.spin_partner(N, k)
+    assert np.all(partner[partner] == np.arange(len(partner)))
+    assert np.all(sign * sign[partner] == 1.0)
+    rng = np.random.default_rng(58)
+    t = rng.uniform(-0.1, 0.1, len(partner))
+    t_sym = 0.5 * (t + sign * t[partner])
+    R, _ = ta.residual(f, et, t_sym)
+    assert np.abs(R[partner] - sign * R).max() < 1e-13
+    Rb, _ = ta.residual(f, et, t)
+    assert np.abs(Rb[partner] - sign * Rb).max() > 1e-4
+    res = solver.solve(lambda x: ta.residual(f, et, x)[0], lambda x: ta.energy(f, et, x),
+                       solver.denominators(f, N, k), tol=1e-12, max_iter=300)
+    assert np.abs(res.t[partner] - sign * res.t).max() < 1e-12
