@@ -115,6 +115,25 @@ typedef struct {
                               reported is then residual evaluations.  In
                               pq_energy_grad it applies to the amplitude
                               solve; lambda uses Jacobi/DIIS.              */
+    int spin_adapted;      /* default 0; 1 = closed-shell spin adaptation
+                              (Sec. V: spin summation for closed shells):
+                              the solver keeps one value per orbit of the
+                              alpha/beta exchange of the packed slots
+                              (t[partner] = sign * t, partner = the same
+                              label set with alpha and beta exchanged on
+                              every pair, sign = the reordering of the
+                              exchanged generators), 2N + 16 C(N,2)
+                              (+ 155 C(N,3) for PH) values instead of
+                              3N + 29 C(N,2) (+ 303 C(N,3)): every solver
+                              vector and DIIS history shrinks to about
+                              half.  The residual itself still runs on the
+                              full packed vectors.  Exact for the spin-free
+                              integrals of this library: the solution is
+                              the one of the full space; start amplitudes
+                              are first projected onto the symmetric
+                              subspace.  Reported norms are those of the
+                              symmetrised full residual.  Not supported by
+                              pq_solve_batched.                           */
 } pqph_solve_opts;
 
 /* Per-solve report (host struct). */

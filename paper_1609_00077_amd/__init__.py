@@ -263,14 +263,14 @@ class SolveResult:
 def pq_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
              tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
              level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
-             max_rank: int = 0, solver: int = 0,
+             max_rank: int = 0, solver: int = 0, spin_adapted: int = 0,
              raise_on_failure: bool = True) -> SolveResult:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)
     na = amp_len(npair)
     t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank, solver)
+                          stall_window, max_rank, solver, spin_adapted)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_solve(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", eri_len(npair)),
@@ -307,14 +307,14 @@ def ph_energy(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor) -> float:
 def ph_solve(h: torch.Tensor, eri: torch.Tensor, t0: torch.Tensor | None = None, *,
              tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
              level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
-             max_rank: int = 0, solver: int = 0,
+             max_rank: int = 0, solver: int = 0, spin_adapted: int = 0,
              raise_on_failure: bool = True) -> SolveResult:
     npair = h.shape[0] // 2
     lib, ctx = _ctx(h.device)
     na = amp_len(npair, "ph")
     t = torch.zeros(na, dtype=torch.float64, device=h.device) if t0 is None else t0.clone()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank, solver)
+                          stall_window, max_rank, solver, spin_adapted)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.ph_solve(ctx, npair, _dev(h, "h", 4 * npair * npair),
@@ -362,7 +362,7 @@ class GradResult:
 def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
                    tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
                    level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
-                   max_rank: int = 0, solver: int = 0,
+                   max_rank: int = 0, solver: int = 0, spin_adapted: int = 0,
                    raise_on_failure: bool = True) -> GradResult:
     """PQ correlation energy and dE/dh, dE/d(packed eri) through the lambda
     equations; t: converged amplitudes, or None to solve them here."""
@@ -373,7 +373,7 @@ def pq_energy_grad(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = 
     ge = torch.empty(ne, dtype=torch.float64, device=h.device)
     lam = torch.empty(na, dtype=torch.float64, device=h.device)
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank, solver)
+                          stall_window, max_rank, solver, spin_adapted)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_energy_grad(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),
@@ -401,7 +401,7 @@ class DensityResult:
 def pq_densities(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = None, *,
                  tol: float = 1e-8, max_iter: int = 200, diis_dim: int = 8, diis_start: int = 2,
                  level_shift: float = 0.0, diverge_factor: float = 1e4, stall_window: int = 40,
-                 max_rank: int = 0, solver: int = 0,
+                 max_rank: int = 0, solver: int = 0, spin_adapted: int = 0,
                  raise_on_failure: bool = True) -> DensityResult:
     """Unrelaxed densities gamma, Gamma of the PQ Lagrangian and the natural
     occupation numbers; t: converged amplitudes, or None to solve them here."""
@@ -412,7 +412,7 @@ def pq_densities(h: torch.Tensor, eri: torch.Tensor, t: torch.Tensor | None = No
     g2 = torch.empty(ne, dtype=torch.float64, device=h.device)
     noons = (C.c_double * (2 * npair))()
     opts = _lib.SolveOpts(max_iter, tol, diis_dim, diis_start, level_shift, diverge_factor,
-                          stall_window, max_rank, solver)
+                          stall_window, max_rank, solver, spin_adapted)
     info = _lib.SolveInfo()
     e = C.c_double()
     st = lib.pq_densities(ctx, npair, _dev(h, "h", 4 * npair * npair), _dev(eri, "eri", ne),

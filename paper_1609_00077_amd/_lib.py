@@ -16,7 +16,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol", C.c_double), ("diis_dim", C.c_int),
                 ("diis_start", C.c_int), ("level_shift", C.c_double),
                 ("diverge_factor", C.c_double), ("stall_window", C.c_int), ("max_rank", C.c_int),
-                ("solver", C.c_int)]
+                ("solver", C.c_int), ("spin_adapted", C.c_int)]
 
 
 class SolveInfo(C.Structure):

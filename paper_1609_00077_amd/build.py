@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpqph.so")
 SOURCES = ["pqph_ctx.hip", "solver_kernels.hip", "pq_residual.hip", "pq_lane.hip", "pq_lane_adj.hip",
-           "integrals.hip", "batched.hip", "ph_residual.hip", "ceilings.hip"]
+           "integrals.hip", "batched.hip", "ph_residual.hip", "ceilings.hip", "spin.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (wrong results seen on this part)

@@ -519,9 +519,10 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     if (opts_in) o = *opts_in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
         !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kRing || o.max_rank != 0 ||
-        (o.solver != 0 && o.solver != 2))
+        (o.solver != 0 && o.solver != 2) || o.spin_adapted != 0)
         return pqph_fail(ctx, PQPH_INVALID_ARG,
-                         "invalid solver options (batched: stall_window < 257, max_rank 0, solver 0 or 2)");
+                         "invalid solver options (batched: stall_window < 257, max_rank 0, solver 0 or 2, "
+                         "spin_adapted 0)");
     PQPH_HIP(ctx, hipSetDevice(ctx->device));
     const int m = b.m = std::max(o.diis_dim, 1);
     const int ns = b.ns = std::min(kMaxStreams, nbatch);

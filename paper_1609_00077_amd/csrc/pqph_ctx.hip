@@ -203,6 +203,7 @@ void pqph_default_opts(pqph_solve_opts* o) {
     o->stall_window = 40;
     o->max_rank = 0;
     o->solver = 0;
+    o->spin_adapted = 0;
 }
 
 pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
@@ -762,6 +763,57 @@ pqph_status amplitude_solve(pqph_ctx* ctx, size_t n, const double* D, double* x,
     return st;
 }
 
+// The solve in the space opts.spin_adapted selects: the full packed space,
+// or the reduced closed-shell space of one value per alpha/beta exchange
+// orbit (the residual runs on full vectors unpacked from it, its result is
+// projected back).  jd_only: Jacobi/DIIS whatever opts.solver says (the
+// lambda equations).  x and rank are full-length; sbuf holds
+// space_doubles(...) doubles.
+size_t space_doubles(size_t n, int npair, int k, int m, const pqph_solve_opts& o) {
+    if (!o.spin_adapted) return solver_doubles(n, m, o.solver);
+    const size_t nred = spin_len(npair, k);
+    return 3 * nred + 2 * n + solver_doubles(nred, m, o.solver);
+}
+
+pqph_status space_solve(pqph_ctx* ctx, int npair, int k, size_t n, const double* D, double* x,
+                        const pqph_solve_opts& o,
+                        const std::function<pqph_status(const double*, double*)>& resid,
+                        double* sbuf, int& iters, double& rn, pqph_status& result, const double* rank,
+                        bool jd_only = false) {
+    auto core = [&](size_t len, const double* Dv, double* xv,
+                    const std::function<pqph_status(const double*, double*)>& rf, double* b,
+                    const double* rk) -> pqph_status {
+        if (jd_only) return jacobi_diis(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk);
+        return amplitude_solve(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk);
+    };
+    if (!o.spin_adapted) return core(n, D, x, resid, sbuf, rank);
+    const size_t nred = spin_len(npair, k);
+    double* xr = sbuf;
+    double* Dr = xr + nred;
+    double* rk = Dr + nred;
+    double* tf = rk + nred;
+    double* rf = tf + n;
+    double* b = rf + n;
+    hipStream_t s = ctx->stream;
+    launch_spin_pack(s, x, xr, npair, k, 0);
+    launch_spin_pack(s, D, Dr, npair, k, 1);
+    const double* rkp = nullptr;
+    if (rank) {
+        launch_spin_pack(s, rank, rk, npair, k, 1);
+        rkp = rk;
+    }
+    auto reduced = [&](const double* xin, double* rout) -> pqph_status {
+        launch_spin_unpack(s, xin, tf, npair, k);
+        if (pqph_status e = resid(tf, rf)) return e;
+        launch_spin_pack(s, rf, rout, npair, k, 0);
+        return PQPH_OK;
+    };
+    if (pqph_status st = core(nred, Dr, xr, reduced, b, rkp)) return st;
+    launch_spin_unpack(s, xr, x, npair, k);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
 // Eigenvalues of the symmetric n x n matrix A (row-major, overwritten) by
 // cyclic Jacobi rotations (the symmetric Schur decomposition): each rotation
 // zeroes one off-diagonal pair; sweeps stop once the off-diagonal Frobenius
@@ -822,7 +874,7 @@ pqph_status read_opts(pqph_ctx* ctx, const pqph_solve_opts* in, pqph_solve_opts&
     if (in) o = *in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
         !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.max_rank < 0 || o.max_rank > 6 ||
-        o.solver < 0 || o.solver > 2)
+        o.solver < 0 || o.solver > 2 || o.spin_adapted < 0 || o.spin_adapted > 1)
         return pqph_fail(ctx, PQPH_INVALID_ARG, "invalid solver options");
     return PQPH_OK;
 }
@@ -851,7 +903,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     const size_t n = pq_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
     const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
-    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + space_doubles(n, npair, 2, m, o)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
@@ -869,7 +921,7 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     auto resid = [&](const double* x, double* r) {
         return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = amplitude_solve(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
+    if ((st = space_solve(ctx, npair, 2, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -929,7 +981,7 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     const size_t n = ph_amp_len(npair);
     const int m = std::max(o.diis_dim, 1);
     const size_t nr = 2 * n + 4 * (size_t)npair * npair;     // D, ranks, rank Fock matrix
-    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + space_doubles(n, npair, 3, m, o)) * sizeof(double)))) return st;
     const size_t wsd = ph_energy_ws_doubles();
     size_t rwsd = 0;      // the residual's partial sums share the workspace (same stream)
     if ((st = ph_residual_ws_doubles(ctx, npair, &rwsd))) return st;
@@ -949,7 +1001,7 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     auto resid = [&](const double* x, double* r) {
         return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws);
     };
-    if ((st = amplitude_solve(ctx, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
+    if ((st = space_solve(ctx, npair, 3, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;
     if ((st = ph_energy_dev(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1000,7 +1052,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     // solver memory: D, t (when solved here), lambda, tbar scratch, ranks, the
     // rank Fock matrix, driver buffers
     const size_t nr = 5 * n + 4 * (size_t)npair * npair;
-    if ((st = pqph_ensure_sv(ctx, (nr + solver_doubles(n, m, o.solver)) * sizeof(double)))) return st;
+    if ((st = pqph_ensure_sv(ctx, (nr + space_doubles(n, npair, 2, m, o)) * sizeof(double)))) return st;
     const size_t wsd = pq_ws_doubles(npair), ad = pq_adj_doubles(npair);
     if ((st = pqph_ensure_ws(ctx, (wsd + ad + 8) * sizeof(double)))) return st;
     if ((st = pqph_ensure_host(ctx, 64))) return st;
@@ -1026,7 +1078,7 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
         auto resid = [&](const double* x, double* r) {
             return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
         };
-        if ((st = amplitude_solve(ctx, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
+        if ((st = space_solve(ctx, npair, 2, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
         if (result != PQPH_OK) return result;
         t = tl;
     }
@@ -1049,7 +1101,8 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
         fwd_ready = fwd_ready || e == PQPH_OK;
         return e;
     };
-    if ((st = jacobi_diis(ctx, n, D, lam, o, lres, bufs, iters, rn, result, rank))) return st;
+    if ((st = space_solve(ctx, npair, 2, n, D, lam, o, lres, bufs, iters, rn, result, rank, true)))
+        return st;
     if ((st = pq_vjp_ws(ctx, s, npair, h, eri, t, lam, 1.0, tbar, dE_dh, dE_deri, ctx->ws, aws, fwd_ready)))
         return st;
     if (lambda_out)

@@ -194,3 +194,10 @@ void launch_axpby(hipStream_t s, double* out, double a, const double* x, double 
 void launch_sub_combine(hipStream_t s, double* y, const double* V, const double* c, int m, size_t n);
 // gamma (2N x 2N) += 2 on the occupied diagonal (p < npair)
 void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair);
+// closed-shell spin adaptation: reduced length (one value per alpha/beta
+// exchange orbit of the packed slots, label sets of up to k pairs), the
+// projection v -> x (mode 0: sqrt-weighted, symmetrising; mode 1: the
+// representative's value) and its inverse x -> v
+size_t spin_len(int npair, int k);
+void launch_spin_pack(hipStream_t s, const double* v, double* x, int npair, int k, int mode);
+void launch_spin_unpack(hipStream_t s, const double* x, double* v, int npair, int k);

@@ -49,3 +49,30 @@ def test_bench_refuses_multi_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stdout
+
+
+def _struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", text).group(1)
+    return re.findall(r"(int|double)\s+(\w+);", body)
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of the option and report structs list the header's
+    fields in the header's order with the same types."""
+    from paper_1609_00077_amd import _lib
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double}
+    for cls, name in ((_lib.SolveOpts, "pqph_solve_opts"), (_lib.SolveInfo, "pqph_solve_info")):
+        want = [(n, ctype[t]) for t, n in _struct_fields(name)]
+        assert list(cls._fields_) == want, name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpqph.so not built")
+def test_default_options():
+    from paper_1609_00077_amd import _lib
+    lib = _lib.load()
+    o = _lib.SolveOpts()
+    o.spin_adapted = 7
+    lib.pqph_default_opts(ctypes.byref(o))
+    assert (o.max_iter, o.tol, o.diis_dim, o.diis_start, o.stall_window) == (200, 1e-8, 8, 2, 40)
+    assert (o.max_rank, o.solver, o.spin_adapted) == (0, 0, 0)

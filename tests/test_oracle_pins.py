@@ -527,6 +527,9 @@ def test_spin_symmetry_of_closed_shell_solutions(N, k):
     partner, sign = layout.spin_partner(N, k)
     assert np.all(partner[partner] == np.arange(len(partner)))
     assert np.all(sign * sign[partner] == 1.0)
+    # orbits: 2 per pair, 16 per pair of pairs, 155 per triple (header counts)
+    orbits = np.sum(partner >= np.arange(len(partner)))
+    assert orbits == 2 * N + 16 * comb(N, 2) + (155 * comb(N, 3) if k == 3 else 0)
     rng = np.random.default_rng(58)
     t = rng.uniform(-0.1, 0.1, len(partner))
     t_sym = 0.5 * (t + sign * t[partner])
