@@ -116,3 +116,40 @@ def restricted_mp2(npair: int, k: int, f: np.ndarray, eri: np.ndarray) -> float:
             d = f[a // 2, a // 2] + f[b // 2, b // 2] - f[i // 2, i // 2] - f[j // 2, j // 2]
             e -= v * v / d
     return e
+
+
+def restricted_mp2_zdo(npair: int, k: int, f: np.ndarray, C: np.ndarray, V: np.ndarray) -> float:
+    """restricted_mp2 for a zero-differential-overlap Hamiltonian at sizes where
+    the dense integral tensor does not fit: every label set S of at most k
+    pairs is visited once, its local chemists' integrals formed from the MO
+    coefficients, (pq|rs) = sum_xy C_xp C_xq V_xy C_yr C_ys, and only the
+    doubles whose four orbitals cover exactly S are summed."""
+    e = 0.0
+    for size in range(1, k + 1):
+        sets = list(itertools.combinations(range(npair), size))
+        if not sets:
+            continue
+        # local spatial orbitals of a set: o_P for P in S, then v_P
+        orbs = np.array([[P for P in s] + [npair + P for P in s] for s in sets])
+        Cs = C[:, orbs].transpose(1, 0, 2)                     # (sets, n, 2*size)
+        m = 2 * size
+        X = (Cs[:, :, :, None] * Cs[:, :, None, :]).reshape(len(sets), C.shape[0], m * m)
+        Y = np.einsum("xy,syk->sxk", V, X)
+        G = np.einsum("sxk,sxl->skl", X, Y).reshape(len(sets), m, m, m, m)   # (pq|rs)
+        label = np.array(list(range(size)) * 2)                 # local orbital -> role
+        occ = [(p, s) for p in range(size) for s in (0, 1)]
+        vir = [(size + p, s) for p in range(size) for s in (0, 1)]
+        fd = np.array([[f[o, o] for o in row] for row in orbs])  # (sets, 2*size)
+        for (i, si), (j, sj) in itertools.combinations(occ, 2):
+            for (a, sa), (b, sb) in itertools.combinations(vir, 2):
+                if len({label[i], label[j], label[a], label[b]}) != size:
+                    continue
+                # <ij||ab> = (ia|jb) d(si,sa) d(sj,sb) - (ib|ja) d(si,sb) d(sj,sa)
+                v = np.zeros(len(sets))
+                if si == sa and sj == sb:
+                    v = v + G[:, i, a, j, b]
+                if si == sb and sj == sa:
+                    v = v - G[:, i, b, j, a]
+                d = fd[:, a] + fd[:, b] - fd[:, i] - fd[:, j]
+                e -= float(np.sum(v * v / d))
+    return e

@@ -150,6 +150,24 @@ def test_full_size_properties(pq):
     assert abs(e1 - e2) < 1e-9
 
 
+@pytest.mark.parametrize("sites,k", [(140, 2), (24, 3)])
+def test_first_step_is_restricted_mp2_at_full_size(pq, sites, k):
+    """At the configured sizes: one Jacobi step from t = 0 (two iterations, no
+    DIIS) leaves t = -R(0)/D, whose energy is the MP2 energy restricted to the
+    doubles within k pairs (Sec. II), summed independently of the oracle and
+    of the packed layout over the label sets of the chain's MO integrals."""
+    import fermi_ref as fr
+    prob = chain_problem(sites, U=4.0, seed=sites)
+    N = prob.npair
+    f, eri = oint.chain_integrals(prob, k)
+    emp2 = fr.restricted_mp2_zdo(N, k, f, prob.C, prob.V)
+    solve = pq.pq_solve if k == 2 else pq.ph_solve
+    res = solve(_d(f), _d(eri), max_iter=2, diis_dim=0, raise_on_failure=False)
+    assert res.status == "NOT_CONVERGED" and res.iterations == 2
+    assert emp2 < -0.1
+    assert abs(res.energy - emp2) < 1e-11, (res.energy, emp2)
+
+
 @pytest.mark.parametrize("N", [24, 90])
 def test_two_spectator_variants_agree(pq, N):
     """The two two-spectator kernel variants (vertex staged in K-chunks,

@@ -540,3 +540,16 @@ def test_spin_symmetry_of_closed_shell_solutions(N, k):
     res = solver.solve(lambda x: ta.residual(f, et, x)[0], lambda x: ta.energy(f, et, x),
                        solver.denominators(f, N, k), tol=1e-12, max_iter=300)
     assert np.abs(res.t[partner] - sign * res.t).max() < 1e-12
+
+
+@pytest.mark.parametrize("N,k", [(3, 2), (4, 3)])
+def test_restricted_mp2_by_label_sets(N, k):
+    """The label-set MP2 sum used at full size equals the spin-orbital sum
+    over the dense integrals of the same chain."""
+    prob = chain_problem(2 * N, U=4.0, seed=70 + N)
+    f = integrals.mo_fock(prob.F_site, prob.C)
+    eri = np.einsum("xp,xq,xy,yr,ys->pqrs", prob.C, prob.C, prob.V, prob.C, prob.C)
+    e_dense = fr.restricted_mp2(N, k, np.diag(np.diag(f)), eri)
+    e_sets = fr.restricted_mp2_zdo(N, k, f, prob.C, prob.V)
+    assert e_dense < -1e-3
+    assert abs(e_dense - e_sets) < 1e-13
