@@ -279,8 +279,10 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
  * 0 = default (by size, or as tuned by pqph_autotune), 1 = each side formed
  * from its factors while staging, 2 = X and Y materialised first and read by
  * the GEMM, 3 = as 1 with the next chunk's loads overlapping the current
- * chunk's matrix-core steps (npair <= 128).  All give the same residual up to
- * rounding order.  INVALID_ARG for another mode.  For tests and tuning. */
+ * chunk's matrix-core steps (npair <= 128), 4 = as 2 with the next chunk's
+ * loads overlapping the current chunk's matrix-core steps (npair <= 128;
+ * bitwise the same as 2).  All give the same residual up to rounding order.
+ * INVALID_ARG for another mode.  For tests and tuning. */
 pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
 
 /* The PQ model variant with two-pair intermediates (Sec. III: the paper

@@ -287,6 +287,68 @@ __device__ __forceinline__ double spec_eval(const SpecPtrs& q, int L0, int L1) {
     return x;
 }
 
+// Both sides of the one-spectator GEMM materialised in one launch (modes 2
+// and 4, and the adjoint): grid (ceil(N*N / 512), PQ_X_N + PQ_Y_N), two
+// consecutive elements per thread.  The factor list of a slice is decoded
+// once (spec_ptrs) and its length, uniform over the block, selects a
+// straight-line product, so all loads of a thread's two elements are in
+// flight together.  Same product order as k_spec: bitwise the same sides.
+__device__ __forceinline__ void spec_two(const SpecPtrs& q, int a0, int a1, int b0, int b1, double& xa,
+                                         double& xb) {
+    auto at = [&](int f, int L0, int L1) { return q.p[f][L0 * q.sa[f] + L1 * q.sb[f]]; };
+    switch (q.n) {
+        case 0:
+            xa = xb = 1.0;
+            break;
+        case 1:
+            xa = at(0, a0, a1);
+            xb = at(0, b0, b1);
+            break;
+        case 2: {
+            const double u0 = at(0, a0, a1), u1 = at(1, a0, a1);
+            const double w0 = at(0, b0, b1), w1 = at(1, b0, b1);
+            xa = u0 * u1;
+            xb = w0 * w1;
+            break;
+        }
+        case 3: {
+            const double u0 = at(0, a0, a1), u1 = at(1, a0, a1), u2 = at(2, a0, a1);
+            const double w0 = at(0, b0, b1), w1 = at(1, b0, b1), w2 = at(2, b0, b1);
+            xa = (u0 * u1) * u2;
+            xb = (w0 * w1) * w2;
+            break;
+        }
+        default: {
+            const double u0 = at(0, a0, a1), u1 = at(1, a0, a1), u2 = at(2, a0, a1), u3 = at(3, a0, a1);
+            const double w0 = at(0, b0, b1), w1 = at(1, b0, b1), w2 = at(2, b0, b1), w3 = at(3, b0, b1);
+            xa = ((u0 * u1) * u2) * u3;
+            xb = ((w0 * w1) * w2) * w3;
+            break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_spec_xy(int N, View v, double* __restrict__ X, double* __restrict__ Y,
+                                                 const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    const int sl = blockIdx.y;
+    const bool ys = sl >= PQ_X_N;
+    const int sx = ys ? sl - PQ_X_N : sl;
+    const SpecPtrs q = ys ? spec_ptrs(pq_y_fac, pq_y_start[sx], pq_y_start[sx + 1], v)
+                          : spec_ptrs(pq_x_fac, pq_x_start[sx], pq_x_start[sx + 1], v);
+    const int NN = N * N;
+    const int e = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= NN) return;
+    const int a0 = e / N, a1 = e - a0 * N;
+    const bool two = e + 1 < NN;
+    const int b0 = two ? (e + 1) / N : a0, b1 = two ? e + 1 - b0 * N : a1;
+    double xa, xb;
+    spec_two(q, a0, a1, b0, b1, xa, xb);
+    double* out = (ys ? Y : X) + (long)sx * NN;
+    out[e] = a0 != a1 ? xa : 0.0;                 // zero diagonal: A != P, Q
+    if (two) out[e + 1] = b0 != b1 ? xb : 0.0;
+}
+
 // FUSED: the sides X_x(P,A) and Y_y(Q,A) are formed while staging, as the
 // products of their factors (amplitudes, vertices, dressed vertices: arrays
 // of at most a few hundred N x N slices that stay in the caches), instead of
@@ -459,6 +521,118 @@ __global__ __launch_bounds__(256) void k_gemm_s1p(int N, View v, double* __restr
         }
         if (c + 1 < nch) store(buf ^ 1);
         __syncthreads();
+    }
+    const long np2 = (long)N * (N - 1) / 2;
+    double* out = SK + (long)p * np2;
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) {
+        if (!tv[u]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ts[i * S1_PITCH + kq + 4 * r] = D[u][r];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int e = lane; e < 256; e += 64) {
+            const int ql = e >> 4, pl = e & 15;
+            const int P = tP[u] * 16 + pl, Q = tQ[u] * 16 + ql;
+            if (P < Q && Q < N) out[(long)Q * (Q - 1) / 2 + P] = Ts[ql * S1_PITCH + pl];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// Mode 4: the materialised sides of mode 2, with the staging software-
+// pipelined.  Each thread holds its share of the next K-chunk (NT slots of two
+// consecutive columns, 16-byte loads when N is even) in registers: the loads
+// are issued before the current chunk's matrix-core steps and written to the
+// single LDS buffer after them, so their latency hides behind the MFMAs
+// without a second buffer (occupancy stays that of mode 2).  Tiles, operand
+// order and the epilogue are those of k_gemm_s1, so S is bitwise the same as
+// in mode 2.  NT = row tiles (N <= 16 NT).
+template <int NT, bool EVEN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gemm_s1m(
+    int N, const double* __restrict__ X, const double* __restrict__ Y, double* __restrict__ SK,
+    const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;   // chain finished (batched solves)
+    extern __shared__ double sm[];
+    constexpr int NR = NT * 16, ntile = NT * (NT + 1) / 2;
+    constexpr int ngrp = (ntile + S1_TPG - 1) / S1_TPG;
+    constexpr int SE = NR * 8;                // two-column slots per side and chunk
+    const long nitem = (long)ngrp * PQ_S1PAIRS_N;
+    const long per = gridDim.x / 8;
+    const long w = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= nitem) return;
+    const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
+    double* Xs = sm;                          // [NR][S1_PITCH]
+    double* Ys = Xs + NR * S1_PITCH;          // [NR][S1_PITCH]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double* Ts = Ys + NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
+    const long NN = (long)N * N;
+    const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
+    const double* Xp = X + (long)xi * NN;
+    const double* Yp = Y + (long)yi * NN;
+    const int i = lane & 15, kq = lane >> 4;
+    int tP[S1_TPW], tQ[S1_TPW];
+    bool tv[S1_TPW];
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) {
+        const int t = tg * S1_TPG + wave + 4 * u;
+        tv[u] = t < ntile;
+        tile_of(tv[u] ? t : 0, NT, tP[u], tQ[u]);
+    }
+    d4 D[S1_TPW];
+#pragma unroll
+    for (int u = 0; u < S1_TPW; ++u) D[u] = d4{0.0, 0.0, 0.0, 0.0};
+    // slot j of this thread: e = tid + 256 j < 2 SE (side = e >= SE), row
+    // r = (e mod SE) / 8, columns A, A + 1 with A = kc + 2 (e mod 8)
+    // every load is issued unconditionally at an in-bounds (clamped) address
+    // and masked only when written to LDS, so a chunk's loads stay in flight
+    // through the matrix-core steps
+    double2 st[NT];
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int e = tid + 256 * j;
+            const bool ys = e >= SE;
+            const int idx = ys ? e - SE : e, r = idx >> 3, A = kc + 2 * (idx & 7);
+            const double* base = ys ? Yp : Xp;
+            if (EVEN) {              // A even, so A < N implies A + 1 < N; 16-byte aligned
+                const bool in = r < N && A < N;
+                st[j] = *(const double2*)(base + (in ? r * N + A : 0));
+            } else {
+                const bool in0 = r < N && A < N, in1 = r < N && A + 1 < N;
+                st[j].x = base[in0 ? r * N + A : 0];
+                st[j].y = base[in1 ? r * N + A + 1 : 0];
+            }
+        }
+    };
+    auto store = [&](int kc) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int e = tid + 256 * j;
+            const bool ys = e >= SE;
+            const int idx = ys ? e - SE : e, r = idx >> 3, k = 2 * (idx & 7), A = kc + k;
+            double* dst = (ys ? Ys : Xs) + r * S1_PITCH + k;
+            dst[0] = r < N && A < N ? st[j].x : 0.0;
+            dst[1] = r < N && A + 1 < N ? st[j].y : 0.0;
+        }
+    };
+    const int nch = (N + 15) / 16;
+    load(0);
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();                      // the previous chunk's operands are consumed
+        store(c * 16);
+        __syncthreads();
+        if (c + 1 < nch) load((c + 1) * 16);  // in flight during this chunk's MFMAs
+#pragma unroll
+        for (int u = 0; u < S1_TPW; ++u) {
+            if (!tv[u]) continue;
+            const double* xa = Xs + (tP[u] * 16 + i) * S1_PITCH + kq;
+            const double* yb = Ys + (tQ[u] * 16 + i) * S1_PITCH + kq;
+#pragma unroll
+            for (int k4 = 0; k4 < 16; k4 += 4)
+                D[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k4], yb[k4], D[u], 0, 0, 0);
+        }
     }
     const long np2 = (long)N * (N - 1) / 2;
     double* out = SK + (long)p * np2;
@@ -1731,10 +1905,9 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
         pqph_mark(ctx);
         if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
         const int s1m = pq_s1_mode(ctx, N);
-        if (s1m == 2) {        // materialised sides (an empty phase in the other modes)
-            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, c.X, gate);
-            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, c.Y, gate);
-        }
+        if (s1m == 2 || s1m == 4)     // materialised sides (an empty phase in the other modes)
+            hipLaunchKernelGGL(k_spec_xy, dim3((N * N + 511) / 512, PQ_X_N + PQ_Y_N), dim3(256), 0, s, N, v,
+                               c.X, c.Y, gate);
         pqph_mark(ctx);
         if (s1m == 3 && (N + 15) / 16 <= 8) {
             const dim3 gg(gemm_s1_grid(N));
@@ -1749,7 +1922,30 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 case 7: hipLaunchKernelGGL(k_gemm_s1p<7>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
                 default: hipLaunchKernelGGL(k_gemm_s1p<8>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
             }
-        } else if (s1m == 2) {
+        } else if (s1m == 4 && (N + 15) / 16 <= 8 &&
+                   ((N & 1) || ((reinterpret_cast<uintptr_t>(c.X) | reinterpret_cast<uintptr_t>(c.Y)) & 15) == 0)) {
+            // (16-byte loads of even-N rows need 16-byte aligned sides; else mode 2)
+            const dim3 gg(gemm_s1_grid(N));
+            const size_t lb = gemm_s1_lds(N);
+#define PQ_S1M_LAUNCH(NT)                                                                        \
+    do {                                                                                         \
+        if (N & 1)                                                                               \
+            hipLaunchKernelGGL((k_gemm_s1m<NT, false>), gg, dim3(256), lb, s, N, c.X, c.Y, c.S, gate); \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_gemm_s1m<NT, true>), gg, dim3(256), lb, s, N, c.X, c.Y, c.S, gate);  \
+    } while (0)
+            switch ((N + 15) / 16) {
+                case 1: PQ_S1M_LAUNCH(1); break;
+                case 2: PQ_S1M_LAUNCH(2); break;
+                case 3: PQ_S1M_LAUNCH(3); break;
+                case 4: PQ_S1M_LAUNCH(4); break;
+                case 5: PQ_S1M_LAUNCH(5); break;
+                case 6: PQ_S1M_LAUNCH(6); break;
+                case 7: PQ_S1M_LAUNCH(7); break;
+                default: PQ_S1M_LAUNCH(8); break;
+            }
+#undef PQ_S1M_LAUNCH
+        } else if (s1m == 2 || s1m == 4) {
             hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
                                c.X, c.Y, c.S, gate);
         } else {
@@ -1914,8 +2110,8 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
             if (pqph_status e_ = gemm_s1_prepare(ctx)) return e_;
             hipLaunchKernelGGL(k_bgemm, dim3(bgemm_tile_groups(N), PQ_DR_N), dim3(256), 0, s, N, 0,
                                c.Lam, c.W, c.D, nullptr);
-            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_X_N), dim3(256), 0, s, N, 0, v, Xf, nullptr);
-            hipLaunchKernelGGL(k_spec, dim3(gsq, PQ_Y_N), dim3(256), 0, s, N, 1, v, Yf, nullptr);
+            hipLaunchKernelGGL(k_spec_xy, dim3((N * N + 511) / 512, PQ_X_N + PQ_Y_N), dim3(256), 0, s, N, v,
+                               Xf, Yf, nullptr);
             hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
                                Xf, Yf, c.S, nullptr);
         }

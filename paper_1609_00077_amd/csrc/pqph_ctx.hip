@@ -354,8 +354,8 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant) {
 pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode) {
     pqph_status st = check_pq(ctx, npair);
     if (st) return st;
-    if (mode < 0 || mode > 3 || (mode == 3 && npair > 128))
-        return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, or 3 (3 needs npair <= 128)");
+    if (mode < 0 || mode > 4 || (mode >= 3 && npair > 128))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, 3 or 4 (3 and 4 need npair <= 128)");
     ctx->s1_mode[npair] = mode;
     return PQPH_OK;
 }
@@ -387,7 +387,7 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
     const int nvar = (npair + 15) / 16 <= 6 ? 2 : 1;
     float best = 1e30f;
     int bestv = 1, bestm = 1;
-    const int nmode = npair <= 128 ? 3 : 2;
+    const int nmode = npair <= 128 ? 4 : 2;
     for (int combo = 0; combo < nmode * nvar; ++combo) {
         const int var = 1 + combo % nvar, mode = 1 + combo / nvar;
         ctx->s2_variant[npair] = var;

@@ -105,7 +105,7 @@ def _golden(name):
         return json.load(fh)
 
 
-@pytest.mark.parametrize("s1_mode", [1, 2, 3])
+@pytest.mark.parametrize("s1_mode", [1, 2, 3, 4])
 @pytest.mark.parametrize("variant", [1, 2])
 def test_full_size_pq140_sampled_blocks(pq, variant, s1_mode):
     """140-site chain (70 pairs, the bench workload), seeded amplitudes, every
@@ -187,26 +187,29 @@ def test_two_spectator_variants_agree(pq, N):
     assert np.isfinite(outs[1]).all() and np.abs(outs[1]).max() > 0
 
 
-@pytest.mark.parametrize("N", [3, 24, 90])
+@pytest.mark.parametrize("N", [3, 24, 37, 90])
 def test_one_spectator_modes_agree(pq, N):
     """The one-spectator GEMM with its sides formed while staging (mode 1),
-    from materialised X, Y (mode 2) and formed while staging with pipelined
-    loads (mode 3) give the same residual; at N = 3 they match the
+    from materialised X, Y (mode 2), formed while staging with pipelined
+    loads (mode 3) and materialised with pipelined loads (mode 4; 16-byte
+    row loads for even N, odd N = 3 and 37 take the two-load path) give the
+    same residual, modes 2 and 4 bitwise; at N = 3 they match the
     definitional oracle."""
     f, eri = _random_system(N, 500 + N)
     t = random_amplitudes(N, "pq", seed=600 + N, scale=0.05)
     outs = {}
-    for mode in (1, 2, 3):
+    for mode in (1, 2, 3, 4):
         pq.set_s1_mode(N, mode)
         assert pq.tuning(N)["s1_mode"] == mode
         outs[mode] = pq.pq_residual(_d(f), _d(eri), _d(t)).cpu().numpy()
     pq.set_s1_mode(N, 0)
     tol = 1e-12 * max(1.0, np.abs(outs[1]).max())
-    for mode in (2, 3):
+    for mode in (2, 3, 4):
         assert np.abs(outs[mode] - outs[1]).max() <= tol, mode
+    assert np.array_equal(outs[4], outs[2])
     if N == 3:
         RA, _ = tier_a.TierA(N, 2).residual(f, layout.unpack_eri(eri, N, 2), t)
-        for mode in (1, 2, 3):
+        for mode in (1, 2, 3, 4):
             assert np.abs(outs[mode] - RA).max() <= 1e-12 * max(1.0, np.abs(RA).max()), mode
 
 
@@ -225,7 +228,7 @@ def test_concurrent_branches_bitwise_equal_serial(pq, N):
     assert torch.equal(R1, R2) and torch.equal(R1, R3)
 
 
-@pytest.mark.parametrize("s1_mode", [1, 2, 3])
+@pytest.mark.parametrize("s1_mode", [1, 2, 3, 4])
 @pytest.mark.parametrize("variant", [1, 2])
 def test_every_slot_pq66(pq, variant, s1_mode):
     """66-site chain (33 pairs): three 16-wide pair tiles with a ragged last
@@ -250,7 +253,7 @@ def test_every_slot_pq66(pq, variant, s1_mode):
     assert abs(pq.pq_energy(f, eri, _d(t)) - g["energy"]) < 1e-10
 
 
-@pytest.mark.parametrize("s1_mode", [1, 2, 3])
+@pytest.mark.parametrize("s1_mode", [1, 2, 3, 4])
 @pytest.mark.parametrize("variant", [1, 2])
 def test_full_size_pq140_edge_blocks(pq, variant, s1_mode):
     """140-site chain: output blocks inside the ragged last 16-wide pair tile
