@@ -360,7 +360,9 @@ def kernel_variant(phase: str, N: int, tuning: dict) -> str:
     counters are keyed by it: variants move different bytes)."""
     ncb = (N + 15) // 16
     if phase == "k_gemm_s1":
-        return {1: "k_gemm_s1<true>", 2: "k_gemm_s1<false>", 3: f"k_gemm_s1p<{ncb}>"}[tuning["s1_mode"]]
+        even = "true" if N % 2 == 0 else "false"
+        return {1: "k_gemm_s1<true>", 2: "k_gemm_s1<false>", 3: f"k_gemm_s1p<{ncb}>",
+                4: f"k_gemm_s1m<{ncb}, {even}>"}[tuning["s1_mode"]]
     if phase == "k_r2s2":
         if tuning["s2_variant"] == 2:
             return f"k_r2s2w<{ncb}>"
@@ -439,7 +441,7 @@ def counter_run(args, pq, torch, dev):
     N = prob.npair
     # every kernel choice the autotuner can make, counter_run residuals each
     for variant in ((1, 2) if (N + 15) // 16 <= 6 else (1,)):
-        for mode in ((1, 2, 3) if N <= 128 else (1, 2)):
+        for mode in ((1, 2, 3, 4) if N <= 128 else (1, 2)):
             pq.set_variant(N, variant)
             pq.set_s1_mode(N, mode)
             for _ in range(args.counter_run):

@@ -370,7 +370,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
     double* Xs = sm;                         // [NR][S1_PITCH]
     double* Ys = Xs + NR * S1_PITCH;         // [NR][S1_PITCH]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: tile indices in SGPRs
     double* Ts = Ys + NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
     const long NN = (long)N * N;
     const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
@@ -458,7 +459,8 @@ __global__ __launch_bounds__(256) void k_gemm_s1p(int N, View v, double* __restr
     const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
     double* Xs = sm;                          // [2][NR][S1_PITCH]
     double* Ys = Xs + 2 * NR * S1_PITCH;      // [2][NR][S1_PITCH]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: tile indices in SGPRs
     double* Ts = Ys + 2 * NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
     const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
     const SpecPtrs xq = spec_ptrs(pq_x_fac, pq_x_start[xi], pq_x_start[xi + 1], v);
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(256) void k_gemm_s1p(int N, View v, double* __restr
 // order and the epilogue are those of k_gemm_s1, so S is bitwise the same as
 // in mode 2.  NT = row tiles (N <= 16 NT).
 template <int NT, bool EVEN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_gemm_s1m(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 5 ? 5 : 4, 8))) void k_gemm_s1m(
     int N, const double* __restrict__ X, const double* __restrict__ Y, double* __restrict__ SK,
     const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int p = (int)(w / ngrp), tg = (int)(w % ngrp);
     double* Xs = sm;                          // [NR][S1_PITCH]
     double* Ys = Xs + NR * S1_PITCH;          // [NR][S1_PITCH]
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: tile indices in SGPRs
     double* Ts = Ys + NR * S1_PITCH + wave * 16 * S1_PITCH;   // [16][S1_PITCH] per wavefront
     const long NN = (long)N * N;
     const int xi = pq_s1pairs[2 * p], yi = pq_s1pairs[2 * p + 1];
