@@ -182,19 +182,28 @@ def ph_leg(args, pq, torch, dev):
                      "flops_per_launch": nfl,
                      "note": "interpreted work: one multiply per factor and one add per evaluated "
                              "term; the kernel is bound by its dependent table gathers"}}
+    # the same residual at spin-symmetric amplitudes, as the spin-adapted solve
+    # evaluates it (orbit representatives only): one iteration of that solve
+    # from t = 0 (the interpreted work does not depend on the amplitude values)
+    one = pq.ph_solve(f, eri, max_iter=1, diis_dim=0, spin_adapted=1, raise_on_failure=False)
+    out["residual"]["spin_symmetric_solve_iteration_ms"] = one.solve_ms
     if args.ph_solve or args.ph_solve_sites != args.ph_sites:
         sites = args.ph_sites if args.ph_solve else args.ph_solve_sites
         sp = chain_problem(sites, U=args.U, seed=sites)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        f, eri = pq.integrals(d(sp.F_site), d(sp.V), d(sp.C), k=3)
-        res = pq.ph_solve(f, eri, tol=args.tol)
-        torch.cuda.synchronize()
-        out["solve"] = {"workload": f"PH solve of a {sites}-site PPP chain ({sp.npair} pairs, "
-                                    f"U={args.U}, seed {sites}) from t=0 to ||R||<={args.tol:g}, "
-                                    "integral transform included",
-                        "solve_s": time.perf_counter() - t0, "iterations": res.iterations,
-                        "energy": res.energy, "status": res.status}
+        for spin in ((1,) if args.ph_solve else (0, 1)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f, eri = pq.integrals(d(sp.F_site), d(sp.V), d(sp.C), k=3)
+            res = pq.ph_solve(f, eri, tol=args.tol, spin_adapted=spin)
+            torch.cuda.synchronize()
+            out["solve_spin_adapted" if spin else "solve"] = {
+                "workload": f"PH solve of a {sites}-site PPP chain ({sp.npair} pairs, "
+                            f"U={args.U}, seed {sites}) from t=0 to ||R||<={args.tol:g}, "
+                            "integral transform included" + (", closed-shell spin adaptation" if spin else ""),
+                "solve_s": time.perf_counter() - t0, "iterations": res.iterations,
+                "energy": res.energy, "status": res.status}
+            print(f"ph solve {sites} sites spin_adapted={spin}: {time.perf_counter() - t0:.1f} s, "
+                  f"{res.iterations} iterations, E = {res.energy:.12f}", file=sys.stderr, flush=True)
     return out
 
 

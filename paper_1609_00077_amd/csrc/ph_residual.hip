@@ -327,20 +327,32 @@ __global__ __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))
 }
 
 // r(slot) = sign * (sum of the slot's unit sums, in unit order)
+// spin (may be null): per pattern of the 1/2/3-label blocks (offsets 0, 3,
+// 32), rep | negative << 16 -- a slot whose pattern is not its orbit's
+// representative takes the representative's value (same labels) with the sign
 __global__ void k_ph_gather(int N, long namp, PhArgs a, const int* __restrict__ ustart,
                             const double* __restrict__ part1, const double* __restrict__ part2,
-                            const double* __restrict__ part3, double* __restrict__ r) {
+                            const double* __restrict__ part3, const int* __restrict__ spin,
+                            double* __restrict__ r) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= namp) return;
     int n, m, L[3];
     decode_slot(s, N, n, m, L);
+    const int base = n == 1 ? 0 : n == 2 ? 3 : 32;
+    bool flip = false;
+    if (spin) {
+        const int w = spin[base + m];
+        m = w & 0xffff;
+        flip = (w >> 16) & 1;
+    }
     const long nsets = ncomb(N, n), si = set_index(L, n);
     const int* us = ustart + (n == 1 ? 0 : n == 2 ? 4 : 34);
     const double* part = n == 1 ? part1 : n == 2 ? part2 : part3;
     double sum = 0.0;
     for (int un = us[m]; un < us[m + 1]; ++un) sum += part[(long)un * nsets + si];
-    const int cn = a.canon[(n == 1 ? 0 : n == 2 ? 3 : 32) + m];
-    r[s] = (cn >> 15) & 1 ? -sum : sum;
+    const int cn = a.canon[base + m];
+    if ((cn >> 15) & 1) sum = -sum;
+    r[s] = flip ? -sum : sum;
 }
 
 // E_c = <0| H_3 e^T |0>: the energy classes (no output labels) over ordered
@@ -408,6 +420,7 @@ struct PhSched {
     void* dev = nullptr;
     PhUnits units[4] = {};
     const int* ustart = nullptr;
+    const int* spin = nullptr;    // pattern -> representative map (spin-symmetric schedules)
     int nunit[4] = {};
     size_t part_off[4] = {};      // partial sums of size n start here (doubles)
     size_t part_doubles = 0;
@@ -419,6 +432,7 @@ struct PhTables {
     int nh = 0;
     std::vector<int> starts_h, canon_h;     // host copies for scheduling
     std::vector<PhSched*> sched = std::vector<PhSched*>(257, nullptr);
+    std::vector<PhSched*> sched_sym = std::vector<PhSched*>(257, nullptr);   // representatives only
 };
 
 namespace {
@@ -656,11 +670,12 @@ pqph_status ph_tables_load(pqph_ctx* ctx) {
 
 void ph_tables_free(pqph_ctx* ctx) {
     if (!ctx->ph) return;
-    for (PhSched* sc : ctx->ph->sched)
-        if (sc) {
-            if (sc->dev) (void)hipFree(sc->dev);
-            delete sc;
-        }
+    for (auto* list : {&ctx->ph->sched, &ctx->ph->sched_sym})
+        for (PhSched* sc : *list)
+            if (sc) {
+                if (sc->dev) (void)hipFree(sc->dev);
+                delete sc;
+            }
     if (ctx->ph->dev) (void)hipFree(ctx->ph->dev);
     delete ctx->ph;
     ctx->ph = nullptr;
@@ -679,10 +694,17 @@ long host_ncomb(int N, int k) {
 }
 
 // units of at most U items, U chosen so that no block size has more than
-// 60000 units (the grid's second dimension)
-pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
+// 60000 units (the grid's second dimension); sym: units only for the output
+// patterns that represent their alpha/beta exchange orbit, and the pattern map
+// the gather uses for the others
+pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out, bool sym = false) {
     PhTables& tb = *ctx->ph;
-    if ((out = tb.sched[N])) return PQPH_OK;
+    std::vector<PhSched*>& cache = sym ? tb.sched_sym : tb.sched;
+    if ((out = cache[N])) return PQPH_OK;
+    int srep[3 + 29 + 303], ssgn[3 + 29 + 303];
+    spin_pattern_reps(1, srep, ssgn);
+    spin_pattern_reps(2, srep + 3, ssgn + 3);
+    spin_pattern_reps(3, srep + 32, ssgn + 32);
     const PhArgs& a = tb.args;
     auto items = [&](int n, int m, int c) -> long {
         const PhClass& k = a.cls[c];
@@ -708,9 +730,10 @@ pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
         const int npat = n == 1 ? 3 : n == 2 ? 29 : 303;
         first[n] = um.size();
         int cnt = 0;
+        const int base = n == 1 ? 0 : n == 2 ? 3 : 32;
         for (int m = 0; m < npat; ++m) {
             ustart.push_back(cnt);
-            if (n > N) continue;
+            if (n > N || (sym && srep[base + m] != m)) continue;
             for (int c = 0; c < a.nclass; ++c) {
                 const long it = items(n, m, c);
                 for (long i0 = 0; i0 < it; i0 += U) {
@@ -728,7 +751,7 @@ pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
         if (n <= N) sc->part_doubles += (size_t)cnt * host_ncomb(N, n);
     }
     const size_t nu = um.size();
-    const size_t bytes = nu * 24 + ustart.size() * 4 + 64;
+    const size_t bytes = nu * 24 + ustart.size() * 4 + (3 + 29 + 303) * 4 + 64;
     if (hipMalloc(&sc->dev, bytes) != hipSuccess) {
         delete sc;
         return pqph_fail(ctx, PQPH_OOM, "PH schedule: device allocation failed");
@@ -741,6 +764,9 @@ pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
     memcpy(p + o_m, um.data(), nu * 4);
     memcpy(p + o_c, uc.data(), nu * 4);
     memcpy(p + o_us, ustart.data(), ustart.size() * 4);
+    const size_t o_sp = o_us + ustart.size() * 4;
+    int* spin = reinterpret_cast<int*>(p + o_sp);
+    for (int i = 0; i < 3 + 29 + 303; ++i) spin[i] = srep[i] | (ssgn[i] < 0 ? 1 << 16 : 0);
     if (hipMemcpy(sc->dev, blob.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(sc->dev);
         delete sc;
@@ -754,7 +780,8 @@ pqph_status ph_schedule(pqph_ctx* ctx, int N, PhSched*& out) {
         sc->units[n].cls = reinterpret_cast<const int*>(d + o_c) + first[n];
     }
     sc->ustart = reinterpret_cast<const int*>(d + o_us);
-    tb.sched[N] = out = sc;
+    sc->spin = sym ? reinterpret_cast<const int*>(d + o_sp) : nullptr;
+    cache[N] = out = sc;
     return PQPH_OK;
 }
 
@@ -770,11 +797,11 @@ pqph_status ph_residual_ws_doubles(pqph_ctx* ctx, int N, size_t* out) {
 }
 
 pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
-                            const double* eri, const double* t, double* r, double* ws) {
+                            const double* eri, const double* t, double* r, double* ws, bool spin_sym) {
     pqph_status st = ph_tables_load(ctx);
     if (st) return st;
     PhSched* sc = nullptr;
-    if ((st = ph_schedule(ctx, N, sc))) return st;
+    if ((st = ph_schedule(ctx, N, sc, spin_sym))) return st;
     for (int n = 1; n <= 3 && n <= N; ++n) {
         if (sc->nunit[n] == 0) continue;
         hipLaunchKernelGGL(k_ph_part, dim3((unsigned)host_ncomb(N, n), (unsigned)sc->nunit[n]),
@@ -785,7 +812,7 @@ pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h
     const long namp = (long)ph_amp_len(N);
     hipLaunchKernelGGL(k_ph_gather, dim3((unsigned)((namp + 255) / 256)), dim3(256), 0, s, N, namp,
                        ctx->ph->args, sc->ustart, ws + sc->part_off[1], ws + sc->part_off[2],
-                       ws + sc->part_off[3], r);
+                       ws + sc->part_off[3], sc->spin, r);
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
 }

@@ -999,7 +999,8 @@ pqph_status ph_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     double rn = 0.0;
     pqph_status result = PQPH_OK;
     auto resid = [&](const double* x, double* r) {
-        return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws);
+        // the spin-adapted solve hands the residual spin-symmetric amplitudes
+        return ph_residual_dev(ctx, s, npair, h, eri, x, r, ctx->ws, o.spin_adapted != 0);
     };
     if ((st = space_solve(ctx, npair, 3, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
     double* edst = ctx->ws + wsd;

@@ -68,8 +68,12 @@ pqph_status ph_tables_load(pqph_ctx* ctx);
 void ph_tables_free(pqph_ctx* ctx);
 // ws: ph_residual_ws_doubles (the work units' partial sums)
 pqph_status ph_residual_ws_doubles(pqph_ctx* ctx, int N, size_t* out);
+// spin_sym: t is spin-symmetric (t[partner] = sign t under the alpha/beta
+// exchange): only the orbit representatives are evaluated, the partners are
+// copied with their sign
 pqph_status ph_residual_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
-                            const double* eri, const double* t, double* r, double* ws);
+                            const double* eri, const double* t, double* r, double* ws,
+                            bool spin_sym = false);
 size_t ph_energy_ws_doubles();
 pqph_status ph_energy_dev(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
                           const double* t, double* out, double* ws);
@@ -201,3 +205,6 @@ void launch_add_reference_occupation(hipStream_t s, double* gamma, int npair);
 size_t spin_len(int npair, int k);
 void launch_spin_pack(hipStream_t s, const double* v, double* x, int npair, int k, int mode);
 void launch_spin_unpack(hipStream_t s, const double* x, double* v, int npair, int k);
+// per pattern m of a label set of n pairs: its orbit representative rep[m]
+// and t[m] = sgn[m] * t[rep[m]] (rep[m] = m, sgn = 1 for a representative)
+void spin_pattern_reps(int n, int* rep, int* sgn);

@@ -215,3 +215,13 @@ void launch_spin_unpack(hipStream_t s, const double* x, double* v, int npair, in
     if (grid == 0) return;
     hipLaunchKernelGGL(k_spin_unpack, dim3(grid), dim3(256), 0, s, x, v, g);
 }
+
+void spin_pattern_reps(int n, int* rep, int* sgn) {
+    for (int q = 0; q < kOrbits.norb[n]; ++q) {
+        const int a = kOrbits.rep[n][q], b = kOrbits.par[n][q];
+        rep[a] = a;
+        sgn[a] = 1;
+        rep[b] = a;
+        sgn[b] = kOrbits.sgn[n][q];
+    }
+}
