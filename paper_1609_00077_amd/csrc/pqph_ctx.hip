@@ -170,10 +170,11 @@ pqph_status pqph_ensure_side(pqph_ctx* ctx) {
 
 int pq_s1_mode(const pqph_ctx* ctx, int npair) {
     if (npair >= 0 && npair <= 256 && ctx->s1_mode[npair]) return ctx->s1_mode[npair];
-    // untuned: forming the sides while staging wins at small N (no 1750 N x N
-    // arrays written and re-read); the materialised sides win once N^2 slices
-    // no longer sit in the caches
-    return npair >= 100 ? 2 : 1;
+    // untuned: the materialised sides with pipelined staging (mode 4) up to 128
+    // pairs (measured: equal to the other modes within noise below 50 pairs,
+    // 1.1x-1.4x faster residuals from 60 to 120), the plain materialised sides
+    // above, where mode 4 is not built
+    return npair <= 128 ? 4 : 2;
 }
 
 void pqph_mark(pqph_ctx* ctx) {
