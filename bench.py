@@ -450,7 +450,7 @@ def counter_run(args, pq, torch, dev):
     N = prob.npair
     # every kernel choice the autotuner can make, counter_run residuals each
     for variant in ((1, 2) if (N + 15) // 16 <= 6 else (1,)):
-        for mode in ((1, 2, 3, 4) if N <= 128 else (1, 2)):
+        for mode in ((1, 2, 3, 4) if N <= 128 else (1, 2, 4)):
             pq.set_variant(N, variant)
             pq.set_s1_mode(N, mode)
             for _ in range(args.counter_run):

@@ -276,13 +276,13 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant);
 
 /* Force how the one-spectator GEMM (Sec. II one-spectator terms, S_p(P,Q) =
  * sum_A X_x(P,A) Y_y(Q,A)) obtains its sides for npair on this context:
- * 0 = default (4 up to 128 pairs, 2 above, or as tuned by pqph_autotune),
+ * 0 = default (4, or as tuned by pqph_autotune),
  * 1 = each side formed
  * from its factors while staging, 2 = X and Y materialised first and read by
  * the GEMM, 3 = as 1 with the next chunk's loads overlapping the current
  * chunk's matrix-core steps (npair <= 128), 4 = as 2 with the next chunk's
- * loads overlapping the current chunk's matrix-core steps (npair <= 128;
- * bitwise the same as 2).  All give the same residual up to rounding order.
+ * loads overlapping the current chunk's matrix-core steps (bitwise the same
+ * as 2).  All give the same residual up to rounding order.
  * INVALID_ARG for another mode.  For tests and tuning. */
 pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
 

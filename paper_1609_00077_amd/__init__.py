@@ -155,8 +155,8 @@ def set_variant(npair: int, variant: int, device: str | torch.device = "cuda:0")
 def set_s1_mode(npair: int, mode: int, device: str | torch.device = "cuda:0") -> None:
     """Force how the one-spectator GEMM gets its sides for npair (1 formed
     while staging, 2 materialised, 3 formed while staging with the loads
-    pipelined, 4 materialised with the loads pipelined; 3 and 4 need
-    npair <= 128; 0 = default) on the context of the current stream."""
+    pipelined, npair <= 128, 4 materialised with the loads pipelined;
+    0 = default) on the context of the current stream."""
     lib, ctx = _ctx(torch.device(device))
     _check(lib, ctx, lib.pqph_set_s1_mode(ctx, npair, mode))
 

@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_gemm_s1p(int N, View v, double* __restr
 // order and the epilogue are those of k_gemm_s1, so S is bitwise the same as
 // in mode 2.  NT = row tiles (N <= 16 NT).
 template <int NT, bool EVEN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 5 ? 5 : 4, 8))) void k_gemm_s1m(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 5 ? 5 : NT <= 8 ? 4 : NT <= 10 ? 3 : 2, 8))) void k_gemm_s1m(
     int N, const double* __restrict__ X, const double* __restrict__ Y, double* __restrict__ SK,
     const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
@@ -1247,8 +1247,13 @@ __global__ void k_energy_adj(int N, View v, double ew, AdjView a) {
 // staged rows of Sbar_p, for fixed Q and running P, are contiguous.
 constexpr int S1A_T = 64, S1A_KC = 16, S1A_PITCH = S1A_KC + 1;
 
+// The staging is software-pipelined over the flattened (pair, K-chunk)
+// steps: each thread loads its four S-bar and four side elements of the next
+// step into registers (at clamped, in-bounds addresses) before the current
+// step's MFMAs and writes them, masked, to LDS after them.  Same staged values
+// and MFMA order as the plain form: the sums are bitwise unchanged.
 template <int SIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_s1_adj(int N, const double* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_s1_adj(int N, const double* __restrict__ X,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ Sb, double* __restrict__ out) {
     __shared__ double Us[S1A_T * S1A_PITCH];     // [row][k]: Sbar (SIDE 0) or Sbar^T (SIDE 1)
@@ -1257,7 +1262,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const int R0 = (blockIdx.x / nAt) * S1A_T, A0 = (blockIdx.x % nAt) * S1A_T;
     const int item = blockIdx.y;
     const long NN = (long)N * N, np2 = (long)N * (N - 1) / 2;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i16 = lane & 15, kq = lane >> 4;
     const int j0 = SIDE == 0 ? pq_s1ax_p0[item] : pq_s1ay_i0[item];
     const int j1 = SIDE == 0 ? pq_s1ax_p0[item + 1] : pq_s1ay_i0[item + 1];
@@ -1266,46 +1272,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     // K runs over Q > P (SIDE 0) or P < Q (SIDE 1): skip chunks that are all zero
     const int kbeg = SIDE == 0 ? R0 / S1A_KC * S1A_KC : 0;
     const int kend = SIDE == 0 ? N : min(N, R0 + S1A_T);
+    const int nkc = (kend - kbeg + S1A_KC - 1) / S1A_KC;
+    const int nstep = (j1 - j0) * nkc;
     d4 D[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int j = j0; j < j1; ++j) {
+    constexpr int NE = S1A_T * S1A_KC / 256;             // elements per thread and side
+    double u[NE], o[NE];
+    auto coords = [&](int i, int kc, int& row, int& k, int& P, int& Q) {
+        const int e = tid + 256 * i;
+        if (SIDE == 0) { row = e % S1A_T; k = e / S1A_T; }   // P fastest
+        else { k = e % S1A_KC; row = e / S1A_KC; }            // P fastest
+        const int R = R0 + row, K = kc + k;
+        P = SIDE == 0 ? R : K;
+        Q = SIDE == 0 ? K : R;
+    };
+    auto load = [&](int step) {
+        const int j = j0 + step / nkc, kc = kbeg + (step % nkc) * S1A_KC;
         const int p = SIDE == 0 ? j : pq_s1y_perm[j];
         const double* Sp = Sb + (long)p * np2;
         const double* other = SIDE == 0 ? Y + (long)pq_s1pairs[2 * p + 1] * NN
                                         : X + (long)pq_s1pairs[2 * p] * NN;
-        for (int kc = kbeg; kc < kend; kc += S1A_KC) {
-            for (int e = tid; e < S1A_T * S1A_KC; e += 256) {
-                int row, k;
-                if (SIDE == 0) { row = e % S1A_T; k = e / S1A_T; }   // P fastest
-                else { k = e % S1A_KC; row = e / S1A_KC; }            // P fastest
-                const int R = R0 + row, K = kc + k;
-                const int P = SIDE == 0 ? R : K, Q = SIDE == 0 ? K : R;
-                Us[row * S1A_PITCH + k] = (P < Q && Q < N) ? Sp[(long)Q * (Q - 1) / 2 + P] : 0.0;
-            }
-            for (int e = tid; e < S1A_KC * S1A_T; e += 256) {
-                const int k = e / S1A_T, A = A0 + e % S1A_T, K = kc + k;
-                Os[e] = (K < N && A < N) ? other[(long)K * N + A] : 0.0;
-            }
-            __syncthreads();
 #pragma unroll
-            for (int k4 = 0; k4 < S1A_KC; k4 += 4) {
-                const double av = Us[(wave * 16 + i16) * S1A_PITCH + k4 + kq];
+        for (int i = 0; i < NE; ++i) {
+            int row, k, P, Q;
+            coords(i, kc, row, k, P, Q);
+            const bool in = P < Q && Q < N;
+            u[i] = Sp[in ? (long)Q * (Q - 1) / 2 + P : 0];
+            const int e = tid + 256 * i, kk = e / S1A_T, A = A0 + e % S1A_T, K = kc + kk;
+            const bool ino = K < N && A < N;
+            o[i] = other[ino ? (long)K * N + A : 0];
+        }
+    };
+    auto store = [&](int step) {
+        const int kc = kbeg + (step % nkc) * S1A_KC;
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Os[(k4 + kq) * S1A_T + cb * 16 + i16], D[cb],
-                                                                 0, 0, 0);
-            }
-            __syncthreads();
+        for (int i = 0; i < NE; ++i) {
+            int row, k, P, Q;
+            coords(i, kc, row, k, P, Q);
+            Us[row * S1A_PITCH + k] = (P < Q && Q < N) ? u[i] : 0.0;
+            const int e = tid + 256 * i, kk = e / S1A_T, A = A0 + e % S1A_T, K = kc + kk;
+            Os[e] = (K < N && A < N) ? o[i] : 0.0;
+        }
+    };
+    if (nstep > 0) load(0);
+    for (int step = 0; step < nstep; ++step) {
+        __syncthreads();                      // the previous step's operands are consumed
+        store(step);
+        __syncthreads();
+        if (step + 1 < nstep) load(step + 1);     // in flight during this step's MFMAs
+#pragma unroll
+        for (int k4 = 0; k4 < S1A_KC; k4 += 4) {
+            const double av = Us[(wave * 16 + i16) * S1A_PITCH + k4 + kq];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                D[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Os[(k4 + kq) * S1A_T + cb * 16 + i16], D[cb],
+                                                             0, 0, 0);
         }
     }
-    double* o = out + (long)side * NN;
+    double* op = out + (long)side * NN;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int R = R0 + wave * 16 + kq + 4 * r, A = A0 + cb * 16 + i16;
-            if (R < N && A < N && R != A && D[cb][r] != 0.0) atomicAdd(&o[(long)R * N + A], D[cb][r]);
+            if (R < N && A < N && R != A && D[cb][r] != 0.0) atomicAdd(&op[(long)R * N + A], D[cb][r]);
         }
 }
 
@@ -1748,6 +1779,41 @@ inline unsigned bgemm_tile_groups(int N) {
     return (unsigned)(nt * ((nt + 3) / 4));
 }
 
+// the mode-4 one-spectator GEMM (materialised sides, pipelined staging);
+// false, launching nothing, when 16-byte row loads would be misaligned
+bool launch_gemm_s1m(hipStream_t s, int N, const double* X, const double* Y, double* S, const int* gate) {
+    if (!(N & 1) && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) != 0) return false;
+    const dim3 gg(gemm_s1_grid(N));
+    const size_t lb = gemm_s1_lds(N);
+#define PQ_S1M_LAUNCH(NT)                                                                             \
+    do {                                                                                              \
+        if (N & 1)                                                                                    \
+            hipLaunchKernelGGL((k_gemm_s1m<NT, false>), gg, dim3(256), lb, s, N, X, Y, S, gate);      \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_gemm_s1m<NT, true>), gg, dim3(256), lb, s, N, X, Y, S, gate);       \
+    } while (0)
+    switch ((N + 15) / 16) {
+        case 1: PQ_S1M_LAUNCH(1); break;
+        case 2: PQ_S1M_LAUNCH(2); break;
+        case 3: PQ_S1M_LAUNCH(3); break;
+        case 4: PQ_S1M_LAUNCH(4); break;
+        case 5: PQ_S1M_LAUNCH(5); break;
+        case 6: PQ_S1M_LAUNCH(6); break;
+        case 7: PQ_S1M_LAUNCH(7); break;
+        case 8: PQ_S1M_LAUNCH(8); break;
+        case 9: PQ_S1M_LAUNCH(9); break;
+        case 10: PQ_S1M_LAUNCH(10); break;
+        case 11: PQ_S1M_LAUNCH(11); break;
+        case 12: PQ_S1M_LAUNCH(12); break;
+        case 13: PQ_S1M_LAUNCH(13); break;
+        case 14: PQ_S1M_LAUNCH(14); break;
+        case 15: PQ_S1M_LAUNCH(15); break;
+        default: PQ_S1M_LAUNCH(16); break;
+    }
+#undef PQ_S1M_LAUNCH
+    return true;
+}
+
 // allows the largest staging (npair 256) once per process
 pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     static bool done = false;
@@ -1764,6 +1830,16 @@ pqph_status gemm_s1_prepare(pqph_ctx* ctx) {
     for (int nt = 1; nt <= 8 && e == hipSuccess; ++nt)
         e = hipFuncSetAttribute(pipelined[nt - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)gemm_s1p_lds(nt * 16));
+#define PQ_S1M_ATTR(NT)                                                                                    \
+    if (e == hipSuccess)                                                                                   \
+        e = hipFuncSetAttribute((const void*)&k_gemm_s1m<NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)gemm_s1_lds(NT * 16));                                                \
+    if (e == hipSuccess)                                                                                   \
+        e = hipFuncSetAttribute((const void*)&k_gemm_s1m<NT, false>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                (int)gemm_s1_lds(NT * 16));
+    PQ_S1M_ATTR(9) PQ_S1M_ATTR(10) PQ_S1M_ATTR(11) PQ_S1M_ATTR(12)
+    PQ_S1M_ATTR(13) PQ_S1M_ATTR(14) PQ_S1M_ATTR(15) PQ_S1M_ATTR(16)
+#undef PQ_S1M_ATTR
     if (e != hipSuccess)
         return pqph_fail(ctx, PQPH_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
     done = true;
@@ -1925,29 +2001,8 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                 case 7: hipLaunchKernelGGL(k_gemm_s1p<7>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
                 default: hipLaunchKernelGGL(k_gemm_s1p<8>, gg, dim3(256), lb, s, N, v, c.S, gate); break;
             }
-        } else if (s1m == 4 && (N + 15) / 16 <= 8 &&
-                   ((N & 1) || ((reinterpret_cast<uintptr_t>(c.X) | reinterpret_cast<uintptr_t>(c.Y)) & 15) == 0)) {
-            // (16-byte loads of even-N rows need 16-byte aligned sides; else mode 2)
-            const dim3 gg(gemm_s1_grid(N));
-            const size_t lb = gemm_s1_lds(N);
-#define PQ_S1M_LAUNCH(NT)                                                                        \
-    do {                                                                                         \
-        if (N & 1)                                                                               \
-            hipLaunchKernelGGL((k_gemm_s1m<NT, false>), gg, dim3(256), lb, s, N, c.X, c.Y, c.S, gate); \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_gemm_s1m<NT, true>), gg, dim3(256), lb, s, N, c.X, c.Y, c.S, gate);  \
-    } while (0)
-            switch ((N + 15) / 16) {
-                case 1: PQ_S1M_LAUNCH(1); break;
-                case 2: PQ_S1M_LAUNCH(2); break;
-                case 3: PQ_S1M_LAUNCH(3); break;
-                case 4: PQ_S1M_LAUNCH(4); break;
-                case 5: PQ_S1M_LAUNCH(5); break;
-                case 6: PQ_S1M_LAUNCH(6); break;
-                case 7: PQ_S1M_LAUNCH(7); break;
-                default: PQ_S1M_LAUNCH(8); break;
-            }
-#undef PQ_S1M_LAUNCH
+        } else if (s1m == 4 && launch_gemm_s1m(s, N, c.X, c.Y, c.S, gate)) {
+            // (16-byte loads of even-N rows need 16-byte aligned sides; else mode 2 below)
         } else if (s1m == 2 || s1m == 4) {
             hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
                                c.X, c.Y, c.S, gate);
@@ -2115,8 +2170,9 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                                c.Lam, c.W, c.D, nullptr);
             hipLaunchKernelGGL(k_spec_xy, dim3((N * N + 511) / 512, PQ_X_N + PQ_Y_N), dim3(256), 0, s, N, v,
                                Xf, Yf, nullptr);
-            hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
-                               Xf, Yf, c.S, nullptr);
+            if (!launch_gemm_s1m(s, N, Xf, Yf, c.S, nullptr))   // bitwise the S of mode 2
+                hipLaunchKernelGGL(k_gemm_s1<false>, dim3(gemm_s1_grid(N)), dim3(256), gemm_s1_lds(N), s, N, v,
+                                   Xf, Yf, c.S, nullptr);
         }
         launch_r2_lane_adj(s, N, t, c.h1, c.h2T, c.S, lam, a.tb1, a.tb2, a.hb1, a.hb2, Sb);
         if (pq_intermediates(ctx, N) == 3) {      // adjoint of the doubly-mixed terms

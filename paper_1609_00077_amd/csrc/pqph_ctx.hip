@@ -170,11 +170,10 @@ pqph_status pqph_ensure_side(pqph_ctx* ctx) {
 
 int pq_s1_mode(const pqph_ctx* ctx, int npair) {
     if (npair >= 0 && npair <= 256 && ctx->s1_mode[npair]) return ctx->s1_mode[npair];
-    // untuned: the materialised sides with pipelined staging (mode 4) up to 128
-    // pairs (measured: equal to the other modes within noise below 50 pairs,
-    // 1.1x-1.4x faster residuals from 60 to 120), the plain materialised sides
-    // above, where mode 4 is not built
-    return npair <= 128 ? 4 : 2;
+    // untuned: the materialised sides with pipelined staging (mode 4; measured:
+    // equal to the other modes within noise below 50 pairs, 1.1x-1.4x faster
+    // residuals from 60 to 120 pairs)
+    return 4;
 }
 
 void pqph_mark(pqph_ctx* ctx) {
@@ -355,8 +354,8 @@ pqph_status pqph_set_variant(pqph_ctx* ctx, int npair, int variant) {
 pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode) {
     pqph_status st = check_pq(ctx, npair);
     if (st) return st;
-    if (mode < 0 || mode > 4 || (mode >= 3 && npair > 128))
-        return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, 3 or 4 (3 and 4 need npair <= 128)");
+    if (mode < 0 || mode > 4 || (mode == 3 && npair > 128))
+        return pqph_fail(ctx, PQPH_INVALID_ARG, "mode must be 0, 1, 2, 3 or 4 (3 needs npair <= 128)");
     ctx->s1_mode[npair] = mode;
     return PQPH_OK;
 }
@@ -388,9 +387,11 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
     const int nvar = (npair + 15) / 16 <= 6 ? 2 : 1;
     float best = 1e30f;
     int bestv = 1, bestm = 1;
-    const int nmode = npair <= 128 ? 4 : 2;
+    // modes 1..4 up to 128 pairs; above, 1, 2 and 4 (mode 3 is not built there)
+    const int modes[4] = {1, 2, npair <= 128 ? 3 : 4, 4};
+    const int nmode = npair <= 128 ? 4 : 3;
     for (int combo = 0; combo < nmode * nvar; ++combo) {
-        const int var = 1 + combo % nvar, mode = 1 + combo / nvar;
+        const int var = 1 + combo % nvar, mode = modes[combo / nvar];
         ctx->s2_variant[npair] = var;
         ctx->s1_mode[npair] = mode;
         for (int rep = 0; rep < 2; ++rep) {      // first run warms up

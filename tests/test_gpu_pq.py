@@ -213,6 +213,24 @@ def test_one_spectator_modes_agree(pq, N):
             assert np.abs(outs[mode] - RA).max() <= 1e-12 * max(1.0, np.abs(RA).max()), mode
 
 
+@pytest.mark.parametrize("N", [150, 201])
+def test_one_spectator_modes_agree_above_128_pairs(pq, N):
+    """Above 128 pairs (where the pipelined fused mode 3 is not built) the
+    pipelined materialised mode 4 (ten and thirteen row tiles, LDS beyond
+    64 KiB; odd N = 201 on the two-load path) is bitwise mode 2 and agrees
+    with the fused mode 1."""
+    prob = chain_problem(2 * N, U=4.0, seed=2 * N)
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    t = _d(random_amplitudes(N, "pq", seed=700 + N, scale=0.05))
+    outs = {}
+    for mode in (1, 2, 4):
+        pq.set_s1_mode(N, mode)
+        outs[mode] = pq.pq_residual(f, eri, t).cpu().numpy()
+    pq.set_s1_mode(N, 0)
+    assert np.array_equal(outs[4], outs[2])
+    assert np.abs(outs[4] - outs[1]).max() <= 1e-12 * max(1.0, np.abs(outs[1]).max())
+
+
 @pytest.mark.parametrize("N", [3, 70])
 def test_concurrent_branches_bitwise_equal_serial(pq, N):
     """pq_residual runs the residual's independent branches on side streams;
