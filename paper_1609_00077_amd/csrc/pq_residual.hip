@@ -810,6 +810,101 @@ constexpr int M2_KC = 16;
 // k_r2s2 20-37 % faster, k_r2s2_adjm 14 %, k_s1_adj up to 19 %, even where a
 // few registers spill).
 
+// Closing of a two-spectator group against one B-side link b of NB factors:
+// s[r] = sum over this lane's columns B of V(row r, B) L_b(P, Q, B), for the
+// wavefront's four rows of this lane.  The loads of a row are issued together
+// (columns clamped in range, masked when added).  QM marks the factors read
+// at Q (bit f): when the wavefront's 16 rows share Q (consecutive output
+// pairs) their product is formed once per column for all four rows, and each
+// row loads only its factors read at P.  Otherwise (QM = 0 call, or rows with
+// different Q) every factor is loaded per row.
+template <int NCB, int NB, int QM>
+__device__ __forceinline__ void r2s2_close(int b, int N, const View& v, const int* rowP, const int* rowQ,
+                                          int wave, int lane, const d4* D, double* s) {
+    const double* base[NB > 0 ? NB : 1];
+    double qp[NCB];
+    if (QM) {
+        const int Q0 = rowQ[wave * 16];
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+            if (QM >> f & 1) base[f] = v.t2 + (long)pq_ld_m[3 * b + f] * v.NN + (long)Q0 * v.N;
+        double lq[NCB][NB > 0 ? NB : 1];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int col = cb * 16 + (lane & 15);
+            const int cc = col < N ? col : 0;
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+                if (QM >> f & 1) lq[cb][f] = base[f][cc];
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            double x = 1.0;
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+                if (QM >> f & 1) x *= lq[cb][f];
+            qp[cb] = x;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        s[r] = 0.0;
+        const int row = wave * 16 + (lane >> 4) + 4 * r;
+        const int P = rowP[row], Q = rowQ[row];
+        if (P < 0) continue;
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+            if (!(QM >> f & 1))
+                base[f] = v.t2 + (long)pq_ld_m[3 * b + f] * v.NN + (long)(pq_ld_q[3 * b + f] ? Q : P) * v.N;
+        double l[NCB][NB > 0 ? NB : 1];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int col = cb * 16 + (lane & 15);
+            const int cc = col < N ? col : 0;
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+                if (!(QM >> f & 1)) l[cb][f] = base[f][cc];
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int col = cb * 16 + (lane & 15);
+            double x = QM ? qp[cb] : 1.0;
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+                if (!(QM >> f & 1)) x *= l[cb][f];
+            if (col < N && col != P && col != Q) s[r] += D[cb][r] * x;
+        }
+    }
+}
+
+// dispatch on the link's factor count and, for wavefronts whose rows share
+// Q, on which factors are read at Q
+template <int NCB>
+__device__ __forceinline__ void r2s2_close_any(int b, int N, const View& v, const int* rowP, const int* rowQ,
+                                              int wave, int lane, const d4* D, double* s, bool qsame) {
+    const int nb = pq_ld_n[b];
+    int qm = 0;
+    if (qsame)
+        for (int f = 0; f < nb; ++f) qm |= (pq_ld_q[3 * b + f] ? 1 : 0) << f;
+    switch (nb * 8 + qm) {
+        case 0: r2s2_close<NCB, 0, 0>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 8: r2s2_close<NCB, 1, 0>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 9: r2s2_close<NCB, 1, 1>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 16: r2s2_close<NCB, 2, 0>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 17: r2s2_close<NCB, 2, 1>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 18: r2s2_close<NCB, 2, 2>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 19: r2s2_close<NCB, 2, 3>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 24: r2s2_close<NCB, 3, 0>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 25: r2s2_close<NCB, 3, 1>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 26: r2s2_close<NCB, 3, 2>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 27: r2s2_close<NCB, 3, 3>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 28: r2s2_close<NCB, 3, 4>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 29: r2s2_close<NCB, 3, 5>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        case 30: r2s2_close<NCB, 3, 6>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+        default: r2s2_close<NCB, 3, 7>(b, N, v, rowP, rowQ, wave, lane, D, s); break;
+    }
+}
+
 template <int NCB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_r2s2(int N, View v, const double* __restrict__ W,
                                               int gchunk, double* __restrict__ part, const int* __restrict__ gate) {
@@ -831,6 +926,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     for (int i = tid; i < M2_ROWS * NP2; i += 256) acc[i] = 0.0;
     __syncthreads();
+    // rows are consecutive output pairs (Q non-decreasing; missing rows last)
+    const bool qsame = rowQ[wave * 16 + 15] >= 0 && rowQ[wave * 16] == rowQ[wave * 16 + 15];
     const int KP = (N + M2_KC - 1) / M2_KC * M2_KC;
     const int g0 = blockIdx.y * gchunk, g1 = min(PQ_G_N, g0 + gchunk);
     for (int g = g0; g < g1; ++g) {
@@ -870,18 +967,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int i = pq_g_start[g]; i < pq_g_start[g + 1]; ++i) {
             const int b = pq_g_b[i], m = pq_g_mu[i];
             double s[4];
+            if constexpr (NCB <= 6) {
+                // the link length is uniform: straight-line products whose loads
+                // are all in flight together, row by row (measured: the closing
+                // took half of this kernel with one round trip per product)
+                r2s2_close_any<NCB>(b, N, v, rowP, rowQ, wave, lane, D, s, qsame);
+            } else {      // wide rows: the registers of the straight-line form would spill
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                s[r] = 0.0;
-                const int row = wave * 16 + (lane >> 4) + 4 * r;
-                const int P = rowP[row], Q = rowQ[row];
-                if (P >= 0) {
-                    Link L;
-                    link_rows(b, P, Q, v, L);
+                for (int r = 0; r < 4; ++r) {
+                    s[r] = 0.0;
+                    const int row = wave * 16 + (lane >> 4) + 4 * r;
+                    const int P = rowP[row], Q = rowQ[row];
+                    if (P >= 0) {
+                        Link L;
+                        link_rows(b, P, Q, v, L);
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) {
-                        const int col = cb * 16 + (lane & 15);
-                        if (col < N && col != P && col != Q) s[r] += D[cb][r] * link_at(L, col);
+                        for (int cb = 0; cb < NCB; ++cb) {
+                            const int col = cb * 16 + (lane & 15);
+                            if (col < N && col != P && col != Q) s[r] += D[cb][r] * link_at(L, col);
+                        }
                     }
                 }
             }
