@@ -218,6 +218,46 @@ __device__ __forceinline__ double link_at(const Link& L, int A) {
     return x;
 }
 
+// Link products of one spec s (NB factors, uniform over the workgroup) for a
+// thread's four staged elements: rows with labels (P[j], Q[j]) at one
+// spectator label A (clamped into range by the caller's masks: every load
+// is in bounds).  All NB x 4 loads are issued together; the factors are
+// multiplied in their listed order, as link_at does.
+template <int NB>
+__device__ __forceinline__ void link_vals4(int s, const int* P, const int* Q, int A, const View& v,
+                                          double* out) {
+    int fm[NB > 0 ? NB : 1];
+    bool fq[NB > 0 ? NB : 1];
+#pragma unroll
+    for (int f = 0; f < NB; ++f) {
+        fm[f] = pq_ld_m[3 * s + f];
+        fq[f] = pq_ld_q[3 * s + f] != 0;
+    }
+    double l[4][NB > 0 ? NB : 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+            l[j][f] = v.t2[(long)fm[f] * v.NN + (long)(fq[f] ? Q[j] : P[j]) * v.N + A];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double x = NB > 0 ? l[j][0] : 1.0;
+#pragma unroll
+        for (int f = 1; f < NB; ++f) x *= l[j][f];
+        out[j] = x;
+    }
+}
+
+__device__ __forceinline__ void link_vals4_any(int s, const int* P, const int* Q, int A, const View& v,
+                                              double* out) {
+    switch (pq_ld_n[s]) {
+        case 0: link_vals4<0>(s, P, Q, A, v, out); break;
+        case 1: link_vals4<1>(s, P, Q, A, v, out); break;
+        case 2: link_vals4<2>(s, P, Q, A, v, out); break;
+        default: link_vals4<3>(s, P, Q, A, v, out); break;
+    }
+}
+
 // ------------------------------------------------------------ one spectator
 
 // S[p][pq] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
@@ -803,6 +843,8 @@ __global__ __launch_bounds__(256) void k_spec_r1(int N, View v, double* __restri
 // the groups, whose partial sums are combined in k_final.
 constexpr int M2_ROWS = 64;
 constexpr int M2_KC = 16;
+// the staging loops give each of 256 threads four elements (rows tid/16 + 16 j, spectator tid % 16)
+static_assert(M2_ROWS * M2_KC == 4 * 256 && M2_KC == 16, "two-spectator staging layout");
 // The matrix-core kernels below ask for more resident wavefronts per SIMD
 // (amdgpu_waves_per_eu) than their register use would give by default: the
 // MFMA accumulators otherwise take AGPRs that halve the occupancy, and the
@@ -937,16 +979,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
         for (int kc = 0; kc < KP; kc += M2_KC) {
-            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
-                const int row = i / M2_KC, A = kc + i % M2_KC;
-                const int P = rowP[row], Q = rowQ[row];
-                double x = 0.0;
-                if (P >= 0 && A < N && A != P && A != Q) {
-                    Link L;
-                    link_rows(a, P, Q, v, L);
-                    x = link_at(L, A);
+            if constexpr (NCB <= 6) {   // four elements: rows tid/16 + 16 j, one spectator A
+                const int A = kc + (tid & 15);
+                int Pj[4], Qj[4];
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = (tid >> 4) + 16 * j;
+                    const int P = rowP[row], Q = rowQ[row];
+                    ok[j] = P >= 0 && A < N && A != P && A != Q;
+                    Pj[j] = P >= 0 ? P : 0;
+                    Qj[j] = P >= 0 ? Q : 0;
                 }
-                La[i] = x;
+                double x[4];
+                link_vals4_any(a, Pj, Qj, A < N ? A : 0, v, x);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) La[tid + 256 * j] = ok[j] ? x[j] : 0.0;
+            } else {      // wide rows: the accumulators leave no registers for batched loads
+                for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
+                    const int row = i / M2_KC, A = kc + i % M2_KC;
+                    const int P = rowP[row], Q = rowQ[row];
+                    double x = 0.0;
+                    if (P >= 0 && A < N && A != P && A != Q) {
+                        Link L;
+                        link_rows(a, P, Q, v, L);
+                        x = link_at(L, A);
+                    }
+                    La[i] = x;
+                }
             }
             for (int i = tid; i < M2_KC * NC; i += 256) {
                 const int A = kc + i / NC, col = i % NC;
@@ -1621,16 +1681,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
         for (int kc = 0; kc < KP; kc += M2_KC) {
-            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
-                const int row = i / M2_KC, A = kc + i % M2_KC;
-                const int P = rowP[row], Q = rowQ[row];
-                double x = 0.0;
-                if (P >= 0 && A < N && A != P && A != Q) {
-                    Link L;
-                    link_rows(sa, P, Q, v, L);
-                    x = link_at(L, A);
+            {   // the thread's four elements: rows tid/16 + 16 j, one spectator A
+                const int A = kc + (tid & 15);
+                int Pj[4], Qj[4];
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = (tid >> 4) + 16 * j;
+                    const int P = rowP[row], Q = rowQ[row];
+                    ok[j] = P >= 0 && A < N && A != P && A != Q;
+                    Pj[j] = P >= 0 ? P : 0;
+                    Qj[j] = P >= 0 ? Q : 0;
                 }
-                Ls[i] = x;
+                double x[4];
+                link_vals4_any(sa, Pj, Qj, A < N ? A : 0, v, x);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) Ls[tid + 256 * j] = ok[j] ? x[j] : 0.0;
             }
             const double* Wg = W + (long)w * v.NN;
             for (int i = tid; i < M2_KC * NC; i += 256) {
@@ -1667,20 +1733,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) D[cb] = d4{0.0, 0.0, 0.0, 0.0};
         for (int kc = 0; kc < KP; kc += M2_KC) {
-            for (int i = tid; i < M2_ROWS * M2_KC; i += 256) {
-                const int row = i / M2_KC, B = kc + i % M2_KC;
-                const int P = rowP[row], Q = rowQ[row];
-                double x = 0.0;
-                if (P >= 0 && B < N && B != P && B != Q) {
-                    for (int ii = ib0; ii < ib1; ++ii) {
-                        const double wb = pq_g_coef[ii] * lamr[row][pq_g_mu[ii]];
-                        if (wb == 0.0) continue;
-                        Link L;
-                        link_rows(pq_g_b[ii], P, Q, v, L);
-                        x += wb * link_at(L, B);
+            {   // Vbar for the thread's four elements, one B-side link at a time
+                const int B = kc + (tid & 15);
+                int Pj[4], Qj[4];
+                bool ok[4];
+                double x[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = (tid >> 4) + 16 * j;
+                    const int P = rowP[row], Q = rowQ[row];
+                    ok[j] = P >= 0 && B < N && B != P && B != Q;
+                    Pj[j] = P >= 0 ? P : 0;
+                    Qj[j] = P >= 0 ? Q : 0;
+                    x[j] = 0.0;
+                }
+                for (int ii = ib0; ii < ib1; ++ii) {
+                    double lv[4];
+                    link_vals4_any(pq_g_b[ii], Pj, Qj, B < N ? B : 0, v, lv);
+                    const double c = pq_g_coef[ii];
+                    const int mu = pq_g_mu[ii];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double wb = c * lamr[(tid >> 4) + 16 * j][mu];
+                        if (wb != 0.0) x[j] += wb * lv[j];
                     }
                 }
-                Ls[i] = x;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) Ls[tid + 256 * j] = ok[j] ? x[j] : 0.0;
             }
             const double* WTg = W + (long)wt * v.NN;     // W^T(B, A) = W(A, B)
             for (int i = tid; i < M2_KC * NC; i += 256) {
