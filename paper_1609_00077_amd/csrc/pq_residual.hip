@@ -258,6 +258,38 @@ __device__ __forceinline__ void link_vals4_any(int s, const int* P, const int* Q
     }
 }
 
+// Link products of one spec s (NB factors) for one row (P, Q) at four
+// spectator labels A[j] (in range): all loads issued together, factors
+// multiplied in their listed order.
+template <int NB>
+__device__ __forceinline__ void link_row4(int s, int P, int Q, const int* A, const View& v, double* out) {
+    const double* base[NB > 0 ? NB : 1];
+#pragma unroll
+    for (int f = 0; f < NB; ++f)
+        base[f] = v.t2 + (long)pq_ld_m[3 * s + f] * v.NN + (long)(pq_ld_q[3 * s + f] ? Q : P) * v.N;
+    double l[4][NB > 0 ? NB : 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int f = 0; f < NB; ++f) l[j][f] = base[f][A[j]];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double x = NB > 0 ? l[j][0] : 1.0;
+#pragma unroll
+        for (int f = 1; f < NB; ++f) x *= l[j][f];
+        out[j] = x;
+    }
+}
+
+__device__ __forceinline__ void link_row4_any(int s, int P, int Q, const int* A, const View& v, double* out) {
+    switch (pq_ld_n[s]) {
+        case 0: link_row4<0>(s, P, Q, A, v, out); break;
+        case 1: link_row4<1>(s, P, Q, A, v, out); break;
+        case 2: link_row4<2>(s, P, Q, A, v, out); break;
+        default: link_row4<3>(s, P, Q, A, v, out); break;
+    }
+}
+
 // ------------------------------------------------------------ one spectator
 
 // S[p][pq] = S_p(P,Q) = sum_A X_x(P,A) Y_y(Q,A) for P < Q, on the FP64
@@ -1797,7 +1829,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // Wbar with one atomic per element (a few per element over all slices).
 constexpr int WB_T = 64, WB_KC = 16, WB_PITCH = WB_KC + 1;
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_wbar(int N, View v, const double* __restrict__ lam,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_wbar(int N, View v, const double* __restrict__ lam,
                                               long per, double* __restrict__ Wb) {
     __shared__ double Ls[WB_T * WB_PITCH];   // [A local][pair in chunk]
     __shared__ double Vs[WB_T * WB_PITCH];   // [B local][pair in chunk]
@@ -1820,22 +1852,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         double la[4], vb[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) la[j] = vb[j] = 0.0;
-        if (P >= 0) {
-            Link L;
-            link_rows(a, P, Q, v, L);
+        if (P >= 0) {      // straight-line link products, four labels at a time
+            int Ac[4], Bc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int A = A0 + l + 16 * j, B = B0 + l + 16 * j;
+                Ac[j] = A < N ? A : 0;
+                Bc[j] = B < N ? B : 0;
+            }
+            double x[4];
+            link_row4_any(a, P, Q, Ac, v, x);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int A = A0 + l + 16 * j;
-                if (A < N && A != P && A != Q) la[j] = link_at(L, A);
+                if (A < N && A != P && A != Q) la[j] = x[j];
             }
             for (int i = ib0; i < ib1; ++i) {
                 const double wb = pq_g_coef[i] * lam[3L * N + (long)pq_g_mu[i] * np2 + ip];
                 if (wb == 0.0) continue;
-                link_rows(pq_g_b[i], P, Q, v, L);
+                link_row4_any(pq_g_b[i], P, Q, Bc, v, x);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int B = B0 + l + 16 * j;
-                    if (B < N && B != P && B != Q) vb[j] += wb * link_at(L, B);
+                    if (B < N && B != P && B != Q) vb[j] += wb * x[j];
                 }
             }
         }
