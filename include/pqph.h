@@ -126,8 +126,11 @@ typedef struct {
                               (+ 155 C(N,3) for PH) values instead of
                               3N + 29 C(N,2) (+ 303 C(N,3)): every solver
                               vector and DIIS history shrinks to about
-                              half.  The residual itself still runs on the
-                              full packed vectors.  Exact for the spin-free
+                              half.  The residual runs on full packed
+                              vectors unpacked from the reduced one; the PH
+                              residual then evaluates only the orbit
+                              representatives and copies their partners
+                              with the sign.  Exact for the spin-free
                               integrals of this library: the solution is
                               the one of the full space; start amplitudes
                               are first projected onto the symmetric
