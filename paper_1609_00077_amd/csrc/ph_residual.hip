@@ -52,31 +52,35 @@ struct PhArgs {
     const int* quad;        // 3 x 1296
 };
 
-__device__ __forceinline__ long ncomb(int N, int k) {
+// Index arithmetic in 32 bits: with npair <= 256 every packed position fits
+// (ph_amp_len(256) = 837 M, ph_eri_len(256) = 233 M, N (N-1) (N-2) <= 16.6 M),
+// and 32-bit multiplies are a fraction of the 64-bit ones in this interpreted
+// hot loop.  Offsets into the per-unit partial sums stay 64-bit.
+__device__ __forceinline__ int ncomb(int N, int k) {
     if (k == 1) return N;
-    if (k == 2) return (long)N * (N - 1) / 2;
-    return (long)N * (N - 1) * (N - 2) / 6;
+    if (k == 2) return N * (N - 1) / 2;
+    return N * (N - 1) * (N - 2) / 6;
 }
 
 // index of an ascending label set in the packed layout
-__device__ __forceinline__ long set_index(const int* l, int n) {
+__device__ __forceinline__ int set_index(const int* l, int n) {
     if (n == 1) return l[0];
-    if (n == 2) return (long)l[1] * (l[1] - 1) / 2 + l[0];
-    return (long)l[2] * (l[2] - 1) * (l[2] - 2) / 6 + (long)l[1] * (l[1] - 1) / 2 + l[0];
+    if (n == 2) return l[1] * (l[1] - 1) / 2 + l[0];
+    return l[2] * (l[2] - 1) * (l[2] - 2) / 6 + l[1] * (l[1] - 1) / 2 + l[0];
 }
 
-__device__ __forceinline__ long amp_off(int N, int n) {
-    return n == 1 ? 0 : n == 2 ? 3L * N : 3L * N + 29 * ncomb(N, 2);
+__device__ __forceinline__ int amp_off(int N, int n) {
+    return n == 1 ? 0 : n == 2 ? 3 * N : 3 * N + 29 * ncomb(N, 2);
 }
 
-__device__ __forceinline__ long eri_off(int N, int n) {
-    return n == 1 ? 0 : n == 2 ? 6L * N : 6L * N + 43 * ncomb(N, 2);
+__device__ __forceinline__ int eri_off(int N, int n) {
+    return n == 1 ? 0 : n == 2 ? 6 * N : 6 * N + 43 * ncomb(N, 2);
 }
 
 // packed position of one amplitude factor: the labels of its roles, put in
 // ascending order (swapping two odd patterns flips the sign); -1 for no
 // factor (code 0) or a pattern tuple the layout does not store
-__device__ __forceinline__ long amp_pos(const PhArgs& a, const int* lab, int code, int N,
+__device__ __forceinline__ int amp_pos(const PhArgs& a, const int* lab, int code, int N,
                                         double& sg) {
     const int n = code & 3;
     int l[3], p[3];
@@ -114,7 +118,7 @@ __device__ __forceinline__ double hval(const PhArgs& a, const int* lab, int hidx
         for (int i = 0; i < 4; ++i) x[i] = (c >> (4 + 4 * i)) & 15;
         if ((c & 15) == 0) {
             const int o0 = lab[x[0] >> 1] + N * (x[0] & 1), o1 = lab[x[1] >> 1] + N * (x[1] & 1);
-            v += a.sym_w[j] * f[(long)o0 * n2 + o1];
+            v += a.sym_w[j] * f[o0 * n2 + o1];
             continue;
         }
         int s[4], ns = 0;
@@ -153,7 +157,7 @@ __device__ __forceinline__ int outside(int j, const int* L, int n) {
 // perm of n_o (n_o - 1) ...); output role i sits at label Lr[i], L is the
 // same set in ascending order
 __device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, int nout,
-                                            int nspec, long perm, int* lab) {
+                                            int nspec, int perm, int* lab) {
     for (int i = 0; i < nout; ++i) lab[i] = Lr[i];
     const int no = N - nout;
     int j[3] = {0, 0, 0};
@@ -173,13 +177,13 @@ __device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, 
 
 // the terms q0 .. q1-1 at one label assignment; consecutive terms of one
 // Hamiltonian term (the tables keep them together) reuse its value
-__device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int* lab, long q0,
-                                              long q1, const double* __restrict__ f,
+__device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int* lab, int q0,
+                                              int q1, const double* __restrict__ f,
                                               const double* __restrict__ eri,
                                               const double* __restrict__ t) {
     double sum = 0.0, hv = 0.0;
     int hprev = -1;
-    for (long q = q0; q < q1; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const int h = a.th[q];
         if (h != hprev) {
             hv = hval(a, lab, h, N, f, eri);
@@ -190,8 +194,9 @@ __device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int*
         const int nf = cw >> 16;
         // the factors are independent: all their loads can be in flight at once
         int code[4];
-        for (int i = 0; i < 4; ++i) code[i] = i < nf ? a.slot_dict[a.ts[i * a.nterm + q]] : 0;
-        long pos[4];
+        const int nt = (int)a.nterm;      // < 2^31 (the file's term count is 32-bit)
+        for (int i = 0; i < 4; ++i) code[i] = i < nf ? a.slot_dict[a.ts[i * nt + q]] : 0;
+        int pos[4];
         double sg[4];
         for (int i = 0; i < 4; ++i) pos[i] = amp_pos(a, lab, code[i], N, sg[i]);
         double v = hv * (double)((cw & 0xffff) - 32768);
@@ -297,17 +302,17 @@ __global__ __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))
     for (int i = 0; i < 3; ++i) Lr[i] = L[(cn >> (9 + 2 * i)) & 3];
     const PhClass& k = a.cls[u.cls[un]];
     const int* st = a.starts + k.soff;
-    const long t0 = k.off + st[mc], t1 = k.off + st[mc + 1];
+    const int t0 = k.off + st[mc], t1 = k.off + st[mc + 1];
     const int np = (int)nperm(N - n, k.nspec);
     const long i0 = u.i0[un], i1 = u.i1[un];
     const int dq = PH_BLOCK / np, dp = PH_BLOCK % np;
-    long ch = (i0 + tid) / np;
+    int ch = (int)((i0 + tid) / np);
     int p = (int)((i0 + tid) % np);
     double acc = 0.0;
     for (long i = i0 + tid; i < i1; i += PH_BLOCK) {
         int lab[6];
         role_labels(N, Lr, L, n, k.nspec, p, lab);
-        const long q0 = t0 + ch * PH_CHUNK;
+        const int q0 = t0 + ch * PH_CHUNK;
         acc += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
         ch += dq;
         p += dp;
@@ -373,8 +378,8 @@ __global__ __launch_bounds__(256) void k_ph_energy(int N, PhArgs a, const double
         for (long i = g; i < tot; i += G) {
             const long q = i / np;
             int lab[6];
-            role_labels(N, L, L, 0, k.nspec, i - q * np, lab);
-            s += chunk_value(a, N, lab, k.off + q, k.off + q + 1, f, eri, t);
+            role_labels(N, L, L, 0, k.nspec, (int)(i - q * np), lab);
+            s += chunk_value(a, N, lab, k.off + (int)q, k.off + (int)q + 1, f, eri, t);
         }
         acc += inv_fact(k.nspec) * s;
     }
