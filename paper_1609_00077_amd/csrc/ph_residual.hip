@@ -77,10 +77,23 @@ __device__ __forceinline__ int eri_off(int N, int n) {
     return n == 1 ? 0 : n == 2 ? 6 * N : 6 * N + 43 * ncomb(N, 2);
 }
 
+// The labels of a term's roles packed 8 bits each (labels < 256): reading
+// role r is one shift, where an indexed local array costs a chain of selects.
+struct Labs {
+    unsigned long long w;
+    __device__ __forceinline__ int operator[](int r) const { return (int)((w >> (8 * r)) & 255); }
+};
+
+__device__ __forceinline__ Labs pack_labels(const int* lab) {
+    unsigned long long w = 0;
+    for (int i = 0; i < 6; ++i) w |= (unsigned long long)lab[i] << (8 * i);
+    return Labs{w};
+}
+
 // packed position of one amplitude factor: the labels of its roles, put in
 // ascending order (swapping two odd patterns flips the sign); -1 for no
 // factor (code 0) or a pattern tuple the layout does not store
-__device__ __forceinline__ int amp_pos(const PhArgs& a, const int* lab, int code, int N,
+__device__ __forceinline__ int amp_pos(const PhArgs& a, const Labs& lab, int code, int N,
                                         double& sg) {
     const int n = code & 3;
     int l[3], p[3];
@@ -107,7 +120,7 @@ __device__ __forceinline__ int amp_pos(const PhArgs& a, const int* lab, int code
 
 // Hamiltonian factor: sum of weighted f and chemists' (pq|rs) symbols, local
 // orbital x = 2 * role + type read at label lab[role]
-__device__ __forceinline__ double hval(const PhArgs& a, const int* lab, int hidx, int N,
+__device__ __forceinline__ double hval(const PhArgs& a, const Labs& lab, int hidx, int N,
                                        const double* __restrict__ f,
                                        const double* __restrict__ eri) {
     double v = 0.0;
@@ -177,7 +190,7 @@ __device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, 
 
 // the terms q0 .. q1-1 at one label assignment; consecutive terms of one
 // Hamiltonian term (the tables keep them together) reuse its value
-__device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const int* lab, int q0,
+__device__ __forceinline__ double chunk_value(const PhArgs& a, int N, const Labs& lab, int q0,
                                               int q1, const double* __restrict__ f,
                                               const double* __restrict__ eri,
                                               const double* __restrict__ t) {
@@ -310,10 +323,11 @@ __global__ __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))
     int p = (int)((i0 + tid) % np);
     double acc = 0.0;
     for (long i = i0 + tid; i < i1; i += PH_BLOCK) {
-        int lab[6];
+        int lab[6] = {0, 0, 0, 0, 0, 0};
         role_labels(N, Lr, L, n, k.nspec, p, lab);
         const int q0 = t0 + ch * PH_CHUNK;
-        acc += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
+        acc += chunk_value(a, N, pack_labels(lab), q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri,
+                           t);
         ch += dq;
         p += dp;
         if (p >= np) {
@@ -377,9 +391,9 @@ __global__ __launch_bounds__(256) void k_ph_energy(int N, PhArgs a, const double
         double s = 0.0;
         for (long i = g; i < tot; i += G) {
             const long q = i / np;
-            int lab[6];
+            int lab[6] = {0, 0, 0, 0, 0, 0};
             role_labels(N, L, L, 0, k.nspec, (int)(i - q * np), lab);
-            s += chunk_value(a, N, lab, k.off + (int)q, k.off + (int)q + 1, f, eri, t);
+            s += chunk_value(a, N, pack_labels(lab), k.off + (int)q, k.off + (int)q + 1, f, eri, t);
         }
         acc += inv_fact(k.nspec) * s;
     }
