@@ -84,12 +84,6 @@ struct Labs {
     __device__ __forceinline__ int operator[](int r) const { return (int)((w >> (8 * r)) & 255); }
 };
 
-__device__ __forceinline__ Labs pack_labels(const int* lab) {
-    unsigned long long w = 0;
-    for (int i = 0; i < 6; ++i) w |= (unsigned long long)lab[i] << (8 * i);
-    return Labs{w};
-}
-
 // packed position of one amplitude factor: the labels of its roles, put in
 // ascending order (swapping two odd patterns flips the sign); -1 for no
 // factor (code 0) or a pattern tuple the layout does not store
@@ -169,9 +163,10 @@ __device__ __forceinline__ int outside(int j, const int* L, int n) {
 // labels of an output slot's roles and of one ordered spectator tuple (number
 // perm of n_o (n_o - 1) ...); output role i sits at label Lr[i], L is the
 // same set in ascending order
-__device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, int nout,
-                                            int nspec, int perm, int* lab) {
-    for (int i = 0; i < nout; ++i) lab[i] = Lr[i];
+__device__ __forceinline__ Labs role_labels(int N, const int* Lr, const int* L, int nout,
+                                            int nspec, int perm) {
+    unsigned long long w = 0;
+    for (int i = 0; i < nout; ++i) w |= (unsigned long long)Lr[i] << (8 * i);
     const int no = N - nout;
     int j[3] = {0, 0, 0};
     for (int i = 0; i < nspec; ++i) {
@@ -185,7 +180,8 @@ __device__ __forceinline__ void role_labels(int N, const int* Lr, const int* L, 
         if (j[2] >= lo) ++j[2];
         if (j[2] >= hi) ++j[2];
     }
-    for (int i = 0; i < nspec; ++i) lab[nout + i] = outside(j[i], L, nout);
+    for (int i = 0; i < nspec; ++i) w |= (unsigned long long)outside(j[i], L, nout) << (8 * (nout + i));
+    return Labs{w};
 }
 
 // the terms q0 .. q1-1 at one label assignment; consecutive terms of one
@@ -323,11 +319,9 @@ __global__ __launch_bounds__(PH_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))
     int p = (int)((i0 + tid) % np);
     double acc = 0.0;
     for (long i = i0 + tid; i < i1; i += PH_BLOCK) {
-        int lab[6] = {0, 0, 0, 0, 0, 0};
-        role_labels(N, Lr, L, n, k.nspec, p, lab);
+        const Labs lab = role_labels(N, Lr, L, n, k.nspec, p);
         const int q0 = t0 + ch * PH_CHUNK;
-        acc += chunk_value(a, N, pack_labels(lab), q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri,
-                           t);
+        acc += chunk_value(a, N, lab, q0, q0 + PH_CHUNK < t1 ? q0 + PH_CHUNK : t1, f, eri, t);
         ch += dq;
         p += dp;
         if (p >= np) {
@@ -391,9 +385,8 @@ __global__ __launch_bounds__(256) void k_ph_energy(int N, PhArgs a, const double
         double s = 0.0;
         for (long i = g; i < tot; i += G) {
             const long q = i / np;
-            int lab[6] = {0, 0, 0, 0, 0, 0};
-            role_labels(N, L, L, 0, k.nspec, (int)(i - q * np), lab);
-            s += chunk_value(a, N, pack_labels(lab), k.off + (int)q, k.off + (int)q + 1, f, eri, t);
+            const Labs lab = role_labels(N, L, L, 0, k.nspec, (int)(i - q * np));
+            s += chunk_value(a, N, lab, k.off + (int)q, k.off + (int)q + 1, f, eri, t);
         }
         acc += inv_fact(k.nspec) * s;
     }
