@@ -347,6 +347,20 @@ pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* npair,
  * comparison).  INVALID_ARG for other values. */
 pqph_status pqph_set_batch_mode(pqph_ctx* ctx, int mode);
 
+/* How pq_solve and the amplitude solve of pq_energy_grad / pq_densities
+ * iterate with the Jacobi/DIIS solver (Sec. III) on this context: 1 (default)
+ * = host-driven: one host synchronisation per iteration, the DIIS system
+ * solved on the host; 0 = device-driven: the norm test, the convergence,
+ * stall and divergence decisions and the DIIS coefficients are computed on
+ * the device, and the host enqueues the next iteration before it reads the
+ * state of the last one (a finished solve gates off the one iteration queued
+ * beyond its end), so the GPU never waits for the host.  Both take the same
+ * steps and tests; the DIIS coefficients may differ in the last bits.  Mode 0
+ * falls back to host-driven when diis_dim > 16 or stall_window > 256.  PH
+ * solves and the lambda equations are always host-driven.  INVALID_ARG for
+ * other values. */
+pqph_status pqph_set_solve_mode(pqph_ctx* ctx, int mode);
+
 /* Transposed-residual contraction (the adjoint of pq_residual and pq_energy,
  * Sec. II: the de-excitation amplitudes lambda of the Lagrangian
  * L = E_c + lambda . R are truncated like t):

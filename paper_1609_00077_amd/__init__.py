@@ -161,6 +161,17 @@ def set_s1_mode(npair: int, mode: int, device: str | torch.device = "cuda:0") ->
     _check(lib, ctx, lib.pqph_set_s1_mode(ctx, npair, mode))
 
 
+def set_solve_mode(mode: str, device: str | torch.device = "cuda:0") -> None:
+    """How PQ amplitude solves iterate on the context of the current stream:
+    "host" (default: one host synchronisation per iteration, DIIS solved on
+    the host) or "device" (the Jacobi/DIIS decisions taken on the device, the
+    next iteration enqueued before the host reads the last one)."""
+    if mode not in ("device", "host"):
+        raise ValueError("mode must be 'device' or 'host'")
+    lib, ctx = _ctx(torch.device(device))
+    _check(lib, ctx, lib.pqph_set_solve_mode(ctx, 0 if mode == "device" else 1))
+
+
 def set_pq_intermediates(npair: int, labels: int, device: str | torch.device = "cuda:0") -> None:
     """PQ model for npair on the context of the current stream: labels = 3
     (exact projection, the default) or 2 (two-pair intermediates: the

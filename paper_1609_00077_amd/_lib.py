@@ -59,6 +59,7 @@ SIGNATURES = {
     "pqph_set_pq_intermediates": (C.c_int, [P, C.c_int, C.c_int]),
     "pqph_tuning": (C.c_int, [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "pqph_set_batch_mode": (C.c_int, [P, C.c_int]),
+    "pqph_set_solve_mode": (C.c_int, [P, C.c_int]),
     "pq_vjp": (C.c_int, [P, C.c_int, P, P, P, P, C.c_double, P, P, P]),
     "pq_energy_grad": (C.c_int, [P, C.c_int, P, P, P, C.POINTER(SolveOpts), C.POINTER(C.c_double),
                                  P, P, P, C.POINTER(SolveInfo)]),

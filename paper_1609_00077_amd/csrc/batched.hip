@@ -193,64 +193,33 @@ __global__ void k_b_gram_partial(const DevChain* __restrict__ st, const double* 
     if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = red[0];
 }
 
-// B-matrix update and the bordered DIIS system (Pulay), by one thread:
-// [B/scale -1; -1 0] [c; l] = [0; -1], partial pivoting; on a (near) singular
-// system the plain Jacobi step is taken.
+// B-matrix update (thread 0) and the bordered DIIS system (Pulay) by the
+// workgroup (diis_coefficients); on a (near) singular system the plain Jacobi
+// step is taken.
 __global__ void k_b_diis(DevChain* __restrict__ st, const double* __restrict__ grow, int m,
                          int diis_start, int diis_on) {
     DevChain& s = *st;
-    if (!s.active) return;
-    const int slot = s.next;
-    s.last = slot;
-    s.next = (slot + 1) % m;
-    s.use = 0;
-    if (!diis_on) return;
-    s.stored = min(s.stored + 1, m);
-    for (int j = 0; j < m; ++j) {
-        s.B[slot * 16 + j] = grow[j];
-        s.B[j * 16 + slot] = grow[j];
-    }
-    const int k = s.stored;
-    if (s.iters < diis_start || k < 2) return;
-    __shared__ double A[17 * 18];
-    const int n = k + 1, w = n + 1;
-    double scale = 0.0;
-    for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(s.B[i * 16 + i]));
-    if (!(scale > 0.0)) return;
-    for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < n; ++j) {
-            double v;
-            if (i < k && j < k) v = s.B[i * 16 + j] / scale;
-            else if (i == k && j == k) v = 0.0;
-            else v = -1.0;
-            A[i * w + j] = v;
-        }
-        A[i * w + n] = (i == k) ? -1.0 : 0.0;
-    }
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int i = col + 1; i < n; ++i)
-            if (fabs(A[i * w + col]) > fabs(A[piv * w + col])) piv = i;
-        if (fabs(A[piv * w + col]) < 1e-300) return;
-        if (piv != col)
-            for (int j = 0; j <= n; ++j) {
-                const double x = A[piv * w + j];
-                A[piv * w + j] = A[col * w + j];
-                A[col * w + j] = x;
+    if (!s.active) return;     // read by every thread before thread 0 writes (barrier below)
+    __shared__ int nk;
+    if (threadIdx.x == 0) {
+        nk = 0;
+        const int slot = s.next;
+        s.last = slot;
+        s.next = (slot + 1) % m;
+        s.use = 0;
+        if (diis_on) {
+            s.stored = min(s.stored + 1, m);
+            for (int j = 0; j < m; ++j) {
+                s.B[slot * 16 + j] = grow[j];
+                s.B[j * 16 + slot] = grow[j];
             }
-        for (int i = 0; i < n; ++i) {
-            if (i == col) continue;
-            const double fct = A[i * w + col] / A[col * w + col];
-            for (int j = col; j <= n; ++j) A[i * w + j] -= fct * A[col * w + j];
+            if (s.iters >= diis_start && s.stored >= 2) nk = s.stored;
         }
     }
-    double c[16];
-    for (int i = 0; i < k; ++i) {
-        c[i] = A[i * w + n] / A[i * w + i];
-        if (!isfinite(c[i])) return;
-    }
-    for (int i = 0; i < 16; ++i) s.coef[i] = i < k ? c[i] : 0.0;
-    s.use = 1;
+    __syncthreads();
+    const int k = nk;
+    if (k == 0) return;
+    if (diis_coefficients(s.B, k, s.coef) && threadIdx.x == 0) s.use = 1;
 }
 
 // t = sum_j c_j tn_j (DIIS) or the Jacobi iterate of this step
@@ -411,7 +380,7 @@ pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
             hipLaunchKernelGGL(k_b_sum_rows, dim3(b.m), dim3(256), 0, s, d, x.part, x.nblk,
                                b.gram + (size_t)c * b.m);
         }
-        hipLaunchKernelGGL(k_b_diis, dim3(1), dim3(1), 0, s, d, b.gram + (size_t)c * b.m, b.m,
+        hipLaunchKernelGGL(k_b_diis, dim3(1), dim3(64), 0, s, d, b.gram + (size_t)c * b.m, b.m,
                            b.o.diis_start, b.o.diis_dim > 0 ? 1 : 0);
         hipLaunchKernelGGL(k_b_update, dim3(x.nblk), dim3(256), 0, s, d, x.th, b.m, x.n, x.t);
     }

@@ -2141,8 +2141,9 @@ View make_view(const double* t, const Carve& c, int N) {
     return v;
 }
 
-pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
-                    const double* t, const Carve& c, const int* gate) {
+// the bare vertices h1, h2, h2K: functions of f and the integrals only
+void launch_vertices(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
+                     const Carve& c, const int* gate) {
     const int tb = 64;
     const int gx = (N + tb - 1) / tb;
     hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1, gate);
@@ -2151,6 +2152,17 @@ pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const 
         hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2, c.h2T,
                            gate);
         pqph_mark(ctx);
+    }
+}
+
+// vertices (unless the workspace already holds them for h and eri) and the
+// mirrored two-pair amplitudes
+pqph_status prepare(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const double* eri,
+                    const double* t, const Carve& c, const int* gate, bool vertices) {
+    if (vertices) launch_vertices(ctx, s, N, h, eri, c, gate);
+    if (N > 1) {
+        const int tb = 64;
+        const int gx = (N + tb - 1) / tb;
         hipLaunchKernelGGL(k_unpack_t2, dim3(gx, N, NP2), dim3(tb), 0, s, N, t, c.t2, gate);
         pqph_mark(ctx);
     }
@@ -2164,11 +2176,18 @@ size_t pq_ws_doubles(int npair) { return carve_size(npair); }
 
 pqph_status pq_residual_prepare(pqph_ctx* ctx) { return gemm_s1_prepare(ctx); }
 
+pqph_status pq_vertices_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                           const double* eri, double* ws) {
+    launch_vertices(ctx, s, N, h, eri, carve(ws, N), nullptr);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate, int fork) {
+                           const int* gate, int fork, bool vertices) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate, vertices);
     if (st) return st;
     View v = make_view(t, c, N);
     // the doubly-mixed two-spectator contraction (three-label intermediates)
@@ -2322,7 +2341,7 @@ pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
 pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                          const double* eri, const double* t, double* dst, double* ws) {
     Carve c = carve(ws, N);
-    pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
+    pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr, true);
     if (st) return st;
     View v = make_view(t, c, N);
     hipLaunchKernelGGL(k_energy, dim3(c.nblkE), dim3(256), 0, s, N, v, c.epart);
@@ -2354,7 +2373,7 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h, cons
                       double* eribar, double* ws, double* aws, bool fwd_ready) {
     Carve c = carve(ws, N);
     if (!fwd_ready) {
-        pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr);
+        pqph_status st = prepare(ctx, s, N, h, eri, t, c, nullptr, true);
         if (st) return st;
     }
     View v = make_view(t, c, N);

@@ -112,17 +112,27 @@ int pq_s2_variant(const pqph_ctx* ctx, int npair) {
 }
 
 pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const double* eri,
-                              const double* t, double* r, double* ws) {
-    if (ctx->profiling) return pq_residual_ws(ctx, ctx->stream, N, h, eri, t, r, ws);
+                              const double* t, double* r, double* ws, const int* gate,
+                              bool vertices) {
+    if (ctx->profiling) return pq_residual_ws(ctx, ctx->stream, N, h, eri, t, r, ws, gate, -1, vertices);
     const int s1 = pq_s1_mode(ctx, N), s2 = pq_s2_variant(ctx, N), li = pq_intermediates(ctx, N);
-    const bool same = ctx->rexec && ctx->rN == N && ctx->rh == h && ctx->reri == eri && ctx->rt == t &&
-                      ctx->rr == r && ctx->rws == ws && ctx->rs1 == s1 && ctx->rs2 == s2 &&
-                      ctx->rint == li;
-    if (!same) {
-        if (ctx->rexec) {
+    using G = pqph_ctx::ResidualGraph;
+    auto same = [&](const G& g) {
+        return g.exec && g.N == N && g.h == h && g.eri == eri && g.t == t && g.r == r && g.ws == ws &&
+               g.s1 == s1 && g.s2 == s2 && g.li == li && g.gate == gate && g.vertices == vertices;
+    };
+    G* hit = nullptr;
+    for (G& g : ctx->rgraph)
+        if (same(g)) hit = &g;
+    if (!hit) {
+        // an empty entry, else the least recently used one
+        hit = &ctx->rgraph[0];
+        for (G& g : ctx->rgraph)
+            if (!g.exec || (hit->exec && g.used < hit->used)) hit = &g;
+        if (hit->exec) {
             PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));    // the old graph may still run
-            (void)hipGraphExecDestroy(ctx->rexec);
-            ctx->rexec = nullptr;
+            (void)hipGraphExecDestroy(hit->exec);
+            *hit = G();
         }
         // capture on a stream of our own (the context's may be the legacy default
         // stream, which cannot be captured), forked to the side streams, then
@@ -131,7 +141,7 @@ pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const doubl
         if (pqph_status e = pqph_ensure_side(ctx)) return e;
         if (!ctx->cap) PQPH_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
         PQPH_HIP(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
-        const pqph_status st = pq_residual_ws(ctx, ctx->cap, N, h, eri, t, r, ws, nullptr, 1);
+        const pqph_status st = pq_residual_ws(ctx, ctx->cap, N, h, eri, t, r, ws, gate, 1, vertices);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
         if (st) {
@@ -140,23 +150,26 @@ pqph_status pq_residual_graph(pqph_ctx* ctx, int N, const double* h, const doubl
         }
         if (ec != hipSuccess || !graph)
             return pqph_fail(ctx, PQPH_DEVICE, std::string("residual capture: ") + hipGetErrorString(ec));
-        const hipError_t ei = hipGraphInstantiate(&ctx->rexec, graph, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            ctx->rexec = nullptr;
+        if (ei != hipSuccess)
             return pqph_fail(ctx, PQPH_DEVICE, std::string("residual instantiate: ") + hipGetErrorString(ei));
-        }
-        ctx->rN = N;
-        ctx->rh = h;
-        ctx->reri = eri;
-        ctx->rt = t;
-        ctx->rr = r;
-        ctx->rws = ws;
-        ctx->rs1 = s1;
-        ctx->rs2 = s2;
-        ctx->rint = li;
+        hit->exec = exec;
+        hit->N = N;
+        hit->h = h;
+        hit->eri = eri;
+        hit->t = t;
+        hit->r = r;
+        hit->ws = ws;
+        hit->s1 = s1;
+        hit->s2 = s2;
+        hit->li = li;
+        hit->gate = gate;
+        hit->vertices = vertices;
     }
-    PQPH_HIP(ctx, hipGraphLaunch(ctx->rexec, ctx->stream));
+    hit->used = ++ctx->rgraph_clock;
+    PQPH_HIP(ctx, hipGraphLaunch(hit->exec, ctx->stream));
     return PQPH_OK;
 }
 
@@ -206,6 +219,13 @@ void pqph_default_opts(pqph_solve_opts* o) {
     o->spin_adapted = 0;
 }
 
+pqph_status pqph_set_solve_mode(pqph_ctx* ctx, int mode) {
+    if (!ctx) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null context");
+    if (mode != 0 && mode != 1) return pqph_fail(ctx, PQPH_INVALID_ARG, "solve mode must be 0 or 1");
+    ctx->solve_mode = mode;
+    return PQPH_OK;
+}
+
 pqph_status pqph_create(pqph_ctx** out, int device, void* hip_stream) {
     if (!out) return pqph_fail(nullptr, PQPH_INVALID_ARG, "null output pointer");
     *out = nullptr;
@@ -243,7 +263,10 @@ void pqph_destroy(pqph_ctx* ctx) {
     for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
     for (hipStream_t st : ctx->bstreams) (void)hipStreamDestroy(st);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
-    if (ctx->rexec) (void)hipGraphExecDestroy(ctx->rexec);
+    for (pqph_ctx::ResidualGraph& g : ctx->rgraph)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (hipEvent_t e : ctx->dsev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (hipEvent_t e : ctx->sev)
         if (e) (void)hipEventDestroy(e);
@@ -454,14 +477,117 @@ pqph_status pqph_denominators(pqph_ctx* ctx, int npair, int k, const double* h, 
 // n*(3 + 2m) + nblk*(m+1) + 64 doubles.  One host sync per iteration.
 namespace {
 size_t driver_doubles(size_t n, int m) {
-    return n * (3 + 2 * (size_t)m) + (size_t)stream_blocks(n) * (m + 1) + 64;
+    return n * (3 + 2 * (size_t)m) + (size_t)stream_blocks(n) * (m + 1) + 64 + dev_solve_doubles();
 }
 
+// The Jacobi/DIIS iteration with every decision on the device (k_ds_* in the
+// solver kernels): the norm test, the history bookkeeping, the Gram row and
+// the DIIS coefficients.  The host enqueues iteration it + 1 before it waits
+// for the state of iteration it, so the GPU never idles while the host reads
+// a norm; the state's active flag is the residual's gate (ctx->solve_gate,
+// for closures that pass it on) and every step kernel obeys it, so the one
+// iteration enqueued beyond the end changes nothing.  Same steps, tests and
+// messages as the host-driven loop below; the DIIS coefficients are solved
+// on the device (same elimination, rounding may differ in the last bits).
+pqph_status jacobi_diis_device(pqph_ctx* ctx, size_t n, const double* D, double* x,
+                               const pqph_solve_opts& o,
+                               const std::function<pqph_status(const double*, double*)>& resid,
+                               double* bufs, int& iters, double& rn, pqph_status& result,
+                               const double* rank, double* best) {
+    const int m = std::max(o.diis_dim, 1);
+    const int nblk = stream_blocks(n);
+    double* r = bufs;
+    double* th = r + 3 * n;                         // the host loop's layout: r, e, xn, xh, eh, part, scal
+    double* eh = th + (size_t)m * n;
+    double* part = eh + (size_t)m * n;
+    double* state = part + (size_t)nblk * (m + 1) + 64;
+    const SolveHead* head = reinterpret_cast<const SolveHead*>(state);
+    hipStream_t s = ctx->stream;
+    PQPH_HIP(ctx, hipStreamSynchronize(s));          // no copy into the host staging is pending
+    if (pqph_status e = pqph_ensure_host(ctx, 64)) return e;
+    for (hipEvent_t& e : ctx->dsev)
+        if (!e) PQPH_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // two slots by iteration parity in the pinned staging, written by the
+    // decide kernel of every iteration that ran (device address hd)
+    SolveHead* hh = reinterpret_cast<SolveHead*>(ctx->host);
+    static_assert(2 * sizeof(SolveHead) <= 64 * sizeof(double), "host staging too small");
+    SolveHead* hd = nullptr;
+    PQPH_HIP(ctx, hipHostGetDevicePointer((void**)&hd, ctx->host, 0));
+    hh[0].active = hh[1].active = 1;
+    hh[0].iters = hh[1].iters = 0;
+    const char* venv = getenv("PQPH_VERBOSE");
+    const bool verbose = venv && venv[0] && venv[0] != '0';
+    const auto t_start = std::chrono::steady_clock::now();
+    int printed = 0;
+    auto report = [&](const SolveHead& hd) {
+        if (!verbose || hd.iters <= printed) return;
+        printed = hd.iters;
+        fprintf(stderr, "pqph: iteration %d  ||R|| = %.3e  (%.1f s)\n", hd.iters, hd.rn,
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+    };
+    DevSolveOpts dopts;
+    dopts.max_iter = o.max_iter;
+    dopts.m = m;
+    dopts.diis_on = o.diis_dim > 0;
+    dopts.diis_start = o.diis_start;
+    dopts.stall_window = o.stall_window;
+    dopts.tol = o.tol;
+    dopts.diverge_factor = o.diverge_factor;
+    const bool masked = rank != nullptr && o.max_rank > 0;
+    launch_dsolve_init(s, state);
+    if (masked) launch_rank_mask(s, x, rank, o.max_rank, n);
+    struct GateScope {      // the gate is published only while this loop runs
+        pqph_ctx* c;
+        ~GateScope() { c->solve_gate = nullptr; }
+    } scope{ctx};
+    ctx->solve_gate = &head->active;
+    for (int it = 1; it <= o.max_iter; ++it) {
+        if (pqph_status e = resid(x, r)) return e;
+        if (masked) launch_rank_mask(s, r, rank, o.max_rank, n);
+        launch_dsolve_step(s, state, x, r, D, n, th, eh, m, part, nblk);
+        launch_dsolve_decide(s, state, part, nblk, dopts, hd + (it & 1));
+        launch_dsolve_update(s, state, th, n, x, best);
+        PQPH_HIP(ctx, hipEventRecord(ctx->dsev[it & 1], s));
+        if (it > 1) {       // the state after iteration it - 1 (iteration it is already queued)
+            PQPH_HIP(ctx, hipEventSynchronize(ctx->dsev[(it - 1) & 1]));
+            const SolveHead prev = hh[(it - 1) & 1];
+            report(prev);
+            // an iteration gated off writes no mirror, but the one that
+            // ended the solve did, and the host reads every iteration's slot
+            if (!prev.active && prev.iters == it - 1) break;
+        }
+    }
+    PQPH_HIP(ctx, hipMemcpyAsync(&hh[0], head, sizeof(SolveHead), hipMemcpyDeviceToHost, s));
+    PQPH_HIP(ctx, hipStreamSynchronize(s));
+    const SolveHead fin = hh[0];
+    report(fin);
+    iters = fin.iters;
+    rn = fin.rn;
+    result = fin.active ? PQPH_NOT_CONVERGED : (pqph_status)fin.status;
+    if (result == PQPH_NONFINITE) {
+        pqph_fail(ctx, result, "non-finite residual at iteration " + std::to_string(fin.iters));
+    } else if (result == PQPH_DIVERGED) {
+        pqph_fail(ctx, result, "residual norm diverged at iteration " + std::to_string(fin.iters));
+    } else if (result == PQPH_NOT_CONVERGED && fin.stalled) {
+        pqph_fail(ctx, result, "stalled: ||R|| did not halve in " + std::to_string(o.stall_window) +
+                                   " iterations (iteration " + std::to_string(fin.iters) + ")");
+    } else if (result == PQPH_NOT_CONVERGED) {
+        pqph_fail(ctx, result, "not converged in " + std::to_string(o.max_iter) + " iterations");
+    }
+    return PQPH_OK;
+}
+
+// pipelined: the caller's residual is cheap next to a host round trip and
+// obeys ctx->solve_gate, so the device-driven loop above may run it
 pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
                         const pqph_solve_opts& o,
                         const std::function<pqph_status(const double*, double*)>& resid,
                         double* bufs, int& iters, double& rn, pqph_status& result,
-                        const double* rank = nullptr, double* best = nullptr) {
+                        const double* rank = nullptr, double* best = nullptr,
+                        bool pipelined = false) {
+    if (pipelined && ctx->solve_mode == 0 && o.max_iter >= 1 && o.diis_dim <= 16 &&
+        o.stall_window <= kSolveRing - 1)
+        return jacobi_diis_device(ctx, n, D, x, o, resid, bufs, iters, rn, result, rank, best);
     const int m = std::max(o.diis_dim, 1);
     const int nblk = stream_blocks(n);
     double* r = bufs;
@@ -752,11 +878,11 @@ pqph_status amplitude_solve(pqph_ctx* ctx, size_t n, const double* D, double* x,
                             const pqph_solve_opts& o,
                             const std::function<pqph_status(const double*, double*)>& resid,
                             double* sbuf, int& iters, double& rn, pqph_status& result,
-                            const double* rank) {
+                            const double* rank, bool pipelined) {
     iters = 0;
     if (o.solver == 1) return newton_krylov(ctx, n, D, x, o, resid, sbuf, iters, rn, result, rank);
     double* best = o.solver == 2 ? sbuf + solver_doubles(n, std::max(o.diis_dim, 1), 1) : nullptr;
-    pqph_status st = jacobi_diis(ctx, n, D, x, o, resid, sbuf, iters, rn, result, rank, best);
+    pqph_status st = jacobi_diis(ctx, n, D, x, o, resid, sbuf, iters, rn, result, rank, best, pipelined);
     if (st || o.solver != 2 || (result != PQPH_NOT_CONVERGED && result != PQPH_DIVERGED)) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(x, best, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     int it2 = 0;
@@ -781,12 +907,12 @@ pqph_status space_solve(pqph_ctx* ctx, int npair, int k, size_t n, const double*
                         const pqph_solve_opts& o,
                         const std::function<pqph_status(const double*, double*)>& resid,
                         double* sbuf, int& iters, double& rn, pqph_status& result, const double* rank,
-                        bool jd_only = false) {
+                        bool jd_only = false, bool pipelined = false) {
     auto core = [&](size_t len, const double* Dv, double* xv,
                     const std::function<pqph_status(const double*, double*)>& rf, double* b,
                     const double* rk) -> pqph_status {
-        if (jd_only) return jacobi_diis(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk);
-        return amplitude_solve(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk);
+        if (jd_only) return jacobi_diis(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk, nullptr, pipelined);
+        return amplitude_solve(ctx, len, Dv, xv, o, rf, b, iters, rn, result, rk, pipelined);
     };
     if (!o.spin_adapted) return core(n, D, x, resid, sbuf, rank);
     const size_t nred = spin_len(npair, k);
@@ -920,10 +1046,14 @@ pqph_status pq_solve(pqph_ctx* ctx, int npair, const double* h, const double* er
     int iters = 0;
     double rn = 0.0;
     pqph_status result = PQPH_OK;
+    // the vertices depend on h and eri only: formed once, read by every
+    // residual of the solve (nothing else writes ws meanwhile)
+    if ((st = pq_vertices_ws(ctx, s, npair, h, eri, ctx->ws))) return st;
     auto resid = [&](const double* x, double* r) {
-        return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
+        return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws, ctx->solve_gate, false);
     };
-    if ((st = space_solve(ctx, npair, 2, n, D, t, o, resid, bufs, iters, rn, result, rank))) return st;
+    if ((st = space_solve(ctx, npair, 2, n, D, t, o, resid, bufs, iters, rn, result, rank, false, true)))
+        return st;
     double* edst = ctx->ws + wsd;
     if ((st = pq_energy_ws(ctx, s, npair, h, eri, t, edst, ctx->ws))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(ctx->host, edst, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1078,10 +1208,13 @@ pqph_status pq_energy_grad(pqph_ctx* ctx, int npair, const double* h, const doub
     const double* t = t_in;
     if (!t) {
         PQPH_HIP(ctx, hipMemsetAsync(tl, 0, n * sizeof(double), s));
+        if ((st = pq_vertices_ws(ctx, s, npair, h, eri, ctx->ws))) return st;   // once per solve
         auto resid = [&](const double* x, double* r) {
-            return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws);
+            return pq_residual_graph(ctx, npair, h, eri, x, r, ctx->ws, ctx->solve_gate, false);
         };
-        if ((st = space_solve(ctx, npair, 2, n, D, tl, o, resid, bufs, iters, rn, result, rank))) return st;
+        if ((st = space_solve(ctx, npair, 2, n, D, tl, o, resid, bufs, iters, rn, result, rank, false,
+                              true)))
+            return st;
         if (result != PQPH_OK) return result;
         t = tl;
     }

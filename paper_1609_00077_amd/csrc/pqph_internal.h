@@ -47,12 +47,28 @@ struct pqph_ctx {
     // its independent branches run concurrently with the main chain
     hipStream_t side[2] = {};
     hipEvent_t sev[4] = {};
-    // the residual captured as a HIP graph, with what it was captured for
+    // the residual captured as HIP graphs, each with what it was captured
+    // for (a few are kept: callers alternate between buffer sets)
+    struct ResidualGraph {
+        hipGraphExec_t exec = nullptr;
+        int N = 0, s1 = 0, s2 = 0, li = 0;
+        const double *h = nullptr, *eri = nullptr, *t = nullptr;
+        double *r = nullptr, *ws = nullptr;
+        const int* gate = nullptr;
+        bool vertices = true;
+        unsigned long long used = 0;     // last use, for replacement
+    };
+    static constexpr int kResidualGraphs = 4;
     hipStream_t cap = nullptr;
-    hipGraphExec_t rexec = nullptr;
-    int rN = 0, rs1 = 0, rs2 = 0, rint = 0;
-    const double *rh = nullptr, *reri = nullptr, *rt = nullptr;
-    double *rr = nullptr, *rws = nullptr;
+    ResidualGraph rgraph[kResidualGraphs];
+    unsigned long long rgraph_clock = 0;
+    // PQ amplitude solves: 0 = device-driven iterations enqueued ahead of
+    // the host, 1 = host-driven (default; one host synchronisation per iteration)
+    int solve_mode = 1;
+    // while a device-driven solve runs: its active flag, the gate the
+    // residual kernels obey (NULL otherwise)
+    const int* solve_gate = nullptr;
+    hipEvent_t dsev[2] = {};
     // batched solves: 0 = device-resident iterations captured in a HIP graph,
     // 1 = host-driven lockstep (three host synchronisations per iteration)
     int batch_mode = 0;
@@ -142,15 +158,23 @@ size_t pq_ws_doubles(int npair);
 // fork: 1 = run the independent branches on the context's side streams, 0 =
 // serially on s, -1 = fork when s is the context's stream, no gate is given
 // and no per-kernel timing is taken
+// vertices: false when ws already holds the bare vertices of h and eri
+// (pq_vertices_ws, nothing written over them since): they depend on the
+// integrals only, so a solve forms them once
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate = nullptr, int fork = -1);
+                           const int* gate = nullptr, int fork = -1, bool vertices = true);
+// the bare vertices of h and eri into ws (where pq_residual_ws reads them)
+pqph_status pq_vertices_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
+                           const double* eri, double* ws);
 // one-time kernel attributes of the residual (outside any stream capture)
 pqph_status pq_residual_prepare(pqph_ctx* ctx);
 // the residual on the context's stream replayed from a HIP graph captured for
 // these arguments and kernel choices (captured again when they change)
+// gate, vertices: as for pq_residual_ws (part of what the graph is captured for)
 pqph_status pq_residual_graph(pqph_ctx* ctx, int npair, const double* h, const double* eri,
-                              const double* t, double* r, double* ws);
+                              const double* t, double* r, double* ws, const int* gate = nullptr,
+                              bool vertices = true);
 // energy: writes one double to dst (device) on stream s, no sync
 pqph_status pq_energy_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                          const double* eri, const double* t, double* dst, double* ws);
@@ -187,6 +211,146 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
                  double* eh, int m, int slot, double* part, int nblk, double* out);
 // t = sum_j c[j] th[j]
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
+// Pulay's bordered DIIS system [B/scale -1; -1 0] [c; l] = [0; -1] for k
+// stored vectors (B: Gram matrix, row stride 16; scale: its largest
+// diagonal), Gauss-Jordan elimination with partial pivoting; false when B is
+// zero, the system is (near) singular or a coefficient is not finite (the
+// caller then takes the plain Jacobi step).  Called by every thread of one
+// workgroup of at least 32 threads: thread i keeps row i in registers and
+// eliminates it with the same operations, in the same order, as the host
+// solve (diis_solve); the pivot column and row pass through LDS.  On success
+// thread 0 writes coef[0..16) (zero beyond k); every thread returns the same
+// flag.
+__device__ inline bool diis_coefficients(const double* B, int k, double* coef) {
+    constexpr int W = 18;                       // k <= 16: n = k + 1 <= 17 rows, n + 1 columns
+    __shared__ double colv[W], prow[W], crow[W], cv[16];
+    const int n = k + 1, tid = threadIdx.x;
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i) scale = fmax(scale, fabs(B[i * 16 + i]));
+    if (!(scale > 0.0)) return false;
+    double a[W], p[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        double v = 0.0;
+        if (tid < n && j <= n) {
+            if (j == n) v = (tid == k) ? -1.0 : 0.0;
+            else if (tid < k && j < k) v = B[tid * 16 + j] / scale;
+            else if (tid == k && j == k) v = 0.0;
+            else v = -1.0;
+        }
+        a[j] = v;
+    }
+    for (int col = 0; col < n; ++col) {
+        double acol = 0.0;
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (j == col) acol = a[j];
+        if (tid < n) colv[tid] = acol;
+        __syncthreads();
+        int piv = col;
+        double pv = fabs(colv[col]);
+#pragma unroll
+        for (int i = 1; i < W - 1; ++i) {
+            if (i > col && i < n) {
+                const double x = fabs(colv[i]);
+                if (x > pv) {
+                    pv = x;
+                    piv = i;
+                }
+            }
+        }
+        if (pv < 1e-300) return false;          // same values in every thread
+        if (tid == piv) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) prow[j] = a[j];
+        }
+        if (tid == col && piv != col) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) crow[j] = a[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < W; ++j) p[j] = prow[j];
+        if (tid == col) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[j] = p[j];
+        } else if (tid == piv) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[j] = crow[j];
+        }
+        if (tid < n && tid != col) {
+            double ac = 0.0, pc = 0.0;
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                if (j == col) {
+                    ac = a[j];
+                    pc = p[j];
+                }
+            const double fct = ac / pc;
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                if (j >= col && j <= n) a[j] -= fct * p[j];
+        }
+        __syncthreads();                        // prow, crow and colv are rewritten next
+    }
+    if (tid < k) {
+        double rhs = 0.0, diag = 0.0;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            if (j == n) rhs = a[j];
+            if (j == tid) diag = a[j];
+        }
+        cv[tid] = rhs / diag;
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int i = 0; i < k; ++i) ok = ok && isfinite(cv[i]);
+    if (ok && tid == 0)
+        for (int i = 0; i < 16; ++i) coef[i] = i < k ? cv[i] : 0.0;
+    return ok;
+}
+
+// Device-driven Jacobi/DIIS solve (one system): the norm test, the
+// convergence / stall / divergence decisions, the Gram row and the DIIS
+// coefficients are all taken on the device, so the host can enqueue
+// iterations ahead and only follow the state.  SolveHead opens the
+// device-resident state; the host copies it back.
+struct SolveHead {
+    int active;     // 1 while iterating, 0 once a decision ended the solve
+    int iters;      // residual norms tested so far
+    int next;       // history slot of the next Jacobi iterate
+    int stored;     // history slots written (at most the DIIS dimension)
+    int use;        // 1: the update extrapolates with the DIIS coefficients
+    int last;       // slot of the latest Jacobi iterate
+    int status;     // PQPH_* once inactive
+    int stalled;    // ended by the stall test
+    int improved;   // the last tested norm was below every earlier one
+    int pad;
+    double rn, rmin;
+};
+constexpr int kSolveRing = 257;   // smallest-norm history: stall_window <= kSolveRing - 1
+struct DevSolveOpts {
+    int max_iter, m, diis_on, diis_start, stall_window;
+    double tol, diverge_factor;
+};
+// doubles of device memory the state takes (SolveHead first)
+size_t dev_solve_doubles();
+void launch_dsolve_init(hipStream_t s, double* state);
+// when active: e = -r/D into eh[next], x + e into th[next]; block partials of
+// ||r||^2 (row 0) and of e . eh[j] (rows 1..m) into part ((m+1) nblk doubles)
+void launch_dsolve_step(hipStream_t s, const double* state, const double* x, const double* r,
+                        const double* D, size_t n, double* th, double* eh, int m, double* part,
+                        int nblk);
+// when active: sums the partials, tests the norm, updates the Gram matrix and
+// solves for the DIIS coefficients (one workgroup); the new head is also
+// written to mirror (device address of pinned host memory; may be NULL)
+void launch_dsolve_decide(hipStream_t s, double* state, const double* part, int nblk,
+                          const DevSolveOpts& o, SolveHead* mirror);
+// when active: x = sum_j c_j th[j] (DIIS) or th[last]; best (may be NULL)
+// takes x first when the last norm was the smallest so far
+void launch_dsolve_update(hipStream_t s, const double* state, const double* th, size_t n,
+                          double* x, double* best);
+
 // f = diag(-1 occupied, 0 virtual): through the denominator kernels, the slot ranks
 void launch_rank_fock(hipStream_t s, double* f, int npair);
 // r[i] = 0 where rank[i] > max_rank

@@ -290,3 +290,222 @@ void launch_axpby(hipStream_t s, double* out, double a, const double* x, double 
 void launch_sub_combine(hipStream_t s, double* y, const double* V, const double* c, int m, size_t n) {
     hipLaunchKernelGGL(k_sub_combine, dim3(stream_blocks(n)), dim3(256), 0, s, y, V, c, m, n);
 }
+
+// ------------------------------------------------ device-driven single solve
+// The iteration of jacobi_diis with its decisions on the device (Sec. III:
+// Jacobi steps with DIIS extrapolation).  The state sits in device memory
+// behind SolveHead; a solve that has ended reads active == 0 and every later
+// kernel returns at once, so iterations enqueued beyond the end do nothing.
+namespace {
+
+struct DevSolve {
+    SolveHead h;
+    double B[16 * 16];              // Gram matrix of the stored error vectors
+    double coef[16];                // DIIS coefficients of the last extrapolation
+    double ring[kSolveRing];        // smallest norm up to iteration i, at (i - 1) % kSolveRing
+};
+
+// sum of v over one wavefront, valid in lane 0 (fixed order)
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__global__ void k_ds_init(DevSolve* __restrict__ ds) {
+    if (threadIdx.x != 0) return;
+    SolveHead& h = ds->h;
+    h.active = 1;
+    h.iters = h.next = h.stored = h.use = h.last = h.stalled = h.improved = h.pad = 0;
+    h.status = PQPH_NOT_CONVERGED;
+    h.rn = h.rmin = INFINITY;
+    for (int i = 0; i < 16 * 16; ++i) ds->B[i] = 0.0;
+    for (int i = 0; i < 16; ++i) ds->coef[i] = 0.0;
+}
+
+// One pass: e = -r/D, th[next] = x + e, eh[next] = e, and the block partials
+// of ||r||^2 and e . eh[j] (j < m; the new slot from the register value).
+// Wavefront sums, then the four wavefronts in a fixed order.
+__global__ __launch_bounds__(256) void k_ds_step(const DevSolve* __restrict__ ds,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ D, size_t n,
+                                                 double* __restrict__ th, double* __restrict__ eh,
+                                                 int m, double* __restrict__ partial) {
+    if (!ds->h.active) return;
+    const int slot = ds->h.next;
+    double* es = eh + (size_t)slot * n;
+    double* xs = th + (size_t)slot * n;
+    double sr = 0.0, sg[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sg[j] = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double ri = r[i];
+        const double d = -ri / D[i];
+        es[i] = d;
+        xs[i] = x[i] + d;
+        sr += ri * ri;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < m) sg[j] += (j == slot ? d : eh[(size_t)j * n + i]) * d;
+    }
+    __shared__ double red[4][17];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 17; ++j) {
+        if (j <= m) {
+            const double v = wave_sum(j == 0 ? sr : sg[j > 0 ? j - 1 : 0]);
+            if (lane == 0) red[wv][j] = v;
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j <= m) partial[(size_t)j * gridDim.x + blockIdx.x] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+}
+
+// One workgroup of 256: row sums of the partials (all loads issued before
+// the sums; nblk <= 1024), then (thread 0, on a register copy of the state
+// loaded up front) the tests of the host loop in its order -- non-finite,
+// converged, stalled, diverged, iteration limit -- and, while the solve goes
+// on, the history bookkeeping and the Gram row; then the DIIS coefficients
+// by the whole workgroup.
+__global__ __launch_bounds__(256) void k_ds_decide(DevSolve* __restrict__ ds,
+                                                   const double* __restrict__ partial, int nblk,
+                                                   DevSolveOpts o, SolveHead* __restrict__ mirror) {
+    SolveHead hd = ds->h;
+    if (!hd.active) return;    // the same copy in every thread; thread 0 writes after the barrier
+    __shared__ double red[4][17];
+    __shared__ int nk;         // DIIS vectors to extrapolate with, 0 = none
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int it = hd.iters + 1;
+    const bool stall_test = o.stall_window > 0 && it > o.stall_window;
+    const double old_min = stall_test ? ds->ring[(it - 1 - o.stall_window) % kSolveRing] : 0.0;
+    double v[17];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) {
+        v[j] = 0.0;
+        if (j <= o.m) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = tid + q * 256;
+                if (i < nblk) v[j] += partial[(size_t)j * nblk + i];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 17; ++j) {
+        if (j <= o.m) {
+            const double x = wave_sum(v[j]);
+            if (lane == 0) red[wv][j] = x;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        nk = 0;
+        auto row = [&](int j) { return (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]); };
+        hd.iters = it;
+        const double rn = sqrt(row(0));
+        hd.rn = rn;
+        hd.improved = 0;
+        int stt = 1;   // 1 = go on
+        if (!isfinite(rn)) {
+            stt = PQPH_NONFINITE;
+        } else {
+            hd.improved = rn < hd.rmin;
+            hd.rmin = fmin(hd.rmin, rn);
+            ds->ring[(it - 1) % kSolveRing] = hd.rmin;
+            if (rn <= o.tol) {
+                stt = PQPH_OK;
+            } else if (stall_test && hd.rmin > 0.5 * old_min) {
+                stt = PQPH_NOT_CONVERGED;
+                hd.stalled = 1;
+            } else if (rn > 1e3 || rn > o.diverge_factor * hd.rmin) {
+                stt = PQPH_DIVERGED;
+            } else if (it >= o.max_iter) {
+                stt = PQPH_NOT_CONVERGED;
+            }
+        }
+        if (stt != 1) {
+            hd.status = stt;
+            hd.active = 0;
+        } else {
+            const int slot = hd.next;
+            hd.last = slot;
+            hd.next = (slot + 1) % o.m;
+            hd.use = 0;
+            if (o.diis_on) {
+                hd.stored = min(hd.stored + 1, o.m);
+                for (int j = 0; j < o.m; ++j) {
+                    const double g = row(1 + j);
+                    ds->B[slot * 16 + j] = g;
+                    ds->B[j * 16 + slot] = g;
+                }
+                if (it >= o.diis_start && hd.stored >= 2) nk = hd.stored;
+            }
+        }
+        if (nk == 0) {
+            ds->h = hd;
+            if (mirror) *mirror = hd;
+        }
+    }
+    __syncthreads();
+    const int k = nk;
+    if (k == 0) return;
+    const bool ok = diis_coefficients(ds->B, k, ds->coef);
+    if (tid != 0) return;
+    if (ok) hd.use = 1;
+    ds->h = hd;
+    if (mirror) *mirror = hd;
+}
+
+__global__ void k_ds_update(const DevSolve* __restrict__ ds, const double* __restrict__ th,
+                            size_t n, double* __restrict__ x, double* __restrict__ best) {
+    const bool active = ds->h.active != 0;
+    const bool keep = best != nullptr && ds->h.improved != 0;
+    if (!active && !keep) return;
+    const bool use = ds->h.use != 0;
+    const int k = ds->h.stored;
+    const double* last = th + (size_t)ds->h.last * n;
+    double c[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c[j] = ds->coef[j];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (keep) best[i] = x[i];
+        if (!active) continue;
+        if (use) {
+            double v = 0.0;
+            for (int j = 0; j < k; ++j) v += c[j] * th[(size_t)j * n + i];
+            x[i] = v;
+        } else {
+            x[i] = last[i];
+        }
+    }
+}
+
+}  // namespace
+
+size_t dev_solve_doubles() { return (sizeof(DevSolve) + sizeof(double) - 1) / sizeof(double); }
+
+void launch_dsolve_init(hipStream_t s, double* state) {
+    hipLaunchKernelGGL(k_ds_init, dim3(1), dim3(64), 0, s, reinterpret_cast<DevSolve*>(state));
+}
+
+void launch_dsolve_step(hipStream_t s, const double* state, const double* x, const double* r,
+                        const double* D, size_t n, double* th, double* eh, int m, double* part,
+                        int nblk) {
+    hipLaunchKernelGGL(k_ds_step, dim3(nblk), dim3(256), 0, s, reinterpret_cast<const DevSolve*>(state),
+                       x, r, D, n, th, eh, m, part);
+}
+
+void launch_dsolve_decide(hipStream_t s, double* state, const double* part, int nblk,
+                          const DevSolveOpts& o, SolveHead* mirror) {
+    hipLaunchKernelGGL(k_ds_decide, dim3(1), dim3(256), 0, s, reinterpret_cast<DevSolve*>(state), part,
+                       nblk, o, mirror);
+}
+
+void launch_dsolve_update(hipStream_t s, const double* state, const double* th, size_t n,
+                          double* x, double* best) {
+    hipLaunchKernelGGL(k_ds_update, dim3(stream_blocks(n)), dim3(256), 0, s,
+                       reinterpret_cast<const DevSolve*>(state), th, n, x, best);
+}
