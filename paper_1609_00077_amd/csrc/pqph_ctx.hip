@@ -596,7 +596,6 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     double* xh = xn + n;
     double* eh = xh + (size_t)m * n;
     double* part = eh + (size_t)m * n;
-    double* scal = part + (size_t)nblk * (m + 1);
     double* hst = ctx->host;
     hipStream_t s = ctx->stream;
     std::vector<double> B(16 * 16, 0.0), c;
@@ -608,9 +607,11 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
     // One host synchronisation per iteration: the Jacobi step, the history
     // copies and the DIIS Gram row are enqueued right behind the residual norm
     // (if the iteration turns out to be the last they are simply unused), and
-    // the norm and the Gram row come back together.  The DIIS coefficients go
-    // to the device from their own pinned slot (hst + 32), which the host
-    // rewrites only after the next synchronisation.
+    // the norm and the Gram row come back together, written by the reduction
+    // kernel straight into the pinned staging (hdev: its device address).
+    // The DIIS coefficients go to the device as kernel arguments.
+    double* hdev = nullptr;
+    PQPH_HIP(ctx, hipHostGetDevicePointer((void**)&hdev, hst, 0));
     const bool diis = o.diis_dim > 0;
     // PQPH_VERBOSE=1: one line per iteration on stderr (long solves report progress)
     const char* venv = getenv("PQPH_VERBOSE");
@@ -626,13 +627,11 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
         const bool step = it < o.max_iter;
         const int slot = next;
         if (step && diis) {      // norm, step and Gram row in one pass, into the history slot
-            launch_step(s, x, r, D, n, xh + (size_t)slot * n, eh, m, slot, part, nblk, scal);
+            launch_step(s, x, r, D, n, xh + (size_t)slot * n, eh, m, slot, part, nblk, hdev);
         } else {
-            launch_norm2(s, r, n, part, nblk, scal);
+            launch_norm2(s, r, n, part, nblk, hdev);
             if (step) launch_jacobi(s, x, r, D, n, xn, e);
         }
-        const int nread = 1 + (step && diis ? m : 0);
-        PQPH_HIP(ctx, hipMemcpyAsync(hst, scal, nread * sizeof(double), hipMemcpyDeviceToHost, s));
         PQPH_HIP(ctx, hipStreamSynchronize(s));
         rn = std::sqrt(hst[0]);
         if (verbose)
@@ -678,10 +677,7 @@ pqph_status jacobi_diis(pqph_ctx* ctx, size_t n, const double* D, double* x,
             for (int a = 0; a < stored; ++a)
                 for (int b = 0; b < stored; ++b) Bs[(size_t)a * 16 + b] = B[(size_t)a * 16 + b];
             if (diis_solve(Bs, stored, c)) {
-                for (int j = 0; j < m; ++j) hst[32 + j] = j < stored ? c[j] : 0.0;
-                PQPH_HIP(ctx, hipMemcpyAsync(scal + 32, hst + 32, m * sizeof(double),
-                                             hipMemcpyHostToDevice, s));
-                launch_combine(s, xh, scal + 32, stored, n, x);   // only written slots
+                launch_combine_host(s, xh, c.data(), stored, n, x);   // only written slots
                 continue;
             }
         }

@@ -195,7 +195,8 @@ pqph_status pq_vjp_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h, 
 int stream_blocks(size_t n);
 // (m+1)x(m+1) DIIS system from the Gram matrix B (row stride 16); false if singular
 bool diis_solve(const std::vector<double>& B, int m, std::vector<double>& c);
-// out[0] = ||r||^2 (fixed-order reduction over nblk partials)
+// out[0] = ||r||^2 (fixed-order reduction over nblk partials); out may be the
+// device address of pinned host memory (launch_step's too)
 void launch_norm2(hipStream_t s, const double* r, size_t n, double* part, int nblk, double* out);
 // e = -r/D, tn = t + e
 void launch_jacobi(hipStream_t s, const double* t, const double* r, const double* D, size_t n,
@@ -211,6 +212,8 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
                  double* eh, int m, int slot, double* part, int nblk, double* out);
 // t = sum_j c[j] th[j]
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
+// the same with c on the host (m <= 16, passed as a kernel argument)
+void launch_combine_host(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t);
 // Pulay's bordered DIIS system [B/scale -1; -1 0] [c; l] = [0; -1] for k
 // stored vectors (B: Gram matrix, row stride 16; scale: its largest
 // diagonal), Gauss-Jordan elimination with partial pivoting; false when B is

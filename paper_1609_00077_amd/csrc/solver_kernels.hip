@@ -54,12 +54,11 @@ __global__ void k_jacobi(const double* __restrict__ t, const double* __restrict_
 // One Jacobi/DIIS step in one pass: e = -r/D into the new history slot
 // eh[slot], tn = t + e, and the block partials of ||r||^2 (row 0) and of
 // e . eh[j] for the m history vectors (rows 1..m; the new slot from the
-// register value).  Same grid-stride order and tree reductions as
-// k_dot_partial / k_dots_partial, so the sums are the same.
-__global__ void k_step(const double* __restrict__ t, const double* __restrict__ r,
-                       const double* __restrict__ D, size_t n, double* __restrict__ tn,
-                       double* __restrict__ eh, int m, int slot, double* __restrict__ partial) {
-    __shared__ double red[256];
+// register value): wavefront sums, then the four wavefronts in a fixed order.
+__global__ __launch_bounds__(256) void k_step(const double* __restrict__ t, const double* __restrict__ r,
+                                              const double* __restrict__ D, size_t n, double* __restrict__ tn,
+                                              double* __restrict__ eh, int m, int slot,
+                                              double* __restrict__ partial) {
     double sr = 0.0, sg[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) sg[j] = 0.0;
@@ -75,16 +74,19 @@ __global__ void k_step(const double* __restrict__ t, const double* __restrict__ 
         for (int j = 0; j < 16; ++j)
             if (j < m) sg[j] += (j == slot ? d : eh[(size_t)j * n + i]) * d;
     }
-    for (int row = 0; row <= m; ++row) {
-        red[threadIdx.x] = row == 0 ? sr : sg[row - 1];
-        __syncthreads();
-        for (int k = 128; k > 0; k >>= 1) {
-            if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-            __syncthreads();
+    __shared__ double red[4][17];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 17; ++j) {
+        if (j <= m) {
+            double v = j == 0 ? sr : sg[j > 0 ? j - 1 : 0];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[wv][j] = v;
         }
-        if (threadIdx.x == 0) partial[(size_t)row * gridDim.x + blockIdx.x] = red[0];
-        __syncthreads();
     }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j <= m) partial[(size_t)j * gridDim.x + blockIdx.x] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
 }
 
 // t = sum_i c[i] * hist[slot_i]
@@ -94,6 +96,20 @@ __global__ void k_combine(const double* __restrict__ hist, const double* __restr
          i += (size_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int j = 0; j < m; ++j) s += c[j] * hist[(size_t)j * n + i];
+        t[i] = s;
+    }
+}
+
+// t = sum_j c.v[j] hist[j], the coefficients passed by value (m <= 16)
+struct Coef16 {
+    double v[16];
+};
+__global__ void k_combine_v(const double* __restrict__ hist, Coef16 c, int m, size_t n,
+                            double* __restrict__ t) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += c.v[j] * hist[(size_t)j * n + i];
         t[i] = s;
     }
 }
@@ -221,6 +237,12 @@ void launch_step(hipStream_t s, const double* t, const double* r, const double* 
 
 void launch_combine(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t) {
     hipLaunchKernelGGL(k_combine, dim3(stream_blocks(n)), dim3(256), 0, s, th, c, m, n, t);
+}
+
+void launch_combine_host(hipStream_t s, const double* th, const double* c, int m, size_t n, double* t) {
+    Coef16 cv;
+    for (int j = 0; j < 16; ++j) cv.v[j] = j < m ? c[j] : 0.0;
+    hipLaunchKernelGGL(k_combine_v, dim3(stream_blocks(n)), dim3(256), 0, s, th, cv, m, n, t);
 }
 
 // gamma_pp += 2 for the occupied orbitals p < npair: the reference part of
