@@ -511,6 +511,17 @@ def main():
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     value = iters / T
+    # the same solves with the Jacobi/DIIS decisions on the device (opt-in mode)
+    pq.set_solve_mode("device")
+    step()
+    torch.cuda.synchronize()
+    iters_dev = 0
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        iters_dev += step()[0].iterations
+    torch.cuda.synchronize()
+    value_dev = iters_dev / (time.perf_counter() - t1)
+    pq.set_solve_mode("host")
 
     # back-to-back residuals at the converged amplitudes (HIP events on the stream)
     t_conv = res.t
@@ -559,6 +570,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": hbm_traffic(kernel_variant(dom, N, pq.tuning(N))),
                      "flops_per_launch": flops[dom], "ms_per_launch": acc[dom]},
+        "device_driven_solve_evals_per_s": value_dev,
         "residual_ms": resid_ms,
         "residual_evals_per_s_back_to_back": 1e3 / resid_ms,
         "residual_flops": sum(flops.values()),
