@@ -34,6 +34,7 @@ struct Chain {
     const double *h = nullptr, *eri = nullptr;
     double* t = nullptr;
     double *D, *r, *e, *tn, *th, *eh, *part;
+    double* vtx = nullptr;        // the chain's bare vertices, formed once per batch
     int stored = 0, next = 0;
     bool active = true;
     int iters = 0;
@@ -272,7 +273,9 @@ pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
         for (int c : b.order) {
             Chain& x = ch[c];
             if (!x.active) continue;
-            if ((st = pq_residual_ws(ctx, S(x), x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream]))) return st;
+            if ((st = pq_residual_ws(ctx, S(x), x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream], nullptr, -1, false,
+                                     x.vtx)))
+                return st;
             launch_norm2(S(x), x.r, x.n, x.part, x.nblk, b.norms + c);
         }
         if ((st = join(ctx, ns))) return st;
@@ -368,7 +371,9 @@ pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
         hipStream_t s = ctx->bstreams[x.stream];
         DevChain* d = b.dst + c;
         const int* gate = &d->active;
-        if ((st = pq_residual_ws(ctx, s, x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream], gate))) return st;
+        if ((st = pq_residual_ws(ctx, s, x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream], gate, -1, false,
+                                 x.vtx)))
+            return st;
         hipLaunchKernelGGL(k_b_norm_partial, dim3(x.nblk), dim3(256), 0, s, d, x.r, x.n, x.part);
         hipLaunchKernelGGL(k_b_sum_rows, dim3(1), dim3(256), 0, s, d, x.part, x.nblk, b.norms + c);
         hipLaunchKernelGGL(k_b_check, dim3(1), dim3(1), 0, s, d, b.norms + c, bo);
@@ -528,7 +533,7 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     // the device-resident chain states
     size_t total = 0;
     for (int s = 0; s < ns; ++s) total += ws_need[s];
-    for (auto& x : ch) total += x.n * (4 + 2 * (size_t)m) + (size_t)x.nblk * (m + 1);
+    for (auto& x : ch) total += x.n * (4 + 2 * (size_t)m) + (size_t)x.nblk * (m + 1) + pq_vertex_doubles(x.N);
     const size_t nsmall = (size_t)nbatch * (2 * m + 4);
     total += nsmall;
     const size_t dstd = (sizeof(DevChain) * nbatch + sizeof(double) - 1) / sizeof(double);
@@ -548,6 +553,7 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
         x.th = p; p += (size_t)m * x.n;
         x.eh = p; p += (size_t)m * x.n;
         x.part = p; p += (size_t)x.nblk * (m + 1);
+        x.vtx = p; p += pq_vertex_doubles(x.N);
     }
     b.norms = p; p += nbatch;
     b.gram = p; p += (size_t)nbatch * m;
@@ -565,6 +571,8 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
         Chain& x = ch[c];
         if ((st = pq_denominators_dev(ctx, S(x), x.N, x.h, o.level_shift, x.D))) return st;
         launch_absmin(S(x), x.D, x.n, x.part, x.nblk, b.dmin + c);
+        // the vertices depend on the chain's integrals only: formed once
+        if ((st = pq_vertices_into(ctx, S(x), x.N, x.h, x.eri, x.vtx))) return st;
     }
     if ((st = join(ctx, ns))) return st;
     PQPH_HIP(ctx, hipMemcpyAsync(hst, b.dmin, nbatch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));

@@ -2183,10 +2183,37 @@ pqph_status pq_vertices_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
     return PQPH_OK;
 }
 
+// a private vertex block: h1 [PQ_H1_N][N], h2 [PQ_H2_N][N][N], h2K [PQ_H2_N][C(N,2)]
+size_t pq_vertex_doubles(int N) {
+    const size_t NN = (size_t)N * N, np2 = (size_t)N * (N - 1) / 2;
+    return (size_t)PQ_H1_N * N + (size_t)PQ_H2_N * NN + (size_t)PQ_H2_N * std::max(np2, (size_t)1);
+}
+
+namespace {
+void vertex_block(double* vtx, int N, Carve& c) {
+    c.h1 = vtx;
+    c.h2 = c.h1 + (size_t)PQ_H1_N * N;
+    c.h2T = c.h2 + (size_t)PQ_H2_N * N * N;
+}
+}  // namespace
+
+pqph_status pq_vertices_into(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
+                             const double* eri, double* vtx) {
+    Carve c;
+    vertex_block(vtx, N, c);
+    launch_vertices(ctx, s, N, h, eri, c, nullptr);
+    PQPH_HIP(ctx, hipGetLastError());
+    return PQPH_OK;
+}
+
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int N, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate, int fork, bool vertices) {
+                           const int* gate, int fork, bool vertices, const double* vtx) {
     Carve c = carve(ws, N);
+    if (vtx) {               // read-only from here on
+        vertex_block(const_cast<double*>(vtx), N, c);
+        vertices = false;
+    }
     pqph_status st = prepare(ctx, s, N, h, eri, t, c, gate, vertices);
     if (st) return st;
     View v = make_view(t, c, N);

@@ -161,12 +161,19 @@ size_t pq_ws_doubles(int npair);
 // vertices: false when ws already holds the bare vertices of h and eri
 // (pq_vertices_ws, nothing written over them since): they depend on the
 // integrals only, so a solve forms them once
+// vtx: a private vertex block (pq_vertices_into) read instead of ws's vertices
 pqph_status pq_residual_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                            const double* eri, const double* t, double* r, double* ws,
-                           const int* gate = nullptr, int fork = -1, bool vertices = true);
+                           const int* gate = nullptr, int fork = -1, bool vertices = true,
+                           const double* vtx = nullptr);
 // the bare vertices of h and eri into ws (where pq_residual_ws reads them)
 pqph_status pq_vertices_ws(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
                            const double* eri, double* ws);
+// the same into a private block of pq_vertex_doubles(npair) doubles (batched
+// chains that share a workspace keep their vertices apart)
+size_t pq_vertex_doubles(int npair);
+pqph_status pq_vertices_into(pqph_ctx* ctx, hipStream_t s, int npair, const double* h,
+                             const double* eri, double* vtx);
 // one-time kernel attributes of the residual (outside any stream capture)
 pqph_status pq_residual_prepare(pqph_ctx* ctx);
 // the residual on the context's stream replayed from a HIP graph captured for
