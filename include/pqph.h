@@ -301,8 +301,8 @@ pqph_status pqph_set_s1_mode(pqph_ctx* ctx, int npair, int mode);
 pqph_status pqph_set_pq_intermediates(pqph_ctx* ctx, int npair, int labels);
 
 /* The choices in effect for npair on this context (host outputs, each may be
- * NULL): the two-spectator variant (1 or 2) and the one-spectator mode (1, 2
- * or 3). */
+ * NULL): the two-spectator variant (1 or 2) and the one-spectator mode
+ * (1-4). */
 pqph_status pqph_tuning(pqph_ctx* ctx, int npair, int* s2_variant, int* s1_mode);
 
 /* Diagnostic: the device's measured ceilings for roofline fractions, host
@@ -322,8 +322,9 @@ pqph_status pqph_measure_ceilings(pqph_ctx* ctx, double* out);
  * NULL) each chain's report.  Returns OK if every chain converged, otherwise
  * the first failing chain's status; one bad chain does not stop the others.
  * Device memory: the residual workspace of the largest chain per stream (up
- * to 8 streams) plus (4 + 2*diis_dim) amplitude vectors per chain and about
- * 4.3 KB of solver state per chain.  By default the iterations run entirely
+ * to 8 streams) plus, per chain, (4 + 2*diis_dim) amplitude vectors, the
+ * chain's bare vertices (formed once per batch: 308 N^2 + 308 C(N,2) + 26 N
+ * doubles, about 15 MB at N = 65) and about 4.3 KB of solver state.  By default the iterations run entirely
  * on the device: one iteration of the whole batch is captured into a HIP graph
  * and replayed, and the host only polls the chains' finished flags every few
  * replays (opts->stall_window must be below 257 here; opts->max_rank must
