@@ -508,7 +508,7 @@ pqph_status jacobi_diis_device(pqph_ctx* ctx, size_t n, const double* D, double*
     for (hipEvent_t& e : ctx->dsev)
         if (!e) PQPH_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // two slots by iteration parity in the pinned staging, written by the
-    // decide kernel of every iteration that ran (device address hd)
+    // update kernel of every iteration (device address hd)
     SolveHead* hh = reinterpret_cast<SolveHead*>(ctx->host);
     static_assert(2 * sizeof(SolveHead) <= 64 * sizeof(double), "host staging too small");
     SolveHead* hd = nullptr;
@@ -545,15 +545,15 @@ pqph_status jacobi_diis_device(pqph_ctx* ctx, size_t n, const double* D, double*
         if (pqph_status e = resid(x, r)) return e;
         if (masked) launch_rank_mask(s, r, rank, o.max_rank, n);
         launch_dsolve_step(s, state, x, r, D, n, th, eh, m, part, nblk);
-        launch_dsolve_decide(s, state, part, nblk, dopts, hd + (it & 1));
-        launch_dsolve_update(s, state, th, n, x, best);
+        launch_dsolve_decide(s, state, part, nblk, dopts);
+        launch_dsolve_update(s, state, th, n, x, best, hd + (it & 1));
         PQPH_HIP(ctx, hipEventRecord(ctx->dsev[it & 1], s));
         if (it > 1) {       // the state after iteration it - 1 (iteration it is already queued)
             PQPH_HIP(ctx, hipEventSynchronize(ctx->dsev[(it - 1) & 1]));
             const SolveHead prev = hh[(it - 1) & 1];
             report(prev);
-            // an iteration gated off writes no mirror, but the one that
-            // ended the solve did, and the host reads every iteration's slot
+            // the iteration that ended the solve wrote its own count (an
+            // iteration gated off copies the unchanged state)
             if (!prev.active && prev.iters == it - 1) break;
         }
     }

@@ -352,14 +352,14 @@ void launch_dsolve_step(hipStream_t s, const double* state, const double* x, con
                         const double* D, size_t n, double* th, double* eh, int m, double* part,
                         int nblk);
 // when active: sums the partials, tests the norm, updates the Gram matrix and
-// solves for the DIIS coefficients (one workgroup); the new head is also
-// written to mirror (device address of pinned host memory; may be NULL)
+// solves for the DIIS coefficients (one workgroup)
 void launch_dsolve_decide(hipStream_t s, double* state, const double* part, int nblk,
-                          const DevSolveOpts& o, SolveHead* mirror);
+                          const DevSolveOpts& o);
 // when active: x = sum_j c_j th[j] (DIIS) or th[last]; best (may be NULL)
-// takes x first when the last norm was the smallest so far
+// takes x first when the last norm was the smallest so far.  Always: the
+// head is copied to mirror (device address of pinned host memory; may be NULL)
 void launch_dsolve_update(hipStream_t s, const double* state, const double* th, size_t n,
-                          double* x, double* best);
+                          double* x, double* best, SolveHead* mirror);
 
 // f = diag(-1 occupied, 0 virtual): through the denominator kernels, the slot ranks
 void launch_rank_fock(hipStream_t s, double* f, int npair);

@@ -393,12 +393,14 @@ __global__ __launch_bounds__(256) void k_ds_step(const DevSolve* __restrict__ ds
 // by the whole workgroup.
 __global__ __launch_bounds__(256) void k_ds_decide(DevSolve* __restrict__ ds,
                                                    const double* __restrict__ partial, int nblk,
-                                                   DevSolveOpts o, SolveHead* __restrict__ mirror) {
+                                                   DevSolveOpts o) {
     SolveHead hd = ds->h;
     if (!hd.active) return;    // the same copy in every thread; thread 0 writes after the barrier
     __shared__ double red[4][17];
+    __shared__ double Bs[16 * 16];   // the Gram matrix, updated here and read by the DIIS solve
     __shared__ int nk;         // DIIS vectors to extrapolate with, 0 = none
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    Bs[tid] = ds->B[tid];
     const int it = hd.iters + 1;
     const bool stall_test = o.stall_window > 0 && it > o.stall_window;
     const double old_min = stall_test ? ds->ring[(it - 1 - o.stall_window) % kSolveRing] : 0.0;
@@ -461,27 +463,29 @@ __global__ __launch_bounds__(256) void k_ds_decide(DevSolve* __restrict__ ds,
                     const double g = row(1 + j);
                     ds->B[slot * 16 + j] = g;
                     ds->B[j * 16 + slot] = g;
+                    Bs[slot * 16 + j] = g;
+                    Bs[j * 16 + slot] = g;
                 }
                 if (it >= o.diis_start && hd.stored >= 2) nk = hd.stored;
             }
         }
-        if (nk == 0) {
-            ds->h = hd;
-            if (mirror) *mirror = hd;
-        }
+        if (nk == 0) ds->h = hd;
     }
     __syncthreads();
     const int k = nk;
     if (k == 0) return;
-    const bool ok = diis_coefficients(ds->B, k, ds->coef);
+    const bool ok = diis_coefficients(Bs, k, ds->coef);
     if (tid != 0) return;
     if (ok) hd.use = 1;
     ds->h = hd;
-    if (mirror) *mirror = hd;
 }
 
+// Also copies the state to mirror (pinned host memory) from one thread: the
+// write to host memory overlaps the other workgroups' work.
 __global__ void k_ds_update(const DevSolve* __restrict__ ds, const double* __restrict__ th,
-                            size_t n, double* __restrict__ x, double* __restrict__ best) {
+                            size_t n, double* __restrict__ x, double* __restrict__ best,
+                            SolveHead* __restrict__ mirror) {
+    if (mirror && blockIdx.x == 0 && threadIdx.x == 0) *mirror = ds->h;
     const bool active = ds->h.active != 0;
     const bool keep = best != nullptr && ds->h.improved != 0;
     if (!active && !keep) return;
@@ -521,13 +525,13 @@ void launch_dsolve_step(hipStream_t s, const double* state, const double* x, con
 }
 
 void launch_dsolve_decide(hipStream_t s, double* state, const double* part, int nblk,
-                          const DevSolveOpts& o, SolveHead* mirror) {
+                          const DevSolveOpts& o) {
     hipLaunchKernelGGL(k_ds_decide, dim3(1), dim3(256), 0, s, reinterpret_cast<DevSolve*>(state), part,
-                       nblk, o, mirror);
+                       nblk, o);
 }
 
 void launch_dsolve_update(hipStream_t s, const double* state, const double* th, size_t n,
-                          double* x, double* best) {
+                          double* x, double* best, SolveHead* mirror) {
     hipLaunchKernelGGL(k_ds_update, dim3(stream_blocks(n)), dim3(256), 0, s,
-                       reinterpret_cast<const DevSolve*>(state), th, n, x, best);
+                       reinterpret_cast<const DevSolve*>(state), th, n, x, best, mirror);
 }
