@@ -168,3 +168,16 @@ def test_solve_mode_rejects_other_values(pq):
     assert lib.pqph_set_solve_mode(ctx, 2) == -1
     with pytest.raises(ValueError):
         pq.set_solve_mode("fast")
+
+
+@pytest.mark.parametrize("max_rank", [2, 3])
+def test_rank_limited_modes_agree(pq, max_rank):
+    """Excitation-rank limits mask the residual inside both loops alike, so
+    the rank-limited solutions agree."""
+    prob = chain_problem(24, U=4.0, seed=24)
+    f, eri = pq.integrals(_d(prob.F_site), _d(prob.V), _d(prob.C), k=2)
+    a, b = _both(pq, f, eri, tol=1e-10, max_rank=max_rank)
+    assert a.status == b.status == "OK"
+    assert abs(a.iterations - b.iterations) <= 1
+    assert abs(a.energy - b.energy) < 1e-11
+    assert (a.t - b.t).abs().max().item() < 1e-9
