@@ -410,8 +410,9 @@ pqph_status pqph_autotune(pqph_ctx* ctx, int npair, const double* h, const doubl
     const int nvar = (npair + 15) / 16 <= 6 ? 2 : 1;
     float best = 1e30f;
     int bestv = 1, bestm = 1;
-    // modes 1..4 up to 128 pairs; above, 1, 2 and 4 (mode 3 is not built there)
-    const int modes[4] = {1, 2, npair <= 128 ? 3 : 4, 4};
+    // the default mode 4 first (near-ties keep it, below), then 1, 2 and,
+    // up to 128 pairs, 3 (not built above)
+    const int modes[4] = {4, 1, 2, 3};
     const int nmode = npair <= 128 ? 4 : 3;
     for (int combo = 0; combo < nmode * nvar; ++combo) {
         const int var = 1 + combo % nvar, mode = modes[combo / nvar];
