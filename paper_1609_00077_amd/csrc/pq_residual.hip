@@ -98,36 +98,59 @@ __global__ void k_vertex1(int N, const double* __restrict__ f, const double* __r
     h1[(long)key * N + P] = v;
 }
 
-__global__ void k_vertex2(int N, const double* __restrict__ f, const double* __restrict__ eri,
-                          double* __restrict__ h2, double* __restrict__ h2T, const int* __restrict__ gate) {
+// h2[key][P][Q] for one key and a 32 x 32 tile of (P, Q) per workgroup, and
+// its k-major copy h2K[key][pq] over the output pairs P < Q.  The values are
+// formed with the lanes along the label whose packed integral index is
+// contiguous, staged in LDS, and written row by row into h2 and, for tiles on
+// or above the diagonal, pair by pair into h2K, so every store is a run of
+// up to 32 consecutive doubles.
+constexpr int V2_TILE = 32;
+__global__ __launch_bounds__(256) void k_vertex2(int N, const double* __restrict__ f,
+                                                 const double* __restrict__ eri, double* __restrict__ h2,
+                                                 double* __restrict__ h2T, const int* __restrict__ gate) {
     if (gate && *gate == 0) return;   // chain finished (batched solves)
-    const int Q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int P = blockIdx.y, key = blockIdx.z;
-    if (Q >= N) return;
-    const long NN = (long)N * N, n2 = 2L * N;
-    double v = 0.0;
-    if (P != Q) {
-        const long np2 = (long)N * (N - 1) / 2;
-        const int lo = min(P, Q), hi = max(P, Q);
-        const long pidx = (long)hi * (hi - 1) / 2 + lo;
-        const double* e2 = eri + 6L * N;
-        for (int i = pq_h2_start[key]; i < pq_h2_start[key + 1]; ++i) {
-            const double w = pq_h2_w[i];
-            if (pq_h2_kind[i] == 0) {
-                const int a = pq_h2_a[i], b = pq_h2_b[i];
-                const int p = ((a >> 1) ? Q : P) + N * (a & 1);
-                const int q = ((b >> 1) ? Q : P) + N * (b & 1);
-                v += w * f[p * n2 + q];
-            } else {
-                const int u = P < Q ? pq_h2_a[i] : pq_h2_b[i];
-                v += w * e2[(long)u * np2 + pidx];
+    __shared__ double tile[V2_TILE][V2_TILE + 1];
+    const int nt = (N + V2_TILE - 1) / V2_TILE;
+    const int tp = blockIdx.x / nt, tq = blockIdx.x % nt, key = blockIdx.y;
+    const int P0 = tp * V2_TILE, Q0 = tq * V2_TILE;
+    const long NN = (long)N * N, n2 = 2L * N, np2 = (long)N * (N - 1) / 2;
+    const double* e2 = eri + 6L * N;
+    const int i0 = pq_h2_start[key], i1 = pq_h2_start[key + 1];
+    const bool upper = tp < tq;          // every P < Q: the packed index runs along P
+    for (int e = threadIdx.x; e < V2_TILE * V2_TILE; e += blockDim.x) {
+        const int a = e & (V2_TILE - 1), b = e / V2_TILE;
+        const int pl = upper ? a : b, ql = upper ? b : a;
+        const int P = P0 + pl, Q = Q0 + ql;
+        double v = 0.0;
+        if (P < N && Q < N && P != Q) {
+            const int lo = min(P, Q), hi = max(P, Q);
+            const long pidx = (long)hi * (hi - 1) / 2 + lo;
+            for (int i = i0; i < i1; ++i) {
+                const double w = pq_h2_w[i];
+                if (pq_h2_kind[i] == 0) {
+                    const int ka = pq_h2_a[i], kb = pq_h2_b[i];
+                    const int p = ((ka >> 1) ? Q : P) + N * (ka & 1);
+                    const int q = ((kb >> 1) ? Q : P) + N * (kb & 1);
+                    v += w * f[p * n2 + q];
+                } else {
+                    const int u = P < Q ? pq_h2_a[i] : pq_h2_b[i];
+                    v += w * e2[(long)u * np2 + pidx];
+                }
             }
         }
+        tile[pl][ql] = v;
     }
-    h2[(long)key * NN + (long)P * N + Q] = v;
-    if (P < Q) {   // k-major copy over output pairs: h2K[key][pq]
-        const long np2 = (long)N * (N - 1) / 2;
-        h2T[(long)key * np2 + (long)Q * (Q - 1) / 2 + P] = v;
+    __syncthreads();
+    for (int e = threadIdx.x; e < V2_TILE * V2_TILE; e += blockDim.x) {
+        const int pl = e / V2_TILE, ql = e & (V2_TILE - 1);
+        const int P = P0 + pl, Q = Q0 + ql;
+        if (P < N && Q < N) h2[(long)key * NN + (long)P * N + Q] = tile[pl][ql];
+    }
+    if (tp > tq) return;                 // no pair P < Q in this tile
+    for (int e = threadIdx.x; e < V2_TILE * V2_TILE; e += blockDim.x) {
+        const int pl = e & (V2_TILE - 1), ql = e / V2_TILE;
+        const int P = P0 + pl, Q = Q0 + ql;
+        if (P < Q && Q < N) h2T[(long)key * np2 + (long)Q * (Q - 1) / 2 + P] = tile[pl][ql];
     }
 }
 
@@ -2149,7 +2172,8 @@ void launch_vertices(pqph_ctx* ctx, hipStream_t s, int N, const double* h, const
     hipLaunchKernelGGL(k_vertex1, dim3(gx, PQ_H1_N), dim3(tb), 0, s, N, h, eri, c.h1, gate);
     pqph_mark(ctx);
     if (N > 1) {
-        hipLaunchKernelGGL(k_vertex2, dim3(gx, N, PQ_H2_N), dim3(tb), 0, s, N, h, eri, c.h2, c.h2T,
+        const int nt = (N + V2_TILE - 1) / V2_TILE;
+        hipLaunchKernelGGL(k_vertex2, dim3(nt * nt, PQ_H2_N), dim3(256), 0, s, N, h, eri, c.h2, c.h2T,
                            gate);
         pqph_mark(ctx);
     }
