@@ -537,9 +537,15 @@ pqph_status jacobi_diis_device(pqph_ctx* ctx, size_t n, const double* D, double*
     const bool masked = rank != nullptr && o.max_rank > 0;
     launch_dsolve_init(s, state);
     if (masked) launch_rank_mask(s, x, rank, o.max_rank, n);
-    struct GateScope {      // the gate is published only while this loop runs
+    // The gate is published only while this loop runs.  On every way out the
+    // stream is drained first: iterations queued ahead write the mirror slots
+    // in the pinned staging, which a later call may reallocate.
+    struct GateScope {
         pqph_ctx* c;
-        ~GateScope() { c->solve_gate = nullptr; }
+        ~GateScope() {
+            (void)hipStreamSynchronize(c->stream);
+            c->solve_gate = nullptr;
+        }
     } scope{ctx};
     ctx->solve_gate = &head->active;
     for (int it = 1; it <= o.max_iter; ++it) {
