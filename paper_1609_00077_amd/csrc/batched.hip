@@ -6,13 +6,14 @@
 // residual workspace.
 //
 // Default (graph) mode: the whole iteration of every chain runs on the device
-// -- residual, norm, convergence/divergence/stall check, Jacobi step written
-// straight into the DIIS history, Gram row, the (m+1)x(m+1) DIIS solve by one
-// thread, extrapolation -- with the chain's state (flags, counters, B matrix,
-// coefficients, best-norm ring) in device memory.  One iteration of the whole
-// batch is captured once into a HIP graph and replayed; a finished chain
-// closes its gate flag and all of its later kernels return at once.  The host
-// only polls the gate flags every few replays.
+// -- the residual, then the single solve's device-driven kernels: one pass for
+// the norm, the Jacobi step into the DIIS history and the Gram row; one
+// workgroup for the convergence/stall/divergence tests and the (m+1)x(m+1)
+// DIIS solve; the extrapolation -- with the chain's state (flags, counters,
+// B matrix, coefficients, best-norm ring) in device memory.  One iteration of
+// the whole batch is captured once into a HIP graph and replayed; a finished
+// chain closes its gate flag and all of its later kernels return at once.
+// The host only polls the gate flags every few replays.
 //
 // Lockstep mode (pqph_set_batch_mode 1): the same iteration driven from the
 // host, with three host synchronisations per iteration for the whole batch.
@@ -75,175 +76,9 @@ pqph_status join(pqph_ctx* ctx, int ns) {
 
 
 // ------------------------------------------------- device-resident iteration
-constexpr int kRing = 257;            // best-norm ring; stall_window <= kRing - 1
-
-struct DevChain {
-    int active, iters, next, stored, status, use, last, pad;
-    double rn, rmin;
-    double B[16 * 16];
-    double coef[16];
-    double best[kRing];
-};
-
-struct BOpts {
-    int max_iter, diis_dim, diis_start, stall_window;
-    double tol, diverge_factor;
-};
-
-__global__ void k_b_init(DevChain* st, int nb) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
-    DevChain& s = st[c];
-    s.active = 1;
-    s.iters = s.next = s.stored = s.use = s.last = s.pad = 0;
-    s.status = PQPH_NOT_CONVERGED;
-    s.rn = s.rmin = INFINITY;
-    for (int i = 0; i < 16 * 16; ++i) s.B[i] = 0.0;
-    for (int i = 0; i < 16; ++i) s.coef[i] = 0.0;
-}
-
-// partial sums of ||r||^2 (grid-stride, fixed order)
-__global__ void k_b_norm_partial(const DevChain* __restrict__ st, const double* __restrict__ r,
-                                 size_t n, double* __restrict__ partial) {
-    if (!st->active) return;
-    __shared__ double red[256];
-    double s = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        s += r[i] * r[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// out[j] = sum of partial[j*nblk .. (j+1)*nblk)
-__global__ void k_b_sum_rows(const DevChain* __restrict__ st, const double* __restrict__ partial,
-                             int nblk, double* __restrict__ out) {
-    if (!st->active) return;
-    __shared__ double red[256];
-    const int j = blockIdx.x;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(size_t)j * nblk + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[j] = red[0];
-}
-
-// convergence, failure and stall decisions of one iteration (one thread)
-__global__ void k_b_check(DevChain* __restrict__ st, const double* __restrict__ norm2, BOpts o) {
-    DevChain& s = *st;
-    if (!s.active) return;
-    const int it = ++s.iters;
-    const double rn = sqrt(*norm2);
-    s.rn = rn;
-    s.rmin = fmin(s.rmin, rn);
-    s.best[(it - 1) % kRing] = s.rmin;
-    const bool stalled = o.stall_window > 0 && it > o.stall_window &&
-                         s.rmin > 0.5 * s.best[(it - 1 - o.stall_window) % kRing];
-    int stt = 1;   // 1 = keep going
-    if (!isfinite(rn)) stt = PQPH_NONFINITE;
-    else if (rn <= o.tol) stt = PQPH_OK;
-    else if (rn > 1e3 || rn > o.diverge_factor * s.rmin) stt = PQPH_DIVERGED;
-    else if (stalled || it >= o.max_iter) stt = PQPH_NOT_CONVERGED;
-    if (stt != 1) {
-        s.status = stt;
-        s.active = 0;
-    }
-}
-
-// e = -r/D and tn = t + e, written into the history slot `next`
-__global__ void k_b_jacobi(const DevChain* __restrict__ st, const double* __restrict__ t,
-                           const double* __restrict__ r, const double* __restrict__ D, size_t n,
-                           double* __restrict__ th, double* __restrict__ eh) {
-    if (!st->active) return;
-    const size_t off = (size_t)st->next * n;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const double d = -r[i] / D[i];
-        eh[off + i] = d;
-        th[off + i] = t[i] + d;
-    }
-}
-
-// partial sums of <e_j, e_new> for every history slot j (blockIdx.y)
-__global__ void k_b_gram_partial(const DevChain* __restrict__ st, const double* __restrict__ eh,
-                                 size_t n, int nblk, double* __restrict__ partial) {
-    if (!st->active) return;
-    __shared__ double red[256];
-    const int j = blockIdx.y;
-    const double* a = eh + (size_t)j * n;
-    const double* b = eh + (size_t)st->next * n;
-    double s = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        s += a[i] * b[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)j * nblk + blockIdx.x] = red[0];
-}
-
-// B-matrix update (thread 0) and the bordered DIIS system (Pulay) by the
-// workgroup (diis_coefficients); on a (near) singular system the plain Jacobi
-// step is taken.
-__global__ void k_b_diis(DevChain* __restrict__ st, const double* __restrict__ grow, int m,
-                         int diis_start, int diis_on) {
-    DevChain& s = *st;
-    if (!s.active) return;     // read by every thread before thread 0 writes (barrier below)
-    __shared__ int nk;
-    if (threadIdx.x == 0) {
-        nk = 0;
-        const int slot = s.next;
-        s.last = slot;
-        s.next = (slot + 1) % m;
-        s.use = 0;
-        if (diis_on) {
-            s.stored = min(s.stored + 1, m);
-            for (int j = 0; j < m; ++j) {
-                s.B[slot * 16 + j] = grow[j];
-                s.B[j * 16 + slot] = grow[j];
-            }
-            if (s.iters >= diis_start && s.stored >= 2) nk = s.stored;
-        }
-    }
-    __syncthreads();
-    const int k = nk;
-    if (k == 0) return;
-    if (diis_coefficients(s.B, k, s.coef) && threadIdx.x == 0) s.use = 1;
-}
-
-// t = sum_j c_j tn_j (DIIS) or the Jacobi iterate of this step
-__global__ void k_b_update(const DevChain* __restrict__ st, const double* __restrict__ th, int m,
-                           size_t n, double* __restrict__ t) {
-    if (!st->active) return;
-    const bool use = st->use;
-    const int k = min(st->stored, m);          // valid history slots 0..k-1
-    const double* last = th + (size_t)st->last * n;
-    double c[16];
-    for (int j = 0; j < 16; ++j) c[j] = st->coef[j];
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        if (use) {
-            double v = 0.0;
-            for (int j = 0; j < k; ++j) v += c[j] * th[(size_t)j * n + i];
-            t[i] = v;
-        } else {
-            t[i] = last[i];
-        }
-    }
-}
-
+// Each chain's Jacobi/DIIS state lives in device memory (the single solve's
+// device-driven state, dev_solve_doubles() doubles per chain); its active
+// flag gates every kernel of the chain, residual included.
 }  // namespace
 
 namespace {
@@ -255,7 +90,9 @@ struct Batch {
     std::vector<int> order;
     std::vector<double*> ws;
     double *norms, *gram, *coef, *edev, *dmin;
-    DevChain* dst;
+    double* dstate;               // nb device-resident chain states, dsd doubles apart
+    size_t dsd;
+    SolveHead* head(int c) const { return reinterpret_cast<SolveHead*>(dstate + (size_t)c * dsd); }
 };
 
 pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
@@ -291,10 +128,12 @@ pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
             x.best.push_back(x.rmin);
             const bool stalled = o.stall_window > 0 && it > o.stall_window &&
                                  x.rmin > 0.5 * x.best[it - 1 - o.stall_window];
+            // the single solve's order: non-finite, converged, stalled, diverged, limit
             if (!std::isfinite(x.rn)) x.st = PQPH_NONFINITE;
             else if (x.rn <= o.tol) x.st = PQPH_OK;
+            else if (stalled) x.st = PQPH_NOT_CONVERGED;
             else if (x.rn > 1e3 || x.rn > o.diverge_factor * x.rmin) x.st = PQPH_DIVERGED;
-            else if (stalled || it == o.max_iter) x.st = PQPH_NOT_CONVERGED;
+            else if (it == o.max_iter) x.st = PQPH_NOT_CONVERGED;
             else continue;
             x.active = false;
             --nactive;
@@ -363,31 +202,21 @@ pqph_status lockstep(pqph_ctx* ctx, Batch& b) {
     return PQPH_OK;
 }
 
-// one iteration of every chain, enqueued on the batch streams (captured)
-pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
+// one iteration of every chain, enqueued on the batch streams (captured): the
+// residual, then the single solve's device-driven step, decision and update
+pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const DevSolveOpts& dopts) {
     pqph_status st;
     for (int c : b.order) {
         Chain& x = b.ch[c];
         hipStream_t s = ctx->bstreams[x.stream];
-        DevChain* d = b.dst + c;
-        const int* gate = &d->active;
+        double* state = b.dstate + (size_t)c * b.dsd;
+        const int* gate = &b.head(c)->active;
         if ((st = pq_residual_ws(ctx, s, x.N, x.h, x.eri, x.t, x.r, b.ws[x.stream], gate, -1, false,
                                  x.vtx)))
             return st;
-        hipLaunchKernelGGL(k_b_norm_partial, dim3(x.nblk), dim3(256), 0, s, d, x.r, x.n, x.part);
-        hipLaunchKernelGGL(k_b_sum_rows, dim3(1), dim3(256), 0, s, d, x.part, x.nblk, b.norms + c);
-        hipLaunchKernelGGL(k_b_check, dim3(1), dim3(1), 0, s, d, b.norms + c, bo);
-        hipLaunchKernelGGL(k_b_jacobi, dim3(x.nblk), dim3(256), 0, s, d, x.t, x.r, x.D, x.n, x.th,
-                           x.eh);
-        if (b.o.diis_dim > 0) {
-            hipLaunchKernelGGL(k_b_gram_partial, dim3(x.nblk, b.m), dim3(256), 0, s, d, x.eh, x.n,
-                               x.nblk, x.part);
-            hipLaunchKernelGGL(k_b_sum_rows, dim3(b.m), dim3(256), 0, s, d, x.part, x.nblk,
-                               b.gram + (size_t)c * b.m);
-        }
-        hipLaunchKernelGGL(k_b_diis, dim3(1), dim3(64), 0, s, d, b.gram + (size_t)c * b.m, b.m,
-                           b.o.diis_start, b.o.diis_dim > 0 ? 1 : 0);
-        hipLaunchKernelGGL(k_b_update, dim3(x.nblk), dim3(256), 0, s, d, x.th, b.m, x.n, x.t);
+        launch_dsolve_step(s, state, x.t, x.r, x.D, x.n, x.th, x.eh, b.m, x.part, x.nblk);
+        launch_dsolve_decide(s, state, x.part, x.nblk, dopts);
+        launch_dsolve_update(s, state, x.th, x.n, x.t, nullptr, nullptr);
     }
     PQPH_HIP(ctx, hipGetLastError());
     return PQPH_OK;
@@ -395,11 +224,17 @@ pqph_status enqueue_iteration(pqph_ctx* ctx, Batch& b, const BOpts& bo) {
 
 pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
     const int ns = b.ns, nb = b.nb;
-    BOpts bo{b.o.max_iter, b.o.diis_dim, b.o.diis_start, b.o.stall_window, b.o.tol,
-             b.o.diverge_factor};
+    DevSolveOpts dopts;
+    dopts.max_iter = b.o.max_iter;
+    dopts.m = b.m;
+    dopts.diis_on = b.o.diis_dim > 0;
+    dopts.diis_start = b.o.diis_start;
+    dopts.stall_window = b.o.stall_window;
+    dopts.tol = b.o.tol;
+    dopts.diverge_factor = b.o.diverge_factor;
     hipStream_t s0 = ctx->bstreams[0];
     pqph_status st;
-    hipLaunchKernelGGL(k_b_init, dim3((nb + 63) / 64), dim3(64), 0, ctx->stream, b.dst, nb);
+    for (int c = 0; c < nb; ++c) launch_dsolve_init(ctx->stream, b.dstate + (size_t)c * b.dsd);
     PQPH_HIP(ctx, hipGetLastError());
     // s0 starts after everything already on the context stream
     PQPH_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
@@ -410,7 +245,7 @@ pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
     auto body = [&]() -> pqph_status {
         PQPH_HIP(ctx, hipEventRecord(ctx->fork, s0));
         for (int i = 1; i < ns; ++i) PQPH_HIP(ctx, hipStreamWaitEvent(ctx->bstreams[i], ctx->fork, 0));
-        pqph_status e = enqueue_iteration(ctx, b, bo);
+        pqph_status e = enqueue_iteration(ctx, b, dopts);
         if (e) return e;
         for (int i = 1; i < ns; ++i) {
             PQPH_HIP(ctx, hipEventRecord(ctx->bevents[i], ctx->bstreams[i]));
@@ -447,8 +282,8 @@ pqph_status graph_mode(pqph_ctx* ctx, Batch& b) {
         }
         ++launched;
         if (launched < next_poll && launched < b.o.max_iter) continue;
-        ec = hipMemcpy2DAsync(flags, sizeof(int), &b.dst[0].active, sizeof(DevChain), sizeof(int), nb,
-                              hipMemcpyDeviceToHost, s0);
+        ec = hipMemcpy2DAsync(flags, sizeof(int), &b.head(0)->active, b.dsd * sizeof(double), sizeof(int),
+                              nb, hipMemcpyDeviceToHost, s0);
         if (ec == hipSuccess) ec = hipStreamSynchronize(s0);
         if (ec != hipSuccess) {
             result = pqph_fail(ctx, PQPH_DEVICE, std::string("poll: ") + hipGetErrorString(ec));
@@ -492,7 +327,7 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     pqph_default_opts(&o);
     if (opts_in) o = *opts_in;
     if (o.max_iter < 1 || !(o.tol > 0.0) || o.diis_dim < 0 || o.diis_dim > 16 ||
-        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kRing || o.max_rank != 0 ||
+        !(o.diverge_factor > 1.0) || o.stall_window < 0 || o.stall_window >= kSolveRing || o.max_rank != 0 ||
         (o.solver != 0 && o.solver != 2) || o.spin_adapted != 0)
         return pqph_fail(ctx, PQPH_INVALID_ARG,
                          "invalid solver options (batched: stall_window < 257, max_rank 0, solver 0 or 2, "
@@ -536,8 +371,8 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     for (auto& x : ch) total += x.n * (4 + 2 * (size_t)m) + (size_t)x.nblk * (m + 1) + pq_vertex_doubles(x.N);
     const size_t nsmall = (size_t)nbatch * (2 * m + 4);
     total += nsmall;
-    const size_t dstd = (sizeof(DevChain) * nbatch + sizeof(double) - 1) / sizeof(double);
-    total += dstd + 32;
+    b.dsd = dev_solve_doubles();
+    total += b.dsd * nbatch + 32;
     st = pqph_ensure_sv(ctx, total * sizeof(double));
     if (st) return st;
     st = pqph_ensure_host(ctx, nsmall);
@@ -561,7 +396,7 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     b.edev = p; p += nbatch;
     b.dmin = p; p += nbatch;
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
-    b.dst = reinterpret_cast<DevChain*>(p);
+    b.dstate = p;
     double* hst = ctx->host;
     auto S = [&](const Chain& x) { return ctx->bstreams[x.stream]; };
 
@@ -587,9 +422,9 @@ extern "C" pqph_status pq_solve_batched(pqph_ctx* ctx, int nbatch, const int* np
     } else {
         if ((st = graph_mode(ctx, b))) return st;
         // per-chain reports from the device states
-        std::vector<DevChain> hs(nbatch);
-        PQPH_HIP(ctx, hipMemcpyAsync(hs.data(), b.dst, sizeof(DevChain) * nbatch, hipMemcpyDeviceToHost,
-                                     ctx->stream));
+        std::vector<SolveHead> hs(nbatch);
+        PQPH_HIP(ctx, hipMemcpy2DAsync(hs.data(), sizeof(SolveHead), b.head(0), b.dsd * sizeof(double),
+                                       sizeof(SolveHead), nbatch, hipMemcpyDeviceToHost, ctx->stream));
         PQPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
         for (int c = 0; c < nbatch; ++c) {
             ch[c].iters = hs[c].iters;
